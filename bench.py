@@ -1,0 +1,283 @@
+"""Throughput of the CGP QG time step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extras]
+
+Workload (the value): single-layer barotropic QG, 512 x 1024 fine grid, FP64,
+CGP factor 2 (256 x 512 coarse solve), Re 450, Ro 0.0036, dt 2.5e-5, seeded
+omega0 = 1e-3 N(0,1), forcing (1/Ro) sin(pi y).  Metric: fine-grid
+Mpoint-steps/s = 512 * 1024 * K / seconds over K timed steps (hipGraph replay
+of one step, inputs resident in HBM).  Beside it: the same basin with the
+full-grid solve (factor 1) and factor 4, the CGP/full-grid speed-up, the
+adjoint/forward time ratio of the 256 x 512, 200-step checkpointed adjoint,
+per-pass launch times (HIP events on the library's stream), the roofline of
+the dominant kernel and the FP64 oracle timed on the host CPU.
+
+Prints ONE JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "Mpoint-steps/s at 512x1024, CGP vs full-grid on 1 GPU; adjoint/forward time ratio"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time two layers, FP32 and the 64-member ensemble")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--only", default="", help="comma list: l0,l1,l2,timed (profiling runs)")
+    return ap.parse_args()
+
+
+def pass_bytes(case, es):
+    """Algorithmic bytes of one launch of each pass (fine node arrays with ring,
+    coarse interior spectra); pass D averaged over the three stages."""
+    fine = (case.nx + 1) * (case.ny + 1) * case.nlayers * es
+    c = 2 ** case.level
+    coarse = (case.nx // c - 1) * (case.ny // c - 1) * case.nlayers * es
+    return {"A": fine + coarse, "B": 2 * coarse, "C": coarse + fine,
+            "D": (4.0 + 2.0 / 3.0) * fine}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("stencil_kernels.hip", "solve_kernels.hip", "fft_lds.hpp", "cgp_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1308_3290_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                          "the multi-GPU design is described, not built (use --gpus 1)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import cgp_inputs as ci
+    from paper_1308_3290_amd import api
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    only = set(filter(None, args.only.split(",")))
+    K, W = args.steps, args.warmup
+
+    def timed_run(case, use_graph=True, steps=K, warm=W, dtype="f64"):
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        rng = np.random.default_rng(case.seed)
+        w0 = ci.initial_field(case, rng)
+        F = torch.as_tensor(ci.forcing_field(case), dtype=tdt, device=dev)
+        ens = api.Ensemble([api.config_from_case(case, dtype)], device=dev)
+        w = torch.as_tensor(w0, dtype=tdt, device=dev).reshape(-1).contiguous()
+        Fp = F.reshape(-1).contiguous()
+        if case.nlayers == 2:
+            Fp = torch.cat([Fp, torch.zeros_like(Fp)])  # layer-2 forcing slot unused
+            Fp = Fp[: w.numel()].contiguous()
+        ens.step(w, Fp, nsteps=warm, use_graph=use_graph)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        ens.step(w, Fp, nsteps=steps, use_graph=use_graph)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        finite = bool(torch.isfinite(w).all().item())
+        return ms, finite, ens, w, Fp
+
+    result = {}
+    # ---------------------------------------------------------------- main line
+    rates = {}
+    for lv in (1, 0, 2):
+        if only and f"l{lv}" not in only:
+            continue
+        case = ci.case_c1(lv)
+        ms, finite, ens, w, Fp = timed_run(case)
+        rate = case.points * K / (ms * 1e-3) / 1e6
+        rates[lv] = dict(ms=ms, rate=rate, finite=finite)
+        log(f"512x1024 FP64 level {lv}: {ms / K * 1e3:.1f} us/step, {rate:.0f} Mpoint-steps/s"
+            f" (finite={finite})")
+        if lv == 1:
+            ms_direct, _, _, _, _ = timed_run(case, use_graph=False, steps=min(K, 200), warm=5)
+            rates["direct"] = case.points * min(K, 200) / (ms_direct * 1e-3) / 1e6
+            log(f"  without graph: {ms_direct / min(K, 200) * 1e3:.1f} us/step")
+        del ens, w, Fp
+    # ---------------------------------------------------------------- per-pass roofline
+    roof = None
+    if not only or "timed" in only:
+        case = ci.case_c1(1)
+        rng = np.random.default_rng(case.seed)
+        b = api.Basin(api.config_from_case(case), device=dev)
+        w = torch.as_tensor(ci.initial_field(case, rng), device=dev)
+        F = torch.as_tensor(ci.forcing_field(case), device=dev)
+        api.cgp_step_timed(b.handle, w, F, 5)
+        ms = api.cgp_step_timed(b.handle, w, F, 50)
+        by = pass_bytes(case, 8)
+        names = ["A", "B", "C", "D"]
+        per_step_ms = {n: 3 * ms[i] for i, n in enumerate(names)}
+        dom = max(names, key=lambda n: per_step_ms[n])
+        i = names.index(dom)
+        achieved = by[dom] / (ms[i] * 1e-3) / 1e9
+        kernel_names = {"A": "k_restrict_rowdst", "B": "k_col_solve", "C": "k_rowdst_prolong",
+                        "D": "k_stencil_rk3"}
+        passes = {kernel_names[n]: {"us_per_launch": ms[j] * 1e3,
+                                    "alg_bytes_per_launch": by[n],
+                                    "achieved_GBs": by[n] / (ms[j] * 1e-3) / 1e9}
+                  for j, n in enumerate(names)}
+        log("per-pass: " + json.dumps(passes))
+        traffic = None
+        tfile = os.path.join(ROOT, "profiles", "traffic_c1_l1.json")
+        if os.path.exists(tfile):
+            t = json.load(open(tfile))
+            if t.get("source_hash") == source_hash() and kernel_names[dom] in t.get("kernels", {}):
+                traffic = t["kernels"][kernel_names[dom]]["hbm_bytes_per_launch"]
+        roof = {"bound": "hbm", "kernel": kernel_names[dom], "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": traffic, "alg_bytes_per_launch": by[dom],
+                "us_per_launch": round(ms[i] * 1e3, 2)}
+        result["passes"] = passes
+        del b, w, F
+    # ---------------------------------------------------------------- adjoint ratio
+    adj = None
+    if not args.no_adjoint and not only:
+        p = ci.adjoint_c4()
+        c = p.case
+        b = api.Basin(api.config_from_case(c), device=dev)
+        w0 = torch.as_tensor(p.omega0, device=dev).requires_grad_(True)
+        F = torch.as_tensor(p.forcing, device=dev).requires_grad_(True)
+        idx = torch.as_tensor(p.obs_index, device=dev)
+        obs = torch.as_tensor(p.obs_value, device=dev)
+        for rep in range(2):  # first pass warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            wT = api.Trajectory.apply(w0, F, b, c.nsteps, p.ckpt_every)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L = ((wT.view(-1)[idx] - obs) ** 2).mean()
+            w0.grad = None
+            F.grad = None
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+        adj = {"forward_ms": (t1 - t0) * 1e3, "backward_ms": (t3 - t2) * 1e3,
+               "ratio": (t3 - t2) / (t1 - t0), "workload": "256x512 FP64 CGP factor 2, "
+               "200 steps, checkpoint every 20, final-time misfit at 1% of nodes"}
+        log(f"adjoint: forward {adj['forward_ms']:.1f} ms, backward {adj['backward_ms']:.1f} ms, "
+            f"ratio {adj['ratio']:.2f}")
+        del b, w0, F
+    # ---------------------------------------------------------------- extras
+    extras = {}
+    if args.extras:
+        for lv in (1, 0, 2):
+            case = ci.case_c2(lv)
+            ms, finite, *_ = timed_run(case, steps=min(K, 500))
+            extras[f"two_layer_l{lv}"] = case.points * min(K, 500) / (ms * 1e-3) / 1e6
+        for lv in (1, 0):
+            case = ci.case_c1(lv)
+            ms, finite, *_ = timed_run(case, dtype="f32")
+            extras[f"fp32_l{lv}"] = case.points * K / (ms * 1e-3) / 1e6
+        for dt_ in ("f64", "f32"):
+            members = ci.ensemble_c3(dtype=dt_)
+            tdt = torch.float64 if dt_ == "f64" else torch.float32
+            ens = api.Ensemble([api.config_from_case(m.case) for m in members], device=dev)
+            Wp = ens.pack([m.omega0 for m in members])
+            Fp = ens.pack([m.forcing for m in members])
+            ens.step(Wp, Fp, nsteps=5)
+            torch.cuda.synchronize()
+            s = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            n_ens = 200
+            e0.record(s)
+            ens.step(Wp, Fp, nsteps=n_ens)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            pts = sum(m.case.points for m in members)
+            extras[f"ensemble64_{dt_}"] = pts * n_ens / (ms * 1e-3) / 1e6
+            extras[f"ensemble64_{dt_}_GBs_model"] = (pts * n_ens * (20 + 12 / 4) * (8 if dt_ == "f64" else 4)
+                                                     / (ms * 1e-3) / 1e9)
+            assert tdt == Wp.dtype
+            del ens, Wp, Fp
+        log("extras: " + json.dumps(extras))
+    # ---------------------------------------------------------------- CPU oracle
+    cpu = None
+    if not args.no_cpu and not only:
+        from oracle import model as om
+        from oracle.grid import Grid
+        from oracle.model import Physics
+        case = ci.case_c1(1)
+        rng = np.random.default_rng(case.seed)
+        w = ci.initial_field(case, rng)
+        F = ci.forcing_field(case)
+        g = Grid(case.nx, case.ny)
+        phys = Physics(inv_re=case.inv_re, inv_ro=case.inv_ro)
+        n = 0
+        t0 = time.perf_counter()
+        while n < 3 or time.perf_counter() - t0 < args.cpu_seconds:
+            w = om.step(w, F, g, case.level, phys, case.dt)
+            n += 1
+        dt_cpu = time.perf_counter() - t0
+        cpu = {"value": round(case.points * n / dt_cpu / 1e6, 4), "unit": "Mpoint-steps/s",
+               "cores": 1, "kind": "oracle",
+               "sample": f"{n} steps of the 512x1024 FP64 CGP-factor-2 workload "
+                         f"({dt_cpu:.1f} s; NumPy/SciPy single-threaded)"}
+        log(f"cpu oracle: {cpu['value']} Mpoint-steps/s over {n} steps")
+
+    main_rate = rates.get(1, {}).get("rate")
+    out = {
+        "metric": METRIC,
+        "value": round(main_rate, 1) if main_rate else None,
+        "unit": "Mpoint-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(rates[1]["ms"] / K, 6) if 1 in rates else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "single-layer barotropic QG, 512x1024 fine grid, FP64, "
+                               "CGP factor 2 (256x512 sine-transform solve), Re 450, Ro 0.0036, "
+                               "dt 2.5e-5, seeded omega0", "global_batch": 1, "seq_len": None,
+                   "parallelism": "single GPU", "launch": "hipGraph replay of one step"},
+        "full_grid_value": round(rates[0]["rate"], 1) if 0 in rates else None,
+        "cgp4_value": round(rates[2]["rate"], 1) if 2 in rates else None,
+        "speedup_cgp2_vs_full": round(rates[1]["rate"] / rates[0]["rate"], 3)
+        if 0 in rates and 1 in rates else None,
+        "speedup_cgp4_vs_full": round(rates[2]["rate"] / rates[0]["rate"], 3)
+        if 0 in rates and 2 in rates else None,
+        "no_graph_value": round(rates["direct"], 1) if "direct" in rates else None,
+        "all_finite": all(v["finite"] for k, v in rates.items() if k != "direct"),
+        "adjoint_forward_ratio": round(adj["ratio"], 3) if adj else None,
+        "adjoint": adj,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if extras:
+        out["extras"] = {k: round(v, 1) for k, v in extras.items()}
+    if "passes" in result:
+        out["passes"] = result["passes"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * cgp.h -- C ABI of the MI355X (gfx950) coarse-grid-projection (CGP) QG time step.
+ *
+ * Method: O. San and A. E. Staples, "An Efficient Coarse Grid Projection
+ * Method for Quasigeostrophic Models of Large-Scale Ocean Circulation"
+ * (arXiv 1308.3290).  One CGPRK3 step (Sec. 3.2) advances the relative
+ * vorticity of the one-layer barotropic model (Sec. 2.1) or the two-layer
+ * stratified model (Sec. 2.2) on a rectangular beta-plane basin with free-slip
+ * walls.  Each of the three TVD-RK3 stages (Sec. 4.2):
+ *   (ii)  restricts the fine vorticity to the coarse grid by full weighting,
+ *         level times (Sec. 3.1);
+ *   (iii) solves the coarse elliptic problem with sine transforms and a
+ *         diagonal eigenvalue divide (Sec. 4.3); for two layers the coupled
+ *         problem is split into a barotropic Poisson and a baroclinic
+ *         Helmholtz problem (equivalent to that section's 2x2 per-mode solve);
+ *   (iv)  prolongs psi bilinearly back to the fine grid (Sec. 3.1);
+ *   (i)   updates the vorticity on the fine grid with the Arakawa Jacobian
+ *         (Sec. 4.1), the beta term, Laplacian eddy viscosity and the forcing.
+ *
+ * Conventions shared by every call
+ *   - nx, ny count grid INTERVALS: nodes i = 0..nx, j = 0..ny (Sec. 4.4 index
+ *     ranges).  Node arrays are y-major with x contiguous, element (j, i) at
+ *     j*(nx+1) + i; two-layer arrays are [2][ny+1][nx+1], layer 1 (top) first.
+ *   - Prognostic variable: omega = Laplacian(psi) (one layer, Sec. 2.1) or
+ *     Q_i = Laplacian(psi_i) + F_i (psi_j - psi_i) (two layers, Sec. 2.2):
+ *     the potential vorticity with the planetary part y removed and divided
+ *     by Ro.  The step solves Laplacian_h psi = omega on the coarse grid.
+ *   - Walls: psi = 0 and omega = 0 on the boundary ring (Sec. 2.1, 2.2).
+ *     Input rings are treated as zero whatever they hold; every output ring
+ *     is written as zero.  The forcing ring is ignored.
+ *   - Memory: every pointer argument named *_dev is DEVICE memory owned by the
+ *     caller; the library never allocates device memory.  The workspace given
+ *     to a create call belongs to the handle until cgp_destroy and must not be
+ *     touched meanwhile.  Host pointers are read during the call only.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  All device work is enqueued asynchronously on it; no call
+ *     synchronises the host except where stated.  A handle is not thread
+ *     safe; two calls on one handle must not overlap in time on the device.
+ *   - Errors: every call returns a cgp_status; nothing aborts or throws
+ *     across the ABI.  cgp_last_error() gives a message for the calling
+ *     thread's most recent failure.  Invalid sizes, pointers or parameters give
+ *     CGP_ERR_INVALID, sizes outside the supported set CGP_ERR_UNSUPPORTED,
+ *     HIP failures CGP_ERR_DEVICE.
+ */
+#ifndef CGP_H
+#define CGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CGP_OK = 0,
+  CGP_ERR_INVALID = 1,
+  CGP_ERR_UNSUPPORTED = 2,
+  CGP_ERR_DEVICE = 3,
+  CGP_ERR_NONFINITE = 4
+} cgp_status;
+
+typedef enum { CGP_F32 = 0, CGP_F64 = 1 } cgp_dtype;
+
+/* One basin.  Vorticity-form coefficients: dividing the nondimensional
+ * equations of Sec. 2.1 / 2.2 by Ro gives
+ *   one layer:  d omega/dt = -J(psi, omega) - inv_ro J(psi, y) + inv_re Lap(omega) + F
+ *   two layers: d Q_i/dt  = -J(psi_i, Q_i) - inv_ro J(psi_i, y) + inv_re Lap(zeta_i)
+ *                           + [i=1] F - [i=2] drag zeta_2,
+ *               zeta_i = Q_i - F_i (psi_j - psi_i),
+ * with inv_ro = 1/Ro, inv_re = 1/Re (= A/Ro for two layers), f1 = Fr/(Ro delta),
+ * f2 = Fr/(Ro (1 - delta)), drag = sigma/Ro.  Supported sizes: level >= 0,
+ * nx and ny divisible by 2^level, and the coarse interval counts
+ * Mx = nx/2^level, My = ny/2^level each of the form 2^k or 3*2^k with
+ * 4 <= M <= 1024 (FP64) or 2048 (FP32). */
+typedef struct cgp_config {
+  int32_t nx, ny;      /* fine grid intervals */
+  int32_t level;       /* coarsening level l; factor 2^l; 0 = plain full-grid step */
+  int32_t nlayers;     /* 1 or 2 */
+  int32_t dtype;       /* cgp_dtype: arithmetic and storage type of every field */
+  int32_t reserved;    /* must be 0 */
+  double lx, ly, y0;   /* basin [0, lx] x [y0, y0 + ly] */
+  double inv_re, inv_ro;
+  double f1, f2, drag; /* two-layer coefficients, ignored for one layer */
+  double dt;           /* fixed time step */
+} cgp_config;
+
+typedef struct cgp_handle cgp_handle;
+
+/* Bytes of device workspace a single-basin handle needs.  Host only. */
+cgp_status cgp_workspace_size(const cgp_config* cfg, size_t* bytes);
+
+/* Create a single-basin handle.  Builds the FP64 sine/cosine and eigenvalue
+ * tables (Sec. 4.3) on the host and uploads them into workspace_dev on
+ * `stream`.  workspace_dev must be 256-byte aligned and at least
+ * cgp_workspace_size bytes. */
+cgp_status cgp_create(const cgp_config* cfg, void* workspace_dev, size_t bytes,
+                      void* stream, cgp_handle** out);
+
+/* Release the handle's host state.  The workspace goes back to the caller
+ * once work enqueued on the handle has finished. */
+cgp_status cgp_destroy(cgp_handle* h);
+
+/* Advance omega_dev ([L][ny+1][nx+1], in/out) by nsteps CGPRK3 steps
+ * (Sec. 3.2 listing: three restrict-solve-prolong cycles and three fine-grid
+ * updates per step).  forcing_dev is the wind-forcing field F
+ * ([ny+1][nx+1], vorticity units, layer 1 only), e.g. inv_ro*sin(pi*y).
+ * psi_out_dev (nullable, [L][ny+1][nx+1]): if set, receives
+ * psi = P^l L_c^-1 R^l omega of the final state.  nsteps >= 0. */
+cgp_status cgp_step(cgp_handle* h, void* omega_dev, const void* forcing_dev,
+                    void* psi_out_dev, int32_t nsteps, void* stream);
+
+/* The CGP elliptic map alone: psi_dev = P^l L_c^-1 R^l omega_dev
+ * (Sec. 3 steps (ii)-(iv); for two layers the coupled solve of Sec. 4.3).
+ * Arrays [L][ny+1][nx+1]. */
+cgp_status cgp_solve(cgp_handle* h, const void* omega_dev, void* psi_dev, void* stream);
+
+/* Domain-averaged diagnostics of a state: out_dev[2*l] = E_l =
+ * 1/(2A) sum over grid links of |forward difference of psi_l|^2 dx dy
+ * (eq. 26 divided by the basin area A), out_dev[2*l+1] = Z_l = 1/(2A) sum of
+ * omega_l^2 dx dy over interior nodes.  out_dev holds 2*L doubles (FP64
+ * accumulation in a fixed order, so the result is deterministic). */
+cgp_status cgp_diagnostics(cgp_handle* h, const void* omega_dev, const void* psi_dev,
+                           double* out_dev, void* stream);
+
+/* flag_dev (one int32 on the device) is set to 1 if any of the count
+ * elements of field_dev (the handle's dtype) is NaN or infinite, else 0. */
+cgp_status cgp_check_finite(cgp_handle* h, const void* field_dev, int64_t count,
+                            int32_t* flag_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Adjoint (one-layer, FP64).  For w_{s+1} = a_s w_n + b_s (w_s + dt G(w_s)),
+ * (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3), the adjoint reverses the stages:
+ *   mu = b_s dt lam_{s+1};  g_F += mu;  acc_n += a_s lam_{s+1};
+ *   lam_s = b_s lam_{s+1} + J(psi_s, mu) + inv_re Lap(mu)
+ *           + A_l[ -J(omega_s, mu) + inv_ro J(mu, y) ],
+ * using (J(psi,.))^T = -J(psi,.), (J(., omega))^T = J(omega, .), the skew
+ * beta stencil and the symmetry of A_l = P^l L_c^-1 R^l (P = 4 R^T per level
+ * in plain sums).  The tape holds the recomputed stage states.
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of device tape cgp_adjoint_step needs for a segment of nsteps. */
+cgp_status cgp_tape_size(const cgp_config* cfg, int32_t nsteps, size_t* bytes);
+
+/* Reverse sweep over one segment of nsteps >= 1 steps that starts from the
+ * state omega_n_dev.  The forward states of the segment are recomputed into
+ * tape_dev; then, on entry lambda_dev holds dL/d omega_{n+nsteps} and on exit
+ * dL/d omega_n, and grad_forcing_dev ([ny+1][nx+1]) is INCREMENTED by the
+ * segment's dL/dF.  All FP64, one layer only. */
+cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n_dev, const void* forcing_dev,
+                            int32_t nsteps, void* lambda_dev, void* grad_forcing_dev,
+                            void* tape_dev, size_t tape_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Ensembles: independent basins of uneven size and coefficients advanced
+ * together, each pass of a stage one launch over every member.  A single
+ * basin is an ensemble of one.  All members share the dtype and nlayers.
+ * Packed arrays hold member m's [L][ny_m+1][nx_m+1] field at element offset
+ * offsets[m] (cgp_ensemble_offsets), members in order, no gaps.
+ * ---------------------------------------------------------------------- */
+cgp_status cgp_ensemble_offsets(const cgp_config* members, int32_t count, int64_t* offsets_host,
+                                int64_t* total_elements);
+cgp_status cgp_ensemble_workspace_size(const cgp_config* members, int32_t count, size_t* bytes);
+cgp_status cgp_ensemble_create(const cgp_config* members, int32_t count, void* workspace_dev,
+                               size_t bytes, void* stream, cgp_handle** out);
+/* Advance every member by nsteps.  With use_graph != 0 the step is captured
+ * once into a HIP graph (per pointer set) and replayed nsteps times. */
+cgp_status cgp_ensemble_step(cgp_handle* h, void* omega_packed_dev,
+                             const void* forcing_packed_dev, int32_t nsteps, int32_t use_graph,
+                             void* stream);
+
+/* Measurement.  Runs nsteps steps exactly as cgp_ensemble_step without a
+ * graph (any handle), recording a HIP event on `stream` before and after every
+ * kernel launch of the step, then SYNCHRONISES the stream and writes to
+ * ms_host[0..3] the mean duration in milliseconds of one launch of each pass
+ * (0: restriction + x transform, 1: y transforms + eigenvalue divide,
+ * 2: x transform + prolongation, 3: Arakawa right-hand side + RK3 combine) and
+ * to ms_host[4] the elapsed time of the whole call. */
+cgp_status cgp_step_timed(cgp_handle* h, void* omega_dev, const void* forcing_dev, int32_t nsteps,
+                          double* ms_host, void* stream);
+
+/* Message for the calling thread's last failure ("" if none). */
+const char* cgp_last_error(void);
+
+/* Library version string. */
+const char* cgp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGP_H */

@@ -32,11 +32,15 @@ def sine_matrix(n: int) -> np.ndarray:
 
 
 def eigenvalues(nx: int, ny: int, dx: float, dy: float) -> np.ndarray:
-    """lambda[l-1, k-1] = (2cos(pi k/nx) - 2)/dx^2 + (2cos(pi l/ny) - 2)/dy^2."""
+    """lambda[l-1, k-1] = (2cos(pi k/nx) - 2)/dx^2 + (2cos(pi l/ny) - 2)/dy^2.
+
+    Evaluated as -4 sin^2(pi k/(2 nx))/dx^2 - 4 sin^2(pi l/(2 ny))/dy^2, the same
+    number without the cancellation of 2cos - 2 (which costs ~2e-11 relative
+    accuracy in the lowest mode at n = 1024)."""
     k = np.arange(1, nx)
     l = np.arange(1, ny)
-    lx = (2.0 * np.cos(np.pi * k / nx) - 2.0) / (dx * dx)
-    ly = (2.0 * np.cos(np.pi * l / ny) - 2.0) / (dy * dy)
+    lx = -4.0 * np.sin(np.pi * k / (2.0 * nx)) ** 2 / (dx * dx)
+    ly = -4.0 * np.sin(np.pi * l / (2.0 * ny)) ** 2 / (dy * dy)
     return ly[:, None] + lx[None, :]
 
 

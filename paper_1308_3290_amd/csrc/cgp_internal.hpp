@@ -1,0 +1,95 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels of
+// the CGP time step.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cgp {
+
+constexpr int kMaxStages = 12;   // radix stages of one complex FFT (L <= 4096)
+constexpr int kThreads = 256;    // threads per block of the transform kernels
+constexpr int kTileX = 64;       // stencil tile (one wavefront wide)
+constexpr int kTileY = 4;
+
+enum Pass { PASS_A = 0, PASS_B = 1, PASS_C = 2, PASS_D = 3, NUM_PASSES = 4 };
+
+// Per-basin descriptor, uploaded once at create.  Offsets are in elements of
+// the handle's scalar type T unless stated.
+struct MemberDesc {
+  int nx, ny;           // fine intervals
+  int c;                // coarsening factor 2^level
+  int Mx, My;           // coarse intervals
+  int nlayers;
+  int Lr, Lc;           // complex FFT lengths 2*Mx (rows) and 2*My (columns)
+  int nst_r, nst_c;     // radix stage counts
+  int rad_r[kMaxStages];
+  int rad_c[kMaxStages];
+  int pa;               // pass A: sequence pairs per block
+  int pb;               // pass B: sequence pairs per block
+  int tj;               // pass C: coarse rows owned per block
+  int pc;               // pass C: sequence pairs per block (derived from tj)
+  int blk0[NUM_PASSES]; // first block of this member in each pass's grid
+  int nblk[NUM_PASSES]; // blocks of this member in each pass
+  long long field_off;  // packed fine fields ([L][ny+1][nx+1] per member)
+  long long wt_off;     // coarse spectra: L modes x (Mx-1) x (My-1), k-major
+  long long twr_off;    // row twiddles, in complex elements of T (Lr entries)
+  long long twc_off;    // column twiddles (Lc entries)
+  long long lam_off;    // doubles: lambda_x (Mx-1) then lambda_y (My-1)
+  double dx, dy;
+  double inv_re, inv_ro, f1, f2, drag, dt;
+  double delta;         // barotropic weight f2/(f1+f2) (0.5 if f1 = f2 = 0)
+};
+
+template <typename T>
+struct cplx {
+  T x, y;
+};
+
+// Locate the member owning block `b` of pass `p` (members are laid out in
+// order in every pass's grid).
+__device__ inline int find_member(const MemberDesc* md, int nm, int p, int b) {
+  int lo = 0, hi = nm - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (md[mid].blk0[p] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Launch wrappers implemented in the kernel translation units.
+template <typename T>
+struct Launch {
+  // pass A: restrict (level times) + forward x sine transform, src -> spectra
+  static hipError_t restrict_rowdst(const MemberDesc* md, int nm, int nblk, size_t lds,
+                                    const T* src, T* wt, const cplx<T>* tw, hipStream_t s);
+  // pass B: y sine transform, eigenvalue divide, y sine transform (in place)
+  static hipError_t col_solve(const MemberDesc* md, int nm, int nblk, size_t lds, T* wt,
+                              const cplx<T>* tw, const double* lam, hipStream_t s);
+  // pass C: inverse x sine transform + prolongation; accumulate != 0 adds to dst
+  static hipError_t rowdst_prolong(const MemberDesc* md, int nm, int nblk, size_t lds,
+                                   const T* wt, T* dst, int accumulate, const cplx<T>* tw,
+                                   hipStream_t s);
+  // pass D: Arakawa right-hand side + TVD-RK3 stage combine
+  static hipError_t stencil_rk3(const MemberDesc* md, int nm, int nblk, const T* ws,
+                                const T* psi, const T* forcing, const T* wn, T* out, double a,
+                                double b, hipStream_t s);
+  // diagnostics partial sums (2 per layer per block) + ordered final sum
+  static hipError_t diagnostics(const MemberDesc* md, const T* w, const T* psi, double* partial,
+                                int nblk, double* out, hipStream_t s);
+  static hipError_t check_finite(const T* f, long long n, int* partial, int nblk, int* flag,
+                                 hipStream_t s);
+};
+
+// Adjoint kernels (FP64 only).
+struct AdjLaunch {
+  // lam_out = b lam_in + J(psi_s, mu) + inv_re Lap(mu) [+ acc if add_acc];
+  // psi_src = -J(omega_s, mu) + inv_ro J(mu, y); acc (+)= a lam_in; gF += mu,
+  // with mu = b dt lam_in.
+  static hipError_t stencil(const MemberDesc* md, int nblk, const double* lam_in,
+                            const double* ws, const double* psi, double* lam_out,
+                            double* psi_src, double* acc, double* gF, double a, double b,
+                            int acc_mode, hipStream_t s);
+};
+
+}  // namespace cgp

@@ -1,0 +1,630 @@
+// Host runtime and C ABI of the CGP time step (see include/cgp.h).
+//
+// A handle describes one or more basins ("members").  Everything it needs on
+// the device lives in the caller's workspace, laid out as
+//   [member descriptors][twiddle tables][eigenvalue tables][coarse spectra]
+//   [psi][stage 1][stage 2][reduction partials]
+// with 256-byte aligned regions.  Fine fields of all members are packed back
+// to back in member order.  Every pass of a stage is ONE launch over all
+// members; the block -> member map is a prefix sum stored in the descriptors.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/cgp.h"
+#include "cgp_internal.hpp"
+
+using namespace cgp;
+
+namespace {
+
+thread_local std::string g_err;
+
+cgp_status fail(cgp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+cgp_status hip_fail(hipError_t e, const char* what) {
+  return fail(CGP_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                      \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kDiagBlocks = 64;
+constexpr int kFiniteBlocks = 256;
+constexpr size_t kMaxLds = 64 * 1024;
+constexpr int kMaxPairElems = 1024;  // complex elements per LDS ping-pong buffer
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool pow2_or_3pow2(int n) {
+  if (n <= 0) return false;
+  while (n % 2 == 0) n /= 2;
+  return n == 1 || n == 3;
+}
+
+// Radix sequence of a complex FFT of length L = 2^k or 3*2^k: radix 4 while
+// more than a factor 4 remains, the radix 3, then 4s, then a final 2.
+int radices(int L, int* out) {
+  int n = 0;
+  while (L % 4 == 0 && L > 4) { out[n++] = 4; L /= 4; }
+  if (L % 3 == 0) { out[n++] = 3; L /= 3; }
+  while (L % 4 == 0) { out[n++] = 4; L /= 4; }
+  while (L % 2 == 0) { out[n++] = 2; L /= 2; }
+  return n;
+}
+
+cgp_status validate(const cgp_config* c) {
+  if (!c) return fail(CGP_ERR_INVALID, "config is NULL");
+  if (c->reserved != 0) return fail(CGP_ERR_INVALID, "reserved field must be 0");
+  if (c->nlayers != 1 && c->nlayers != 2)
+    return fail(CGP_ERR_INVALID, "nlayers must be 1 or 2 (got %d)", c->nlayers);
+  if (c->dtype != CGP_F32 && c->dtype != CGP_F64)
+    return fail(CGP_ERR_INVALID, "dtype must be CGP_F32 or CGP_F64 (got %d)", c->dtype);
+  if (c->level < 0 || c->level > 6) return fail(CGP_ERR_INVALID, "level must be in 0..6");
+  if (c->nx < 4 || c->ny < 4) return fail(CGP_ERR_INVALID, "nx, ny must be >= 4");
+  const int f = 1 << c->level;
+  if (c->nx % f || c->ny % f)
+    return fail(CGP_ERR_INVALID, "nx=%d, ny=%d not divisible by 2^level=%d", c->nx, c->ny, f);
+  const int Mx = c->nx / f, My = c->ny / f;
+  if (Mx < 4 || My < 4)
+    return fail(CGP_ERR_UNSUPPORTED, "coarse grid %dx%d below 4x4", Mx, My);
+  if (!pow2_or_3pow2(Mx) || !pow2_or_3pow2(My))
+    return fail(CGP_ERR_UNSUPPORTED, "coarse sizes %dx%d must be 2^k or 3*2^k", Mx, My);
+  const int mmax = c->dtype == CGP_F64 ? 1024 : 2048;
+  if (Mx > mmax || My > mmax)
+    return fail(CGP_ERR_UNSUPPORTED, "coarse size above %d", mmax);
+  const double vals[] = {c->lx, c->ly, c->y0, c->inv_re, c->inv_ro, c->f1, c->f2, c->drag, c->dt};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(CGP_ERR_INVALID, "non-finite coefficient");
+  if (!(c->lx > 0) || !(c->ly > 0)) return fail(CGP_ERR_INVALID, "lx, ly must be > 0");
+  if (c->inv_re < 0 || c->f1 < 0 || c->f2 < 0 || c->drag < 0)
+    return fail(CGP_ERR_INVALID, "inv_re, f1, f2, drag must be >= 0");
+  return CGP_OK;
+}
+
+struct Layout {
+  size_t desc = 0, tw = 0, lam = 0, wt = 0, psi = 0, st1 = 0, st2 = 0, diag = 0, fin = 0, total = 0;
+  long long field_elems = 0;
+};
+
+struct Plan {
+  std::vector<MemberDesc> md;
+  Layout lay;
+  int nblk[NUM_PASSES] = {0, 0, 0, 0};
+  size_t lds[3] = {0, 0, 0};
+  int dtype = CGP_F64, nlayers = 1;
+};
+
+cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
+  if (!cfgs || count < 1) return fail(CGP_ERR_INVALID, "need at least one member");
+  const int dtype = cfgs[0].dtype, nl = cfgs[0].nlayers;
+  const size_t es = dtype == CGP_F64 ? 8 : 4;
+  plan->dtype = dtype;
+  plan->nlayers = nl;
+  plan->md.assign(count, MemberDesc{});
+  long long fld = 0, wt = 0, tw = 0, lam = 0;
+  for (int m = 0; m < count; ++m) {
+    const cgp_config& c = cfgs[m];
+    cgp_status st = validate(&c);
+    if (st != CGP_OK) return st;
+    if (c.dtype != dtype || c.nlayers != nl)
+      return fail(CGP_ERR_INVALID, "all members must share dtype and nlayers");
+    MemberDesc& d = plan->md[m];
+    d.nx = c.nx;
+    d.ny = c.ny;
+    d.c = 1 << c.level;
+    d.Mx = c.nx / d.c;
+    d.My = c.ny / d.c;
+    d.nlayers = nl;
+    d.Lr = 2 * d.Mx;
+    d.Lc = 2 * d.My;
+    d.nst_r = radices(d.Lr, d.rad_r);
+    d.nst_c = radices(d.Lc, d.rad_c);
+    d.pa = std::max(1, kMaxPairElems / d.Lr);
+    d.pb = std::max(1, kMaxPairElems / d.Lc);
+    const int halo = d.c > 1 ? 1 : 0;
+    if (nl == 1) {
+      d.pc = std::max(1, kMaxPairElems / d.Lr);
+      d.tj = 2 * d.pc - halo;
+    } else {
+      d.pc = std::max(1 + halo, kMaxPairElems / d.Lr);
+      d.tj = d.pc - halo;
+    }
+    const int rows_a = nl == 1 ? 2 * d.pa : d.pa;
+    const int cols_b = nl == 1 ? 2 * d.pb : d.pb;
+    d.nblk[PASS_A] = (d.My - 1 + rows_a - 1) / rows_a;
+    d.nblk[PASS_B] = (d.Mx - 1 + cols_b - 1) / cols_b;
+    d.nblk[PASS_C] = halo ? (d.My + d.tj - 1) / d.tj : (d.My + 1 + d.tj - 1) / d.tj;
+    d.nblk[PASS_D] = ((d.nx + kTileX) / kTileX) * ((d.ny + kTileY) / kTileY);
+    for (int p = 0; p < NUM_PASSES; ++p) {
+      d.blk0[p] = plan->nblk[p];
+      plan->nblk[p] += d.nblk[p];
+    }
+    d.field_off = fld;
+    fld += (long long)nl * (c.ny + 1) * (c.nx + 1);
+    d.wt_off = wt;
+    wt += (long long)nl * (d.Mx - 1) * (d.My - 1);
+    d.twr_off = tw;
+    tw += d.Lr;
+    d.twc_off = tw;
+    tw += d.Lc;
+    d.lam_off = lam;
+    lam += (d.Mx - 1) + (d.My - 1);
+    d.dx = c.lx / c.nx;
+    d.dy = c.ly / c.ny;
+    d.inv_re = c.inv_re;
+    d.inv_ro = c.inv_ro;
+    d.f1 = nl == 2 ? c.f1 : 0.0;
+    d.f2 = nl == 2 ? c.f2 : 0.0;
+    d.drag = nl == 2 ? c.drag : 0.0;
+    d.dt = c.dt;
+    d.delta = (d.f1 + d.f2 > 0) ? d.f2 / (d.f1 + d.f2) : 0.5;
+    const size_t cs = 2 * es;
+    const size_t la = 2 * (size_t)d.pa * d.Lr * cs;
+    const size_t lb = 2 * (size_t)d.pb * d.Lc * cs;
+    const size_t lc = 2 * (size_t)d.pc * d.Lr * cs + (size_t)nl * (d.tj + 1) * (d.Mx + 1) * es;
+    plan->lds[0] = std::max(plan->lds[0], la);
+    plan->lds[1] = std::max(plan->lds[1], lb);
+    plan->lds[2] = std::max(plan->lds[2], lc);
+    if (la > kMaxLds || lb > kMaxLds || lc > kMaxLds)
+      return fail(CGP_ERR_UNSUPPORTED, "member %d needs more than 64 KiB LDS per block", m);
+  }
+  Layout& L = plan->lay;
+  size_t off = 0;
+  L.desc = off; off = align_up(off + sizeof(MemberDesc) * count);
+  L.tw = off; off = align_up(off + (size_t)tw * 2 * es);
+  L.lam = off; off = align_up(off + (size_t)lam * sizeof(double));
+  L.wt = off; off = align_up(off + (size_t)wt * es);
+  L.field_elems = fld;
+  L.psi = off; off = align_up(off + (size_t)fld * es);
+  L.st1 = off; off = align_up(off + (size_t)fld * es);
+  L.st2 = off; off = align_up(off + (size_t)fld * es);
+  L.diag = off; off = align_up(off + (size_t)kDiagBlocks * 2 * 3 * sizeof(double));
+  L.fin = off; off = align_up(off + (size_t)kFiniteBlocks * sizeof(int));
+  L.total = off;
+  return CGP_OK;
+}
+
+}  // namespace
+
+struct cgp_handle {
+  Plan plan;
+  char* ws = nullptr;
+  std::vector<char> host_tables;  // kept alive until destroy (async upload source)
+  // graph cache: (omega, forcing) -> executable graph of one step
+  std::map<std::pair<const void*, const void*>, hipGraphExec_t> graphs;
+  int nm() const { return (int)plan.md.size(); }
+  template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  const MemberDesc* d_md() const { return at<MemberDesc>(plan.lay.desc); }
+};
+
+namespace {
+
+const double kRkA[3] = {0.0, 0.75, 1.0 / 3.0};
+const double kRkB[3] = {1.0, 0.25, 2.0 / 3.0};
+
+template <typename T>
+hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hipStream_t s) {
+  const Plan& p = h->plan;
+  const cplx<T>* tw = h->at<cplx<T>>(p.lay.tw);
+  T* wt = h->at<T>(p.lay.wt);
+  hipError_t e = Launch<T>::restrict_rowdst(h->d_md(), h->nm(), p.nblk[PASS_A], p.lds[0], src, wt,
+                                            tw, s);
+  if (e != hipSuccess) return e;
+  e = Launch<T>::col_solve(h->d_md(), h->nm(), p.nblk[PASS_B], p.lds[1], wt, tw,
+                           h->at<double>(p.lay.lam), s);
+  if (e != hipSuccess) return e;
+  return Launch<T>::rowdst_prolong(h->d_md(), h->nm(), p.nblk[PASS_C], p.lds[2], wt, dst,
+                                   accumulate, tw, s);
+}
+
+// One CGPRK3 step: w1 -> stage 1 buffer, w2 -> stage 2 buffer, w_{n+1} -> omega.
+template <typename T>
+hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s,
+                        T* st1 = nullptr, T* st2 = nullptr, T* psi0 = nullptr,
+                        T* psi1 = nullptr, T* psi2 = nullptr) {
+  const Plan& p = h->plan;
+  T* b1 = st1 ? st1 : h->at<T>(p.lay.st1);
+  T* b2 = st2 ? st2 : h->at<T>(p.lay.st2);
+  T* pd = h->at<T>(p.lay.psi);
+  T* psis[3] = {psi0 ? psi0 : pd, psi1 ? psi1 : pd, psi2 ? psi2 : pd};
+  const T* src[3] = {omega, b1, b2};
+  T* dst[3] = {b1, b2, omega};
+  for (int st = 0; st < 3; ++st) {
+    hipError_t e = enqueue_solve<T>(h, src[st], psis[st], 0, s);
+    if (e != hipSuccess) return e;
+    e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), p.nblk[PASS_D], src[st], psis[st], forcing,
+                               omega, dst[st], kRkA[st], kRkB[st], s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// enqueue_step with an event recorded after each of its 12 launches
+template <typename T>
+hipError_t enqueue_step_events(cgp_handle* h, T* omega, const T* forcing, hipStream_t s,
+                               hipEvent_t* ev) {
+  const Plan& p = h->plan;
+  T* b1 = h->at<T>(p.lay.st1);
+  T* b2 = h->at<T>(p.lay.st2);
+  T* pd = h->at<T>(p.lay.psi);
+  const cplx<T>* tw = h->at<cplx<T>>(p.lay.tw);
+  T* wt = h->at<T>(p.lay.wt);
+  const T* src[3] = {omega, b1, b2};
+  T* dst[3] = {b1, b2, omega};
+  int k = 0;
+  hipError_t e;
+  for (int st = 0; st < 3; ++st) {
+    e = Launch<T>::restrict_rowdst(h->d_md(), h->nm(), p.nblk[PASS_A], p.lds[0], src[st], wt, tw, s);
+    if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
+    e = Launch<T>::col_solve(h->d_md(), h->nm(), p.nblk[PASS_B], p.lds[1], wt, tw,
+                             h->at<double>(p.lay.lam), s);
+    if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
+    e = Launch<T>::rowdst_prolong(h->d_md(), h->nm(), p.nblk[PASS_C], p.lds[2], wt, pd, 0, tw, s);
+    if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
+    e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), p.nblk[PASS_D], src[st], pd, forcing, omega,
+                               dst[st], kRkA[st], kRkB[st], s);
+    if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+cgp_status create_tables(cgp_handle* h, hipStream_t s) {
+  const Plan& p = h->plan;
+  const Layout& L = p.lay;
+  // host image of [desc][tw][lam]
+  h->host_tables.assign(L.wt, 0);
+  std::memcpy(h->host_tables.data() + L.desc, p.md.data(), sizeof(MemberDesc) * p.md.size());
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(h->host_tables.data() + L.tw);
+  double* lam = reinterpret_cast<double*>(h->host_tables.data() + L.lam);
+  const double pi = 3.14159265358979323846264338327950288;
+  for (const MemberDesc& d : p.md) {
+    for (int pass = 0; pass < 2; ++pass) {
+      const int Ln = pass == 0 ? d.Lr : d.Lc;
+      cplx<T>* t = tw + (pass == 0 ? d.twr_off : d.twc_off);
+      for (int mm = 0; mm < Ln; ++mm) {
+        const double ang = 2.0 * pi * (double)mm / (double)Ln;
+        t[mm].x = (T)std::cos(ang);
+        t[mm].y = (T)(-std::sin(ang));
+      }
+    }
+    // lambda_k = (2cos(pi k/M) - 2)/h^2 = -4 sin^2(pi k/(2M))/h^2 on the coarse grid
+    const double hx = d.dx * d.c, hy = d.dy * d.c;
+    double* lx = lam + d.lam_off;
+    double* ly = lx + (d.Mx - 1);
+    for (int k = 1; k < d.Mx; ++k) {
+      const double sn = std::sin(pi * k / (2.0 * d.Mx));
+      lx[k - 1] = -4.0 * sn * sn / (hx * hx);
+    }
+    for (int l = 1; l < d.My; ++l) {
+      const double sn = std::sin(pi * l / (2.0 * d.My));
+      ly[l - 1] = -4.0 * sn * sn / (hy * hy);
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(h->ws, h->host_tables.data(), L.wt, hipMemcpyHostToDevice, s),
+          "table upload");
+  // ring of the internal psi / stage buffers: produced fields always write
+  // their ring, so no clearing is needed; the spectra are fully overwritten.
+  return CGP_OK;
+}
+
+cgp_status check_handle(cgp_handle* h) {
+  if (!h) return fail(CGP_ERR_INVALID, "handle is NULL");
+  return CGP_OK;
+}
+
+cgp_status create_common(const cgp_config* cfgs, int count, void* ws, size_t bytes, void* stream,
+                         cgp_handle** out) {
+  if (!out) return fail(CGP_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  Plan plan;
+  cgp_status st = make_plan(cfgs, count, &plan);
+  if (st != CGP_OK) return st;
+  if (!ws) return fail(CGP_ERR_INVALID, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+    return fail(CGP_ERR_INVALID, "workspace must be 256-byte aligned");
+  if (bytes < plan.lay.total)
+    return fail(CGP_ERR_INVALID, "workspace too small: %zu < %zu", bytes, plan.lay.total);
+  cgp_handle* h = new cgp_handle;
+  h->plan = std::move(plan);
+  h->ws = static_cast<char*>(ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = h->plan.dtype == CGP_F64 ? create_tables<double>(h, s) : create_tables<float>(h, s);
+  if (st != CGP_OK) {
+    delete h;
+    return st;
+  }
+  // the host image must outlive the copy
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "table upload sync");
+  }
+  *out = h;
+  return CGP_OK;
+}
+
+template <typename T>
+cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_out, int nsteps,
+                     int use_graph, hipStream_t s) {
+  T* w = static_cast<T*>(omega);
+  const T* F = static_cast<const T*>(forcing);
+  if (use_graph && s != nullptr && nsteps > 0) {
+    auto key = std::make_pair(static_cast<const void*>(omega), forcing);
+    auto it = h->graphs.find(key);
+    hipGraphExec_t exec = nullptr;
+    if (it == h->graphs.end()) {
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+      hipError_t e = enqueue_step<T>(h, w, F, s);
+      hipError_t e2 = hipStreamEndCapture(s, &g);
+      if (e != hipSuccess) return hip_fail(e, "capture step");
+      if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+      e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+      h->graphs[key] = exec;
+    } else {
+      exec = it->second;
+    }
+    for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
+  } else {
+    for (int n = 0; n < nsteps; ++n) HIP_TRY(enqueue_step<T>(h, w, F, s), "step launch");
+  }
+  if (psi_out) HIP_TRY(enqueue_solve<T>(h, w, static_cast<T*>(psi_out), 0, s), "psi launch");
+  return CGP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* cgp_last_error(void) { return g_err.c_str(); }
+
+const char* cgp_version(void) { return "cgp-mi355x 0.1 (gfx950)"; }
+
+cgp_status cgp_workspace_size(const cgp_config* cfg, size_t* bytes) {
+  return cgp_ensemble_workspace_size(cfg, 1, bytes);
+}
+
+cgp_status cgp_ensemble_workspace_size(const cgp_config* members, int32_t count, size_t* bytes) {
+  if (!bytes) return fail(CGP_ERR_INVALID, "bytes is NULL");
+  Plan plan;
+  cgp_status st = make_plan(members, count, &plan);
+  if (st != CGP_OK) return st;
+  *bytes = plan.lay.total;
+  return CGP_OK;
+}
+
+cgp_status cgp_ensemble_offsets(const cgp_config* members, int32_t count, int64_t* offsets,
+                                int64_t* total) {
+  Plan plan;
+  cgp_status st = make_plan(members, count, &plan);
+  if (st != CGP_OK) return st;
+  if (offsets)
+    for (int m = 0; m < count; ++m) offsets[m] = plan.md[m].field_off;
+  if (total) *total = plan.lay.field_elems;
+  return CGP_OK;
+}
+
+cgp_status cgp_create(const cgp_config* cfg, void* ws, size_t bytes, void* stream,
+                      cgp_handle** out) {
+  return create_common(cfg, 1, ws, bytes, stream, out);
+}
+
+cgp_status cgp_ensemble_create(const cgp_config* members, int32_t count, void* ws, size_t bytes,
+                               void* stream, cgp_handle** out) {
+  return create_common(members, count, ws, bytes, stream, out);
+}
+
+cgp_status cgp_destroy(cgp_handle* h) {
+  if (!h) return CGP_OK;
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  delete h;
+  return CGP_OK;
+}
+
+cgp_status cgp_ensemble_step(cgp_handle* h, void* omega, const void* forcing, int32_t nsteps,
+                             int32_t use_graph, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!omega || !forcing) return fail(CGP_ERR_INVALID, "omega or forcing is NULL");
+  if (nsteps < 0) return fail(CGP_ERR_INVALID, "nsteps < 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return h->plan.dtype == CGP_F64
+             ? step_impl<double>(h, omega, forcing, nullptr, nsteps, use_graph, s)
+             : step_impl<float>(h, omega, forcing, nullptr, nsteps, use_graph, s);
+}
+
+cgp_status cgp_step(cgp_handle* h, void* omega, const void* forcing, void* psi_out,
+                    int32_t nsteps, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (h->nm() != 1) return fail(CGP_ERR_INVALID, "cgp_step needs a single-basin handle");
+  if (!omega || !forcing) return fail(CGP_ERR_INVALID, "omega or forcing is NULL");
+  if (nsteps < 0) return fail(CGP_ERR_INVALID, "nsteps < 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return h->plan.dtype == CGP_F64
+             ? step_impl<double>(h, omega, forcing, psi_out, nsteps, 0, s)
+             : step_impl<float>(h, omega, forcing, psi_out, nsteps, 0, s);
+}
+
+cgp_status cgp_solve(cgp_handle* h, const void* omega, void* psi, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!omega || !psi) return fail(CGP_ERR_INVALID, "omega or psi is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = h->plan.dtype == CGP_F64
+                     ? enqueue_solve<double>(h, static_cast<const double*>(omega),
+                                             static_cast<double*>(psi), 0, s)
+                     : enqueue_solve<float>(h, static_cast<const float*>(omega),
+                                            static_cast<float*>(psi), 0, s);
+  if (e != hipSuccess) return hip_fail(e, "solve launch");
+  return CGP_OK;
+}
+
+cgp_status cgp_diagnostics(cgp_handle* h, const void* omega, const void* psi, double* out,
+                           void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (h->nm() != 1) return fail(CGP_ERR_INVALID, "diagnostics need a single-basin handle");
+  if (!omega || !psi || !out) return fail(CGP_ERR_INVALID, "NULL pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* part = h->at<double>(h->plan.lay.diag);
+  hipError_t e = h->plan.dtype == CGP_F64
+                     ? Launch<double>::diagnostics(h->d_md(), static_cast<const double*>(omega),
+                                                   static_cast<const double*>(psi), part,
+                                                   kDiagBlocks, out, s)
+                     : Launch<float>::diagnostics(h->d_md(), static_cast<const float*>(omega),
+                                                  static_cast<const float*>(psi), part,
+                                                  kDiagBlocks, out, s);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics launch");
+  return CGP_OK;
+}
+
+cgp_status cgp_check_finite(cgp_handle* h, const void* field, int64_t count, int32_t* flag,
+                            void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!field || !flag || count < 0) return fail(CGP_ERR_INVALID, "bad argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int* part = h->at<int>(h->plan.lay.fin);
+  hipError_t e = h->plan.dtype == CGP_F64
+                     ? Launch<double>::check_finite(static_cast<const double*>(field), count,
+                                                    part, kFiniteBlocks, flag, s)
+                     : Launch<float>::check_finite(static_cast<const float*>(field), count, part,
+                                                   kFiniteBlocks, flag, s);
+  if (e != hipSuccess) return hip_fail(e, "finite-check launch");
+  return CGP_OK;
+}
+
+cgp_status cgp_step_timed(cgp_handle* h, void* omega, const void* forcing, int32_t nsteps,
+                          double* ms, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!omega || !forcing || !ms || nsteps < 1) return fail(CGP_ERR_INVALID, "bad argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nev = 1 + 12 * nsteps;
+  std::vector<hipEvent_t> ev(nev, nullptr);
+  cgp_status st = CGP_OK;
+  for (int i = 0; i < nev && st == CGP_OK; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) st = fail(CGP_ERR_DEVICE, "event create");
+  if (st == CGP_OK) {
+    hipError_t e = hipEventRecord(ev[0], s);
+    for (int n = 0; n < nsteps && e == hipSuccess; ++n)
+      e = h->plan.dtype == CGP_F64
+              ? enqueue_step_events<double>(h, static_cast<double*>(omega),
+                                            static_cast<const double*>(forcing), s,
+                                            ev.data() + 1 + 12 * n)
+              : enqueue_step_events<float>(h, static_cast<float*>(omega),
+                                           static_cast<const float*>(forcing), s,
+                                           ev.data() + 1 + 12 * n);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[nev - 1]);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "timed step");
+    } else {
+      double acc[4] = {0, 0, 0, 0};
+      for (int k = 1; k < nev; ++k) {
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, ev[k - 1], ev[k]);
+        acc[(k - 1) % 4] += t;
+      }
+      float tot = 0.f;
+      (void)hipEventElapsedTime(&tot, ev[0], ev[nev - 1]);
+      for (int p = 0; p < 4; ++p) ms[p] = acc[p] / (3.0 * nsteps);
+      ms[4] = tot;
+    }
+  }
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint.  Tape layout (FP64 node arrays of the single member, N elements
+// each): per step s of the segment the stage states w0 w1 w2 and psi0 psi1
+// psi2 (6 arrays), then four work arrays X1 X2 P ACC.
+// ---------------------------------------------------------------------------
+cgp_status cgp_tape_size(const cgp_config* cfg, int32_t nsteps, size_t* bytes) {
+  cgp_status st = validate(cfg);
+  if (st != CGP_OK) return st;
+  if (!bytes || nsteps < 1) return fail(CGP_ERR_INVALID, "bad argument");
+  const size_t N = (size_t)(cfg->nx + 1) * (cfg->ny + 1);
+  *bytes = (6 * (size_t)nsteps + 4) * N * sizeof(double);
+  return CGP_OK;
+}
+
+cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forcing,
+                            int32_t nsteps, void* lambda, void* grad_forcing, void* tape,
+                            size_t tape_bytes, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (h->nm() != 1 || h->plan.nlayers != 1 || h->plan.dtype != CGP_F64)
+    return fail(CGP_ERR_UNSUPPORTED, "adjoint needs a one-layer FP64 single-basin handle");
+  if (!omega_n || !forcing || !lambda || !grad_forcing || !tape || nsteps < 1)
+    return fail(CGP_ERR_INVALID, "bad argument");
+  const MemberDesc& d = h->plan.md[0];
+  const size_t N = (size_t)(d.nx + 1) * (d.ny + 1);
+  const size_t need = (6 * (size_t)nsteps + 4) * N * sizeof(double);
+  if (tape_bytes < need) return fail(CGP_ERR_INVALID, "tape too small: %zu < %zu", tape_bytes, need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* tp = static_cast<double*>(tape);
+  auto slot = [&](int n, int k) { return tp + ((size_t)n * 6 + k) * N; };
+  double* X1 = tp + (size_t)nsteps * 6 * N;
+  double* X2 = X1 + N;
+  double* P = X2 + N;
+  double* ACC = P + N;
+  const double* F = static_cast<const double*>(forcing);
+  // forward recompute: step n reads w0(n) (a copy of the state) and leaves
+  // w_{n+1} in w0(n+1), or in X1 for the last step (not needed afterwards).
+  HIP_TRY(hipMemcpyAsync(slot(0, 0), omega_n, N * sizeof(double), hipMemcpyDeviceToDevice, s),
+          "tape copy");
+  for (int n = 0; n < nsteps; ++n) {
+    double* next = (n + 1 < nsteps) ? slot(n + 1, 0) : X1;
+    HIP_TRY(hipMemcpyAsync(next, slot(n, 0), N * sizeof(double), hipMemcpyDeviceToDevice, s),
+            "tape copy");
+    // enqueue_step updates its omega argument in place: run it on `next`
+    // (holding w_n) so that w0(n) stays intact.
+    HIP_TRY(enqueue_step<double>(h, next, F, s, slot(n, 1), slot(n, 2), slot(n, 3), slot(n, 4),
+                                 slot(n, 5)),
+            "forward recompute");
+  }
+  // reverse sweep
+  double* lam = static_cast<double*>(lambda);
+  double* gF = static_cast<double*>(grad_forcing);
+  const MemberDesc* md = h->d_md();
+  const int nb = h->plan.nblk[PASS_D];
+  for (int n = nsteps - 1; n >= 0; --n) {
+    // stage 2: lam_3 = lam -> X2 ; stage 1: X2 -> X1 ; stage 0: X1 -> lam
+    const double* lin[3] = {X1, X2, lam};
+    double* lout[3] = {lam, X1, X2};
+    for (int st = 2; st >= 0; --st) {
+      const double* ws = slot(n, st);
+      const double* ps = slot(n, 3 + st);
+      const int mode = st == 2 ? 0 : (st == 1 ? 1 : 2);
+      HIP_TRY(AdjLaunch::stencil(md, nb, lin[st], ws, ps, lout[st], P, ACC, gF, kRkA[st],
+                                 kRkB[st], mode, s),
+              "adjoint stencil");
+      HIP_TRY(enqueue_solve<double>(h, P, lout[st], 1, s), "adjoint solve");
+    }
+  }
+  return CGP_OK;
+}
+
+}  // extern "C"

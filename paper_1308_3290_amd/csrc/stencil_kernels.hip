@@ -1,0 +1,328 @@
+// Fine-grid kernels of the CGP step on gfx950:
+//   pass D     right-hand side G (Arakawa Jacobian of Sec. 4.1, beta term,
+//              Laplacian eddy viscosity, forcing, two-layer coupling and
+//              bottom drag) fused with the TVD-RK3 stage combine (Sec. 4.2);
+//   adjoint D  the transposed right-hand side of one stage (one layer, FP64);
+//   diagnostics and a non-finite check (deterministic two-stage reductions).
+//
+// One thread per fine node, 64 x 4 node tiles (one wavefront per tile row),
+// neighbour values through the vector L1/L2.  The boundary ring of every
+// output is written as zero; the ring of every vorticity-like input is read
+// as zero whatever it holds.
+#include "cgp_internal.hpp"
+
+namespace cgp {
+
+// Arakawa Jacobian J(p, q) of Sec. 4.1 times 12 dx dy: the sum of the
+// brackets of J1, J2 and J3.  Arguments are the 3x3 neighbourhoods
+// (E = i+1, W = i-1, N = j+1, S = j-1).
+template <typename T>
+struct Nbr {
+  T C, E, W, N, S, NE, NW, SE, SW;
+};
+
+template <typename T>
+__device__ __forceinline__ T arakawa12(const Nbr<T>& p, const Nbr<T>& q) {
+  const T j1 = -(q.E - q.W) * (p.N - p.S) + (q.N - q.S) * (p.E - p.W);
+  const T j2 = -q.E * (p.NE - p.SE) + q.W * (p.NW - p.SW) + q.N * (p.NE - p.NW) -
+               q.S * (p.SE - p.SW);
+  const T j3 = -q.NE * (p.N - p.E) + q.SW * (p.W - p.S) + q.NW * (p.N - p.W) -
+               q.SE * (p.E - p.S);
+  return j1 + j2 + j3;
+}
+
+// J(p, y) times 3 dx: the Jacobian with the coordinate y reduces to a centred
+// x difference of p with corner averaging.
+template <typename T>
+__device__ __forceinline__ T beta3(const Nbr<T>& p) {
+  return (p.E - p.W) + T(0.25) * ((p.NE - p.NW) + (p.SE - p.SW));
+}
+
+template <typename T>
+__device__ __forceinline__ Nbr<T> load_nbr(const T* __restrict__ f, int pitch, int i, int j) {
+  const T* c = f + (size_t)j * pitch + i;
+  Nbr<T> n;
+  n.C = c[0];
+  n.E = c[1];
+  n.W = c[-1];
+  n.N = c[pitch];
+  n.S = c[-pitch];
+  n.NE = c[pitch + 1];
+  n.NW = c[pitch - 1];
+  n.SE = c[-pitch + 1];
+  n.SW = c[-pitch - 1];
+  return n;
+}
+
+// Same, with ring nodes read as zero.
+template <typename T>
+__device__ __forceinline__ Nbr<T> load_nbr_masked(const T* __restrict__ f, int pitch, int nx,
+                                                  int ny, int i, int j) {
+  Nbr<T> n = load_nbr(f, pitch, i, j);
+  if (i == 1) { n.W = T(0); n.NW = T(0); n.SW = T(0); }
+  if (i == nx - 1) { n.E = T(0); n.NE = T(0); n.SE = T(0); }
+  if (j == 1) { n.S = T(0); n.SE = T(0); n.SW = T(0); }
+  if (j == ny - 1) { n.N = T(0); n.NE = T(0); n.NW = T(0); }
+  return n;
+}
+
+template <typename T>
+__device__ __forceinline__ T lap5(const Nbr<T>& q, T idx2, T idy2) {
+  return (q.E - T(2) * q.C + q.W) * idx2 + (q.N - T(2) * q.C + q.S) * idy2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileX* kTileY) void k_stencil_rk3(
+    const MemberDesc* __restrict__ md, int nm, const T* __restrict__ ws, const T* __restrict__ psi,
+    const T* __restrict__ forcing, const T* __restrict__ wn, T* __restrict__ out, double a_,
+    double b_) {
+  const int m = find_member(md, nm, PASS_D, blockIdx.x);
+  const MemberDesc& d = md[m];
+  const int lb = blockIdx.x - d.blk0[PASS_D];
+  const int nx = d.nx, ny = d.ny, pitch = nx + 1;
+  const int tiles_x = (nx + kTileX) / kTileX;
+  const int by = lb / tiles_x, bx = lb - by * tiles_x;
+  const int i = bx * kTileX + (threadIdx.x & (kTileX - 1));
+  const int j = by * kTileY + (threadIdx.x / kTileX);
+  if (i > nx || j > ny) return;
+  const size_t plane = (size_t)(ny + 1) * pitch;
+  const size_t o = d.field_off + (size_t)j * pitch + i;
+  const int nl = d.nlayers;
+  if (i == 0 || j == 0 || i == nx || j == ny) {
+    out[o] = T(0);
+    if (nl == 2) out[o + plane] = T(0);
+    return;
+  }
+  const T dt = T(d.dt), a = T(a_), b = T(b_);
+  const T cj = T(1.0 / (12.0 * d.dx * d.dy));
+  const T cb = T(d.inv_ro / (3.0 * d.dx));
+  const T idx2 = T(1.0 / (d.dx * d.dx)), idy2 = T(1.0 / (d.dy * d.dy));
+  const T nu = T(d.inv_re);
+  const T* W = ws + d.field_off;
+  const T* PS = psi + d.field_off;
+  if (nl == 1) {
+    const Nbr<T> p = load_nbr(PS, pitch, i, j);
+    const Nbr<T> q = load_nbr_masked(W, pitch, nx, ny, i, j);
+    const T G = -cj * arakawa12(p, q) - cb * beta3(p) + nu * lap5(q, idx2, idy2) +
+                forcing[o];
+    T v = b * (q.C + dt * G);
+    if (a_ != 0.0) v += a * wn[o];
+    out[o] = v;
+  } else {
+    const T F1 = T(d.f1), F2 = T(d.f2), drag = T(d.drag);
+    const Nbr<T> p1 = load_nbr(PS, pitch, i, j);
+    const Nbr<T> p2 = load_nbr(PS + plane, pitch, i, j);
+    const Nbr<T> q1 = load_nbr_masked(W, pitch, nx, ny, i, j);
+    const Nbr<T> q2 = load_nbr_masked(W + plane, pitch, nx, ny, i, j);
+    // zeta_i = Q_i - F_i (psi_j - psi_i) on the 5-point cross (zero on walls)
+    Nbr<T> z1, z2;
+    z1.C = q1.C - F1 * (p2.C - p1.C);
+    z1.E = q1.E - F1 * (p2.E - p1.E);
+    z1.W = q1.W - F1 * (p2.W - p1.W);
+    z1.N = q1.N - F1 * (p2.N - p1.N);
+    z1.S = q1.S - F1 * (p2.S - p1.S);
+    z2.C = q2.C - F2 * (p1.C - p2.C);
+    z2.E = q2.E - F2 * (p1.E - p2.E);
+    z2.W = q2.W - F2 * (p1.W - p2.W);
+    z2.N = q2.N - F2 * (p1.N - p2.N);
+    z2.S = q2.S - F2 * (p1.S - p2.S);
+    const T G1 = -cj * arakawa12(p1, q1) - cb * beta3(p1) + nu * lap5(z1, idx2, idy2) +
+                 forcing[o];
+    const T G2 = -cj * arakawa12(p2, q2) - cb * beta3(p2) + nu * lap5(z2, idx2, idy2) -
+                 drag * z2.C;
+    T v1 = b * (q1.C + dt * G1);
+    T v2 = b * (q2.C + dt * G2);
+    if (a_ != 0.0) {
+      v1 += a * wn[o];
+      v2 += a * wn[o + plane];
+    }
+    out[o] = v1;
+    out[o + plane] = v2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of one stage's right-hand side (one layer, FP64).  mu = b dt lam_in.
+//   lam_out = b lam_in + J(psi_s, mu) + inv_re Lap(mu) [+ acc]
+//   psi_src = -J(omega_s, mu) + inv_ro J(mu, y)
+//   acc = a lam_in (acc_mode 0) / acc += a lam_in (1) / read into lam_out (2)
+//   gF += mu
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kTileX* kTileY) void k_adjoint_stencil(
+    const MemberDesc* __restrict__ md, const double* __restrict__ lam_in,
+    const double* __restrict__ ws, const double* __restrict__ psi, double* __restrict__ lam_out,
+    double* __restrict__ psi_src, double* __restrict__ acc, double* __restrict__ gF, double a,
+    double b, int acc_mode) {
+  const MemberDesc& d = md[0];
+  const int nx = d.nx, ny = d.ny, pitch = nx + 1;
+  const int tiles_x = (nx + kTileX) / kTileX;
+  const int by = blockIdx.x / tiles_x, bx = blockIdx.x - by * tiles_x;
+  const int i = bx * kTileX + (threadIdx.x & (kTileX - 1));
+  const int j = by * kTileY + (threadIdx.x / kTileX);
+  if (i > nx || j > ny) return;
+  const size_t o = (size_t)j * pitch + i;
+  if (i == 0 || j == 0 || i == nx || j == ny) {
+    lam_out[o] = 0.0;
+    psi_src[o] = 0.0;
+    if (acc_mode == 0) acc[o] = 0.0;
+    return;
+  }
+  const double cj = 1.0 / (12.0 * d.dx * d.dy);
+  const double cb = d.inv_ro / (3.0 * d.dx);
+  const double idx2 = 1.0 / (d.dx * d.dx), idy2 = 1.0 / (d.dy * d.dy);
+  const double bdt = b * d.dt;
+  Nbr<double> mu = load_nbr_masked(lam_in, pitch, nx, ny, i, j);
+  const double lc = mu.C;
+  mu.C *= bdt; mu.E *= bdt; mu.W *= bdt; mu.N *= bdt; mu.S *= bdt;
+  mu.NE *= bdt; mu.NW *= bdt; mu.SE *= bdt; mu.SW *= bdt;
+  const Nbr<double> p = load_nbr(psi, pitch, i, j);
+  const Nbr<double> w = load_nbr_masked(ws, pitch, nx, ny, i, j);
+  double lo = b * lc + cj * arakawa12(p, mu) + d.inv_re * lap5(mu, idx2, idy2);
+  if (acc_mode == 0) acc[o] = a * lc;
+  else if (acc_mode == 1) acc[o] += a * lc;
+  else lo += acc[o];
+  lam_out[o] = lo;
+  psi_src[o] = -cj * arakawa12(w, mu) + cb * beta3(mu);
+  gF[o] += mu.C;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics.  Block b sums rows j = b, b + nblk, ... of member 0 in a fixed
+// order: per layer the x-link energy, y-link energy and enstrophy terms.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_partial(const MemberDesc* __restrict__ md,
+                                                      const T* __restrict__ w,
+                                                      const T* __restrict__ psi,
+                                                      double* __restrict__ partial) {
+  __shared__ double red[3][256];
+  const MemberDesc& d = md[0];
+  const int nx = d.nx, ny = d.ny, pitch = nx + 1;
+  const size_t plane = (size_t)(ny + 1) * pitch;
+  const double idx = 1.0 / d.dx, idy = 1.0 / d.dy;
+  for (int l = 0; l < d.nlayers; ++l) {
+    const T* P = psi + l * plane;
+    const T* Q = w + l * plane;
+    double ex = 0.0, ey = 0.0, z = 0.0;
+    for (int j = blockIdx.x; j <= ny; j += gridDim.x) {
+      for (int i = threadIdx.x; i <= nx; i += blockDim.x) {
+        const size_t o = (size_t)j * pitch + i;
+        const double pc = (double)P[o];
+        if (j >= 1 && j <= ny - 1 && i <= nx - 1) {
+          const double g = ((double)P[o + 1] - pc) * idx;
+          ex += g * g;
+        }
+        if (j <= ny - 1 && i >= 1 && i <= nx - 1) {
+          const double g = ((double)P[o + pitch] - pc) * idy;
+          ey += g * g;
+        }
+        if (j >= 1 && j <= ny - 1 && i >= 1 && i <= nx - 1) {
+          const double q = (double)Q[o];
+          z += q * q;
+        }
+      }
+    }
+    red[0][threadIdx.x] = ex;
+    red[1][threadIdx.x] = ey;
+    red[2][threadIdx.x] = z;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + s];
+        red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        red[2][threadIdx.x] += red[2][threadIdx.x + s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      partial[(blockIdx.x * 2 + l) * 3 + 0] = red[0][0];
+      partial[(blockIdx.x * 2 + l) * 3 + 1] = red[1][0];
+      partial[(blockIdx.x * 2 + l) * 3 + 2] = red[2][0];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_diag_final(const MemberDesc* __restrict__ md, const double* __restrict__ partial,
+                             int nblk, double* __restrict__ out) {
+  const MemberDesc& d = md[0];
+  const int l = threadIdx.x;
+  if (l >= d.nlayers) return;
+  double ex = 0.0, ey = 0.0, z = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    ex += partial[(b * 2 + l) * 3 + 0];
+    ey += partial[(b * 2 + l) * 3 + 1];
+    z += partial[(b * 2 + l) * 3 + 2];
+  }
+  const double area = (double)d.nx * d.dx * (double)d.ny * d.dy;
+  const double f = d.dx * d.dy / (2.0 * area);
+  out[2 * l] = f * (ex + ey);
+  out[2 * l + 1] = f * z;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_finite_partial(const T* __restrict__ f, long long n,
+                                                        int* __restrict__ partial) {
+  __shared__ int red[256];
+  int bad = 0;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    const T v = f[k];
+    bad |= !(v - v == T(0));  // NaN or +-inf
+  }
+  red[threadIdx.x] = bad;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] |= red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_finite_final(const int* __restrict__ partial, int nblk, int* __restrict__ flag) {
+  if (threadIdx.x == 0) {
+    int bad = 0;
+    for (int b = 0; b < nblk; ++b) bad |= partial[b];
+    flag[0] = bad;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t Launch<T>::stencil_rk3(const MemberDesc* md, int nm, int nblk, const T* ws,
+                                  const T* psi, const T* forcing, const T* wn, T* out, double a,
+                                  double b, hipStream_t s) {
+  hipLaunchKernelGGL(k_stencil_rk3<T>, dim3(nblk), dim3(kTileX * kTileY), 0, s, md, nm, ws, psi,
+                     forcing, wn, out, a, b);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::diagnostics(const MemberDesc* md, const T* w, const T* psi, double* partial,
+                                  int nblk, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_partial<T>, dim3(nblk), dim3(256), 0, s, md, w, psi, partial);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, md, partial, nblk, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::check_finite(const T* f, long long n, int* partial, int nblk, int* flag,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_finite_partial<T>, dim3(nblk), dim3(256), 0, s, f, n, partial);
+  hipLaunchKernelGGL(k_finite_final, dim3(1), dim3(64), 0, s, partial, nblk, flag);
+  return hipGetLastError();
+}
+
+hipError_t AdjLaunch::stencil(const MemberDesc* md, int nblk, const double* lam_in,
+                              const double* ws, const double* psi, double* lam_out,
+                              double* psi_src, double* acc, double* gF, double a, double b,
+                              int acc_mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_adjoint_stencil, dim3(nblk), dim3(kTileX * kTileY), 0, s, md, lam_in, ws,
+                     psi, lam_out, psi_src, acc, gF, a, b, acc_mode);
+  return hipGetLastError();
+}
+
+template struct Launch<float>;
+template struct Launch<double>;
+
+}  // namespace cgp

@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+declared in include/cgp.h, and sizes/validates configurations without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cgp.h")
+LIB = os.path.join(ROOT, "paper_1308_3290_amd", "libcgp.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libcgp.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:cgp_status|const char\*)\s+(cgp_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("cgp_create", "cgp_step", "cgp_adjoint_step", "cgp_workspace_size",
+                     "cgp_ensemble_step", "cgp_diagnostics", "cgp_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1308_3290_amd import _lib
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"binding lacks {name}"
+    assert "gfx950" in lib.cgp_version().decode()
+
+
+def _cfg(**kw):
+    from paper_1308_3290_amd.api import make_config
+    base = dict(nx=64, ny=128, level=1, nlayers=1, dtype="f64", inv_re=1 / 450, inv_ro=1 / 0.0036,
+                dt=1e-4)
+    base.update(kw)
+    return make_config(**base)
+
+
+def test_workspace_size_is_positive_and_grows():
+    from paper_1308_3290_amd.api import cgp_workspace_size
+    a = cgp_workspace_size(_cfg())
+    b = cgp_workspace_size(_cfg(nx=128, ny=256))
+    c = cgp_workspace_size(_cfg(nlayers=2, f1=2000, f2=500))
+    assert 0 < a < b and c > a
+    assert a % 256 == 0
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(nx=65), 1),                  # not divisible by 2^level
+    (dict(nlayers=3), 1),
+    (dict(dtype=7), 1),
+    (dict(level=-1), 1),
+    (dict(nx=80, ny=160, level=0), 2),  # 80 = 5 * 16: radix 5 unsupported
+    (dict(nx=8, ny=16, level=2), 2),    # coarse 2 x 4
+    (dict(nx=4096, ny=4096, level=0), 2),
+    (dict(inv_re=float("nan")), 1),
+    (dict(inv_re=-1.0), 1),
+])
+def test_invalid_configs_return_status(kw, status):
+    from paper_1308_3290_amd.api import CGPError, cgp_workspace_size
+    with pytest.raises(CGPError) as e:
+        cgp_workspace_size(_cfg(**kw))
+    assert e.value.status == status
+    assert str(e.value)
+
+
+def test_reserved_field_and_null_pointers():
+    from paper_1308_3290_amd import _lib
+    lib = _lib.load()
+    cfg = _cfg()
+    cfg.reserved = 1
+    n = ctypes.c_size_t()
+    assert lib.cgp_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == _lib.CGP_ERR_INVALID
+    cfg.reserved = 0
+    assert lib.cgp_workspace_size(ctypes.byref(cfg), None) == _lib.CGP_ERR_INVALID
+    assert lib.cgp_step(None, None, None, None, 1, None) == _lib.CGP_ERR_INVALID
+    assert lib.cgp_destroy(None) == _lib.CGP_OK
+    h = ctypes.c_void_p()
+    # NULL workspace is rejected before any device call
+    assert lib.cgp_create(ctypes.byref(cfg), None, 0, None, ctypes.byref(h)) == _lib.CGP_ERR_INVALID
+
+
+def test_ensemble_offsets_pack_members_in_order():
+    from paper_1308_3290_amd.api import cgp_ensemble_offsets, cgp_ensemble_workspace_size
+    cfgs = [_cfg(nx=64, ny=128), _cfg(nx=96, ny=192), _cfg(nx=128, ny=256)]
+    offs, tot = cgp_ensemble_offsets(cfgs)
+    sizes = [65 * 129, 97 * 193, 129 * 257]
+    assert offs == [0, sizes[0], sizes[0] + sizes[1]] and tot == sum(sizes)
+    assert cgp_ensemble_workspace_size(cfgs) > 0
+    from paper_1308_3290_amd.api import CGPError
+    with pytest.raises(CGPError):
+        cgp_ensemble_offsets([_cfg(), _cfg(dtype="f32")])
+
+
+def test_tape_size():
+    from paper_1308_3290_amd.api import cgp_tape_size
+    assert cgp_tape_size(_cfg(), 20) == (6 * 20 + 4) * 65 * 129 * 8
