@@ -72,7 +72,7 @@ typedef enum { CGP_F32 = 0, CGP_F64 = 1 } cgp_dtype;
  * f2 = Fr/(Ro (1 - delta)), drag = sigma/Ro.  Supported sizes: level >= 0,
  * nx and ny divisible by 2^level, and the coarse interval counts
  * Mx = nx/2^level, My = ny/2^level each of the form 2^k or 3*2^k with
- * 4 <= M <= 1024 (FP64) or 2048 (FP32). */
+ * 4 <= M <= 1024; two layers with coarsening need Mx <= 512. */
 typedef struct cgp_config {
   int32_t nx, ny;      /* fine grid intervals */
   int32_t level;       /* coarsening level l; factor 2^l; 0 = plain full-grid step */

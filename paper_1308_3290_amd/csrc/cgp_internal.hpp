@@ -23,18 +23,19 @@ struct MemberDesc {
   int nlayers;
   int Lr, Lc;           // complex FFT lengths 2*Mx (rows) and 2*My (columns)
   int nst_r, nst_c;     // radix stage counts
-  int rad_r[kMaxStages];
-  int rad_c[kMaxStages];
+  int rad_r[kMaxStages], rad_c[kMaxStages];  // radix of each stage
+  int lns_r[kMaxStages], lns_c[kMaxStages];  // log2 of the stage's span Ns
+  int tws_r[kMaxStages], tws_c[kMaxStages];  // twiddle step L/(Ns R)
   int pa;               // pass A: sequence pairs per block
   int pb;               // pass B: sequence pairs per block
   int tj;               // pass C: coarse rows owned per block
   int pc;               // pass C: sequence pairs per block (derived from tj)
-  int blk0[NUM_PASSES]; // first block of this member in each pass's grid
+  int blk0[NUM_PASSES]; // first block of this member in its launch of each pass
   int nblk[NUM_PASSES]; // blocks of this member in each pass
   long long field_off;  // packed fine fields ([L][ny+1][nx+1] per member)
   long long wt_off;     // coarse spectra: L modes x (Mx-1) x (My-1), k-major
-  long long twr_off;    // row twiddles, in complex elements of T (Lr entries)
-  long long twc_off;    // column twiddles (Lc entries)
+  long long twr_off;    // row twiddles w_Lr^m, m < Lr/2, in complex elements of T
+  long long twc_off;    // column twiddles w_Lc^m, m < Lc/2
   long long lam_off;    // doubles: lambda_x (Mx-1) then lambda_y (My-1)
   double dx, dy;
   double inv_re, inv_ro, f1, f2, drag, dt;
@@ -46,8 +47,8 @@ struct cplx {
   T x, y;
 };
 
-// Locate the member owning block `b` of pass `p` (members are laid out in
-// order in every pass's grid).
+// Locate the member owning block `b` of the stencil pass (members are laid
+// out in order in its grid).
 __device__ inline int find_member(const MemberDesc* md, int nm, int p, int b) {
   int lo = 0, hi = nm - 1;
   while (lo < hi) {
@@ -57,19 +58,27 @@ __device__ inline int find_member(const MemberDesc* md, int nm, int p, int b) {
   return lo;
 }
 
+// One launch of a transform pass over a group of members.
+struct Group {
+  int L;               // unused (0)
+  int count;           // members in the group
+  const int* members;  // device array of the group's member indices
+  int nblk, threads;  // threads = kThreads
+  size_t lds;
+};
+
 // Launch wrappers implemented in the kernel translation units.
 template <typename T>
 struct Launch {
   // pass A: restrict (level times) + forward x sine transform, src -> spectra
-  static hipError_t restrict_rowdst(const MemberDesc* md, int nm, int nblk, size_t lds,
-                                    const T* src, T* wt, const cplx<T>* tw, hipStream_t s);
+  static hipError_t restrict_rowdst(const MemberDesc* md, const Group& g, const T* src, T* wt,
+                                    const cplx<T>* tw, hipStream_t s);
   // pass B: y sine transform, eigenvalue divide, y sine transform (in place)
-  static hipError_t col_solve(const MemberDesc* md, int nm, int nblk, size_t lds, T* wt,
-                              const cplx<T>* tw, const double* lam, hipStream_t s);
+  static hipError_t col_solve(const MemberDesc* md, const Group& g, T* wt, const cplx<T>* tw,
+                              const double* lam, hipStream_t s);
   // pass C: inverse x sine transform + prolongation; accumulate != 0 adds to dst
-  static hipError_t rowdst_prolong(const MemberDesc* md, int nm, int nblk, size_t lds,
-                                   const T* wt, T* dst, int accumulate, const cplx<T>* tw,
-                                   hipStream_t s);
+  static hipError_t rowdst_prolong(const MemberDesc* md, const Group& g, const T* wt, T* dst,
+                                   int accumulate, const cplx<T>* tw, hipStream_t s);
   // pass D: Arakawa right-hand side + TVD-RK3 stage combine
   static hipError_t stencil_rk3(const MemberDesc* md, int nm, int nblk, const T* ws,
                                 const T* psi, const T* forcing, const T* wn, T* out, double a,

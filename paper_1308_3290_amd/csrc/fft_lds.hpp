@@ -9,13 +9,17 @@
 // The transform is its own inverse up to 2/n, so the same routine serves
 // the analysis and the synthesis sums of Sec. 4.3.
 //
-// The DFT is a Stockham autosort FFT over radices {4, 3, 2} (L = 2^k or
-// 3*2^k): at a stage of radix R with span Ns (product of earlier radices),
-// butterfly j reads x[j + r L/R], twiddles element r by w_L^(r (j mod Ns) L/(Ns R)),
-// takes an R-point DFT and writes y[(j div Ns) Ns R + (j mod Ns) + r Ns].
-// Twiddles w_L^m = exp(-2 pi i m / L) come from a host-built FP64 table.
-// Ping-pong LDS buffers; one barrier per stage; all threads of the block
-// share the butterflies of all sequences.
+// The DFT is a Stockham autosort FFT over radices 4 and 2, with the radix-3
+// stage of L = 3*2^k placed last, so that the span Ns of every stage is a
+// power of two and all index arithmetic is shifts and masks.  At a stage of
+// radix R, butterfly j reads x[j + r L/R], twiddles element r by
+// w_L^(r (j mod Ns) L/(Ns R)), takes an R-point DFT and writes
+// y[(j div Ns) Ns R + (j mod Ns) + r Ns].  The stage loop is a runtime loop
+// (compact code), each stage runs in place on one LDS buffer: every thread
+// reads the inputs of its butterflies, the block synchronises, every thread
+// writes its outputs, the block synchronises.  Twiddles w_L^m, m < L/2, come
+// from an LDS copy of a host-built FP64 table (w^(m + L/2) = -w^m).
+// A block transforms one or two sequences (nseq <= 2) of length L <= 2048.
 #pragma once
 
 #include "cgp_internal.hpp"
@@ -48,56 +52,86 @@ __device__ __forceinline__ void small_dft(cplx<T>* v) {
     cplx<T> a0 = v[0], s = {v[1].x + v[2].x, v[1].y + v[2].y};
     cplx<T> d = {v[1].x - v[2].x, v[1].y - v[2].y};
     cplx<T> t = {a0.x - T(0.5) * s.x, a0.y - T(0.5) * s.y};
-    // u = -i h d = (h d.y, -h d.x)
     v[0] = {a0.x + s.x, a0.y + s.y};
     v[1] = {t.x + h * d.y, t.y - h * d.x};
     v[2] = {t.x - h * d.y, t.y + h * d.x};
   }
 }
 
-template <typename T, int R>
-__device__ __forceinline__ void fft_stage(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
-                                          int nseq, int L, int Ns, const cplx<T>* __restrict__ tw) {
+// w_L^m from the half table (m < L).
+template <typename T>
+__device__ __forceinline__ cplx<T> twiddle(const cplx<T>* tw, int m, int half) {
+  if (m < half) return tw[m];
+  const cplx<T> w = tw[m - half];
+  return {-w.x, -w.y};
+}
+
+// One in-place stage of radix R over nseq sequences of length L in `buf`.
+// Thread `tid` owns butterflies b = tid + NT q (q < MAXB).
+template <typename T, int R, int MAXB>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int nseq, int L, int lns,
+                                          int twscale, const cplx<T>* tw) {
   const int LR = L / R;
-  const int total = nseq * LR;
-  const int twscale = L / (Ns * R);
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int p = t / LR;
-    const int j = t - p * LR;
-    const int k = j % Ns;
-    const cplx<T>* src = in + p * L;
-    cplx<T> v[R];
+  const int nb = nseq * LR;
+  const int ns = 1 << lns;
+  constexpr int NT = kThreads;
+  cplx<T> v[MAXB][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[j + r * LR];
-    if (k != 0) {
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = threadIdx.x + NT * q;
+    if (b < nb) {
+      const int p = b >= LR ? 1 : 0;
+      const int j = b - p * LR;
+      const int k = j & (ns - 1);
+      const cplx<T>* src = buf + p * L + j;
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * twscale]);
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * LR];
+      if (k != 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], twiddle(tw, r * k * twscale, L >> 1));
+      }
+      small_dft<T, R>(v[q]);
     }
-    small_dft<T, R>(v);
-    cplx<T>* dst = out + p * L + (j / Ns) * Ns * R + k;
+  }
+  __syncthreads();
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[r * Ns] = v[r];
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = threadIdx.x + NT * q;
+    if (b < nb) {
+      const int p = b >= LR ? 1 : 0;
+      const int j = b - p * LR;
+      const int k = j & (ns - 1);
+      cplx<T>* dst = buf + p * L + ((j >> lns) << lns) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * ns] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Forward DFT of nseq (1 or 2) sequences of length L held back to back in
+// `buf` (LDS), in place.  nseq * L <= 2 * blockDim.x * 4 is required (at most
+// four radix-2 butterflies per thread).  Every thread of the block must call
+// it; it begins and ends with a barrier.
+template <typename T>
+__device__ __forceinline__ void fft_lds(cplx<T>* buf, int nseq, int L, int nst, const int* rad,
+                                        const int* lns,
+                        const int* tws, const cplx<T>* tw) {
+  __syncthreads();
+#pragma unroll 1
+  for (int s = 0; s < nst; ++s) {
+    const int R = rad[s];
+    if (R == 4) fft_stage<T, 4, 2>(buf, nseq, L, lns[s], tws[s], tw);
+    else if (R == 2) fft_stage<T, 2, 4>(buf, nseq, L, lns[s], tws[s], tw);
+    else fft_stage<T, 3, 3>(buf, nseq, L, lns[s], tws[s], tw);
   }
 }
 
-// Forward DFT of nseq sequences of length L held back to back in `a`.
-// `b` is scratch of the same size.  Returns the buffer holding the result.
-// Must be called by every thread of the block; begins and ends with a barrier.
+// Copy the half twiddle table (L/2 values) from global memory to LDS.
 template <typename T>
-__device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nseq, int L, int nst, const int* rad,
-                            const cplx<T>* __restrict__ tw) {
-  __syncthreads();
-  int Ns = 1;
-  for (int s = 0; s < nst; ++s) {
-    const int R = rad[s];
-    if (R == 4) fft_stage<T, 4>(a, b, nseq, L, Ns, tw);
-    else if (R == 2) fft_stage<T, 2>(a, b, nseq, L, Ns, tw);
-    else fft_stage<T, 3>(a, b, nseq, L, Ns, tw);
-    __syncthreads();
-    cplx<T>* t = a; a = b; b = t;
-    Ns *= R;
-  }
-  return a;
+__device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __restrict__ src,
+                                              int L) {
+  for (int m = threadIdx.x; m < (L >> 1); m += kThreads) dst[m] = src[m];
 }
 
 }  // namespace cgp

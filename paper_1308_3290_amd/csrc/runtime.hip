@@ -18,7 +18,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/cgp.h"
+#include "cgp.h"
 #include "cgp_internal.hpp"
 
 using namespace cgp;
@@ -51,7 +51,6 @@ constexpr size_t kAlign = 256;
 constexpr int kDiagBlocks = 64;
 constexpr int kFiniteBlocks = 256;
 constexpr size_t kMaxLds = 64 * 1024;
-constexpr int kMaxPairElems = 1024;  // complex elements per LDS ping-pong buffer
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -61,14 +60,24 @@ bool pow2_or_3pow2(int n) {
   return n == 1 || n == 3;
 }
 
-// Radix sequence of a complex FFT of length L = 2^k or 3*2^k: radix 4 while
-// more than a factor 4 remains, the radix 3, then 4s, then a final 2.
-int radices(int L, int* out) {
-  int n = 0;
-  while (L % 4 == 0 && L > 4) { out[n++] = 4; L /= 4; }
-  if (L % 3 == 0) { out[n++] = 3; L /= 3; }
-  while (L % 4 == 0) { out[n++] = 4; L /= 4; }
-  while (L % 2 == 0) { out[n++] = 2; L /= 2; }
+// Stage plan of a complex FFT of length L = 2^k or 3*2^k: radix 4 while
+// possible, then 2, then the radix 3 last, so every stage's span Ns (the
+// product of the earlier radices) is a power of two.
+int plan_stages(int L, int* rad, int* lns, int* tws) {
+  int n = 0, rest = L, ns = 1;
+  auto push = [&](int r) {
+    rad[n] = r;
+    int lg = 0;
+    while ((1 << lg) < ns) ++lg;
+    lns[n] = lg;
+    tws[n] = L / (ns * r);
+    ns *= r;
+    rest /= r;
+    ++n;
+  };
+  while (rest % 4 == 0) push(4);
+  while (rest % 2 == 0) push(2);
+  if (rest == 3) push(3);
   return n;
 }
 
@@ -89,9 +98,10 @@ cgp_status validate(const cgp_config* c) {
     return fail(CGP_ERR_UNSUPPORTED, "coarse grid %dx%d below 4x4", Mx, My);
   if (!pow2_or_3pow2(Mx) || !pow2_or_3pow2(My))
     return fail(CGP_ERR_UNSUPPORTED, "coarse sizes %dx%d must be 2^k or 3*2^k", Mx, My);
-  const int mmax = c->dtype == CGP_F64 ? 1024 : 2048;
-  if (Mx > mmax || My > mmax)
-    return fail(CGP_ERR_UNSUPPORTED, "coarse size above %d", mmax);
+  if (Mx > 1024 || My > 1024)
+    return fail(CGP_ERR_UNSUPPORTED, "coarse size above 1024");
+  if (c->nlayers == 2 && f > 1 && Mx > 512)
+    return fail(CGP_ERR_UNSUPPORTED, "two-layer coarse rows above 512 with coarsening");
   const double vals[] = {c->lx, c->ly, c->y0, c->inv_re, c->inv_ro, c->f1, c->f2, c->drag, c->dt};
   for (double v : vals)
     if (!std::isfinite(v)) return fail(CGP_ERR_INVALID, "non-finite coefficient");
@@ -102,22 +112,64 @@ cgp_status validate(const cgp_config* c) {
 }
 
 struct Layout {
-  size_t desc = 0, tw = 0, lam = 0, wt = 0, psi = 0, st1 = 0, st2 = 0, diag = 0, fin = 0, total = 0;
+  size_t desc = 0, order = 0, tw = 0, lam = 0, wt = 0, psi = 0, st1 = 0, st2 = 0, diag = 0,
+         fin = 0, total = 0;
   long long field_elems = 0;
+};
+
+// One launch of a transform pass on the host side.
+struct HostGroup {
+  int L = 0;                 // fast-engine length, 0 = generic engine
+  std::vector<int> members;  // member indices in member order
+  int nblk = 0;
+  size_t lds = 0;
+  int order_off = 0;         // offset of the member list in the order region (ints)
 };
 
 struct Plan {
   std::vector<MemberDesc> md;
   Layout lay;
-  int nblk[NUM_PASSES] = {0, 0, 0, 0};
-  size_t lds[3] = {0, 0, 0};
+  std::vector<HostGroup> groups[3];  // passes A, B, C
+  int nblk_d = 0;                    // pass D: one launch over every member
   int dtype = CGP_F64, nlayers = 1;
 };
+
+constexpr int kGenericThreads = 256;
+
+// Group the members of one transform pass by length and size each launch.
+// `len` gives a member's transform length, `fill` sets its per-block share
+// for the group's block size and returns (blocks, LDS bytes).
+template <typename LenF, typename FillF>
+void build_groups(std::vector<MemberDesc>& md, int pass, LenF len, FillF fill,
+                  std::vector<HostGroup>& groups) {
+  std::map<int, int> by_len;
+  for (int m = 0; m < (int)md.size(); ++m) {
+    const int key = len(md[m]);
+    auto it = by_len.find(key);
+    if (it == by_len.end()) {
+      it = by_len.emplace(key, (int)groups.size()).first;
+      HostGroup g;
+      g.L = key;
+      groups.push_back(g);
+    }
+    groups[it->second].members.push_back(m);
+  }
+  for (HostGroup& g : groups) {
+    for (int m : g.members) {
+      auto r = fill(md[m], g);
+      md[m].blk0[pass] = g.nblk;
+      md[m].nblk[pass] = r.first;
+      g.nblk += r.first;
+      g.lds = std::max(g.lds, r.second);
+    }
+  }
+}
 
 cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   if (!cfgs || count < 1) return fail(CGP_ERR_INVALID, "need at least one member");
   const int dtype = cfgs[0].dtype, nl = cfgs[0].nlayers;
   const size_t es = dtype == CGP_F64 ? 8 : 4;
+  const size_t cs = 2 * es;
   plan->dtype = dtype;
   plan->nlayers = nl;
   plan->md.assign(count, MemberDesc{});
@@ -137,36 +189,16 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     d.nlayers = nl;
     d.Lr = 2 * d.Mx;
     d.Lc = 2 * d.My;
-    d.nst_r = radices(d.Lr, d.rad_r);
-    d.nst_c = radices(d.Lc, d.rad_c);
-    d.pa = std::max(1, kMaxPairElems / d.Lr);
-    d.pb = std::max(1, kMaxPairElems / d.Lc);
-    const int halo = d.c > 1 ? 1 : 0;
-    if (nl == 1) {
-      d.pc = std::max(1, kMaxPairElems / d.Lr);
-      d.tj = 2 * d.pc - halo;
-    } else {
-      d.pc = std::max(1 + halo, kMaxPairElems / d.Lr);
-      d.tj = d.pc - halo;
-    }
-    const int rows_a = nl == 1 ? 2 * d.pa : d.pa;
-    const int cols_b = nl == 1 ? 2 * d.pb : d.pb;
-    d.nblk[PASS_A] = (d.My - 1 + rows_a - 1) / rows_a;
-    d.nblk[PASS_B] = (d.Mx - 1 + cols_b - 1) / cols_b;
-    d.nblk[PASS_C] = halo ? (d.My + d.tj - 1) / d.tj : (d.My + 1 + d.tj - 1) / d.tj;
-    d.nblk[PASS_D] = ((d.nx + kTileX) / kTileX) * ((d.ny + kTileY) / kTileY);
-    for (int p = 0; p < NUM_PASSES; ++p) {
-      d.blk0[p] = plan->nblk[p];
-      plan->nblk[p] += d.nblk[p];
-    }
+    d.nst_r = plan_stages(d.Lr, d.rad_r, d.lns_r, d.tws_r);
+    d.nst_c = plan_stages(d.Lc, d.rad_c, d.lns_c, d.tws_c);
     d.field_off = fld;
     fld += (long long)nl * (c.ny + 1) * (c.nx + 1);
     d.wt_off = wt;
     wt += (long long)nl * (d.Mx - 1) * (d.My - 1);
     d.twr_off = tw;
-    tw += d.Lr;
+    tw += d.Lr / 2;
     d.twc_off = tw;
-    tw += d.Lc;
+    tw += d.Lc / 2;
     d.lam_off = lam;
     lam += (d.Mx - 1) + (d.My - 1);
     d.dx = c.lx / c.nx;
@@ -178,19 +210,56 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     d.drag = nl == 2 ? c.drag : 0.0;
     d.dt = c.dt;
     d.delta = (d.f1 + d.f2 > 0) ? d.f2 / (d.f1 + d.f2) : 0.5;
-    const size_t cs = 2 * es;
-    const size_t la = 2 * (size_t)d.pa * d.Lr * cs;
-    const size_t lb = 2 * (size_t)d.pb * d.Lc * cs;
-    const size_t lc = 2 * (size_t)d.pc * d.Lr * cs + (size_t)nl * (d.tj + 1) * (d.Mx + 1) * es;
-    plan->lds[0] = std::max(plan->lds[0], la);
-    plan->lds[1] = std::max(plan->lds[1], lb);
-    plan->lds[2] = std::max(plan->lds[2], lc);
-    if (la > kMaxLds || lb > kMaxLds || lc > kMaxLds)
-      return fail(CGP_ERR_UNSUPPORTED, "member %d needs more than 64 KiB LDS per block", m);
+    d.blk0[PASS_D] = plan->nblk_d;
+    d.nblk[PASS_D] = ((d.nx + kTileX) / kTileX) * ((d.ny + kTileY) / kTileY);
+    plan->nblk_d += d.nblk[PASS_D];
   }
+  // A block transforms at most two sequences and at most 2048 complex values.
+  auto pairs = [](int L) { return L <= 512 ? 2 : 1; };
+  // pass A: pairs of coarse rows (one layer) or one coarse row's two modes
+  build_groups(plan->md, PASS_A, [](const MemberDesc&) { return 0; },
+               [&](MemberDesc& d, HostGroup&) {
+                 d.pa = pairs(d.Lr);
+                 const int rows = nl == 1 ? 2 * d.pa : d.pa;
+                 const size_t lds = ((size_t)d.pa * d.Lr + d.Lr / 2) * cs;
+                 return std::make_pair((d.My - 1 + rows - 1) / rows, lds);
+               },
+               plan->groups[0]);
+  // pass B: pairs of spectral columns (one layer) or one column's two modes
+  build_groups(plan->md, PASS_B, [](const MemberDesc&) { return 0; },
+               [&](MemberDesc& d, HostGroup&) {
+                 d.pb = pairs(d.Lc);
+                 const int cols = nl == 1 ? 2 * d.pb : d.pb;
+                 const size_t lds = ((size_t)d.pb * d.Lc + d.Lc / 2) * cs;
+                 return std::make_pair((d.Mx - 1 + cols - 1) / cols, lds);
+               },
+               plan->groups[1]);
+  // pass C: tj owned coarse rows (+1 halo row when c > 1) per block
+  build_groups(plan->md, PASS_C, [](const MemberDesc&) { return 0; },
+               [&](MemberDesc& d, HostGroup&) {
+                 const int halo = d.c > 1 ? 1 : 0;
+                 d.pc = nl == 1 ? pairs(d.Lr) : (d.Lr <= 1024 ? 2 : 1);
+                 d.tj = (nl == 1 ? 2 * d.pc : d.pc) - halo;
+                 const size_t lds = ((size_t)d.pc * d.Lr + d.Lr / 2) * cs +
+                                    (halo ? (size_t)nl * (d.tj + 1) * (d.Mx + 1) * es : 0);
+                 const int nb = halo ? (d.My + d.tj - 1) / d.tj : (d.My + 1 + d.tj - 1) / d.tj;
+                 return std::make_pair(nb, lds);
+               },
+               plan->groups[2]);
+  for (int p = 0; p < 3; ++p)
+    for (const HostGroup& g : plan->groups[p])
+      if (g.lds > kMaxLds)
+        return fail(CGP_ERR_UNSUPPORTED, "a transform pass needs more than 64 KiB LDS per block");
   Layout& L = plan->lay;
   size_t off = 0;
   L.desc = off; off = align_up(off + sizeof(MemberDesc) * count);
+  L.order = off; off = align_up(off + sizeof(int) * 3 * count);
+  int o = 0;
+  for (int p = 0; p < 3; ++p)
+    for (HostGroup& g : plan->groups[p]) {
+      g.order_off = o;
+      o += (int)g.members.size();
+    }
   L.tw = off; off = align_up(off + (size_t)tw * 2 * es);
   L.lam = off; off = align_up(off + (size_t)lam * sizeof(double));
   L.wt = off; off = align_up(off + (size_t)wt * es);
@@ -215,6 +284,12 @@ struct cgp_handle {
   int nm() const { return (int)plan.md.size(); }
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   const MemberDesc* d_md() const { return at<MemberDesc>(plan.lay.desc); }
+  Group group(int pass, int i) const {
+    const HostGroup& g = plan.groups[pass][i];
+    return Group{g.L, (int)g.members.size(), at<int>(plan.lay.order) + g.order_off, g.nblk,
+                 kThreads, g.lds};
+  }
+  int ngroups(int pass) const { return (int)plan.groups[pass].size(); }
 };
 
 namespace {
@@ -222,19 +297,30 @@ namespace {
 const double kRkA[3] = {0.0, 0.75, 1.0 / 3.0};
 const double kRkB[3] = {1.0, 0.25, 2.0 / 3.0};
 
+// One pass of the coarse solve (0: A, 1: B, 2: C) over every member.
 template <typename T>
-hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hipStream_t s) {
+hipError_t enqueue_pass(cgp_handle* h, int pass, const T* src, T* dst, int accumulate,
+                        hipStream_t s) {
   const Plan& p = h->plan;
   const cplx<T>* tw = h->at<cplx<T>>(p.lay.tw);
   T* wt = h->at<T>(p.lay.wt);
-  hipError_t e = Launch<T>::restrict_rowdst(h->d_md(), h->nm(), p.nblk[PASS_A], p.lds[0], src, wt,
-                                            tw, s);
-  if (e != hipSuccess) return e;
-  e = Launch<T>::col_solve(h->d_md(), h->nm(), p.nblk[PASS_B], p.lds[1], wt, tw,
-                           h->at<double>(p.lay.lam), s);
-  if (e != hipSuccess) return e;
-  return Launch<T>::rowdst_prolong(h->d_md(), h->nm(), p.nblk[PASS_C], p.lds[2], wt, dst,
-                                   accumulate, tw, s);
+  for (int i = 0; i < h->ngroups(pass); ++i) {
+    const Group g = h->group(pass, i);
+    hipError_t e;
+    if (pass == 0) e = Launch<T>::restrict_rowdst(h->d_md(), g, src, wt, tw, s);
+    else if (pass == 1) e = Launch<T>::col_solve(h->d_md(), g, wt, tw, h->at<double>(p.lay.lam), s);
+    else e = Launch<T>::rowdst_prolong(h->d_md(), g, wt, dst, accumulate, tw, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hipStream_t s) {
+  hipError_t e = enqueue_pass<T>(h, 0, src, nullptr, 0, s);
+  if (e == hipSuccess) e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s);
+  if (e == hipSuccess) e = enqueue_pass<T>(h, 2, nullptr, dst, accumulate, s);
+  return e;
 }
 
 // One CGPRK3 step: w1 -> stage 1 buffer, w2 -> stage 2 buffer, w_{n+1} -> omega.
@@ -252,14 +338,14 @@ hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s
   for (int st = 0; st < 3; ++st) {
     hipError_t e = enqueue_solve<T>(h, src[st], psis[st], 0, s);
     if (e != hipSuccess) return e;
-    e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), p.nblk[PASS_D], src[st], psis[st], forcing,
+    e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), p.nblk_d, src[st], psis[st], forcing,
                                omega, dst[st], kRkA[st], kRkB[st], s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-// enqueue_step with an event recorded after each of its 12 launches
+// enqueue_step with an event recorded after each of its 12 passes
 template <typename T>
 hipError_t enqueue_step_events(cgp_handle* h, T* omega, const T* forcing, hipStream_t s,
                                hipEvent_t* ev) {
@@ -267,21 +353,18 @@ hipError_t enqueue_step_events(cgp_handle* h, T* omega, const T* forcing, hipStr
   T* b1 = h->at<T>(p.lay.st1);
   T* b2 = h->at<T>(p.lay.st2);
   T* pd = h->at<T>(p.lay.psi);
-  const cplx<T>* tw = h->at<cplx<T>>(p.lay.tw);
-  T* wt = h->at<T>(p.lay.wt);
   const T* src[3] = {omega, b1, b2};
   T* dst[3] = {b1, b2, omega};
   int k = 0;
   hipError_t e;
   for (int st = 0; st < 3; ++st) {
-    e = Launch<T>::restrict_rowdst(h->d_md(), h->nm(), p.nblk[PASS_A], p.lds[0], src[st], wt, tw, s);
+    e = enqueue_pass<T>(h, 0, src[st], nullptr, 0, s);
     if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
-    e = Launch<T>::col_solve(h->d_md(), h->nm(), p.nblk[PASS_B], p.lds[1], wt, tw,
-                             h->at<double>(p.lay.lam), s);
+    e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s);
     if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
-    e = Launch<T>::rowdst_prolong(h->d_md(), h->nm(), p.nblk[PASS_C], p.lds[2], wt, pd, 0, tw, s);
+    e = enqueue_pass<T>(h, 2, nullptr, pd, 0, s);
     if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
-    e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), p.nblk[PASS_D], src[st], pd, forcing, omega,
+    e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), p.nblk_d, src[st], pd, forcing, omega,
                                dst[st], kRkA[st], kRkB[st], s);
     if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
   }
@@ -295,6 +378,10 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
   // host image of [desc][tw][lam]
   h->host_tables.assign(L.wt, 0);
   std::memcpy(h->host_tables.data() + L.desc, p.md.data(), sizeof(MemberDesc) * p.md.size());
+  int* order = reinterpret_cast<int*>(h->host_tables.data() + L.order);
+  for (int pass = 0; pass < 3; ++pass)
+    for (const HostGroup& g : p.groups[pass])
+      for (size_t i = 0; i < g.members.size(); ++i) order[g.order_off + i] = g.members[i];
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(h->host_tables.data() + L.tw);
   double* lam = reinterpret_cast<double*>(h->host_tables.data() + L.lam);
   const double pi = 3.14159265358979323846264338327950288;
@@ -302,7 +389,7 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
     for (int pass = 0; pass < 2; ++pass) {
       const int Ln = pass == 0 ? d.Lr : d.Lc;
       cplx<T>* t = tw + (pass == 0 ? d.twr_off : d.twc_off);
-      for (int mm = 0; mm < Ln; ++mm) {
+      for (int mm = 0; mm < Ln / 2; ++mm) {
         const double ang = 2.0 * pi * (double)mm / (double)Ln;
         t[mm].x = (T)std::cos(ang);
         t[mm].y = (T)(-std::sin(ang));
@@ -609,7 +696,7 @@ cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forc
   double* lam = static_cast<double*>(lambda);
   double* gF = static_cast<double*>(grad_forcing);
   const MemberDesc* md = h->d_md();
-  const int nb = h->plan.nblk[PASS_D];
+  const int nb = h->plan.nblk_d;
   for (int n = nsteps - 1; n >= 0; --n) {
     // stage 2: lam_3 = lam -> X2 ; stage 1: X2 -> X1 ; stage 0: X1 -> lam
     const double* lin[3] = {X1, X2, lam};

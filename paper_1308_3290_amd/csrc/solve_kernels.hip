@@ -11,6 +11,10 @@
 // wt[m][k-1][j-1] (x-wavenumber k = 1..Mx-1, coarse row j = 1..My-1), so the
 // y transforms of pass B read contiguous lines and passes A and C do the
 // transposition through LDS.
+//
+// Every block has kThreads threads.  Memory phases map one thread to one
+// coarse column (or spectral index) and handle all of the block's rows in
+// registers, so that each thread issues its global loads together.
 #include "cgp_internal.hpp"
 #include "fft_lds.hpp"
 
@@ -39,10 +43,8 @@ __device__ __forceinline__ T restrict_fixed(const T* __restrict__ f, int pitch, 
 }
 
 template <typename T>
-__device__ __forceinline__ T restrict_any(const T* __restrict__ f, int pitch, int c, int I, int J) {
-  if (c == 2) return restrict_fixed<T, 2>(f, pitch, I, J);
-  if (c == 1) return restrict_fixed<T, 1>(f, pitch, I, J);
-  if (c == 4) return restrict_fixed<T, 4>(f, pitch, I, J);
+__device__ __forceinline__ T restrict_generic(const T* __restrict__ f, int pitch, int c, int I,
+                                              int J) {
   const T* base = f + (size_t)(c * J) * pitch + c * I;
   T acc = T(0);
   for (int dy = -(c - 1); dy <= c - 1; ++dy) {
@@ -55,72 +57,109 @@ __device__ __forceinline__ T restrict_any(const T* __restrict__ f, int pitch, in
   return acc / (c2 * c2);
 }
 
+__device__ __forceinline__ int group_member(const MemberDesc* md, const int* grp, int ng, int p,
+                                           int b) {
+  int lo = 0, hi = ng - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (md[grp[mid]].blk0[p] <= b) lo = mid; else hi = mid - 1;
+  }
+  return grp[lo];
+}
+
 // ---------------------------------------------------------------------------
-// Pass A.  Block = `pa` sequence pairs.  One layer: a pair is two consecutive
-// coarse rows; two layers: a pair is the barotropic and the baroclinic
-// combination of one coarse row.
+// Pass A.  A block restricts `rows` (<= 4) consecutive coarse rows starting at
+// j0 and transforms them along x: one layer, pairs of rows share one complex
+// FFT; two layers, the barotropic and baroclinic combinations of a row do.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
-    const MemberDesc* __restrict__ md, int nm, const T* __restrict__ src, T* __restrict__ wt,
-    const cplx<T>* __restrict__ tw) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int m = find_member(md, nm, PASS_A, blockIdx.x);
-  const MemberDesc& d = md[m];
-  const int lb = blockIdx.x - d.blk0[PASS_A];
-  const int Mx = d.Mx, My = d.My, L = d.Lr, P = d.pa, c = d.c, nl = d.nlayers;
+template <typename T, int C>
+__device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __restrict__ f,
+                                               cplx<T>* buf, int j0, int nr, int L) {
+  const int Mx = d.Mx, c = d.c, nl = d.nlayers;
   const int pitch = d.nx + 1;
   const size_t plane = (size_t)(d.ny + 1) * pitch;
-  const T* f = src + d.field_off;
-  cplx<T>* bufA = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* bufB = bufA + P * L;
-  const int per = (nl == 1) ? 2 : 1;  // coarse rows per pair
-  const int rows_blk = per * P;
-  const int j0 = 1 + lb * rows_blk;
   const T wbt1 = T(d.delta), wbt2 = T(1.0 - d.delta);
-
-  for (int t = threadIdx.x; t < P * Mx; t += blockDim.x) {
-    const int p = t / Mx;
-    const int i = t - p * Mx;
-    cplx<T>* z = bufA + p * L;
-    if (i == 0) {
-      z[0] = {T(0), T(0)};
-      z[Mx] = {T(0), T(0)};
-      continue;
-    }
-    T a = T(0), b = T(0);
-    if (nl == 1) {
-      const int ja = j0 + 2 * p;
-      if (ja < My) a = restrict_any(f, pitch, c, i, ja);
-      if (ja + 1 < My) b = restrict_any(f, pitch, c, i, ja + 1);
-    } else {
-      const int j = j0 + p;
-      if (j < My) {
-        const T q1 = restrict_any(f, pitch, c, i, j);
-        const T q2 = restrict_any(f + plane, pitch, c, i, j);
-        a = wbt1 * q1 + wbt2 * q2;  // barotropic right-hand side
-        b = q1 - q2;                // baroclinic right-hand side
+  for (int i = 1 + threadIdx.x; i < Mx; i += kThreads) {
+    T v[4], u[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      v[r] = T(0);
+      u[r] = T(0);
+      if (r < nr) {
+        if constexpr (C > 0) {
+          v[r] = restrict_fixed<T, C>(f, pitch, i, j0 + r);
+          if (nl == 2) u[r] = restrict_fixed<T, C>(f + plane, pitch, i, j0 + r);
+        } else {
+          v[r] = restrict_generic<T>(f, pitch, c, i, j0 + r);
+          if (nl == 2) u[r] = restrict_generic<T>(f + plane, pitch, c, i, j0 + r);
+        }
       }
     }
-    z[i] = {a, b};
-    z[2 * Mx - i] = {-a, -b};
+    if (nl == 1) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        if (2 * p < nr) {
+          const cplx<T> z = {v[2 * p], v[2 * p + 1]};
+          buf[p * L + i] = z;
+          buf[p * L + 2 * Mx - i] = {-z.x, -z.y};
+        }
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        if (p < nr) {
+          const cplx<T> z = {wbt1 * v[p] + wbt2 * u[p], v[p] - u[p]};  // (barotropic, baroclinic)
+          buf[p * L + i] = z;
+          buf[p * L + 2 * Mx - i] = {-z.x, -z.y};
+        }
+      }
+    }
   }
-  const cplx<T>* Z = fft_lds(bufA, bufB, P, L, d.nst_r, d.rad_r, tw + d.twr_off);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
+    const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng,
+    const T* __restrict__ src, T* __restrict__ wt, const cplx<T>* __restrict__ twg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const MemberDesc& d = md[group_member(md, grp, ng, PASS_A, blockIdx.x)];
+  const int lb = blockIdx.x - d.blk0[PASS_A];
+  const int Mx = d.Mx, My = d.My, L = d.Lr, P = d.pa, nl = d.nlayers;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = buf + P * L;
+  const int rows_blk = (nl == 1) ? 2 * P : P;  // 1, 2 or 4
+  const int j0 = 1 + lb * rows_blk;
+  const int nr = min(rows_blk, My - j0);
+  const int nseq = (nl == 1) ? (nr + 1) / 2 : nr;
+
+  load_twiddles(tw, twg + d.twr_off, L);
+  if (threadIdx.x < nseq) {
+    buf[threadIdx.x * L] = {T(0), T(0)};
+    buf[threadIdx.x * L + Mx] = {T(0), T(0)};
+  }
+  const T* f = src + d.field_off;
+  switch (d.c) {
+    case 1: restrict_block<T, 1>(d, f, buf, j0, nr, L); break;
+    case 2: restrict_block<T, 2>(d, f, buf, j0, nr, L); break;
+    case 4: restrict_block<T, 4>(d, f, buf, j0, nr, L); break;
+    default: restrict_block<T, 0>(d, f, buf, j0, nr, L);
+  }
+  fft_lds<T>(buf, nseq, L, d.nst_r, d.rad_r, d.lns_r, d.tws_r, tw);
 
   T* w = wt + d.wt_off;
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
-  const int nvals = (Mx - 1) * rows_blk;
-  for (int t = threadIdx.x; t < nvals; t += blockDim.x) {
-    const int k = 1 + t / rows_blk;
-    const int r = t - (k - 1) * rows_blk;
-    const int j = j0 + r;
-    if (j >= My) continue;
-    const size_t o = (size_t)(k - 1) * (My - 1) + (j - 1);
+  const int sh = rows_blk == 4 ? 2 : (rows_blk == 2 ? 1 : 0);
+  const int nvals = (Mx - 1) << sh;
+  for (int q = threadIdx.x; q < nvals; q += kThreads) {
+    const int k = 1 + (q >> sh);
+    const int r = q & (rows_blk - 1);
+    if (r >= nr) continue;
+    const size_t o = (size_t)(k - 1) * (My - 1) + (j0 + r - 1);
     if (nl == 1) {
-      const cplx<T> zk = Z[(r >> 1) * L + k];
+      const cplx<T> zk = buf[(r >> 1) * L + k];
       w[o] = (r & 1) ? T(0.5) * zk.x : T(-0.5) * zk.y;
     } else {
-      const cplx<T> zk = Z[r * L + k];
+      const cplx<T> zk = buf[r * L + k];
       w[o] = T(-0.5) * zk.y;
       w[mplane + o] = T(0.5) * zk.x;
     }
@@ -128,124 +167,131 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
 }
 
 // ---------------------------------------------------------------------------
-// Pass B.  Block = `pb` pairs of coarse spectral columns (one layer: columns
-// k, k+1; two layers: barotropic and baroclinic column k).  Forward y
-// transform, multiply by (2/Mx)(2/My)/lambda_kl, inverse y transform.
+// Pass B.  A block transforms `pb` (<= 2) pairs of coarse spectral columns
+// (one layer: columns k, k+1; two layers: the barotropic and baroclinic
+// column k) along y, multiplies by (2/Mx)(2/My)/lambda_kl (baroclinic:
+// 1/(lambda_kl - F1 - F2)), and transforms back.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __restrict__ md, int nm,
+__global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __restrict__ md,
+                                                        const int* __restrict__ grp, int ng,
                                                         T* __restrict__ wt,
-                                                        const cplx<T>* __restrict__ tw,
+                                                        const cplx<T>* __restrict__ twg,
                                                         const double* __restrict__ lam) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int m = find_member(md, nm, PASS_B, blockIdx.x);
-  const MemberDesc& d = md[m];
+  const MemberDesc& d = md[group_member(md, grp, ng, PASS_B, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_B];
   const int Mx = d.Mx, My = d.My, L = d.Lc, P = d.pb, nl = d.nlayers;
   const int ny1 = My - 1;
-  cplx<T>* bufA = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* bufB = bufA + P * L;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = buf + P * L;
   T* w = wt + d.wt_off;
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
   const double* lamx = lam + d.lam_off;
   const double* lamy = lamx + (Mx - 1);
   const double scale = 4.0 / ((double)Mx * (double)My);
-  const double shift = d.f1 + d.f2;  // Helmholtz shift of the baroclinic mode
+  const double shift = nl == 2 ? d.f1 + d.f2 : 0.0;
 
-  // column indices (1-based) of the two sequences of pair p; 0 = absent
-  auto cols = [&](int p, int& ka, int& kb) {
+  // columns (1-based, 0 = absent) of the two sequences of each pair
+  int ka[2], kb[2];
+  int nseq = 0;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
     if (nl == 1) {
-      ka = 1 + 2 * (lb * P + p);
-      kb = ka + 1;
-      if (ka > Mx - 1) ka = 0;
-      if (kb > Mx - 1) kb = 0;
+      ka[p] = 1 + 2 * (lb * P + p);
+      kb[p] = ka[p] + 1;
+      if (ka[p] > Mx - 1) ka[p] = 0;
+      if (kb[p] > Mx - 1) kb[p] = 0;
     } else {
-      ka = 1 + lb * P + p;
-      if (ka > Mx - 1) ka = 0;
-      kb = ka;
+      ka[p] = 1 + lb * P + p;
+      if (ka[p] > Mx - 1) ka[p] = 0;
+      kb[p] = ka[p];
     }
-  };
-  auto col_ptr = [&](int seq, int k) -> T* {
-    // seq 0 / 1 of the pair; two layers: seq 1 is the baroclinic plane
-    return w + ((nl == 2 && seq == 1) ? mplane : 0) + (size_t)(k - 1) * ny1;
-  };
-
-  for (int t = threadIdx.x; t < P * My; t += blockDim.x) {
-    const int p = t / My;
-    const int l = t - p * My;
-    cplx<T>* z = bufA + p * L;
-    if (l == 0) {
-      z[0] = {T(0), T(0)};
-      z[My] = {T(0), T(0)};
-      continue;
-    }
-    int ka, kb;
-    cols(p, ka, kb);
-    const T a = ka ? col_ptr(0, ka)[l - 1] : T(0);
-    const T b = kb ? col_ptr(1, kb)[l - 1] : T(0);
-    z[l] = {a, b};
-    z[2 * My - l] = {-a, -b};
+    if (p >= P) ka[p] = kb[p] = 0;
+    if (ka[p]) nseq = p + 1;
   }
-  cplx<T>* Z = fft_lds(bufA, bufB, P, L, d.nst_c, d.rad_c, tw + d.twc_off);
-  cplx<T>* Y = (Z == bufA) ? bufB : bufA;
-
-  for (int t = threadIdx.x; t < P * My; t += blockDim.x) {
-    const int p = t / My;
-    const int l = t - p * My;
-    cplx<T>* y = Y + p * L;
-    if (l == 0) {
-      y[0] = {T(0), T(0)};
-      y[My] = {T(0), T(0)};
-      continue;
-    }
-    int ka, kb;
-    cols(p, ka, kb);
-    const cplx<T> zl = Z[p * L + l];
-    T a = T(0), b = T(0);
-    if (ka) a = T(-0.5) * zl.y * T(scale / (lamx[ka - 1] + lamy[l - 1]));
-    if (kb) {
-      const double lb_ = lamx[kb - 1] + lamy[l - 1] - (nl == 2 ? shift : 0.0);
-      b = T(0.5) * zl.x * T(scale / lb_);
-    }
-    y[l] = {a, b};
-    y[2 * My - l] = {-a, -b};
+  T* cola[2];
+  T* colb[2];
+  double lxa[2], lxb[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    cola[p] = w + (size_t)(ka[p] ? ka[p] - 1 : 0) * ny1;
+    colb[p] = w + ((nl == 2) ? mplane : 0) + (size_t)(kb[p] ? kb[p] - 1 : 0) * ny1;
+    lxa[p] = ka[p] ? lamx[ka[p] - 1] : -1.0;
+    lxb[p] = (kb[p] ? lamx[kb[p] - 1] : -1.0) - shift;
   }
-  cplx<T>* Zs = (Z == bufA) ? bufA : bufB;  // scratch for the second transform
-  const cplx<T>* R = fft_lds(Y, Zs, P, L, d.nst_c, d.rad_c, tw + d.twc_off);
 
-  for (int t = threadIdx.x; t < P * ny1; t += blockDim.x) {
-    const int p = t / ny1;
-    const int l = 1 + (t - p * ny1);
-    int ka, kb;
-    cols(p, ka, kb);
-    const cplx<T> r = R[p * L + l];
-    if (ka) col_ptr(0, ka)[l - 1] = T(-0.5) * r.y;
-    if (kb) col_ptr(1, kb)[l - 1] = T(0.5) * r.x;
+  load_twiddles(tw, twg + d.twc_off, L);
+  if (threadIdx.x < nseq) {
+    buf[threadIdx.x * L] = {T(0), T(0)};
+    buf[threadIdx.x * L + My] = {T(0), T(0)};
+  }
+  for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p < nseq) {
+        const T a = ka[p] ? cola[p][l - 1] : T(0);
+        const T b = kb[p] ? colb[p][l - 1] : T(0);
+        buf[p * L + l] = {a, b};
+        buf[p * L + 2 * My - l] = {-a, -b};
+      }
+    }
+  }
+  fft_lds<T>(buf, nseq, L, d.nst_c, d.rad_c, d.lns_c, d.tws_c, tw);
+
+  for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
+    const double ly = lamy[l - 1];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p < nseq) {
+        const cplx<T> z = buf[p * L + l];
+        const T a = T(-0.5) * z.y * T(scale / (lxa[p] + ly));
+        const T b = T(0.5) * z.x * T(scale / (lxb[p] + ly));
+        buf[p * L + l] = {a, b};
+        buf[p * L + 2 * My - l] = {-a, -b};
+      }
+    }
+  }
+  if (threadIdx.x < nseq) {
+    buf[threadIdx.x * L] = {T(0), T(0)};
+    buf[threadIdx.x * L + My] = {T(0), T(0)};
+  }
+  fft_lds<T>(buf, nseq, L, d.nst_c, d.rad_c, d.lns_c, d.tws_c, tw);
+
+  for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p < nseq) {
+        const cplx<T> z = buf[p * L + l];
+        if (ka[p]) cola[p][l - 1] = T(-0.5) * z.y;
+        if (kb[p]) colb[p][l - 1] = T(0.5) * z.x;
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Pass C.  Block owns coarse rows j0 .. j0+tj-1 and writes the fine rows
 // c*j0 .. c*(j0+tj)-1 (the last block also the top wall row).  It
-// synthesises coarse rows j0 .. j0+tj-1 (+1 halo row when c > 1), keeps them
-// in LDS with their zero walls, and interpolates bilinearly.
+// synthesises coarse rows j0 .. j0+tj-1 (+1 halo row when c > 1) along x,
+// keeps them in LDS with their zero walls and interpolates bilinearly
+// (c = 1: the rows are written directly).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* __restrict__ md,
-                                                             int nm, const T* __restrict__ wt,
+                                                             const int* __restrict__ grp, int ng,
+                                                             const T* __restrict__ wt,
                                                              T* __restrict__ dst, int accumulate,
-                                                             const cplx<T>* __restrict__ tw) {
+                                                             const cplx<T>* __restrict__ twg) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int m = find_member(md, nm, PASS_C, blockIdx.x);
-  const MemberDesc& d = md[m];
+  const MemberDesc& d = md[group_member(md, grp, ng, PASS_C, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_C];
-  const int Mx = d.Mx, My = d.My, L = d.Lr, c = d.c, nl = d.nlayers, TJ = d.tj;
+  const int Mx = d.Mx, My = d.My, L = d.Lr, c = d.c, nl = d.nlayers, TJ = d.tj, P = d.pc;
   const int nx = d.nx, ny = d.ny, pitch = nx + 1;
   const size_t plane = (size_t)(ny + 1) * pitch;
-  const int PC = d.pc;
-  cplx<T>* bufA = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* bufB = bufA + PC * L;
-  T* ps = reinterpret_cast<T*>(bufB + PC * L);  // [nl][TJ+1][Mx+1]
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = buf + P * L;
+  T* ps = reinterpret_cast<T*>(tw + (L >> 1));  // [nl][TJ+1][Mx+1] (c > 1 only)
   const int prow = Mx + 1;
   const size_t pplane = (size_t)(TJ + 1) * prow;
 
@@ -254,111 +300,126 @@ __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* _
   const int ilo = max(1, j0);
   const int ihi = min(My - 1, jend);
   const int nint = ihi >= ilo ? ihi - ilo + 1 : 0;
-  const int npairs = (nl == 1) ? (nint + 1) / 2 : nint;
+  const int nseq = (nl == 1) ? (nint + 1) / 2 : nint;
   const T* w = wt + d.wt_off;
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
 
-  for (int t = threadIdx.x; t < npairs * Mx; t += blockDim.x) {
-    const int i = t / npairs;  // pair index fastest: neighbouring rows of one k
-    const int p = t - i * npairs;
-    cplx<T>* z = bufA + p * L;
-    if (i == 0) {
-      z[0] = {T(0), T(0)};
-      z[Mx] = {T(0), T(0)};
-      continue;
-    }
-    T a, b;
-    const size_t kbase = (size_t)(i - 1) * (My - 1);
-    if (nl == 1) {
-      const int ja = ilo + 2 * p;
-      a = w[kbase + ja - 1];
-      b = (ja + 1 <= ihi) ? w[kbase + ja] : T(0);
-    } else {
-      const int j = ilo + p;
-      a = w[kbase + j - 1];
-      b = w[mplane + kbase + j - 1];
-    }
-    z[i] = {a, b};
-    z[2 * Mx - i] = {-a, -b};
+  load_twiddles(tw, twg + d.twr_off, L);
+  if (threadIdx.x < nseq) {
+    buf[threadIdx.x * L] = {T(0), T(0)};
+    buf[threadIdx.x * L + Mx] = {T(0), T(0)};
   }
-  const cplx<T>* Z = fft_lds(bufA, bufB, npairs, L, d.nst_r, d.rad_r, tw + d.twr_off);
-  // fft_lds may have left its result in bufB; ps lies beyond both buffers.
+  for (int k = 1 + threadIdx.x; k < Mx; k += kThreads) {
+    const T* col = w + (size_t)(k - 1) * (My - 1) + (ilo - 1);
+    T v[4], u[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      v[r] = r < nint ? col[r] : T(0);
+      u[r] = (nl == 2 && r < nint) ? col[mplane + r] : T(0);
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p < nseq) {
+        const cplx<T> z = (nl == 1) ? cplx<T>{v[2 * p], v[2 * p + 1]} : cplx<T>{v[p], u[p]};
+        buf[p * L + k] = z;
+        buf[p * L + 2 * Mx - k] = {-z.x, -z.y};
+      }
+    }
+  }
+  fft_lds<T>(buf, nseq, L, d.nst_r, d.rad_r, d.lns_r, d.tws_r, tw);
 
-  const int nrows = jend - j0 + 1;
   const T wbc1 = T(1.0 - d.delta), wbc2 = T(d.delta);
-  for (int t = threadIdx.x; t < nrows * prow; t += blockDim.x) {
-    const int r = t / prow;
-    const int i = t - r * prow;
-    const int jj = j0 + r;
-    T v0 = T(0), v1 = T(0);
+  T* out = dst + d.field_off;
+  // coarse psi of row jj, column i (both layers), zero on the walls
+  auto coarse = [&](int jj, int i, T& v0, T& v1) {
+    v0 = T(0);
+    v1 = T(0);
     if (jj >= 1 && jj <= My - 1 && i >= 1 && i <= Mx - 1) {
       const int idx = jj - ilo;
       if (nl == 1) {
-        const cplx<T> zi = Z[(idx >> 1) * L + i];
+        const cplx<T> zi = buf[(idx >> 1) * L + i];
         v0 = (idx & 1) ? T(0.5) * zi.x : T(-0.5) * zi.y;
       } else {
-        const cplx<T> zi = Z[idx * L + i];
+        const cplx<T> zi = buf[idx * L + i];
         const T bt = T(-0.5) * zi.y, bc = T(0.5) * zi.x;
         v0 = bt + wbc1 * bc;  // psi_1 = psi_bt + (1 - delta) psi_bc
         v1 = bt - wbc2 * bc;  // psi_2 = psi_bt - delta psi_bc
       }
     }
-    ps[(size_t)r * prow + i] = v0;
-    if (nl == 2) ps[pplane + (size_t)r * prow + i] = v1;
+  };
+  const int last = (lb == d.nblk[PASS_C] - 1);
+  if (c == 1) {
+    const int rend = last ? ny + 1 : j0 + TJ;
+    for (int x = threadIdx.x; x <= nx; x += kThreads) {
+      for (int rr = j0; rr < rend; ++rr) {
+        T v0, v1;
+        coarse(rr, x, v0, v1);
+        const size_t o = (size_t)rr * pitch + x;
+        out[o] = accumulate ? out[o] + v0 : v0;
+        if (nl == 2) out[o + plane] = accumulate ? out[o + plane] + v1 : v1;
+      }
+    }
+    return;
+  }
+  const int nrows = jend - j0 + 1;
+  for (int i = threadIdx.x; i <= Mx; i += kThreads) {
+    for (int r = 0; r < nrows; ++r) {
+      T v0, v1;
+      coarse(j0 + r, i, v0, v1);
+      ps[(size_t)r * prow + i] = v0;
+      if (nl == 2) ps[pplane + (size_t)r * prow + i] = v1;
+    }
   }
   __syncthreads();
 
-  const int last = (lb == d.nblk[PASS_C] - 1);
   const int rbeg = c * j0;
   const int rend = last ? ny + 1 : c * (j0 + TJ);
   const T inv_c2 = T(1) / (T(c) * T(c));
-  T* out = dst + d.field_off;
-  const int nfr = rend - rbeg;
-  for (int t = threadIdx.x; t < nfr * pitch; t += blockDim.x) {
-    const int rr = rbeg + t / pitch;
-    const int x = t - (rr - rbeg) * pitch;
-    const int J = rr / c, fy = rr - J * c;
+  for (int x = threadIdx.x; x <= nx; x += kThreads) {
     const int I = x / c, fx = x - I * c;
-    const int r = J - j0;
     for (int l = 0; l < nl; ++l) {
-      const T* P0 = ps + l * pplane + (size_t)r * prow;
-      T v = T(c - fx) * P0[I];
-      if (fx) v += T(fx) * P0[I + 1];
-      v *= T(c - fy);
-      if (fy) {
-        const T* P1 = P0 + prow;
-        T u = T(c - fx) * P1[I];
-        if (fx) u += T(fx) * P1[I + 1];
-        v += T(fy) * u;
+      for (int rr = rbeg; rr < rend; ++rr) {
+        const int J = rr / c, fy = rr - J * c;
+        const T* P0 = ps + l * pplane + (size_t)(J - j0) * prow;
+        T v = T(c - fx) * P0[I];
+        if (fx) v += T(fx) * P0[I + 1];
+        v *= T(c - fy);
+        if (fy) {
+          const T* P1 = P0 + prow;
+          T u = T(c - fx) * P1[I];
+          if (fx) u += T(fx) * P1[I + 1];
+          v += T(fy) * u;
+        }
+        v *= inv_c2;
+        const size_t o = l * plane + (size_t)rr * pitch + x;
+        out[o] = accumulate ? out[o] + v : v;
       }
-      v *= inv_c2;
-      const size_t o = l * plane + (size_t)rr * pitch + x;
-      out[o] = accumulate ? out[o] + v : v;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t Launch<T>::restrict_rowdst(const MemberDesc* md, int nm, int nblk, size_t lds,
-                                      const T* src, T* wt, const cplx<T>* tw, hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict_rowdst<T>, dim3(nblk), dim3(kThreads), lds, s, md, nm, src, wt, tw);
+hipError_t Launch<T>::restrict_rowdst(const MemberDesc* md, const Group& g, const T* src, T* wt,
+                                      const cplx<T>* tw, hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict_rowdst<T>, dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members,
+                     g.count, src, wt, tw);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Launch<T>::col_solve(const MemberDesc* md, int nm, int nblk, size_t lds, T* wt,
-                                const cplx<T>* tw, const double* lam, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_solve<T>, dim3(nblk), dim3(kThreads), lds, s, md, nm, wt, tw, lam);
+hipError_t Launch<T>::col_solve(const MemberDesc* md, const Group& g, T* wt, const cplx<T>* tw,
+                                const double* lam, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_solve<T>, dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members,
+                     g.count, wt, tw, lam);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Launch<T>::rowdst_prolong(const MemberDesc* md, int nm, int nblk, size_t lds,
-                                     const T* wt, T* dst, int accumulate, const cplx<T>* tw,
-                                     hipStream_t s) {
-  hipLaunchKernelGGL(k_rowdst_prolong<T>, dim3(nblk), dim3(kThreads), lds, s, md, nm, wt, dst,
-                     accumulate, tw);
+hipError_t Launch<T>::rowdst_prolong(const MemberDesc* md, const Group& g, const T* wt, T* dst,
+                                     int accumulate, const cplx<T>* tw, hipStream_t s) {
+  hipLaunchKernelGGL(k_rowdst_prolong<T>, dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members,
+                     g.count, wt, dst, accumulate, tw);
   return hipGetLastError();
 }
 
