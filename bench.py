@@ -45,17 +45,66 @@ def parse():
                     help="also time two layers, FP32 and the 64-member ensemble")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", default="", help="comma list: l0,l1,l2,timed (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration runs)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) into "
+                         "profiles/traffic_c1_l1.json and exit (no GPU needed)")
     return ap.parse_args()
 
 
+COPY_BYTES = 256 << 20
+
+
+def summarize_pmc(fetch_csv, write_csv):
+    """HBM bytes per dispatch of each CGP kernel from FETCH_SIZE / WRITE_SIZE (KiB),
+    each scaled so that the plain copy of COPY_BYTES reads and writes exactly that."""
+    import csv
+    import statistics
+
+    def load(path, counter):
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name", counter) != counter:
+                continue
+            name = r["Kernel_Name"]
+            per.setdefault(name, {}).setdefault(r["Dispatch_Id"], 0.0)
+            per[name][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return {k: statistics.median(v.values()) for k, v in per.items()}
+
+    fetch = load(fetch_csv, "FETCH_SIZE")
+    write = load(write_csv, "WRITE_SIZE")
+
+    def copy_value(d):
+        cands = [v for k, v in d.items() if "MulFunctor" in k]
+        return max(cands) if cands else None
+
+    cf, cw = copy_value(fetch), copy_value(write)
+    sf = COPY_BYTES / (cf * 1024.0) if cf else 1.0
+    sw = COPY_BYTES / (cw * 1024.0) if cw else 1.0
+    out = {"source_hash": source_hash(), "copy_bytes": COPY_BYTES,
+           "scale_fetch": sf, "scale_write": sw, "kernels": {}}
+    for name in fetch:
+        if "cgp::" not in name:
+            continue
+        short = name.split("cgp::")[1].split("<")[0].split("(")[0]
+        fb = fetch[name] * 1024.0 * sf
+        wb = write.get(name, 0.0) * 1024.0 * sw
+        out["kernels"][short] = {"fetch_bytes": fb, "write_bytes": wb,
+                                 "hbm_bytes_per_launch": fb + wb}
+    path = os.path.join(ROOT, "profiles", "traffic_c1_l1.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def pass_bytes(case, es):
-    """Algorithmic bytes of one launch of each pass (fine node arrays with ring,
-    coarse interior spectra); pass D averaged over the three stages."""
+    """Algorithmic bytes of one launch of each pass as timed by cgp_time_passes
+    (fine node arrays with ring, coarse interior spectra); pass D in its
+    stage-2 form reads four fine fields and writes one."""
     fine = (case.nx + 1) * (case.ny + 1) * case.nlayers * es
     c = 2 ** case.level
     coarse = (case.nx // c - 1) * (case.ny // c - 1) * case.nlayers * es
-    return {"A": fine + coarse, "B": 2 * coarse, "C": coarse + fine,
-            "D": (4.0 + 2.0 / 3.0) * fine}
+    return {"A": fine + coarse, "B": 2 * coarse, "C": coarse + fine, "D": 5.0 * fine}
 
 
 def source_hash():
@@ -67,6 +116,9 @@ def source_hash():
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
                           "the multi-GPU design is described, not built (use --gpus 1)"}))
@@ -107,6 +159,13 @@ def main():
         return ms, finite, ens, w, Fp
 
     result = {}
+    if args.copy_calibration:
+        a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)  # one elementwise kernel: reads and writes COPY_BYTES
+        torch.cuda.synchronize()
+        del a, b
     # ---------------------------------------------------------------- main line
     rates = {}
     for lv in (1, 0, 2):
@@ -131,8 +190,9 @@ def main():
         b = api.Basin(api.config_from_case(case), device=dev)
         w = torch.as_tensor(ci.initial_field(case, rng), device=dev)
         F = torch.as_tensor(ci.forcing_field(case), device=dev)
-        api.cgp_step_timed(b.handle, w, F, 5)
-        ms = api.cgp_step_timed(b.handle, w, F, 50)
+        b.step(w, F, nsteps=2)  # fills psi, the stage buffers and the spectra
+        api.cgp_time_passes(b.handle, w, F, 10)
+        ms = api.cgp_time_passes(b.handle, w, F, 200)
         by = pass_bytes(case, 8)
         names = ["A", "B", "C", "D"]
         per_step_ms = {n: 3 * ms[i] for i, n in enumerate(names)}

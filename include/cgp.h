@@ -169,15 +169,16 @@ cgp_status cgp_ensemble_step(cgp_handle* h, void* omega_packed_dev,
                              const void* forcing_packed_dev, int32_t nsteps, int32_t use_graph,
                              void* stream);
 
-/* Measurement.  Runs nsteps steps exactly as cgp_ensemble_step without a
- * graph (any handle), recording a HIP event on `stream` before and after every
- * kernel launch of the step, then SYNCHRONISES the stream and writes to
- * ms_host[0..3] the mean duration in milliseconds of one launch of each pass
- * (0: restriction + x transform, 1: y transforms + eigenvalue divide,
- * 2: x transform + prolongation, 3: Arakawa right-hand side + RK3 combine) and
- * to ms_host[4] the elapsed time of the whole call. */
-cgp_status cgp_step_timed(cgp_handle* h, void* omega_dev, const void* forcing_dev, int32_t nsteps,
-                          double* ms_host, void* stream);
+/* Measurement.  Times each pass of one RK3 stage on the handle's current
+ * workspace contents: pass 0 (restriction + x transform of omega_dev),
+ * 1 (y transforms + eigenvalue divide), 2 (x transform + prolongation into
+ * psi), 3 (Arakawa right-hand side + RK3 combine in the form of stage 2:
+ * reads stage 1, psi, the forcing and omega_dev, writes stage 2).  Each pass
+ * is launched `reps` times back to back on `stream` between two HIP events;
+ * ms_host[p] receives the mean milliseconds per launch.  Synchronises the
+ * stream.  omega_dev is only read. */
+cgp_status cgp_time_passes(cgp_handle* h, const void* omega_dev, const void* forcing_dev,
+                           int32_t reps, double* ms_host, void* stream);
 
 /* Message for the calling thread's last failure ("" if none). */
 const char* cgp_last_error(void);

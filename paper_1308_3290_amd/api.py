@@ -139,10 +139,11 @@ def cgp_ensemble_step(h, omega_packed, forcing_packed, nsteps=1, use_graph=True,
          1 if use_graph else 0, ctypes.c_void_p(stream_ptr(stream)))
 
 
-def cgp_step_timed(h, omega, forcing, nsteps, stream=None):
-    """Mean ms per launch of passes A, B, C, D and the total ms (synchronises)."""
-    ms = (ctypes.c_double * 5)()
-    call("cgp_step_timed", h, _ptr(omega), _ptr(forcing), int(nsteps), ms,
+def cgp_time_passes(h, omega, forcing, reps, stream=None):
+    """Mean ms per launch of passes A, B, C, D (reps back-to-back launches each;
+    synchronises)."""
+    ms = (ctypes.c_double * 4)()
+    call("cgp_time_passes", h, _ptr(omega), _ptr(forcing), int(reps), ms,
          ctypes.c_void_p(stream_ptr(stream)))
     return list(ms)
 

@@ -23,9 +23,8 @@ struct MemberDesc {
   int nlayers;
   int Lr, Lc;           // complex FFT lengths 2*Mx (rows) and 2*My (columns)
   int nst_r, nst_c;     // radix stage counts
-  int rad_r[kMaxStages], rad_c[kMaxStages];  // radix of each stage
-  int lns_r[kMaxStages], lns_c[kMaxStages];  // log2 of the stage's span Ns
-  int tws_r[kMaxStages], tws_c[kMaxStages];  // twiddle step L/(Ns R)
+  int stw_r[kMaxStages], stw_c[kMaxStages];  // stage words: radix, log2 span, table offset
+  int ntw_r, ntw_c;                          // twiddle table sizes (complex values)
   int pa;               // pass A: sequence pairs per block
   int pb;               // pass B: sequence pairs per block
   int tj;               // pass C: coarse rows owned per block
@@ -34,8 +33,8 @@ struct MemberDesc {
   int nblk[NUM_PASSES]; // blocks of this member in each pass
   long long field_off;  // packed fine fields ([L][ny+1][nx+1] per member)
   long long wt_off;     // coarse spectra: L modes x (Mx-1) x (My-1), k-major
-  long long twr_off;    // row twiddles w_Lr^m, m < Lr/2, in complex elements of T
-  long long twc_off;    // column twiddles w_Lc^m, m < Lc/2
+  long long twr_off;    // row twiddle tables, in complex elements of T (ntw_r values)
+  long long twc_off;    // column twiddle tables (ntw_c values)
   long long lam_off;    // doubles: lambda_x (Mx-1) then lambda_y (My-1)
   double dx, dy;
   double inv_re, inv_ro, f1, f2, drag, dt;
@@ -79,6 +78,8 @@ struct Launch {
   // pass C: inverse x sine transform + prolongation; accumulate != 0 adds to dst
   static hipError_t rowdst_prolong(const MemberDesc* md, const Group& g, const T* wt, T* dst,
                                    int accumulate, const cplx<T>* tw, hipStream_t s);
+  // allow the transform kernels up to `bytes` of dynamic LDS per block
+  static hipError_t prepare(size_t bytes);
   // pass D: Arakawa right-hand side + TVD-RK3 stage combine
   static hipError_t stencil_rk3(const MemberDesc* md, int nm, int nblk, const T* ws,
                                 const T* psi, const T* forcing, const T* wn, T* out, double a,

@@ -9,129 +9,158 @@
 // The transform is its own inverse up to 2/n, so the same routine serves
 // the analysis and the synthesis sums of Sec. 4.3.
 //
-// The DFT is a Stockham autosort FFT over radices 4 and 2, with the radix-3
-// stage of L = 3*2^k placed last, so that the span Ns of every stage is a
-// power of two and all index arithmetic is shifts and masks.  At a stage of
-// radix R, butterfly j reads x[j + r L/R], twiddles element r by
+// The DFT is a Stockham autosort FFT over radices 8, 4 and 2, with the
+// radix-3 stage of L = 3*2^k placed last, so that the span Ns of every stage
+// is a power of two and all index arithmetic is shifts and masks.  At a stage
+// of radix R, butterfly j reads x[j + r L/R], twiddles element r by
 // w_L^(r (j mod Ns) L/(Ns R)), takes an R-point DFT and writes
-// y[(j div Ns) Ns R + (j mod Ns) + r Ns].  The stage loop is a runtime loop
-// (compact code), each stage runs in place on one LDS buffer: every thread
-// reads the inputs of its butterflies, the block synchronises, every thread
-// writes its outputs, the block synchronises.  Twiddles w_L^m, m < L/2, come
-// from an LDS copy of a host-built FP64 table (w^(m + L/2) = -w^m).
-// A block transforms one or two sequences (nseq <= 2) of length L <= 2048.
+// y[(j div Ns) Ns R + (j mod Ns) + r Ns].  Stages ping-pong between two LDS
+// buffers with one barrier each; the stage loop is a runtime loop (compact
+// code).  Twiddles come from per-stage tables built on the host in FP64:
+// stage s keeps, for r = 1..R-1, the values w^(r k L/(Ns R)) for k < Ns
+// contiguously in k, so that neighbouring butterflies read neighbouring
+// entries.  A block transforms one or two sequences (nseq <= 2) with
+// nseq * L <= 2048.
+//
+// LDS layout: element i of sequence p sits at p * lpad(L) + pad(i), with one
+// padding slot after every 8 elements, which spreads the stride-8 and
+// stride-64 write patterns of the first stages over all LDS banks.
 #pragma once
 
 #include "cgp_internal.hpp"
 
 namespace cgp {
 
+__host__ __device__ constexpr int pad(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int lpad(int L) { return L + (L >> 3); }
+
 template <typename T>
 __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+
+// 4-point DFT of v[0], v[S], v[2S], v[3S] in place, natural order.
+template <typename T, int S>
+__device__ __forceinline__ void dft4s(cplx<T>* v) {
+  const cplx<T> s02 = cadd(v[0], v[2 * S]), d02 = csub(v[0], v[2 * S]);
+  const cplx<T> s13 = cadd(v[S], v[3 * S]), e = csub(v[S], v[3 * S]);
+  const cplx<T> d13 = {e.y, -e.x};  // -i (v1 - v3)
+  v[0] = cadd(s02, s13);
+  v[2 * S] = csub(s02, s13);
+  v[S] = cadd(d02, d13);
+  v[3 * S] = csub(d02, d13);
 }
 
 template <typename T, int R>
 __device__ __forceinline__ void small_dft(cplx<T>* v) {
   if constexpr (R == 2) {
-    cplx<T> a = v[0], b = v[1];
-    v[0] = {a.x + b.x, a.y + b.y};
-    v[1] = {a.x - b.x, a.y - b.y};
+    const cplx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
   } else if constexpr (R == 4) {
-    cplx<T> s02 = {v[0].x + v[2].x, v[0].y + v[2].y};
-    cplx<T> d02 = {v[0].x - v[2].x, v[0].y - v[2].y};
-    cplx<T> s13 = {v[1].x + v[3].x, v[1].y + v[3].y};
-    cplx<T> d13 = {v[1].x - v[3].x, v[1].y - v[3].y};
-    v[0] = {s02.x + s13.x, s02.y + s13.y};
-    v[2] = {s02.x - s13.x, s02.y - s13.y};
-    // -i * d13 = (d13.y, -d13.x)
-    v[1] = {d02.x + d13.y, d02.y - d13.x};
-    v[3] = {d02.x - d13.y, d02.y + d13.x};
+    dft4s<T, 1>(v);
+  } else if constexpr (R == 8) {
+    // n = 2 n1 + n2, k = k1 + 4 k2: two 4-point DFTs, twiddles w8^(n2 k1), 2-point DFTs
+    const T h = T(0.70710678118654752440084436210484904);
+    dft4s<T, 2>(v);
+    dft4s<T, 2>(v + 1);
+    v[3] = cmul(v[3], cplx<T>{h, -h});
+    v[5] = cplx<T>{v[5].y, -v[5].x};
+    v[7] = cmul(v[7], cplx<T>{-h, -h});
+    cplx<T> o[8];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      o[k1] = cadd(v[2 * k1], v[2 * k1 + 1]);
+      o[k1 + 4] = csub(v[2 * k1], v[2 * k1 + 1]);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = o[k];
   } else {  // R == 3, w = exp(-2 pi i / 3) = -1/2 - i sqrt(3)/2
     const T h = T(0.8660254037844386467637231707529362);
-    cplx<T> a0 = v[0], s = {v[1].x + v[2].x, v[1].y + v[2].y};
-    cplx<T> d = {v[1].x - v[2].x, v[1].y - v[2].y};
-    cplx<T> t = {a0.x - T(0.5) * s.x, a0.y - T(0.5) * s.y};
-    v[0] = {a0.x + s.x, a0.y + s.y};
+    const cplx<T> a0 = v[0], s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    const cplx<T> t = {a0.x - T(0.5) * s.x, a0.y - T(0.5) * s.y};
+    v[0] = cadd(a0, s);
     v[1] = {t.x + h * d.y, t.y - h * d.x};
     v[2] = {t.x - h * d.y, t.y + h * d.x};
   }
 }
 
-// w_L^m from the half table (m < L).
-template <typename T>
-__device__ __forceinline__ cplx<T> twiddle(const cplx<T>* tw, int m, int half) {
-  if (m < half) return tw[m];
-  const cplx<T> w = tw[m - half];
-  return {-w.x, -w.y};
-}
-
-// One in-place stage of radix R over nseq sequences of length L in `buf`.
-// Thread `tid` owns butterflies b = tid + NT q (q < MAXB).
+// One stage of radix R (span Ns = 2^lns) over nseq sequences of length L,
+// from `in` to `out` (padded layout); `tw` is this stage's twiddle table
+// ((R-1) x Ns).  Thread t owns butterflies b = t + kThreads q, q < MAXB.
 template <typename T, int R, int MAXB>
-__device__ __forceinline__ void fft_stage(cplx<T>* buf, int nseq, int L, int lns,
-                                          int twscale, const cplx<T>* tw) {
+__device__ __forceinline__ void fft_stage(const cplx<T>* in, cplx<T>* out, int nseq, int L,
+                                          int lns, const cplx<T>* tw) {
   const int LR = L / R;
   const int nb = nseq * LR;
   const int ns = 1 << lns;
-  constexpr int NT = kThreads;
-  cplx<T> v[MAXB][R];
+  const int LP = lpad(L);
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
-    const int b = threadIdx.x + NT * q;
+    const int b = threadIdx.x + kThreads * q;
     if (b < nb) {
       const int p = b >= LR ? 1 : 0;
       const int j = b - p * LR;
       const int k = j & (ns - 1);
-      const cplx<T>* src = buf + p * L + j;
+      const cplx<T>* src = in + p * LP;
+      cplx<T> v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src[r * LR];
-      if (k != 0) {
+      for (int r = 0; r < R; ++r) v[r] = src[pad(j + r * LR)];
+      if (lns > 0) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], twiddle(tw, r * k * twscale, L >> 1));
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[(r - 1) * ns + k]);
       }
-      small_dft<T, R>(v[q]);
+      small_dft<T, R>(v);
+      cplx<T>* dst = out + p * LP;
+      const int o = ((j >> lns) << lns) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[pad(o + r * ns)] = v[r];
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
-    const int b = threadIdx.x + NT * q;
-    if (b < nb) {
-      const int p = b >= LR ? 1 : 0;
-      const int j = b - p * LR;
-      const int k = j & (ns - 1);
-      cplx<T>* dst = buf + p * L + ((j >> lns) << lns) * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * ns] = v[q][r];
-    }
-  }
-  __syncthreads();
+}
+
+// Stage word: radix (bits 0-3), log2 span (bits 4-8), twiddle offset (bits 9+).
+__host__ __device__ constexpr int stage_word(int R, int lns, int two) {
+  return R | (lns << 4) | (two << 9);
 }
 
 // Forward DFT of nseq (1 or 2) sequences of length L held back to back in
-// `buf` (LDS), in place.  nseq * L <= 2 * blockDim.x * 4 is required (at most
-// four radix-2 butterflies per thread).  Every thread of the block must call
-// it; it begins and ends with a barrier.
+// buffer a (LDS, padded layout); b is scratch of the same size.  Returns the
+// buffer holding the result.  Every thread of the block must call it; it
+// begins and ends with a barrier.
 template <typename T>
-__device__ __forceinline__ void fft_lds(cplx<T>* buf, int nseq, int L, int nst, const int* rad,
-                                        const int* lns,
-                        const int* tws, const cplx<T>* tw) {
+__device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nseq, int L, int nst,
+                                            const int* words, const cplx<T>* tw) {
+  int w[kMaxStages];
+#pragma unroll
+  for (int s = 0; s < kMaxStages; ++s) w[s] = words[s];
   __syncthreads();
 #pragma unroll 1
   for (int s = 0; s < nst; ++s) {
-    const int R = rad[s];
-    if (R == 4) fft_stage<T, 4, 2>(buf, nseq, L, lns[s], tws[s], tw);
-    else if (R == 2) fft_stage<T, 2, 4>(buf, nseq, L, lns[s], tws[s], tw);
-    else fft_stage<T, 3, 3>(buf, nseq, L, lns[s], tws[s], tw);
+    const int word = w[s];
+    const int R = word & 15, lns = (word >> 4) & 31;
+    const cplx<T>* t = tw + (word >> 9);
+    if (R == 8) fft_stage<T, 8, 1>(a, b, nseq, L, lns, t);
+    else if (R == 4) fft_stage<T, 4, 2>(a, b, nseq, L, lns, t);
+    else if (R == 2) fft_stage<T, 2, 4>(a, b, nseq, L, lns, t);
+    else fft_stage<T, 3, 3>(a, b, nseq, L, lns, t);
+    cplx<T>* x = a;
+    a = b;
+    b = x;
   }
+  return a;
 }
 
-// Copy the half twiddle table (L/2 values) from global memory to LDS.
+// Copy n twiddle values from global memory to LDS.
 template <typename T>
 __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __restrict__ src,
-                                              int L) {
-  for (int m = threadIdx.x; m < (L >> 1); m += kThreads) dst[m] = src[m];
+                                              int n) {
+  for (int m = threadIdx.x; m < n; m += kThreads) dst[m] = src[m];
 }
 
 }  // namespace cgp

@@ -20,6 +20,7 @@
 
 #include "cgp.h"
 #include "cgp_internal.hpp"
+#include "fft_lds.hpp"
 
 using namespace cgp;
 
@@ -50,7 +51,7 @@ cgp_status hip_fail(hipError_t e, const char* what) {
 constexpr size_t kAlign = 256;
 constexpr int kDiagBlocks = 64;
 constexpr int kFiniteBlocks = 256;
-constexpr size_t kMaxLds = 64 * 1024;
+constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -60,24 +61,27 @@ bool pow2_or_3pow2(int n) {
   return n == 1 || n == 3;
 }
 
-// Stage plan of a complex FFT of length L = 2^k or 3*2^k: radix 4 while
-// possible, then 2, then the radix 3 last, so every stage's span Ns (the
-// product of the earlier radices) is a power of two.
-int plan_stages(int L, int* rad, int* lns, int* tws) {
-  int n = 0, rest = L, ns = 1;
+// Stage plan of a complex FFT of length L = 2^k or 3*2^k: radix 8 while
+// possible, then 4, then 2, the radix 3 last, so that every stage's span Ns
+// (the product of the earlier radices) is a power of two.  two[s] is the
+// offset of stage s's twiddle table ((R-1) x Ns values); returns the stage
+// count and the total table size in *ntw.
+int plan_stages(int L, int* words, int* ntw) {
+  int n = 0, rest = L, ns = 1, off = 0;
   auto push = [&](int r) {
-    rad[n] = r;
     int lg = 0;
     while ((1 << lg) < ns) ++lg;
-    lns[n] = lg;
-    tws[n] = L / (ns * r);
+    words[n] = stage_word(r, lg, off);
+    off += (r - 1) * ns;
     ns *= r;
     rest /= r;
     ++n;
   };
+  while (rest % 8 == 0) push(8);
   while (rest % 4 == 0) push(4);
   while (rest % 2 == 0) push(2);
   if (rest == 3) push(3);
+  *ntw = off;
   return n;
 }
 
@@ -189,16 +193,16 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     d.nlayers = nl;
     d.Lr = 2 * d.Mx;
     d.Lc = 2 * d.My;
-    d.nst_r = plan_stages(d.Lr, d.rad_r, d.lns_r, d.tws_r);
-    d.nst_c = plan_stages(d.Lc, d.rad_c, d.lns_c, d.tws_c);
+    d.nst_r = plan_stages(d.Lr, d.stw_r, &d.ntw_r);
+    d.nst_c = plan_stages(d.Lc, d.stw_c, &d.ntw_c);
     d.field_off = fld;
     fld += (long long)nl * (c.ny + 1) * (c.nx + 1);
     d.wt_off = wt;
     wt += (long long)nl * (d.Mx - 1) * (d.My - 1);
     d.twr_off = tw;
-    tw += d.Lr / 2;
+    tw += d.ntw_r;
     d.twc_off = tw;
-    tw += d.Lc / 2;
+    tw += d.ntw_c;
     d.lam_off = lam;
     lam += (d.Mx - 1) + (d.My - 1);
     d.dx = c.lx / c.nx;
@@ -221,7 +225,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                [&](MemberDesc& d, HostGroup&) {
                  d.pa = pairs(d.Lr);
                  const int rows = nl == 1 ? 2 * d.pa : d.pa;
-                 const size_t lds = ((size_t)d.pa * d.Lr + d.Lr / 2) * cs;
+                 const size_t lds = ((size_t)2 * d.pa * lpad(d.Lr) + d.ntw_r) * cs;
                  return std::make_pair((d.My - 1 + rows - 1) / rows, lds);
                },
                plan->groups[0]);
@@ -230,7 +234,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                [&](MemberDesc& d, HostGroup&) {
                  d.pb = pairs(d.Lc);
                  const int cols = nl == 1 ? 2 * d.pb : d.pb;
-                 const size_t lds = ((size_t)d.pb * d.Lc + d.Lc / 2) * cs;
+                 const size_t lds = ((size_t)2 * d.pb * lpad(d.Lc) + d.ntw_c) * cs;
                  return std::make_pair((d.Mx - 1 + cols - 1) / cols, lds);
                },
                plan->groups[1]);
@@ -240,7 +244,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                  const int halo = d.c > 1 ? 1 : 0;
                  d.pc = nl == 1 ? pairs(d.Lr) : (d.Lr <= 1024 ? 2 : 1);
                  d.tj = (nl == 1 ? 2 * d.pc : d.pc) - halo;
-                 const size_t lds = ((size_t)d.pc * d.Lr + d.Lr / 2) * cs +
+                 const size_t lds = ((size_t)2 * d.pc * lpad(d.Lr) + d.ntw_r) * cs +
                                     (halo ? (size_t)nl * (d.tj + 1) * (d.Mx + 1) * es : 0);
                  const int nb = halo ? (d.My + d.tj - 1) / d.tj : (d.My + 1 + d.tj - 1) / d.tj;
                  return std::make_pair(nb, lds);
@@ -249,7 +253,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   for (int p = 0; p < 3; ++p)
     for (const HostGroup& g : plan->groups[p])
       if (g.lds > kMaxLds)
-        return fail(CGP_ERR_UNSUPPORTED, "a transform pass needs more than 64 KiB LDS per block");
+        return fail(CGP_ERR_UNSUPPORTED, "a transform pass needs more than 160 KiB LDS per block");
   Layout& L = plan->lay;
   size_t off = 0;
   L.desc = off; off = align_up(off + sizeof(MemberDesc) * count);
@@ -345,28 +349,20 @@ hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s
   return hipSuccess;
 }
 
-// enqueue_step with an event recorded after each of its 12 passes
+// reps back-to-back launches of pass p (3 = stencil in its stage-2 form)
 template <typename T>
-hipError_t enqueue_step_events(cgp_handle* h, T* omega, const T* forcing, hipStream_t s,
-                               hipEvent_t* ev) {
-  const Plan& p = h->plan;
-  T* b1 = h->at<T>(p.lay.st1);
-  T* b2 = h->at<T>(p.lay.st2);
-  T* pd = h->at<T>(p.lay.psi);
-  const T* src[3] = {omega, b1, b2};
-  T* dst[3] = {b1, b2, omega};
-  int k = 0;
-  hipError_t e;
-  for (int st = 0; st < 3; ++st) {
-    e = enqueue_pass<T>(h, 0, src[st], nullptr, 0, s);
-    if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
-    e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s);
-    if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
-    e = enqueue_pass<T>(h, 2, nullptr, pd, 0, s);
-    if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
-    e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), p.nblk_d, src[st], pd, forcing, omega,
-                               dst[st], kRkA[st], kRkB[st], s);
-    if (e != hipSuccess || (e = hipEventRecord(ev[k++], s)) != hipSuccess) return e;
+hipError_t enqueue_pass_reps(cgp_handle* h, int p, const T* omega, const T* forcing, int reps,
+                             hipStream_t s) {
+  const Plan& pl = h->plan;
+  T* b1 = h->at<T>(pl.lay.st1);
+  T* b2 = h->at<T>(pl.lay.st2);
+  T* pd = h->at<T>(pl.lay.psi);
+  for (int r = 0; r < reps; ++r) {
+    hipError_t e;
+    if (p < 3) e = enqueue_pass<T>(h, p, omega, pd, 0, s);
+    else e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), pl.nblk_d, b1, pd, forcing, omega, b2,
+                                    kRkA[1], kRkB[1], s);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -388,11 +384,20 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
   for (const MemberDesc& d : p.md) {
     for (int pass = 0; pass < 2; ++pass) {
       const int Ln = pass == 0 ? d.Lr : d.Lc;
+      const int nst = pass == 0 ? d.nst_r : d.nst_c;
+      const int* words = pass == 0 ? d.stw_r : d.stw_c;
       cplx<T>* t = tw + (pass == 0 ? d.twr_off : d.twc_off);
-      for (int mm = 0; mm < Ln / 2; ++mm) {
-        const double ang = 2.0 * pi * (double)mm / (double)Ln;
-        t[mm].x = (T)std::cos(ang);
-        t[mm].y = (T)(-std::sin(ang));
+      for (int st = 0; st < nst; ++st) {
+        const int R = words[st] & 15, ns = 1 << ((words[st] >> 4) & 31), off = words[st] >> 9;
+        const int step = Ln / (ns * R);
+        for (int r = 1; r < R; ++r)
+          for (int k = 0; k < ns; ++k) {
+            // w_L^m, m = r k L/(Ns R), reduced mod L for an exact argument
+            const long long m = ((long long)r * k * step) % Ln;
+            const double ang = 2.0 * pi * (double)m / (double)Ln;
+            t[off + (r - 1) * ns + k].x = (T)std::cos(ang);
+            t[off + (r - 1) * ns + k].y = (T)(-std::sin(ang));
+          }
       }
     }
     // lambda_k = (2cos(pi k/M) - 2)/h^2 = -4 sin^2(pi k/(2M))/h^2 on the coarse grid
@@ -408,6 +413,10 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
       ly[l - 1] = -4.0 * sn * sn / (hy * hy);
     }
   }
+  size_t lds_max = 0;
+  for (int pass = 0; pass < 3; ++pass)
+    for (const HostGroup& g : p.groups[pass]) lds_max = std::max(lds_max, g.lds);
+  HIP_TRY(Launch<T>::prepare(lds_max), "LDS attribute");
   HIP_TRY(hipMemcpyAsync(h->ws, h->host_tables.data(), L.wt, hipMemcpyHostToDevice, s),
           "table upload");
   // ring of the internal psi / stage buffers: produced fields always write
@@ -603,44 +612,32 @@ cgp_status cgp_check_finite(cgp_handle* h, const void* field, int64_t count, int
   return CGP_OK;
 }
 
-cgp_status cgp_step_timed(cgp_handle* h, void* omega, const void* forcing, int32_t nsteps,
-                          double* ms, void* stream) {
+cgp_status cgp_time_passes(cgp_handle* h, const void* omega, const void* forcing, int32_t reps,
+                           double* ms, void* stream) {
   if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
-  if (!omega || !forcing || !ms || nsteps < 1) return fail(CGP_ERR_INVALID, "bad argument");
+  if (!omega || !forcing || !ms || reps < 1) return fail(CGP_ERR_INVALID, "bad argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int nev = 1 + 12 * nsteps;
-  std::vector<hipEvent_t> ev(nev, nullptr);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(CGP_ERR_DEVICE, "event create");
   cgp_status st = CGP_OK;
-  for (int i = 0; i < nev && st == CGP_OK; ++i)
-    if (hipEventCreate(&ev[i]) != hipSuccess) st = fail(CGP_ERR_DEVICE, "event create");
-  if (st == CGP_OK) {
-    hipError_t e = hipEventRecord(ev[0], s);
-    for (int n = 0; n < nsteps && e == hipSuccess; ++n)
+  for (int p = 0; p < 4 && st == CGP_OK; ++p) {
+    hipError_t e = hipEventRecord(e0, s);
+    if (e == hipSuccess)
       e = h->plan.dtype == CGP_F64
-              ? enqueue_step_events<double>(h, static_cast<double*>(omega),
-                                            static_cast<const double*>(forcing), s,
-                                            ev.data() + 1 + 12 * n)
-              : enqueue_step_events<float>(h, static_cast<float*>(omega),
-                                           static_cast<const float*>(forcing), s,
-                                           ev.data() + 1 + 12 * n);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[nev - 1]);
-    if (e != hipSuccess) {
-      st = hip_fail(e, "timed step");
-    } else {
-      double acc[4] = {0, 0, 0, 0};
-      for (int k = 1; k < nev; ++k) {
-        float t = 0.f;
-        (void)hipEventElapsedTime(&t, ev[k - 1], ev[k]);
-        acc[(k - 1) % 4] += t;
-      }
-      float tot = 0.f;
-      (void)hipEventElapsedTime(&tot, ev[0], ev[nev - 1]);
-      for (int p = 0; p < 4; ++p) ms[p] = acc[p] / (3.0 * nsteps);
-      ms[4] = tot;
-    }
+              ? enqueue_pass_reps<double>(h, p, static_cast<const double*>(omega),
+                                          static_cast<const double*>(forcing), reps, s)
+              : enqueue_pass_reps<float>(h, p, static_cast<const float*>(omega),
+                                         static_cast<const float*>(forcing), reps, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) st = hip_fail(e, "timed passes");
+    else ms[p] = (double)t / reps;
   }
-  for (hipEvent_t e : ev)
-    if (e) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return st;
 }
 

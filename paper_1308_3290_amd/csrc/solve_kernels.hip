@@ -74,7 +74,7 @@ __device__ __forceinline__ int group_member(const MemberDesc* md, const int* grp
 // ---------------------------------------------------------------------------
 template <typename T, int C>
 __device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __restrict__ f,
-                                               cplx<T>* buf, int j0, int nr, int L) {
+                                               cplx<T>* buf, int j0, int nr, int LP) {
   const int Mx = d.Mx, c = d.c, nl = d.nlayers;
   const int pitch = d.nx + 1;
   const size_t plane = (size_t)(d.ny + 1) * pitch;
@@ -100,8 +100,8 @@ __device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __r
       for (int p = 0; p < 2; ++p) {
         if (2 * p < nr) {
           const cplx<T> z = {v[2 * p], v[2 * p + 1]};
-          buf[p * L + i] = z;
-          buf[p * L + 2 * Mx - i] = {-z.x, -z.y};
+          buf[p * LP + pad(i)] = z;
+          buf[p * LP + pad(2 * Mx - i)] = {-z.x, -z.y};
         }
       }
     } else {
@@ -109,8 +109,8 @@ __device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __r
       for (int p = 0; p < 2; ++p) {
         if (p < nr) {
           const cplx<T> z = {wbt1 * v[p] + wbt2 * u[p], v[p] - u[p]};  // (barotropic, baroclinic)
-          buf[p * L + i] = z;
-          buf[p * L + 2 * Mx - i] = {-z.x, -z.y};
+          buf[p * LP + pad(i)] = z;
+          buf[p * LP + pad(2 * Mx - i)] = {-z.x, -z.y};
         }
       }
     }
@@ -125,26 +125,27 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_A, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_A];
   const int Mx = d.Mx, My = d.My, L = d.Lr, P = d.pa, nl = d.nlayers;
+  const int LP = lpad(L);
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = buf + P * L;
+  cplx<T>* tw = buf + 2 * P * LP;
   const int rows_blk = (nl == 1) ? 2 * P : P;  // 1, 2 or 4
   const int j0 = 1 + lb * rows_blk;
   const int nr = min(rows_blk, My - j0);
   const int nseq = (nl == 1) ? (nr + 1) / 2 : nr;
 
-  load_twiddles(tw, twg + d.twr_off, L);
+  load_twiddles(tw, twg + d.twr_off, d.ntw_r);
   if (threadIdx.x < nseq) {
-    buf[threadIdx.x * L] = {T(0), T(0)};
-    buf[threadIdx.x * L + Mx] = {T(0), T(0)};
+    buf[threadIdx.x * LP + pad(0)] = {T(0), T(0)};
+    buf[threadIdx.x * LP + pad(Mx)] = {T(0), T(0)};
   }
   const T* f = src + d.field_off;
   switch (d.c) {
-    case 1: restrict_block<T, 1>(d, f, buf, j0, nr, L); break;
-    case 2: restrict_block<T, 2>(d, f, buf, j0, nr, L); break;
-    case 4: restrict_block<T, 4>(d, f, buf, j0, nr, L); break;
-    default: restrict_block<T, 0>(d, f, buf, j0, nr, L);
+    case 1: restrict_block<T, 1>(d, f, buf, j0, nr, LP); break;
+    case 2: restrict_block<T, 2>(d, f, buf, j0, nr, LP); break;
+    case 4: restrict_block<T, 4>(d, f, buf, j0, nr, LP); break;
+    default: restrict_block<T, 0>(d, f, buf, j0, nr, LP);
   }
-  fft_lds<T>(buf, nseq, L, d.nst_r, d.rad_r, d.lns_r, d.tws_r, tw);
+  const cplx<T>* Z = fft_lds<T>(buf, buf + P * LP, nseq, L, d.nst_r, d.stw_r, tw);
 
   T* w = wt + d.wt_off;
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
@@ -156,10 +157,10 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     if (r >= nr) continue;
     const size_t o = (size_t)(k - 1) * (My - 1) + (j0 + r - 1);
     if (nl == 1) {
-      const cplx<T> zk = buf[(r >> 1) * L + k];
+      const cplx<T> zk = Z[(r >> 1) * LP + pad(k)];
       w[o] = (r & 1) ? T(0.5) * zk.x : T(-0.5) * zk.y;
     } else {
-      const cplx<T> zk = buf[r * L + k];
+      const cplx<T> zk = Z[r * LP + pad(k)];
       w[o] = T(-0.5) * zk.y;
       w[mplane + o] = T(0.5) * zk.x;
     }
@@ -183,8 +184,10 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
   const int lb = blockIdx.x - d.blk0[PASS_B];
   const int Mx = d.Mx, My = d.My, L = d.Lc, P = d.pb, nl = d.nlayers;
   const int ny1 = My - 1;
+  const int LP = lpad(L);
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = buf + P * L;
+  cplx<T>* buf2 = buf + P * LP;
+  cplx<T>* tw = buf2 + P * LP;
   T* w = wt + d.wt_off;
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
   const double* lamx = lam + d.lam_off;
@@ -221,10 +224,10 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
     lxb[p] = (kb[p] ? lamx[kb[p] - 1] : -1.0) - shift;
   }
 
-  load_twiddles(tw, twg + d.twc_off, L);
+  load_twiddles(tw, twg + d.twc_off, d.ntw_c);
   if (threadIdx.x < nseq) {
-    buf[threadIdx.x * L] = {T(0), T(0)};
-    buf[threadIdx.x * L + My] = {T(0), T(0)};
+    buf[threadIdx.x * LP + pad(0)] = {T(0), T(0)};
+    buf[threadIdx.x * LP + pad(My)] = {T(0), T(0)};
   }
   for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
 #pragma unroll
@@ -232,37 +235,38 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
       if (p < nseq) {
         const T a = ka[p] ? cola[p][l - 1] : T(0);
         const T b = kb[p] ? colb[p][l - 1] : T(0);
-        buf[p * L + l] = {a, b};
-        buf[p * L + 2 * My - l] = {-a, -b};
+        buf[p * LP + pad(l)] = {a, b};
+        buf[p * LP + pad(2 * My - l)] = {-a, -b};
       }
     }
   }
-  fft_lds<T>(buf, nseq, L, d.nst_c, d.rad_c, d.lns_c, d.tws_c, tw);
+  cplx<T>* Z = fft_lds<T>(buf, buf2, nseq, L, d.nst_c, d.stw_c, tw);
+  cplx<T>* Y = (Z == buf) ? buf2 : buf;
 
   for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
     const double ly = lamy[l - 1];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       if (p < nseq) {
-        const cplx<T> z = buf[p * L + l];
+        const cplx<T> z = Z[p * LP + pad(l)];
         const T a = T(-0.5) * z.y * T(scale / (lxa[p] + ly));
         const T b = T(0.5) * z.x * T(scale / (lxb[p] + ly));
-        buf[p * L + l] = {a, b};
-        buf[p * L + 2 * My - l] = {-a, -b};
+        Y[p * LP + pad(l)] = {a, b};
+        Y[p * LP + pad(2 * My - l)] = {-a, -b};
       }
     }
   }
   if (threadIdx.x < nseq) {
-    buf[threadIdx.x * L] = {T(0), T(0)};
-    buf[threadIdx.x * L + My] = {T(0), T(0)};
+    Y[threadIdx.x * LP + pad(0)] = {T(0), T(0)};
+    Y[threadIdx.x * LP + pad(My)] = {T(0), T(0)};
   }
-  fft_lds<T>(buf, nseq, L, d.nst_c, d.rad_c, d.lns_c, d.tws_c, tw);
+  const cplx<T>* R = fft_lds<T>(Y, Z, nseq, L, d.nst_c, d.stw_c, tw);
 
   for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       if (p < nseq) {
-        const cplx<T> z = buf[p * L + l];
+        const cplx<T> z = R[p * LP + pad(l)];
         if (ka[p]) cola[p][l - 1] = T(-0.5) * z.y;
         if (kb[p]) colb[p][l - 1] = T(0.5) * z.x;
       }
@@ -289,9 +293,10 @@ __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* _
   const int Mx = d.Mx, My = d.My, L = d.Lr, c = d.c, nl = d.nlayers, TJ = d.tj, P = d.pc;
   const int nx = d.nx, ny = d.ny, pitch = nx + 1;
   const size_t plane = (size_t)(ny + 1) * pitch;
+  const int LP = lpad(L);
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = buf + P * L;
-  T* ps = reinterpret_cast<T*>(tw + (L >> 1));  // [nl][TJ+1][Mx+1] (c > 1 only)
+  cplx<T>* tw = buf + 2 * P * LP;
+  T* ps = reinterpret_cast<T*>(tw + d.ntw_r);  // [nl][TJ+1][Mx+1] (c > 1 only)
   const int prow = Mx + 1;
   const size_t pplane = (size_t)(TJ + 1) * prow;
 
@@ -304,10 +309,10 @@ __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* _
   const T* w = wt + d.wt_off;
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
 
-  load_twiddles(tw, twg + d.twr_off, L);
+  load_twiddles(tw, twg + d.twr_off, d.ntw_r);
   if (threadIdx.x < nseq) {
-    buf[threadIdx.x * L] = {T(0), T(0)};
-    buf[threadIdx.x * L + Mx] = {T(0), T(0)};
+    buf[threadIdx.x * LP + pad(0)] = {T(0), T(0)};
+    buf[threadIdx.x * LP + pad(Mx)] = {T(0), T(0)};
   }
   for (int k = 1 + threadIdx.x; k < Mx; k += kThreads) {
     const T* col = w + (size_t)(k - 1) * (My - 1) + (ilo - 1);
@@ -321,12 +326,12 @@ __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* _
     for (int p = 0; p < 2; ++p) {
       if (p < nseq) {
         const cplx<T> z = (nl == 1) ? cplx<T>{v[2 * p], v[2 * p + 1]} : cplx<T>{v[p], u[p]};
-        buf[p * L + k] = z;
-        buf[p * L + 2 * Mx - k] = {-z.x, -z.y};
+        buf[p * LP + pad(k)] = z;
+        buf[p * LP + pad(2 * Mx - k)] = {-z.x, -z.y};
       }
     }
   }
-  fft_lds<T>(buf, nseq, L, d.nst_r, d.rad_r, d.lns_r, d.tws_r, tw);
+  const cplx<T>* Z = fft_lds<T>(buf, buf + P * LP, nseq, L, d.nst_r, d.stw_r, tw);
 
   const T wbc1 = T(1.0 - d.delta), wbc2 = T(d.delta);
   T* out = dst + d.field_off;
@@ -337,10 +342,10 @@ __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* _
     if (jj >= 1 && jj <= My - 1 && i >= 1 && i <= Mx - 1) {
       const int idx = jj - ilo;
       if (nl == 1) {
-        const cplx<T> zi = buf[(idx >> 1) * L + i];
+        const cplx<T> zi = Z[(idx >> 1) * LP + pad(i)];
         v0 = (idx & 1) ? T(0.5) * zi.x : T(-0.5) * zi.y;
       } else {
-        const cplx<T> zi = buf[idx * L + i];
+        const cplx<T> zi = Z[idx * LP + pad(i)];
         const T bt = T(-0.5) * zi.y, bc = T(0.5) * zi.x;
         v0 = bt + wbc1 * bc;  // psi_1 = psi_bt + (1 - delta) psi_bc
         v1 = bt - wbc2 * bc;  // psi_2 = psi_bt - delta psi_bc
@@ -421,6 +426,20 @@ hipError_t Launch<T>::rowdst_prolong(const MemberDesc* md, const Group& g, const
   hipLaunchKernelGGL(k_rowdst_prolong<T>, dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members,
                      g.count, wt, dst, accumulate, tw);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::prepare(size_t bytes) {
+  const int b = (int)bytes;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_restrict_rowdst<T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_col_solve<T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rowdst_prolong<T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  return e;
 }
 
 template struct Launch<float>;
