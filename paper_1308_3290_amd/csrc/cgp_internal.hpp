@@ -12,7 +12,10 @@ constexpr int kThreads = 256;    // threads per block of the transform kernels
 constexpr int kTileX = 64;       // stencil tile (one wavefront wide)
 constexpr int kTileY = 4;
 
-enum Pass { PASS_A = 0, PASS_B = 1, PASS_C = 2, PASS_D = 3, NUM_PASSES = 4 };
+// PASS_CD: passes C and D fused (one layer).
+enum Pass { PASS_A = 0, PASS_B = 1, PASS_C = 2, PASS_D = 3, PASS_CD = 4, NUM_PASSES = 5 };
+
+constexpr int kFusedTj = 2;  // coarse rows owned by a block of the fused C + D pass
 
 // Per-basin descriptor, uploaded once at create.  Offsets are in elements of
 // the handle's scalar type T unless stated.
@@ -57,9 +60,21 @@ __device__ inline int find_member(const MemberDesc* md, int nm, int p, int b) {
   return lo;
 }
 
+// Locate the member of group `grp` (ng members, ordered by first block)
+// owning block `b` of pass `p`.
+__device__ __forceinline__ int group_member(const MemberDesc* md, const int* grp, int ng, int p,
+                                           int b) {
+  int lo = 0, hi = ng - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (md[grp[mid]].blk0[p] <= b) lo = mid; else hi = mid - 1;
+  }
+  return grp[lo];
+}
+
 // One launch of a transform pass over a group of members.
 struct Group {
-  int L;               // unused (0)
+  int L;               // fused C + D pass: the coarsening factor; otherwise 0
   int count;           // members in the group
   const int* members;  // device array of the group's member indices
   int nblk, threads;  // threads = kThreads
@@ -80,6 +95,12 @@ struct Launch {
                                    int accumulate, const cplx<T>* tw, hipStream_t s);
   // allow the transform kernels up to `bytes` of dynamic LDS per block
   static hipError_t prepare(size_t bytes);
+  // passes C + D fused (one layer): x transform, prolongation into LDS,
+  // stencil + RK3 (g.L holds the group's coarsening factor)
+  static hipError_t prolong_stencil(const MemberDesc* md, const Group& g, const T* wt,
+                                    const cplx<T>* tw, const T* ws, const T* forcing, const T* wn,
+                                    T* out, double a, double b, hipStream_t s);
+  static hipError_t prepare_fused(size_t bytes);
   // pass D: Arakawa right-hand side + TVD-RK3 stage combine
   static hipError_t stencil_rk3(const MemberDesc* md, int nm, int nblk, const T* ws,
                                 const T* psi, const T* forcing, const T* wn, T* out, double a,

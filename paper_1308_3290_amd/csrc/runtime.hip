@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <string>
 #include <utility>
@@ -133,9 +134,10 @@ struct HostGroup {
 struct Plan {
   std::vector<MemberDesc> md;
   Layout lay;
-  std::vector<HostGroup> groups[3];  // passes A, B, C
+  std::vector<HostGroup> groups[4];  // passes A, B, C and the fused C + D pass
   int nblk_d = 0;                    // pass D: one launch over every member
   int dtype = CGP_F64, nlayers = 1;
+  bool fused = false;                // time steps use the fused C + D pass
 };
 
 constexpr int kGenericThreads = 256;
@@ -254,12 +256,32 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     for (const HostGroup& g : plan->groups[p])
       if (g.lds > kMaxLds)
         return fail(CGP_ERR_UNSUPPORTED, "a transform pass needs more than 160 KiB LDS per block");
+  // fused C + D (one layer, rows of at most 1024 complex values): a block
+  // owns kFusedTj coarse rows and synthesises the two neighbouring ones, i.e.
+  // at most two packed sequences; one launch per coarsening factor.
+  bool fusable = nl == 1;
+  for (const MemberDesc& d : plan->md) fusable = fusable && d.Lr <= 1024;
+  if (fusable) {
+    build_groups(plan->md, PASS_CD, [](const MemberDesc& d) { return d.c; },
+                 [&](MemberDesc& d, HostGroup&) {
+                   const size_t head =
+                       (std::max((size_t)4 * lpad(d.Lr) * cs,
+                                 (size_t)(d.c * kFusedTj + 3) * (d.nx + 1) * es) + 15) & ~(size_t)15;
+                   const size_t lds = head + (size_t)d.ntw_r * cs +
+                                      (size_t)(kFusedTj + 2) * (d.Mx + 1) * es;
+                   return std::make_pair((d.My + kFusedTj - 1) / kFusedTj, lds);
+                 },
+                 plan->groups[3]);
+    plan->fused = true;
+    for (const HostGroup& g : plan->groups[3]) plan->fused = plan->fused && g.lds <= kMaxLds;
+    if (!plan->fused) plan->groups[3].clear();
+  }
   Layout& L = plan->lay;
   size_t off = 0;
   L.desc = off; off = align_up(off + sizeof(MemberDesc) * count);
-  L.order = off; off = align_up(off + sizeof(int) * 3 * count);
+  L.order = off; off = align_up(off + sizeof(int) * 4 * count);
   int o = 0;
-  for (int p = 0; p < 3; ++p)
+  for (int p = 0; p < 4; ++p)
     for (HostGroup& g : plan->groups[p]) {
       g.order_off = o;
       o += (int)g.members.size();
@@ -327,7 +349,23 @@ hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hi
   return e;
 }
 
+// Fused pass C + D over every member: out = a wn + b (ws + dt G(ws, psi(ws))).
+template <typename T>
+hipError_t enqueue_fused(cgp_handle* h, const T* ws, const T* forcing, const T* wn, T* out,
+                         double a, double b, hipStream_t s) {
+  const Plan& p = h->plan;
+  for (int i = 0; i < h->ngroups(3); ++i) {
+    hipError_t e = Launch<T>::prolong_stencil(h->d_md(), h->group(3, i), h->at<T>(p.lay.wt),
+                                              h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, a,
+                                              b, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // One CGPRK3 step: w1 -> stage 1 buffer, w2 -> stage 2 buffer, w_{n+1} -> omega.
+// psi0..psi2, when given, receive the stage stream functions (the unfused
+// passes run then).
 template <typename T>
 hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s,
                         T* st1 = nullptr, T* st2 = nullptr, T* psi0 = nullptr,
@@ -339,7 +377,16 @@ hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s
   T* psis[3] = {psi0 ? psi0 : pd, psi1 ? psi1 : pd, psi2 ? psi2 : pd};
   const T* src[3] = {omega, b1, b2};
   T* dst[3] = {b1, b2, omega};
+  const bool fused = p.fused && !psi0 && !psi1 && !psi2;
   for (int st = 0; st < 3; ++st) {
+    if (fused) {
+      hipError_t e = enqueue_pass<T>(h, 0, src[st], nullptr, 0, s);
+      if (e == hipSuccess) e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s);
+      if (e == hipSuccess)
+        e = enqueue_fused<T>(h, src[st], forcing, omega, dst[st], kRkA[st], kRkB[st], s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     hipError_t e = enqueue_solve<T>(h, src[st], psis[st], 0, s);
     if (e != hipSuccess) return e;
     e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), p.nblk_d, src[st], psis[st], forcing,
@@ -349,7 +396,8 @@ hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s
   return hipSuccess;
 }
 
-// reps back-to-back launches of pass p (3 = stencil in its stage-2 form)
+// reps back-to-back launches of pass p (3 = stencil, 4 = fused C + D, both in
+// their stage-2 form)
 template <typename T>
 hipError_t enqueue_pass_reps(cgp_handle* h, int p, const T* omega, const T* forcing, int reps,
                              hipStream_t s) {
@@ -360,8 +408,10 @@ hipError_t enqueue_pass_reps(cgp_handle* h, int p, const T* omega, const T* forc
   for (int r = 0; r < reps; ++r) {
     hipError_t e;
     if (p < 3) e = enqueue_pass<T>(h, p, omega, pd, 0, s);
-    else e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), pl.nblk_d, b1, pd, forcing, omega, b2,
-                                    kRkA[1], kRkB[1], s);
+    else if (p == 3)
+      e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), pl.nblk_d, b1, pd, forcing, omega, b2,
+                                 kRkA[1], kRkB[1], s);
+    else e = enqueue_fused<T>(h, b1, forcing, omega, b2, kRkA[1], kRkB[1], s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -375,7 +425,7 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
   h->host_tables.assign(L.wt, 0);
   std::memcpy(h->host_tables.data() + L.desc, p.md.data(), sizeof(MemberDesc) * p.md.size());
   int* order = reinterpret_cast<int*>(h->host_tables.data() + L.order);
-  for (int pass = 0; pass < 3; ++pass)
+  for (int pass = 0; pass < 4; ++pass)
     for (const HostGroup& g : p.groups[pass])
       for (size_t i = 0; i < g.members.size(); ++i) order[g.order_off + i] = g.members[i];
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(h->host_tables.data() + L.tw);
@@ -417,6 +467,11 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
   for (int pass = 0; pass < 3; ++pass)
     for (const HostGroup& g : p.groups[pass]) lds_max = std::max(lds_max, g.lds);
   HIP_TRY(Launch<T>::prepare(lds_max), "LDS attribute");
+  if (p.fused) {
+    size_t lds_f = 0;
+    for (const HostGroup& g : p.groups[3]) lds_f = std::max(lds_f, g.lds);
+    HIP_TRY(Launch<T>::prepare_fused(lds_f), "LDS attribute (fused pass)");
+  }
   HIP_TRY(hipMemcpyAsync(h->ws, h->host_tables.data(), L.wt, hipMemcpyHostToDevice, s),
           "table upload");
   // ring of the internal psi / stage buffers: produced fields always write
@@ -621,7 +676,11 @@ cgp_status cgp_time_passes(cgp_handle* h, const void* omega, const void* forcing
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(CGP_ERR_DEVICE, "event create");
   cgp_status st = CGP_OK;
-  for (int p = 0; p < 4 && st == CGP_OK; ++p) {
+  for (int p = 0; p < 5 && st == CGP_OK; ++p) {
+    if (p == 4 && !h->plan.fused) {
+      ms[p] = 0.0;
+      break;
+    }
     hipError_t e = hipEventRecord(e0, s);
     if (e == hipSuccess)
       e = h->plan.dtype == CGP_F64

@@ -57,16 +57,6 @@ __device__ __forceinline__ T restrict_generic(const T* __restrict__ f, int pitch
   return acc / (c2 * c2);
 }
 
-__device__ __forceinline__ int group_member(const MemberDesc* md, const int* grp, int ng, int p,
-                                           int b) {
-  int lo = 0, hi = ng - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (md[grp[mid]].blk0[p] <= b) lo = mid; else hi = mid - 1;
-  }
-  return grp[lo];
-}
-
 // ---------------------------------------------------------------------------
 // Pass A.  A block restricts `rows` (<= 4) consecutive coarse rows starting at
 // j0 and transforms them along x: one layer, pairs of rows share one complex

@@ -10,66 +10,9 @@
 // output is written as zero; the ring of every vorticity-like input is read
 // as zero whatever it holds.
 #include "cgp_internal.hpp"
+#include "stencil.hpp"
 
 namespace cgp {
-
-// Arakawa Jacobian J(p, q) of Sec. 4.1 times 12 dx dy: the sum of the
-// brackets of J1, J2 and J3.  Arguments are the 3x3 neighbourhoods
-// (E = i+1, W = i-1, N = j+1, S = j-1).
-template <typename T>
-struct Nbr {
-  T C, E, W, N, S, NE, NW, SE, SW;
-};
-
-template <typename T>
-__device__ __forceinline__ T arakawa12(const Nbr<T>& p, const Nbr<T>& q) {
-  const T j1 = -(q.E - q.W) * (p.N - p.S) + (q.N - q.S) * (p.E - p.W);
-  const T j2 = -q.E * (p.NE - p.SE) + q.W * (p.NW - p.SW) + q.N * (p.NE - p.NW) -
-               q.S * (p.SE - p.SW);
-  const T j3 = -q.NE * (p.N - p.E) + q.SW * (p.W - p.S) + q.NW * (p.N - p.W) -
-               q.SE * (p.E - p.S);
-  return j1 + j2 + j3;
-}
-
-// J(p, y) times 3 dx: the Jacobian with the coordinate y reduces to a centred
-// x difference of p with corner averaging.
-template <typename T>
-__device__ __forceinline__ T beta3(const Nbr<T>& p) {
-  return (p.E - p.W) + T(0.25) * ((p.NE - p.NW) + (p.SE - p.SW));
-}
-
-template <typename T>
-__device__ __forceinline__ Nbr<T> load_nbr(const T* __restrict__ f, int pitch, int i, int j) {
-  const T* c = f + (size_t)j * pitch + i;
-  Nbr<T> n;
-  n.C = c[0];
-  n.E = c[1];
-  n.W = c[-1];
-  n.N = c[pitch];
-  n.S = c[-pitch];
-  n.NE = c[pitch + 1];
-  n.NW = c[pitch - 1];
-  n.SE = c[-pitch + 1];
-  n.SW = c[-pitch - 1];
-  return n;
-}
-
-// Same, with ring nodes read as zero.
-template <typename T>
-__device__ __forceinline__ Nbr<T> load_nbr_masked(const T* __restrict__ f, int pitch, int nx,
-                                                  int ny, int i, int j) {
-  Nbr<T> n = load_nbr(f, pitch, i, j);
-  if (i == 1) { n.W = T(0); n.NW = T(0); n.SW = T(0); }
-  if (i == nx - 1) { n.E = T(0); n.NE = T(0); n.SE = T(0); }
-  if (j == 1) { n.S = T(0); n.SE = T(0); n.SW = T(0); }
-  if (j == ny - 1) { n.N = T(0); n.NE = T(0); n.NW = T(0); }
-  return n;
-}
-
-template <typename T>
-__device__ __forceinline__ T lap5(const Nbr<T>& q, T idx2, T idy2) {
-  return (q.E - T(2) * q.C + q.W) * idx2 + (q.N - T(2) * q.C + q.S) * idy2;
-}
 
 template <typename T>
 __global__ __launch_bounds__(kTileX* kTileY) void k_stencil_rk3(
