@@ -15,7 +15,12 @@ constexpr int kTileY = 4;
 // PASS_CD: passes C and D fused (one layer).
 enum Pass { PASS_A = 0, PASS_B = 1, PASS_C = 2, PASS_D = 3, PASS_CD = 4, NUM_PASSES = 5 };
 
-constexpr int kFusedTj = 2;  // coarse rows owned by a block of the fused C + D pass
+// Fused C + D pass: rows of at most kFusedMaxNx intervals, coarsening
+// factors 1, 2 and 4; a block owns fused_tj(c) coarse rows and writes at most
+// fused_nr(c) fine rows.
+constexpr int kFusedMaxNx = 512;
+__host__ __device__ constexpr int fused_tj(int c) { return c >= 4 ? 1 : 2; }
+__host__ __device__ constexpr int fused_nr(int c) { return c * fused_tj(c) + 1; }
 
 // Per-basin descriptor, uploaded once at create.  Offsets are in elements of
 // the handle's scalar type T unless stated.

@@ -3,76 +3,151 @@
 // Arakawa right-hand side with the TVD-RK3 stage combine (Sec. 4.1, 4.2), so
 // that the prolonged psi never travels through HBM.
 //
-// A block owns coarse rows j0 .. j0+tj-1 (tj = 2) and writes omega_{s+1} on
-// the fine rows c*j0 .. c*(j0+tj)-1 (the last block also the top wall row).
-// The stencil on those rows needs psi on one more fine row above and below,
-// i.e. the coarse rows j0-1 .. j0+tj, which the block synthesises itself (at
-// most four rows: two complex sequences).  Each thread then owns one fine
-// column and slides down the block's rows with a 3 x 3 vorticity window in
-// registers.
+// A block owns coarse rows j0 .. j0+TJ-1 and writes omega_{s+1} on the fine
+// rows C*j0 .. C*(j0+TJ)-1 (the last block also the top wall row).  The
+// stencil on those rows needs psi on one more fine row above and below, i.e.
+// the coarse rows j0-1 .. j0+TJ, which the block synthesises itself (at most
+// four rows: two complex sequences) and keeps in LDS.  Each thread then owns
+// fine columns and interpolates psi at its column and both neighbours for all
+// of the block's rows in registers; the row weights are compile-time
+// constants.
+//
+// Latency: a block is the only one on its CU, so its phases do not overlap
+// with other blocks.  Every global load of the block is therefore issued at
+// the start: the twiddles and spectra first (the transform waits for them
+// only), then the vorticity rows, the forcing and omega_n, which arrive while
+// the transform runs.  Rows are at most kFusedMaxNx + 1 nodes wide.
 #include "cgp_internal.hpp"
 #include "fft_lds.hpp"
 #include "stencil.hpp"
 
 namespace cgp {
 
-// NR: the most fine output rows a block writes (c * tj, +1 for the top wall
-// row of the last block).
-template <typename T, int NR>
-__global__ __launch_bounds__(kThreads) void k_prolong_stencil(
+// C: coarsening factor; TJ: coarse rows owned per block.
+template <typename T, int C, int TJ>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void
+k_prolong_stencil(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
     const T* __restrict__ wt, const cplx<T>* __restrict__ twg, const T* __restrict__ ws,
     const T* __restrict__ forcing, const T* __restrict__ wn, T* __restrict__ out, double a_,
     double b_) {
+  constexpr int NR = C * TJ + 1;  // the most fine rows a block writes (+1: top wall row)
+  constexpr int kTwPer = 4;   // twiddles per thread: (R-1) Ns summed over stages < L <= 1024
+  constexpr int kSpPer = 2;   // spectral columns per thread: Mx - 1 <= 511
+  constexpr int kCol = 2;     // interior fine columns per thread: nx - 1 <= 511
+  constexpr int kWPer = ((NR + 2) * (kFusedMaxNx + 1) + kThreads - 1) / kThreads;
   extern __shared__ __align__(16) unsigned char smem[];
+  const int t = threadIdx.x;
   const int bid = xcd_contiguous(blockIdx.x, nblk);
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_CD, bid)];
   const int lb = bid - d.blk0[PASS_CD];
-  const int Mx = d.Mx, My = d.My, L = d.Lr, c = d.c, TJ = kFusedTj;
+  const int Mx = d.Mx, My = d.My, L = d.Lr, c = C;
   const int nx = d.nx, ny = d.ny, pitch = nx + 1;
   const int LP = lpad(L);
-
-  // LDS: [ max(FFT buffers, fine psi rows) | twiddles | coarse psi rows ]
-  const int nx1 = nx + 1;
-  const int head =
-      (max(4 * LP * (int)sizeof(cplx<T>), (c * TJ + 3) * nx1 * (int)sizeof(T)) + 15) & ~15;
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + head);
-  T* psc = reinterpret_cast<T*>(tw + d.ntw_r);  // coarse psi rows j0-1 .. j0+TJ
-  T* psf = reinterpret_cast<T*>(smem);          // fine psi rows R0-1 .. R1 (after the FFT)
-  const int prow = Mx + 1;
+  const int ntw = d.ntw_r;
 
   const int j0 = lb * TJ;
   const int ilo = max(1, j0 - 1);
   const int ihi = min(My - 1, j0 + TJ);
   const int nint = ihi >= ilo ? ihi - ilo + 1 : 0;
   const int nseq = (nint + 1) / 2;
-  const T* w = wt + d.wt_off;
+  const int last = (lb == d.nblk[PASS_CD] - 1);
+  const int R0 = c * j0;
+  const int R1 = last ? ny + 1 : c * (j0 + TJ);  // exclusive end of the output rows
+  const int nfr = R1 - R0;                       // output rows (<= NR)
+  const int nW = (nfr + 2) * pitch;              // vorticity tile: rows R0-1 .. R1
 
-  // ---- coarse spectra rows ilo..ihi -> two packed sequences, odd extension
-  load_twiddles(tw, twg + d.twr_off, d.ntw_r);
-  if (threadIdx.x < nseq) {
-    buf[threadIdx.x * LP + pad(0)] = {T(0), T(0)};
-    buf[threadIdx.x * LP + pad(Mx)] = {T(0), T(0)};
+  // LDS: [ FFT buffers ] [ twiddles ] [ coarse psi rows ] [ vorticity tile ]
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = buf + 4 * LP;
+  T* psc = reinterpret_cast<T*>(tw + ntw);
+  const int prow = Mx + 1;
+  T* wtile = psc + (TJ + 2) * prow;
+
+  // ---- issue the block's global loads.  They are unconditional (a lane
+  // without an element reads element 0 of the same array and discards it), so
+  // that they sit in one basic block and the transform below waits only for
+  // the twiddles and spectra, not for the loads issued after them.
+  T twx[kTwPer], twy[kTwPer];
+#pragma unroll
+  for (int q = 0; q < kTwPer; ++q) {
+    const int m = t + kThreads * q;
+    const cplx<T> z = twg[d.twr_off + (m < ntw ? m : 0)];
+    twx[q] = z.x;
+    twy[q] = z.y;
   }
-  for (int k = 1 + threadIdx.x; k < Mx; k += kThreads) {
-    const T* col = w + (size_t)(k - 1) * (My - 1) + (ilo - 1);
-    T v[4];
+  const T* w = wt + d.wt_off;
+  T sv[kSpPer][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = r < nint ? col[r] : T(0);
+  for (int q = 0; q < kSpPer; ++q) {
+    const int k = 1 + t + kThreads * q;
+    const size_t cbase = (size_t)(k - 1) * (My - 1) + (ilo - 1);
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      if (p < nseq) {
-        const cplx<T> z = {v[2 * p], v[2 * p + 1]};
-        buf[p * LP + pad(k)] = z;
-        buf[p * LP + pad(2 * Mx - k)] = {-z.x, -z.y};
+    for (int r = 0; r < 4; ++r) {
+      const bool in = k < Mx && r < nint;
+      const T v = w[in ? cbase + r : 0];
+      sv[q][r] = in ? v : T(0);
+    }
+  }
+  const T* W = ws + d.field_off;
+  const T* FF = forcing + d.field_off;
+  const T* WN = wn + d.field_off;
+  T* O = out + d.field_off;
+  const long long g0 = (long long)(R0 - 1) * pitch;
+  const long long gend = (long long)(ny + 1) * pitch;
+  T wv[kWPer];
+#pragma unroll
+  for (int q = 0; q < kWPer; ++q) {
+    const int e = t + kThreads * q;
+    const long long g = g0 + e;
+    const bool in = e < nW && g >= 0 && g < gend;
+    const T v = W[in ? g : 0];
+    wv[q] = in ? v : T(0);
+  }
+  // forcing and omega_n at the thread's columns x = 1 + t + 256 k, rows R0 + r
+  T fv[kCol][NR], nv[kCol][NR];
+#pragma unroll
+  for (int k = 0; k < kCol; ++k) {
+    const int x = 1 + t + kThreads * k;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int rr = R0 + r;
+      const bool in = x < nx && r < nfr && rr >= 1 && rr < ny;
+      const size_t o = in ? (size_t)rr * pitch + x : 0;
+      const T f = FF[o], n = WN[o];
+      fv[k][r] = in ? f : T(0);
+      nv[k][r] = in ? n : T(0);
+    }
+  }
+
+  // ---- twiddles and the two packed sequences (odd extension) into LDS
+#pragma unroll
+  for (int q = 0; q < kTwPer; ++q) {
+    const int m = t + kThreads * q;
+    if (m < ntw) tw[m] = {twx[q], twy[q]};
+  }
+  if (t < nseq) {
+    buf[t * LP + pad(0)] = {T(0), T(0)};
+    buf[t * LP + pad(Mx)] = {T(0), T(0)};
+  }
+#pragma unroll
+  for (int q = 0; q < kSpPer; ++q) {
+    const int k = 1 + t + kThreads * q;
+    if (k < Mx) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        if (p < nseq) {
+          const cplx<T> z = {sv[q][2 * p], sv[q][2 * p + 1]};
+          buf[p * LP + pad(k)] = z;
+          buf[p * LP + pad(2 * Mx - k)] = {-z.x, -z.y};
+        }
       }
     }
   }
   const cplx<T>* Z = fft_lds<T>(buf, buf + 2 * LP, nseq, L, d.nst_r, d.stw_r, tw);
 
   // ---- coarse psi rows J = j0-1 .. j0+TJ (zero walls) into psc
-  for (int i = threadIdx.x; i <= Mx; i += kThreads) {
+  for (int i = t; i <= Mx; i += kThreads) {
 #pragma unroll
     for (int r = 0; r < TJ + 2; ++r) {
       const int J = j0 - 1 + r;
@@ -85,94 +160,105 @@ __global__ __launch_bounds__(kThreads) void k_prolong_stencil(
       psc[r * prow + i] = v;
     }
   }
-  __syncthreads();
-
-  // ---- fine psi rows R0-1 .. R1 into psf (bilinear, Sec. 3.1)
-  const int last = (lb == d.nblk[PASS_CD] - 1);
-  const int R0 = c * j0;
-  const int R1 = last ? ny + 1 : c * (j0 + TJ);  // exclusive end of the output rows
-  const int nfr = R1 - R0;                       // output rows (<= c*TJ + 1)
-  const T inv_c2 = T(1) / (T(c) * T(c));
-  for (int x = threadIdx.x; x <= nx; x += kThreads) {
-    const int I = x / c, fx = x - I * c;
-    for (int r = 0; r < nfr + 2; ++r) {
-      const int rr = R0 - 1 + r;  // fine row
-      T v = T(0);
-      if (rr >= 0 && rr <= ny) {
-        const int J = rr / c, fy = rr - J * c;
-        const T* P0 = psc + (J - (j0 - 1)) * prow;
-        v = T(c - fx) * P0[I];
-        if (fx) v += T(fx) * P0[I + 1];
-        v *= T(c - fy);
-        if (fy) {
-          const T* P1 = P0 + prow;
-          T u = T(c - fx) * P1[I];
-          if (fx) u += T(fx) * P1[I + 1];
-          v += T(fy) * u;
-        }
-        v *= inv_c2;
-      }
-      psf[r * pitch + x] = v;
-    }
+#pragma unroll
+  for (int q = 0; q < kWPer; ++q) {
+    const int e = t + kThreads * q;
+    if (e < nW) wtile[e] = wv[q];
   }
   __syncthreads();
 
-  // ---- stencil + RK3 on fine rows R0 .. R1-1, one column per thread
+  // ---- walls: columns 0 and nx of the output rows
+  if (t < nfr) O[(size_t)(R0 + t) * pitch] = T(0);
+  else if (t >= 64 && t < 64 + nfr) O[(size_t)(R0 + t - 64) * pitch + nx] = T(0);
+
+  // ---- stencil + RK3 on fine rows R0 .. R1-1 (tile row q = fine row R0-1+q)
   const T dt = T(d.dt), a = T(a_), b = T(b_);
   const T cj = T(1.0 / (12.0 * d.dx * d.dy));
   const T cb = T(d.inv_ro / (3.0 * d.dx));
   const T idx2 = T(1.0 / (d.dx * d.dx)), idy2 = T(1.0 / (d.dy * d.dy));
   const T nu = T(d.inv_re);
-  const T* W = ws + d.field_off;
-  const T* FF = forcing + d.field_off;
-  const T* WN = wn + d.field_off;
-  T* O = out + d.field_off;
-  for (int x = threadIdx.x; x <= nx; x += kThreads) {
-    if (x == 0 || x == nx) {
-      for (int r = 0; r < nfr; ++r) O[(size_t)(R0 + r) * pitch + x] = T(0);
-      continue;
-    }
-    // vorticity rows r-1, r, r+1 (fine rows R0-2+r ..) at columns x-1, x, x+1,
-    // sliding down the block's rows; the ring is read as 0
-    auto load = [&](int r, T& w0, T& w1, T& w2) {
-      const int rr = R0 - 1 + r;
-      const bool in = r < nfr + 2 && rr >= 1 && rr <= ny - 1;
-      const T* row = W + (size_t)(in ? rr : 0) * pitch + x;
-      w0 = (in && x > 1) ? row[-1] : T(0);
-      w1 = in ? row[0] : T(0);
-      w2 = (in && x < nx - 1) ? row[1] : T(0);
-    };
-    T s0, s1, s2, c0, c1, c2;
-    load(0, s0, s1, s2);
-    load(1, c0, c1, c2);
+  constexpr T kInvC2 = T(1) / T(C * C);
 #pragma unroll
-    for (int r = 1; r <= NR; ++r) {
-      T n0, n1, n2;
-      load(r + 1, n0, n1, n2);
-      const int rr = R0 - 1 + r;
-      const size_t o = (size_t)rr * pitch + x;
-      if (r <= nfr) {
-        if (rr == 0 || rr == ny) {
-          O[o] = T(0);
+  for (int k = 0; k < kCol; ++k) {
+    const int x = 1 + t + kThreads * k;
+    if (x >= nx) continue;
+    // coarse columns I0 .. I0+2 (clamped to the wall column Mx) cover the
+    // fine columns x-1 .. x+1 for C >= 2; for C = 1 they are those columns
+    const int I0 = (x - 1) / C;
+    T A[3][TJ + 2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int I = min(I0 + m, Mx);
+#pragma unroll
+      for (int r = 0; r < TJ + 2; ++r) A[m][r] = psc[r * prow + I];
+    }
+    // P[dx][q]: psi at fine column x-1+dx, tile row q (bilinear, Sec. 3.1;
+    // times C^2, scaled below)
+    T P[3][NR + 2];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int xx = x - 1 + dx;
+      const int rel = xx / C - I0;  // 0 or 1 (0 .. 2 when C = 1)
+      const int fx = xx - (xx / C) * C;
+      T cv[TJ + 2];
+#pragma unroll
+      for (int r = 0; r < TJ + 2; ++r) {
+        T lo, hi;
+        if constexpr (C == 1) {
+          lo = dx == 0 ? A[0][r] : (dx == 1 ? A[1][r] : A[2][r]);
+          hi = T(0);
         } else {
-          const T* pc = psf + r * pitch + x;
-          Nbr<T> p, q;
-          p.C = pc[0]; p.E = pc[1]; p.W = pc[-1];
-          p.N = pc[pitch]; p.S = pc[-pitch];
-          p.NE = pc[pitch + 1]; p.NW = pc[pitch - 1];
-          p.SE = pc[-pitch + 1]; p.SW = pc[-pitch - 1];
-          q.C = c1; q.E = c2; q.W = c0;
-          q.N = n1; q.S = s1;
-          q.NE = n2; q.NW = n0;
-          q.SE = s2; q.SW = s0;
-          const T G = -cj * arakawa12(p, q) - cb * beta3(p) + nu * lap5(q, idx2, idy2) + FF[o];
-          T v = b * (q.C + dt * G);
-          if (a_ != 0.0) v += a * WN[o];
-          O[o] = v;
+          lo = rel == 0 ? A[0][r] : A[1][r];
+          hi = rel == 0 ? A[1][r] : A[2][r];
         }
+        cv[r] = T(C - fx) * lo + T(fx) * hi;
       }
-      s0 = c0; s1 = c1; s2 = c2;
-      c0 = n0; c1 = n1; c2 = n2;
+#pragma unroll
+      for (int q = 0; q < NR + 2; ++q) {
+        // fine row R0-1+q = C*(j0-1) + (C-1+q): coarse row j0-1+jr, weight fy
+        const int u = C - 1 + q;
+        const int jr = u / C, fy = u - jr * C;
+        const T top = jr + 1 < TJ + 2 ? cv[jr + 1 < TJ + 2 ? jr + 1 : TJ + 1] : T(0);
+        P[dx][q] = (T(C - fy) * cv[jr < TJ + 2 ? jr : TJ + 1] + T(fy) * top) * kInvC2;
+      }
+    }
+    const bool mw = x > 1, me = x < nx - 1;
+    auto wrow = [&](int q, T& w0, T& w1, T& w2) {
+      const int rr = R0 - 1 + q;
+      const bool in = rr >= 1 && rr <= ny - 1;
+      const T* p = wtile + q * pitch + x;
+      w0 = (in && mw) ? p[-1] : T(0);
+      w1 = in ? p[0] : T(0);
+      w2 = (in && me) ? p[1] : T(0);
+    };
+    T ws0, ws1, ws2, wc0, wc1, wc2;
+    wrow(0, ws0, ws1, ws2);
+    wrow(1, wc0, wc1, wc2);
+#pragma unroll
+    for (int q = 1; q <= NR; ++q) {
+      if (q > nfr) break;
+      T wn0, wn1, wn2;
+      wrow(q + 1, wn0, wn1, wn2);
+      const int rr = R0 - 1 + q;
+      T v = T(0);
+      if (rr != 0 && rr != ny) {
+        Nbr<T> p, w;
+        p.C = P[1][q]; p.E = P[2][q]; p.W = P[0][q];
+        p.N = P[1][q + 1]; p.S = P[1][q - 1];
+        p.NE = P[2][q + 1]; p.NW = P[0][q + 1];
+        p.SE = P[2][q - 1]; p.SW = P[0][q - 1];
+        w.C = wc1; w.E = wc2; w.W = wc0;
+        w.N = wn1; w.S = ws1;
+        w.NE = wn2; w.NW = wn0;
+        w.SE = ws2; w.SW = ws0;
+        const T G =
+            -cj * arakawa12(p, w) - cb * beta3(p) + nu * lap5(w, idx2, idy2) + fv[k][q - 1];
+        v = b * (w.C + dt * G);
+        if (a_ != 0.0) v += a * nv[k][q - 1];
+      }
+      O[(size_t)rr * pitch + x] = v;
+      ws0 = wc0; ws1 = wc1; ws2 = wc2;
+      wc0 = wn0; wc1 = wn1; wc2 = wn2;
     }
   }
 }
@@ -184,18 +270,19 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
                                       const T* wn, T* out, double a, double b, hipStream_t s) {
   switch (g.L) {
     case 1:
-      hipLaunchKernelGGL((k_prolong_stencil<T, kFusedTj + 1>), dim3(g.nblk), dim3(kThreads), g.lds,
-                         s, md, g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b);
+      hipLaunchKernelGGL((k_prolong_stencil<T, 1, 2>), dim3(g.nblk), dim3(kThreads), g.lds, s, md,
+                         g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b);
       break;
     case 2:
-      hipLaunchKernelGGL((k_prolong_stencil<T, 2 * kFusedTj + 1>), dim3(g.nblk), dim3(kThreads),
-                         g.lds, s, md, g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out,
-                         a, b);
+      hipLaunchKernelGGL((k_prolong_stencil<T, 2, 2>), dim3(g.nblk), dim3(kThreads), g.lds, s, md,
+                         g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_prolong_stencil<T, 4, 1>), dim3(g.nblk), dim3(kThreads), g.lds, s, md,
+                         g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b);
       break;
     default:
-      hipLaunchKernelGGL((k_prolong_stencil<T, 4 * kFusedTj + 1>), dim3(g.nblk), dim3(kThreads),
-                         g.lds, s, md, g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out,
-                         a, b);
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -203,15 +290,14 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
 template <typename T>
 hipError_t Launch<T>::prepare_fused(size_t bytes) {
   const int b = (int)bytes;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_prolong_stencil<T, 3>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_prolong_stencil<T, 5>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_prolong_stencil<T, 9>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  return e;
+  const void* fns[3] = {reinterpret_cast<const void*>(&k_prolong_stencil<T, 1, 2>),
+                        reinterpret_cast<const void*>(&k_prolong_stencil<T, 2, 2>),
+                        reinterpret_cast<const void*>(&k_prolong_stencil<T, 4, 1>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template struct Launch<float>;

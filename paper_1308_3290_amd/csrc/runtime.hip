@@ -256,20 +256,19 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     for (const HostGroup& g : plan->groups[p])
       if (g.lds > kMaxLds)
         return fail(CGP_ERR_UNSUPPORTED, "a transform pass needs more than 160 KiB LDS per block");
-  // fused C + D (one layer, rows of at most 1024 complex values): a block
-  // owns kFusedTj coarse rows and synthesises the two neighbouring ones, i.e.
-  // at most two packed sequences; one launch per coarsening factor.
+  // fused C + D (one layer, rows of at most kFusedMaxNx intervals, c <= 4): a
+  // block owns fused_tj(c) coarse rows and synthesises the two neighbouring
+  // ones (at most two packed sequences); one launch per coarsening factor.
   bool fusable = nl == 1;
-  for (const MemberDesc& d : plan->md) fusable = fusable && d.Lr <= 1024;
+  for (const MemberDesc& d : plan->md) fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4;
   if (fusable) {
     build_groups(plan->md, PASS_CD, [](const MemberDesc& d) { return d.c; },
                  [&](MemberDesc& d, HostGroup&) {
-                   const size_t head =
-                       (std::max((size_t)4 * lpad(d.Lr) * cs,
-                                 (size_t)(d.c * kFusedTj + 3) * (d.nx + 1) * es) + 15) & ~(size_t)15;
-                   const size_t lds = head + (size_t)d.ntw_r * cs +
-                                      (size_t)(kFusedTj + 2) * (d.Mx + 1) * es;
-                   return std::make_pair((d.My + kFusedTj - 1) / kFusedTj, lds);
+                   const int tj = fused_tj(d.c), nr = fused_nr(d.c);
+                   const size_t lds = ((size_t)4 * lpad(d.Lr) + d.ntw_r) * cs +
+                                      ((size_t)(tj + 2) * (d.Mx + 1) +
+                                       (size_t)(nr + 2) * (d.nx + 1)) * es;
+                   return std::make_pair((d.My + tj - 1) / tj, lds);
                  },
                  plan->groups[3]);
     plan->fused = true;

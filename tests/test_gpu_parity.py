@@ -138,10 +138,11 @@ def test_c0_physics_100_steps_fp32(level):
     assert errs.max() < TOL32
 
 
-# (1024, 64, 1): fused C + D pass at its longest rows (1024 complex values);
-# (1024, 48, 0): rows too long for it, the unfused one-layer step.
+# (512, 32, 0): the fused transform + stencil pass at its widest rows (512
+# intervals, transforms of 1024 complex values); (1024, 64, 1), (1024, 48, 0):
+# rows too wide for it, the unfused one-layer step.
 @pytest.mark.parametrize("nx,ny,level", [(96, 192, 1), (48, 96, 0), (192, 96, 2),
-                                         (1024, 64, 1), (1024, 48, 0)])
+                                         (512, 32, 0), (1024, 64, 1), (1024, 48, 0)])
 def test_ragged_and_radix3_trajectories(nx, ny, level):
     case = ci.make_case(nx, ny, level=level, dt=1e-4)
     say(f"{nx}x{ny} level {level}, 30 steps FP64")
