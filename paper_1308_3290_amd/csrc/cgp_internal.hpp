@@ -79,7 +79,8 @@ __device__ __forceinline__ int group_member(const MemberDesc* md, const int* grp
 
 // One launch of a transform pass over a group of members.
 struct Group {
-  int L;               // fused C + D pass: the coarsening factor; otherwise 0
+  int L;               // transform length with a compile-time transform, or 0
+                       // (fused C + D pass: (c << 16) | that length)
   int count;           // members in the group
   const int* members;  // device array of the group's member indices
   int nblk, threads;  // threads = kThreads

@@ -129,6 +129,43 @@ __host__ __device__ constexpr int stage_word(int R, int lns, int two) {
   return R | (lns << 4) | (two << 9);
 }
 
+// Stage plan of a complex FFT of length L = 2^k or 3*2^k: radix 8 while
+// possible, then 4, then 2, the radix 3 last, so that every stage's span Ns
+// (the product of the earlier radices) is a power of two.  Stage s has radix
+// R[s], span 2^lns[s] and its twiddle table ((R-1) x Ns values) at off[s];
+// ntw is the total table size.  Shared by the host (tables, stage words) and
+// the compile-time transforms below.
+struct StagePlan {
+  int n = 0, ntw = 0;
+  int R[kMaxStages] = {}, lns[kMaxStages] = {}, off[kMaxStages] = {};
+};
+
+__host__ __device__ constexpr StagePlan stage_plan(int L) {
+  StagePlan p{};
+  int rest = L, ns = 1, lg = 0;
+  const int radix[3] = {8, 4, 2}, lgr[3] = {3, 2, 1};
+  for (int i = 0; i < 3; ++i) {
+    while (rest % radix[i] == 0 && p.n < kMaxStages) {
+      p.R[p.n] = radix[i];
+      p.lns[p.n] = lg;
+      p.off[p.n] = p.ntw;
+      p.ntw += (radix[i] - 1) * ns;
+      ns *= radix[i];
+      lg += lgr[i];
+      rest /= radix[i];
+      ++p.n;
+    }
+  }
+  if (rest == 3 && p.n < kMaxStages) {
+    p.R[p.n] = 3;
+    p.lns[p.n] = lg;
+    p.off[p.n] = p.ntw;
+    p.ntw += 2 * ns;
+    ++p.n;
+  }
+  return p;
+}
+
 // Forward DFT of nseq (1 or 2) sequences of length L held back to back in
 // buffer a (LDS, padded layout); b is scratch of the same size.  Returns the
 // buffer holding the result.  Every thread of the block must call it; it
@@ -154,6 +191,81 @@ __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nseq, in
     b = x;
   }
   return a;
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time transforms for the common lengths.  The stage plan, strides
+// and twiddle offsets are constants, so that every LDS address of a butterfly
+// is a per-thread base plus an immediate offset: the padded index of
+// j + r L/R is pad(j) + r lpad(L/R) (L/R is a multiple of 8), and that of the
+// output o + r Ns is pad(o) + r lpad(Ns) (Ns a multiple of 8) or pad(o) + r Ns
+// (Ns R divides 8).
+// ---------------------------------------------------------------------------
+template <typename T, int L, int S>
+__device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int nseq,
+                                         const cplx<T>* tw) {
+  constexpr StagePlan P = stage_plan(L);
+  constexpr int R = P.R[S], LNS = P.lns[S], NS = 1 << LNS, OFF = P.off[S];
+  constexpr int LR = L / R, LP = lpad(L), RS = lpad(LR);
+  static_assert(LR % 8 == 0, "read offsets need L/R to be a multiple of 8");
+  static_assert(NS % 8 == 0 || 8 % (NS * R) == 0, "write offsets need Ns % 8 == 0 or Ns R | 8");
+  constexpr int WS = NS % 8 == 0 ? lpad(NS) : NS;
+  constexpr int Q = (2 * LR + kThreads - 1) / kThreads;  // nseq <= 2
+  const int nb = nseq * LR;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int b = threadIdx.x + kThreads * q;
+    if (b < nb) {
+      const int p = b / LR;
+      const int j = b - p * LR;
+      const int k = j & (NS - 1);
+      const cplx<T>* src = in + p * LP + pad(j);
+      cplx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = src[r * RS];
+      if constexpr (NS > 1) {
+        const cplx<T>* t = tw + OFF + k;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * NS]);
+      }
+      small_dft<T, R>(v);
+      const int o = ((j >> LNS) << LNS) * R + k;
+      cplx<T>* dst = out + p * LP + pad(o);
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * WS] = v[r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int L, int S>
+__device__ __forceinline__ cplx<T>* ct_stages(cplx<T>* a, cplx<T>* b, int nseq,
+                                              const cplx<T>* tw) {
+  constexpr StagePlan P = stage_plan(L);
+  if constexpr (S == P.n) {
+    return a;
+  } else {
+    ct_stage<T, L, S>(a, b, nseq, tw);
+    return ct_stages<T, L, S + 1>(b, a, nseq, tw);
+  }
+}
+
+// Forward DFT with the contract of fft_lds; LC = 0 selects the runtime
+// engine (any supported length), otherwise L must equal LC.
+template <typename T, int LC>
+__device__ __forceinline__ cplx<T>* fft_run(cplx<T>* a, cplx<T>* b, int nseq, int L, int nst,
+                                            const int* words, const cplx<T>* tw) {
+  if constexpr (LC == 0) {
+    return fft_lds<T>(a, b, nseq, L, nst, words, tw);
+  } else {
+    __syncthreads();
+    return ct_stages<T, LC, 0>(a, b, nseq, tw);
+  }
+}
+
+// Lengths with a compile-time transform (0: none).
+__host__ __device__ constexpr int fft_special(int L) {
+  return (L == 256 || L == 512 || L == 1024 || L == 2048) ? L : 0;
 }
 
 // Copy n twiddle values from global memory to LDS.

@@ -23,8 +23,9 @@
 
 namespace cgp {
 
-// C: coarsening factor; TJ: coarse rows owned per block.
-template <typename T, int C, int TJ>
+// C: coarsening factor; TJ: coarse rows owned per block; LC: transform
+// length with a compile-time transform, or 0.
+template <typename T, int C, int TJ, int LC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 k_prolong_stencil(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
@@ -144,7 +145,7 @@ k_prolong_stencil(
       }
     }
   }
-  const cplx<T>* Z = fft_lds<T>(buf, buf + 2 * LP, nseq, L, d.nst_r, d.stw_r, tw);
+  const cplx<T>* Z = fft_run<T, LC>(buf, buf + 2 * LP, nseq, L, d.nst_r, d.stw_r, tw);
 
   // ---- coarse psi rows J = j0-1 .. j0+TJ (zero walls) into psc
   for (int i = t; i <= Mx; i += kThreads) {
@@ -263,36 +264,44 @@ k_prolong_stencil(
   }
 }
 
-// g.L carries the group's coarsening factor c (1, 2 or 4).
+// g.L = (c << 16) | transform length with a compile-time transform (or 0).
 template <typename T>
 hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, const T* wt,
                                       const cplx<T>* tw, const T* ws, const T* forcing,
                                       const T* wn, T* out, double a, double b, hipStream_t s) {
-  switch (g.L) {
-    case 1:
-      hipLaunchKernelGGL((k_prolong_stencil<T, 1, 2>), dim3(g.nblk), dim3(kThreads), g.lds, s, md,
-                         g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_prolong_stencil<T, 2, 2>), dim3(g.nblk), dim3(kThreads), g.lds, s, md,
-                         g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_prolong_stencil<T, 4, 1>), dim3(g.nblk), dim3(kThreads), g.lds, s, md,
-                         g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b);
-      break;
-    default:
-      return hipErrorInvalidValue;
+#define LAUNCH(C, TJ, LC)                                                                     \
+  hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC>), dim3(g.nblk), dim3(kThreads), g.lds, s, \
+                     md, g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b)
+#define BY_LEN(C, TJ)                         \
+  switch (g.L & 0xffff) {                     \
+    case 256: LAUNCH(C, TJ, 256); break;      \
+    case 512: LAUNCH(C, TJ, 512); break;      \
+    case 1024: LAUNCH(C, TJ, 1024); break;    \
+    default: LAUNCH(C, TJ, 0);                \
   }
+  switch (g.L >> 16) {
+    case 1: BY_LEN(1, 2); break;
+    case 2: BY_LEN(2, 2); break;
+    case 4: BY_LEN(4, 1); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef BY_LEN
+#undef LAUNCH
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t Launch<T>::prepare_fused(size_t bytes) {
   const int b = (int)bytes;
-  const void* fns[3] = {reinterpret_cast<const void*>(&k_prolong_stencil<T, 1, 2>),
-                        reinterpret_cast<const void*>(&k_prolong_stencil<T, 2, 2>),
-                        reinterpret_cast<const void*>(&k_prolong_stencil<T, 4, 1>)};
+  const void* fns[] = {
+#define FNS(C, TJ)                                                          \
+  reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 0>),           \
+      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 256>),     \
+      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 512>),     \
+      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 1024>)
+      FNS(1, 2), FNS(2, 2), FNS(4, 1)
+#undef FNS
+  };
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;

@@ -62,28 +62,13 @@ bool pow2_or_3pow2(int n) {
   return n == 1 || n == 3;
 }
 
-// Stage plan of a complex FFT of length L = 2^k or 3*2^k: radix 8 while
-// possible, then 4, then 2, the radix 3 last, so that every stage's span Ns
-// (the product of the earlier radices) is a power of two.  two[s] is the
-// offset of stage s's twiddle table ((R-1) x Ns values); returns the stage
-// count and the total table size in *ntw.
+// Stage words of the runtime transform (see stage_plan); returns the stage
+// count and the twiddle table size in *ntw.
 int plan_stages(int L, int* words, int* ntw) {
-  int n = 0, rest = L, ns = 1, off = 0;
-  auto push = [&](int r) {
-    int lg = 0;
-    while ((1 << lg) < ns) ++lg;
-    words[n] = stage_word(r, lg, off);
-    off += (r - 1) * ns;
-    ns *= r;
-    rest /= r;
-    ++n;
-  };
-  while (rest % 8 == 0) push(8);
-  while (rest % 4 == 0) push(4);
-  while (rest % 2 == 0) push(2);
-  if (rest == 3) push(3);
-  *ntw = off;
-  return n;
+  const StagePlan p = stage_plan(L);
+  for (int s = 0; s < p.n; ++s) words[s] = stage_word(p.R[s], p.lns[s], p.off[s]);
+  *ntw = p.ntw;
+  return p.n;
 }
 
 cgp_status validate(const cgp_config* c) {
@@ -124,7 +109,8 @@ struct Layout {
 
 // One launch of a transform pass on the host side.
 struct HostGroup {
-  int L = 0;                 // fast-engine length, 0 = generic engine
+  int L = 0;                 // launch key: compile-time transform length or 0
+                             // (fused pass: (c << 16) | length)
   std::vector<int> members;  // member indices in member order
   int nblk = 0;
   size_t lds = 0;
@@ -223,7 +209,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   // A block transforms at most two sequences and at most 2048 complex values.
   auto pairs = [](int L) { return L <= 512 ? 2 : 1; };
   // pass A: pairs of coarse rows (one layer) or one coarse row's two modes
-  build_groups(plan->md, PASS_A, [](const MemberDesc&) { return 0; },
+  build_groups(plan->md, PASS_A, [](const MemberDesc& d) { return fft_special(d.Lr); },
                [&](MemberDesc& d, HostGroup&) {
                  d.pa = pairs(d.Lr);
                  const int rows = nl == 1 ? 2 * d.pa : d.pa;
@@ -232,7 +218,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                },
                plan->groups[0]);
   // pass B: pairs of spectral columns (one layer) or one column's two modes
-  build_groups(plan->md, PASS_B, [](const MemberDesc&) { return 0; },
+  build_groups(plan->md, PASS_B, [](const MemberDesc& d) { return fft_special(d.Lc); },
                [&](MemberDesc& d, HostGroup&) {
                  d.pb = pairs(d.Lc);
                  const int cols = nl == 1 ? 2 * d.pb : d.pb;
@@ -241,7 +227,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                },
                plan->groups[1]);
   // pass C: tj owned coarse rows (+1 halo row when c > 1) per block
-  build_groups(plan->md, PASS_C, [](const MemberDesc&) { return 0; },
+  build_groups(plan->md, PASS_C, [](const MemberDesc& d) { return fft_special(d.Lr); },
                [&](MemberDesc& d, HostGroup&) {
                  const int halo = d.c > 1 ? 1 : 0;
                  d.pc = nl == 1 ? pairs(d.Lr) : (d.Lr <= 1024 ? 2 : 1);
@@ -262,7 +248,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   bool fusable = nl == 1;
   for (const MemberDesc& d : plan->md) fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4;
   if (fusable) {
-    build_groups(plan->md, PASS_CD, [](const MemberDesc& d) { return d.c; },
+    build_groups(plan->md, PASS_CD,
+                 [](const MemberDesc& d) { return (d.c << 16) | fft_special(d.Lr); },
                  [&](MemberDesc& d, HostGroup&) {
                    const int tj = fused_tj(d.c), nr = fused_nr(d.c);
                    const size_t lds = ((size_t)4 * lpad(d.Lr) + d.ntw_r) * cs +

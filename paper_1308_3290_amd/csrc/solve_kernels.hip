@@ -107,7 +107,7 @@ __device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __r
   }
 }
 
-template <typename T>
+template <typename T, int LC>
 __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng,
     const T* __restrict__ src, T* __restrict__ wt, const cplx<T>* __restrict__ twg) {
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     case 4: restrict_block<T, 4>(d, f, buf, j0, nr, LP); break;
     default: restrict_block<T, 0>(d, f, buf, j0, nr, LP);
   }
-  const cplx<T>* Z = fft_lds<T>(buf, buf + P * LP, nseq, L, d.nst_r, d.stw_r, tw);
+  const cplx<T>* Z = fft_run<T, LC>(buf, buf + P * LP, nseq, L, d.nst_r, d.stw_r, tw);
 
   T* w = wt + d.wt_off;
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
 // column k) along y, multiplies by (2/Mx)(2/My)/lambda_kl (baroclinic:
 // 1/(lambda_kl - F1 - F2)), and transforms back.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int LC>
 __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __restrict__ md,
                                                         const int* __restrict__ grp, int ng,
                                                         T* __restrict__ wt,
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
       }
     }
   }
-  cplx<T>* Z = fft_lds<T>(buf, buf2, nseq, L, d.nst_c, d.stw_c, tw);
+  cplx<T>* Z = fft_run<T, LC>(buf, buf2, nseq, L, d.nst_c, d.stw_c, tw);
   cplx<T>* Y = (Z == buf) ? buf2 : buf;
 
   for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
     Y[threadIdx.x * LP + pad(0)] = {T(0), T(0)};
     Y[threadIdx.x * LP + pad(My)] = {T(0), T(0)};
   }
-  const cplx<T>* R = fft_lds<T>(Y, Z, nseq, L, d.nst_c, d.stw_c, tw);
+  const cplx<T>* R = fft_run<T, LC>(Y, Z, nseq, L, d.nst_c, d.stw_c, tw);
 
   for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
 #pragma unroll
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
 // keeps them in LDS with their zero walls and interpolates bilinearly
 // (c = 1: the rows are written directly).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int LC>
 __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* __restrict__ md,
                                                              const int* __restrict__ grp, int ng,
                                                              const T* __restrict__ wt,
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* _
       }
     }
   }
-  const cplx<T>* Z = fft_lds<T>(buf, buf + P * LP, nseq, L, d.nst_r, d.stw_r, tw);
+  const cplx<T>* Z = fft_run<T, LC>(buf, buf + P * LP, nseq, L, d.nst_r, d.stw_r, tw);
 
   const T wbc1 = T(1.0 - d.delta), wbc2 = T(d.delta);
   T* out = dst + d.field_off;
@@ -394,42 +394,66 @@ __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* _
 }
 
 // ---------------------------------------------------------------------------
+// Launch the instantiation for the group's transform length (g.L: a length
+// with a compile-time transform, or 0 for the runtime engine).
+#define CGP_BY_LENGTH(LEN, CALL) \
+  switch (LEN) {                 \
+    case 256: CALL(256); break;  \
+    case 512: CALL(512); break;  \
+    case 1024: CALL(1024); break; \
+    case 2048: CALL(2048); break; \
+    default: CALL(0);            \
+  }
+
 template <typename T>
 hipError_t Launch<T>::restrict_rowdst(const MemberDesc* md, const Group& g, const T* src, T* wt,
                                       const cplx<T>* tw, hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict_rowdst<T>, dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members,
-                     g.count, src, wt, tw);
+#define CALL(LC)                                                                             \
+  hipLaunchKernelGGL((k_restrict_rowdst<T, LC>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
+                     g.members, g.count, src, wt, tw)
+  CGP_BY_LENGTH(g.L, CALL)
+#undef CALL
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t Launch<T>::col_solve(const MemberDesc* md, const Group& g, T* wt, const cplx<T>* tw,
                                 const double* lam, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_solve<T>, dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members,
-                     g.count, wt, tw, lam);
+#define CALL(LC)                                                                                \
+  hipLaunchKernelGGL((k_col_solve<T, LC>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members, \
+                     g.count, wt, tw, lam)
+  CGP_BY_LENGTH(g.L, CALL)
+#undef CALL
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t Launch<T>::rowdst_prolong(const MemberDesc* md, const Group& g, const T* wt, T* dst,
                                      int accumulate, const cplx<T>* tw, hipStream_t s) {
-  hipLaunchKernelGGL(k_rowdst_prolong<T>, dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members,
-                     g.count, wt, dst, accumulate, tw);
+#define CALL(LC)                                                                             \
+  hipLaunchKernelGGL((k_rowdst_prolong<T, LC>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
+                     g.members, g.count, wt, dst, accumulate, tw)
+  CGP_BY_LENGTH(g.L, CALL)
+#undef CALL
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t Launch<T>::prepare(size_t bytes) {
   const int b = (int)bytes;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_restrict_rowdst<T>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_col_solve<T>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rowdst_prolong<T>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  return e;
+  const void* fns[] = {
+#define FNS(LC)                                                      \
+  reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC>),          \
+      reinterpret_cast<const void*>(&k_col_solve<T, LC>),            \
+      reinterpret_cast<const void*>(&k_rowdst_prolong<T, LC>)
+      FNS(0), FNS(256), FNS(512), FNS(1024), FNS(2048)
+#undef FNS
+  };
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template struct Launch<float>;
