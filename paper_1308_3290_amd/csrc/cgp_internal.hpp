@@ -19,6 +19,7 @@ enum Pass { PASS_A = 0, PASS_B = 1, PASS_C = 2, PASS_D = 3, PASS_CD = 4, NUM_PAS
 // factors 1, 2 and 4; a block owns fused_tj(c) coarse rows and writes at most
 // fused_nr(c) fine rows.
 constexpr int kFusedMaxNx = 512;
+constexpr int kFusedThreads = 512;  // threads per block of the fused pass
 __host__ __device__ constexpr int fused_tj(int c) { return c >= 4 ? 1 : 2; }
 __host__ __device__ constexpr int fused_nr(int c) { return c * fused_tj(c) + 1; }
 
@@ -33,8 +34,8 @@ struct MemberDesc {
   int nst_r, nst_c;     // radix stage counts
   int stw_r[kMaxStages], stw_c[kMaxStages];  // stage words: radix, log2 span, table offset
   int ntw_r, ntw_c;                          // twiddle table sizes (complex values)
-  int pa;               // pass A: sequence pairs per block
-  int pb;               // pass B: sequence pairs per block
+  int pa;               // pass A: sequences per block (1)
+  int pb;               // pass B: sequences per block (1)
   int tj;               // pass C: coarse rows owned per block
   int pc;               // pass C: sequence pairs per block (derived from tj)
   int blk0[NUM_PASSES]; // first block of this member in its launch of each pass
@@ -47,6 +48,8 @@ struct MemberDesc {
   double dx, dy;
   double inv_re, inv_ro, f1, f2, drag, dt;
   double delta;         // barotropic weight f2/(f1+f2) (0.5 if f1 = f2 = 0)
+  // stencil coefficients: 1/(12 dx dy), inv_ro/(3 dx), 1/dx^2, 1/dy^2
+  double cj, cb, idx2, idy2;
 };
 
 template <typename T>
@@ -85,6 +88,7 @@ struct Group {
   const int* members;  // device array of the group's member indices
   int nblk, threads;  // threads = kThreads
   size_t lds;
+  int nlayers;         // layers of every member of the handle
 };
 
 // Launch wrappers implemented in the kernel translation units.

@@ -91,8 +91,8 @@ __device__ __forceinline__ void small_dft(cplx<T>* v) {
 
 // One stage of radix R (span Ns = 2^lns) over nseq sequences of length L,
 // from `in` to `out` (padded layout); `tw` is this stage's twiddle table
-// ((R-1) x Ns).  Thread t owns butterflies b = t + kThreads q, q < MAXB.
-template <typename T, int R, int MAXB>
+// ((R-1) x Ns).  Thread t of NT owns butterflies b = t + NT q, q < MAXB.
+template <typename T, int R, int MAXB, int NT>
 __device__ __forceinline__ void fft_stage(const cplx<T>* in, cplx<T>* out, int nseq, int L,
                                           int lns, const cplx<T>* tw) {
   const int LR = L / R;
@@ -101,7 +101,7 @@ __device__ __forceinline__ void fft_stage(const cplx<T>* in, cplx<T>* out, int n
   const int LP = lpad(L);
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
-    const int b = threadIdx.x + kThreads * q;
+    const int b = threadIdx.x + NT * q;
     if (b < nb) {
       const int p = b >= LR ? 1 : 0;
       const int j = b - p * LR;
@@ -168,9 +168,9 @@ __host__ __device__ constexpr StagePlan stage_plan(int L) {
 
 // Forward DFT of nseq (1 or 2) sequences of length L held back to back in
 // buffer a (LDS, padded layout); b is scratch of the same size.  Returns the
-// buffer holding the result.  Every thread of the block must call it; it
-// begins and ends with a barrier.
-template <typename T>
+// buffer holding the result.  Every thread of the block (NT threads) must
+// call it; it begins and ends with a barrier.
+template <typename T, int NT = kThreads>
 __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nseq, int L, int nst,
                                             const int* words, const cplx<T>* tw) {
   int w[kMaxStages];
@@ -182,10 +182,10 @@ __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nseq, in
     const int word = w[s];
     const int R = word & 15, lns = (word >> 4) & 31;
     const cplx<T>* t = tw + (word >> 9);
-    if (R == 8) fft_stage<T, 8, 1>(a, b, nseq, L, lns, t);
-    else if (R == 4) fft_stage<T, 4, 2>(a, b, nseq, L, lns, t);
-    else if (R == 2) fft_stage<T, 2, 4>(a, b, nseq, L, lns, t);
-    else fft_stage<T, 3, 3>(a, b, nseq, L, lns, t);
+    if (R == 8) fft_stage<T, 8, 1, NT>(a, b, nseq, L, lns, t);
+    else if (R == 4) fft_stage<T, 4, 2, NT>(a, b, nseq, L, lns, t);
+    else if (R == 2) fft_stage<T, 2, 4, NT>(a, b, nseq, L, lns, t);
+    else fft_stage<T, 3, 3, NT>(a, b, nseq, L, lns, t);
     cplx<T>* x = a;
     a = b;
     b = x;
@@ -201,7 +201,7 @@ __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nseq, in
 // output o + r Ns is pad(o) + r lpad(Ns) (Ns a multiple of 8) or pad(o) + r Ns
 // (Ns R divides 8).
 // ---------------------------------------------------------------------------
-template <typename T, int L, int S>
+template <typename T, int L, int S, int NT>
 __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int nseq,
                                          const cplx<T>* tw) {
   constexpr StagePlan P = stage_plan(L);
@@ -210,11 +210,11 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
   static_assert(LR % 8 == 0, "read offsets need L/R to be a multiple of 8");
   static_assert(NS % 8 == 0 || 8 % (NS * R) == 0, "write offsets need Ns % 8 == 0 or Ns R | 8");
   constexpr int WS = NS % 8 == 0 ? lpad(NS) : NS;
-  constexpr int Q = (2 * LR + kThreads - 1) / kThreads;  // nseq <= 2
+  constexpr int Q = (2 * LR + NT - 1) / NT;  // nseq <= 2
   const int nb = nseq * LR;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int b = threadIdx.x + kThreads * q;
+    const int b = threadIdx.x + NT * q;
     if (b < nb) {
       const int p = b / LR;
       const int j = b - p * LR;
@@ -238,29 +238,36 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
   __syncthreads();
 }
 
-template <typename T, int L, int S>
+template <typename T, int L, int S, int NT>
 __device__ __forceinline__ cplx<T>* ct_stages(cplx<T>* a, cplx<T>* b, int nseq,
                                               const cplx<T>* tw) {
   constexpr StagePlan P = stage_plan(L);
   if constexpr (S == P.n) {
     return a;
   } else {
-    ct_stage<T, L, S>(a, b, nseq, tw);
-    return ct_stages<T, L, S + 1>(b, a, nseq, tw);
+    ct_stage<T, L, S, NT>(a, b, nseq, tw);
+    return ct_stages<T, L, S + 1, NT>(b, a, nseq, tw);
   }
 }
 
 // Forward DFT with the contract of fft_lds; LC = 0 selects the runtime
 // engine (any supported length), otherwise L must equal LC.
-template <typename T, int LC>
+template <typename T, int LC, int NT = kThreads>
 __device__ __forceinline__ cplx<T>* fft_run(cplx<T>* a, cplx<T>* b, int nseq, int L, int nst,
                                             const int* words, const cplx<T>* tw) {
   if constexpr (LC == 0) {
-    return fft_lds<T>(a, b, nseq, L, nst, words, tw);
+    return fft_lds<T, NT>(a, b, nseq, L, nst, words, tw);
   } else {
     __syncthreads();
-    return ct_stages<T, LC, 0>(a, b, nseq, tw);
+    return ct_stages<T, LC, 0, NT>(a, b, nseq, tw);
   }
+}
+
+// Twiddle values a thread of NT prefetches for a transform of length LC (0:
+// any supported length, L <= 2048).
+template <int LC, int NT>
+__host__ __device__ constexpr int tw_per_thread() {
+  return ((LC ? stage_plan(LC).ntw : 2047) + NT - 1) / NT;
 }
 
 // Lengths with a compile-time transform (0: none).

@@ -26,17 +26,17 @@ namespace cgp {
 // C: coarsening factor; TJ: coarse rows owned per block; LC: transform
 // length with a compile-time transform, or 0.
 template <typename T, int C, int TJ, int LC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void
-k_prolong_stencil(
+__global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
     const T* __restrict__ wt, const cplx<T>* __restrict__ twg, const T* __restrict__ ws,
     const T* __restrict__ forcing, const T* __restrict__ wn, T* __restrict__ out, double a_,
     double b_) {
+  constexpr int NT = kFusedThreads;
   constexpr int NR = C * TJ + 1;  // the most fine rows a block writes (+1: top wall row)
-  constexpr int kTwPer = 4;   // twiddles per thread: (R-1) Ns summed over stages < L <= 1024
-  constexpr int kSpPer = 2;   // spectral columns per thread: Mx - 1 <= 511
-  constexpr int kCol = 2;     // interior fine columns per thread: nx - 1 <= 511
-  constexpr int kWPer = ((NR + 2) * (kFusedMaxNx + 1) + kThreads - 1) / kThreads;
+  // twiddles per thread: (R-1) Ns summed over the stages, < L <= 1024
+  constexpr int kTwPer = ((LC ? stage_plan(LC).ntw : 1023) + NT - 1) / NT;
+  static_assert(kFusedMaxNx - 1 <= NT, "one spectral column and one fine column per thread");
+  constexpr int kWPer = ((NR + 2) * (kFusedMaxNx + 1) + NT - 1) / NT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int t = threadIdx.x;
   const int bid = xcd_contiguous(blockIdx.x, nblk);
@@ -72,22 +72,21 @@ k_prolong_stencil(
   T twx[kTwPer], twy[kTwPer];
 #pragma unroll
   for (int q = 0; q < kTwPer; ++q) {
-    const int m = t + kThreads * q;
+    const int m = t + NT * q;
     const cplx<T> z = twg[d.twr_off + (m < ntw ? m : 0)];
     twx[q] = z.x;
     twy[q] = z.y;
   }
   const T* w = wt + d.wt_off;
-  T sv[kSpPer][4];
-#pragma unroll
-  for (int q = 0; q < kSpPer; ++q) {
-    const int k = 1 + t + kThreads * q;
+  T sv[4];
+  {
+    const int k = 1 + t;
     const size_t cbase = (size_t)(k - 1) * (My - 1) + (ilo - 1);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const bool in = k < Mx && r < nint;
       const T v = w[in ? cbase + r : 0];
-      sv[q][r] = in ? v : T(0);
+      sv[r] = in ? v : T(0);
     }
   }
   const T* W = ws + d.field_off;
@@ -99,56 +98,50 @@ k_prolong_stencil(
   T wv[kWPer];
 #pragma unroll
   for (int q = 0; q < kWPer; ++q) {
-    const int e = t + kThreads * q;
+    const int e = t + NT * q;
     const long long g = g0 + e;
     const bool in = e < nW && g >= 0 && g < gend;
     const T v = W[in ? g : 0];
     wv[q] = in ? v : T(0);
   }
-  // forcing and omega_n at the thread's columns x = 1 + t + 256 k, rows R0 + r
-  T fv[kCol][NR], nv[kCol][NR];
+  // forcing and omega_n at the thread's column x = 1 + t, rows R0 + r
+  const int x = 1 + t;
+  T fv[NR], nv[NR];
 #pragma unroll
-  for (int k = 0; k < kCol; ++k) {
-    const int x = 1 + t + kThreads * k;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int rr = R0 + r;
-      const bool in = x < nx && r < nfr && rr >= 1 && rr < ny;
-      const size_t o = in ? (size_t)rr * pitch + x : 0;
-      const T f = FF[o], n = WN[o];
-      fv[k][r] = in ? f : T(0);
-      nv[k][r] = in ? n : T(0);
-    }
+  for (int r = 0; r < NR; ++r) {
+    const int rr = R0 + r;
+    const bool in = x < nx && r < nfr && rr >= 1 && rr < ny;
+    const size_t o = in ? (size_t)rr * pitch + x : 0;
+    const T f = FF[o], n = WN[o];
+    fv[r] = in ? f : T(0);
+    nv[r] = in ? n : T(0);
   }
 
   // ---- twiddles and the two packed sequences (odd extension) into LDS
 #pragma unroll
   for (int q = 0; q < kTwPer; ++q) {
-    const int m = t + kThreads * q;
+    const int m = t + NT * q;
     if (m < ntw) tw[m] = {twx[q], twy[q]};
   }
   if (t < nseq) {
     buf[t * LP + pad(0)] = {T(0), T(0)};
     buf[t * LP + pad(Mx)] = {T(0), T(0)};
   }
+  if (1 + t < Mx) {
+    const int k = 1 + t;
 #pragma unroll
-  for (int q = 0; q < kSpPer; ++q) {
-    const int k = 1 + t + kThreads * q;
-    if (k < Mx) {
-#pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        if (p < nseq) {
-          const cplx<T> z = {sv[q][2 * p], sv[q][2 * p + 1]};
-          buf[p * LP + pad(k)] = z;
-          buf[p * LP + pad(2 * Mx - k)] = {-z.x, -z.y};
-        }
+    for (int p = 0; p < 2; ++p) {
+      if (p < nseq) {
+        const cplx<T> z = {sv[2 * p], sv[2 * p + 1]};
+        buf[p * LP + pad(k)] = z;
+        buf[p * LP + pad(2 * Mx - k)] = {-z.x, -z.y};
       }
     }
   }
-  const cplx<T>* Z = fft_run<T, LC>(buf, buf + 2 * LP, nseq, L, d.nst_r, d.stw_r, tw);
+  const cplx<T>* Z = fft_run<T, LC, NT>(buf, buf + 2 * LP, nseq, L, d.nst_r, d.stw_r, tw);
 
   // ---- coarse psi rows J = j0-1 .. j0+TJ (zero walls) into psc
-  for (int i = t; i <= Mx; i += kThreads) {
+  for (int i = t; i <= Mx; i += NT) {
 #pragma unroll
     for (int r = 0; r < TJ + 2; ++r) {
       const int J = j0 - 1 + r;
@@ -163,7 +156,7 @@ k_prolong_stencil(
   }
 #pragma unroll
   for (int q = 0; q < kWPer; ++q) {
-    const int e = t + kThreads * q;
+    const int e = t + NT * q;
     if (e < nW) wtile[e] = wv[q];
   }
   __syncthreads();
@@ -174,15 +167,11 @@ k_prolong_stencil(
 
   // ---- stencil + RK3 on fine rows R0 .. R1-1 (tile row q = fine row R0-1+q)
   const T dt = T(d.dt), a = T(a_), b = T(b_);
-  const T cj = T(1.0 / (12.0 * d.dx * d.dy));
-  const T cb = T(d.inv_ro / (3.0 * d.dx));
-  const T idx2 = T(1.0 / (d.dx * d.dx)), idy2 = T(1.0 / (d.dy * d.dy));
+  const T cj = T(d.cj), cb = T(d.cb);
+  const T idx2 = T(d.idx2), idy2 = T(d.idy2);
   const T nu = T(d.inv_re);
   constexpr T kInvC2 = T(1) / T(C * C);
-#pragma unroll
-  for (int k = 0; k < kCol; ++k) {
-    const int x = 1 + t + kThreads * k;
-    if (x >= nx) continue;
+  if (x < nx) {
     // coarse columns I0 .. I0+2 (clamped to the wall column Mx) cover the
     // fine columns x-1 .. x+1 for C >= 2; for C = 1 they are those columns
     const int I0 = (x - 1) / C;
@@ -253,9 +242,9 @@ k_prolong_stencil(
         w.NE = wn2; w.NW = wn0;
         w.SE = ws2; w.SW = ws0;
         const T G =
-            -cj * arakawa12(p, w) - cb * beta3(p) + nu * lap5(w, idx2, idy2) + fv[k][q - 1];
+            -cj * arakawa12(p, w) - cb * beta3(p) + nu * lap5(w, idx2, idy2) + fv[q - 1];
         v = b * (w.C + dt * G);
-        if (a_ != 0.0) v += a * nv[k][q - 1];
+        if (a_ != 0.0) v += a * nv[q - 1];
       }
       O[(size_t)rr * pitch + x] = v;
       ws0 = wc0; ws1 = wc1; ws2 = wc2;
@@ -270,8 +259,8 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
                                       const cplx<T>* tw, const T* ws, const T* forcing,
                                       const T* wn, T* out, double a, double b, hipStream_t s) {
 #define LAUNCH(C, TJ, LC)                                                                     \
-  hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC>), dim3(g.nblk), dim3(kThreads), g.lds, s, \
-                     md, g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b)
+  hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC>), dim3(g.nblk), dim3(kFusedThreads), g.lds, \
+                     s, md, g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b)
 #define BY_LEN(C, TJ)                         \
   switch (g.L & 0xffff) {                     \
     case 256: LAUNCH(C, TJ, 256); break;      \

@@ -202,27 +202,33 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     d.drag = nl == 2 ? c.drag : 0.0;
     d.dt = c.dt;
     d.delta = (d.f1 + d.f2 > 0) ? d.f2 / (d.f1 + d.f2) : 0.5;
+    d.cj = 1.0 / (12.0 * d.dx * d.dy);
+    d.cb = d.inv_ro / (3.0 * d.dx);
+    d.idx2 = 1.0 / (d.dx * d.dx);
+    d.idy2 = 1.0 / (d.dy * d.dy);
     d.blk0[PASS_D] = plan->nblk_d;
     d.nblk[PASS_D] = ((d.nx + kTileX) / kTileX) * ((d.ny + kTileY) / kTileY);
     plan->nblk_d += d.nblk[PASS_D];
   }
   // A block transforms at most two sequences and at most 2048 complex values.
   auto pairs = [](int L) { return L <= 512 ? 2 : 1; };
-  // pass A: pairs of coarse rows (one layer) or one coarse row's two modes
+  // pass A: one complex sequence per block: a pair of coarse rows (one
+  // layer) or one coarse row's two modes
   build_groups(plan->md, PASS_A, [](const MemberDesc& d) { return fft_special(d.Lr); },
                [&](MemberDesc& d, HostGroup&) {
-                 d.pa = pairs(d.Lr);
-                 const int rows = nl == 1 ? 2 * d.pa : d.pa;
-                 const size_t lds = ((size_t)2 * d.pa * lpad(d.Lr) + d.ntw_r) * cs;
+                 d.pa = 1;
+                 const int rows = nl == 1 ? 2 : 1;
+                 const size_t lds = ((size_t)2 * lpad(d.Lr) + d.ntw_r) * cs;
                  return std::make_pair((d.My - 1 + rows - 1) / rows, lds);
                },
                plan->groups[0]);
-  // pass B: pairs of spectral columns (one layer) or one column's two modes
+  // pass B: one complex sequence per block: a pair of spectral columns (one
+  // layer) or one column's two modes
   build_groups(plan->md, PASS_B, [](const MemberDesc& d) { return fft_special(d.Lc); },
                [&](MemberDesc& d, HostGroup&) {
-                 d.pb = pairs(d.Lc);
-                 const int cols = nl == 1 ? 2 * d.pb : d.pb;
-                 const size_t lds = ((size_t)2 * d.pb * lpad(d.Lc) + d.ntw_c) * cs;
+                 d.pb = 1;
+                 const int cols = nl == 1 ? 2 : 1;
+                 const size_t lds = ((size_t)2 * lpad(d.Lc) + d.ntw_c) * cs;
                  return std::make_pair((d.Mx - 1 + cols - 1) / cols, lds);
                },
                plan->groups[1]);
@@ -298,8 +304,8 @@ struct cgp_handle {
   const MemberDesc* d_md() const { return at<MemberDesc>(plan.lay.desc); }
   Group group(int pass, int i) const {
     const HostGroup& g = plan.groups[pass][i];
-    return Group{g.L, (int)g.members.size(), at<int>(plan.lay.order) + g.order_off, g.nblk,
-                 kThreads, g.lds};
+    return Group{g.L,   (int)g.members.size(), at<int>(plan.lay.order) + g.order_off, g.nblk,
+                 kThreads, g.lds, plan.nlayers};
   }
   int ngroups(int pass) const { return (int)plan.groups[pass].size(); }
 };

@@ -23,25 +23,6 @@ namespace cgp {
 // Full weighting applied `level` times equals one tent-weighted average with
 // 1-D weights (c - |d|)/c^2, |d| < c = 2^level (the l = 2 case is the
 // [1 2 3 4 3 2 1]/16 stencil); it reads fine interior nodes only.
-template <typename T, int C>
-__device__ __forceinline__ T restrict_fixed(const T* __restrict__ f, int pitch, int I, int J) {
-  if constexpr (C == 1) {
-    return f[(size_t)J * pitch + I];
-  } else {
-    const T* base = f + (size_t)(C * J) * pitch + C * I;
-    T acc = T(0);
-#pragma unroll
-    for (int dy = -(C - 1); dy <= C - 1; ++dy) {
-      const T* row = base + (ptrdiff_t)dy * pitch;
-      T racc = T(0);
-#pragma unroll
-      for (int dx = -(C - 1); dx <= C - 1; ++dx) racc += T(C - (dx < 0 ? -dx : dx)) * row[dx];
-      acc += T(C - (dy < 0 ? -dy : dy)) * racc;
-    }
-    return acc * (T(1) / T(C * C * C * C));
-  }
-}
-
 template <typename T>
 __device__ __forceinline__ T restrict_generic(const T* __restrict__ f, int pitch, int c, int I,
                                               int J) {
@@ -58,99 +39,143 @@ __device__ __forceinline__ T restrict_generic(const T* __restrict__ f, int pitch
 }
 
 // ---------------------------------------------------------------------------
-// Pass A.  A block restricts `rows` (<= 4) consecutive coarse rows starting at
-// j0 and transforms them along x: one layer, pairs of rows share one complex
-// FFT; two layers, the barotropic and baroclinic combinations of a row do.
+// Pass A.  A block restricts RB consecutive coarse rows starting at j0 (one
+// layer: RB = 2, packed as the real and imaginary parts of one complex
+// sequence; two layers: RB = 1, its barotropic and baroclinic combinations)
+// and transforms them along x.  The twiddles and every fine value of the
+// block are loaded before any is used: the loads are unconditional (a lane
+// without a column reads a valid neighbour), so that they are in flight
+// together.
 // ---------------------------------------------------------------------------
-template <typename T, int C>
-__device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __restrict__ f,
-                                               cplx<T>* buf, int j0, int nr, int LP) {
-  const int Mx = d.Mx, c = d.c, nl = d.nlayers;
-  const int pitch = d.nx + 1;
-  const size_t plane = (size_t)(d.ny + 1) * pitch;
-  const T wbt1 = T(d.delta), wbt2 = T(1.0 - d.delta);
-  for (int i = 1 + threadIdx.x; i < Mx; i += kThreads) {
-    T v[4], u[4];
+// Restriction of coarse rows j0 .. j0+RB-1 at coarse column i, separably: the
+// x-weighted sums of the fine rows C j0-(C-1) .. C (j0+RB-1)+(C-1) first, then
+// the y weights.  Rows of absent coarse rows are clamped to the array.
+template <typename T, int C, int RB>
+__device__ __forceinline__ void restrict_rows(const T* __restrict__ f, int pitch, int ny, int i,
+                                              int j0, T* v) {
+  constexpr int NF = C * (RB + 1) - 1;
+  const int fr0 = C * j0 - (C - 1);
+  T racc[NF];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      v[r] = T(0);
-      u[r] = T(0);
-      if (r < nr) {
-        if constexpr (C > 0) {
-          v[r] = restrict_fixed<T, C>(f, pitch, i, j0 + r);
-          if (nl == 2) u[r] = restrict_fixed<T, C>(f + plane, pitch, i, j0 + r);
-        } else {
-          v[r] = restrict_generic<T>(f, pitch, c, i, j0 + r);
-          if (nl == 2) u[r] = restrict_generic<T>(f + plane, pitch, c, i, j0 + r);
-        }
+  for (int q = 0; q < NF; ++q) {
+    const T* row = f + (size_t)min(fr0 + q, ny) * pitch + C * i;
+    T acc = T(0);
+#pragma unroll
+    for (int dx = -(C - 1); dx <= C - 1; ++dx) acc += T(C - (dx < 0 ? -dx : dx)) * row[dx];
+    racc[q] = acc;
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    T acc = T(0);
+#pragma unroll
+    for (int dy = -(C - 1); dy <= C - 1; ++dy)
+      acc += T(C - (dy < 0 ? -dy : dy)) * racc[C * r + dy + (C - 1)];
+    v[r] = acc * (T(1) / T(C * C * C * C));
+  }
+}
+
+template <typename T, int NL>
+__device__ __forceinline__ void put_rows(cplx<T>* buf, int Mx, int i, const T* v, const T* u,
+                                         T wbt1, T wbt2) {
+  cplx<T> z;
+  if constexpr (NL == 1) z = {v[0], v[1]};
+  else z = {wbt1 * v[0] + wbt2 * u[0], v[0] - u[0]};  // (barotropic, baroclinic)
+  buf[pad(i)] = z;
+  buf[pad(2 * Mx - i)] = {-z.x, -z.y};
+}
+
+// Coarse columns i = 1 + t + kThreads q, q < kColIter, of rows j0 .. j0+RB-1.
+constexpr int kColIter = 4;  // Mx - 1 <= 1023
+
+template <typename T, int C, int NL>
+__device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __restrict__ f,
+                                               cplx<T>* buf, int j0) {
+  constexpr int RB = NL == 1 ? 2 : 1;
+  const int Mx = d.Mx, pitch = d.nx + 1, ny = d.ny;
+  const size_t plane = (size_t)(ny + 1) * pitch;
+  const T wbt1 = T(d.delta), wbt2 = T(1.0 - d.delta);
+  if constexpr (C > 0) {
+    T v[kColIter][RB], u[kColIter][RB];
+#pragma unroll
+    for (int q = 0; q < kColIter; ++q) {
+      const int i = min(1 + (int)threadIdx.x + kThreads * q, Mx - 1);
+      if (q * kThreads < Mx - 1) {
+        restrict_rows<T, C, RB>(f, pitch, ny, i, j0, v[q]);
+        if constexpr (NL == 2) restrict_rows<T, C, RB>(f + plane, pitch, ny, i, j0, u[q]);
       }
     }
-    if (nl == 1) {
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        if (2 * p < nr) {
-          const cplx<T> z = {v[2 * p], v[2 * p + 1]};
-          buf[p * LP + pad(i)] = z;
-          buf[p * LP + pad(2 * Mx - i)] = {-z.x, -z.y};
-        }
-      }
-    } else {
+    for (int q = 0; q < kColIter; ++q) {
+      const int i = 1 + threadIdx.x + kThreads * q;
+      if (i < Mx) put_rows<T, NL>(buf, Mx, i, v[q], u[q], wbt1, wbt2);
+    }
+  } else {
+    const int c = d.c;
+    for (int i = 1 + threadIdx.x; i < Mx; i += kThreads) {
+      T v[RB], u[RB];
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        if (p < nr) {
-          const cplx<T> z = {wbt1 * v[p] + wbt2 * u[p], v[p] - u[p]};  // (barotropic, baroclinic)
-          buf[p * LP + pad(i)] = z;
-          buf[p * LP + pad(2 * Mx - i)] = {-z.x, -z.y};
-        }
+      for (int r = 0; r < RB; ++r) {
+        const int j = min(j0 + r, d.My - 1);
+        v[r] = restrict_generic<T>(f, pitch, c, i, j);
+        u[r] = NL == 2 ? restrict_generic<T>(f + plane, pitch, c, i, j) : T(0);
       }
+      put_rows<T, NL>(buf, Mx, i, v, u, wbt1, wbt2);
     }
   }
 }
 
-template <typename T, int LC>
+template <typename T, int LC, int NL>
 __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng,
     const T* __restrict__ src, T* __restrict__ wt, const cplx<T>* __restrict__ twg) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int RB = NL == 1 ? 2 : 1;
+  constexpr int kTw = tw_per_thread<LC, kThreads>();
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_A, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_A];
-  const int Mx = d.Mx, My = d.My, L = d.Lr, P = d.pa, nl = d.nlayers;
+  const int Mx = d.Mx, My = d.My, L = d.Lr, ntw = d.ntw_r;
   const int LP = lpad(L);
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = buf + 2 * P * LP;
-  const int rows_blk = (nl == 1) ? 2 * P : P;  // 1, 2 or 4
-  const int j0 = 1 + lb * rows_blk;
-  const int nr = min(rows_blk, My - j0);
-  const int nseq = (nl == 1) ? (nr + 1) / 2 : nr;
+  cplx<T>* tw = buf + 2 * LP;
+  const int j0 = 1 + lb * RB;
+  const int nr = min(RB, My - j0);
 
-  load_twiddles(tw, twg + d.twr_off, d.ntw_r);
-  if (threadIdx.x < nseq) {
-    buf[threadIdx.x * LP + pad(0)] = {T(0), T(0)};
-    buf[threadIdx.x * LP + pad(Mx)] = {T(0), T(0)};
+  T twx[kTw], twy[kTw];
+#pragma unroll
+  for (int q = 0; q < kTw; ++q) {
+    const int m = threadIdx.x + kThreads * q;
+    const cplx<T> z = twg[d.twr_off + (m < ntw ? m : 0)];
+    twx[q] = z.x;
+    twy[q] = z.y;
+  }
+  if (threadIdx.x == 0) {
+    buf[pad(0)] = {T(0), T(0)};
+    buf[pad(Mx)] = {T(0), T(0)};
   }
   const T* f = src + d.field_off;
   switch (d.c) {
-    case 1: restrict_block<T, 1>(d, f, buf, j0, nr, LP); break;
-    case 2: restrict_block<T, 2>(d, f, buf, j0, nr, LP); break;
-    case 4: restrict_block<T, 4>(d, f, buf, j0, nr, LP); break;
-    default: restrict_block<T, 0>(d, f, buf, j0, nr, LP);
+    case 1: restrict_block<T, 1, NL>(d, f, buf, j0); break;
+    case 2: restrict_block<T, 2, NL>(d, f, buf, j0); break;
+    case 4: restrict_block<T, 4, NL>(d, f, buf, j0); break;
+    default: restrict_block<T, 0, NL>(d, f, buf, j0);
   }
-  const cplx<T>* Z = fft_run<T, LC>(buf, buf + P * LP, nseq, L, d.nst_r, d.stw_r, tw);
+#pragma unroll
+  for (int q = 0; q < kTw; ++q) {
+    const int m = threadIdx.x + kThreads * q;
+    if (m < ntw) tw[m] = {twx[q], twy[q]};
+  }
+  const cplx<T>* Z = fft_run<T, LC>(buf, buf + LP, 1, L, d.nst_r, d.stw_r, tw);
 
+  // spectra of the block's rows, k-major (two consecutive values per k)
   T* w = wt + d.wt_off;
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
-  const int sh = rows_blk == 4 ? 2 : (rows_blk == 2 ? 1 : 0);
-  const int nvals = (Mx - 1) << sh;
-  for (int q = threadIdx.x; q < nvals; q += kThreads) {
-    const int k = 1 + (q >> sh);
-    const int r = q & (rows_blk - 1);
-    if (r >= nr) continue;
-    const size_t o = (size_t)(k - 1) * (My - 1) + (j0 + r - 1);
-    if (nl == 1) {
-      const cplx<T> zk = Z[(r >> 1) * LP + pad(k)];
-      w[o] = (r & 1) ? T(0.5) * zk.x : T(-0.5) * zk.y;
+  for (int k = 1 + threadIdx.x; k < Mx; k += kThreads) {
+    const cplx<T> zk = Z[pad(k)];
+    const size_t o = (size_t)(k - 1) * (My - 1) + (j0 - 1);
+    if constexpr (NL == 1) {
+      w[o] = T(-0.5) * zk.y;
+      if (nr > 1) w[o + 1] = T(0.5) * zk.x;
     } else {
-      const cplx<T> zk = Z[r * LP + pad(k)];
       w[o] = T(-0.5) * zk.y;
       w[mplane + o] = T(0.5) * zk.x;
     }
@@ -158,10 +183,10 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
 }
 
 // ---------------------------------------------------------------------------
-// Pass B.  A block transforms `pb` (<= 2) pairs of coarse spectral columns
-// (one layer: columns k, k+1; two layers: the barotropic and baroclinic
-// column k) along y, multiplies by (2/Mx)(2/My)/lambda_kl (baroclinic:
-// 1/(lambda_kl - F1 - F2)), and transforms back.
+// Pass B.  A block transforms one pair of coarse spectral columns (one layer:
+// columns k, k+1; two layers: the barotropic and baroclinic column k) along
+// y, multiplies by (2/Mx)(2/My)/lambda_kl (baroclinic: 1/(lambda_kl - F1 -
+// F2)), and transforms back.  Loads are batched as in pass A.
 // ---------------------------------------------------------------------------
 template <typename T, int LC>
 __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __restrict__ md,
@@ -170,14 +195,16 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
                                                         const cplx<T>* __restrict__ twg,
                                                         const double* __restrict__ lam) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int kTw = tw_per_thread<LC, kThreads>();
+  constexpr int kRowIter = 4;  // My - 1 <= 1023
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_B, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_B];
-  const int Mx = d.Mx, My = d.My, L = d.Lc, P = d.pb, nl = d.nlayers;
+  const int Mx = d.Mx, My = d.My, L = d.Lc, nl = d.nlayers, ntw = d.ntw_c;
   const int ny1 = My - 1;
   const int LP = lpad(L);
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* buf2 = buf + P * LP;
-  cplx<T>* tw = buf2 + P * LP;
+  cplx<T>* buf2 = buf + LP;
+  cplx<T>* tw = buf2 + LP;
   T* w = wt + d.wt_off;
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
   const double* lamx = lam + d.lam_off;
@@ -185,81 +212,77 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
   const double scale = 4.0 / ((double)Mx * (double)My);
   const double shift = nl == 2 ? d.f1 + d.f2 : 0.0;
 
-  // columns (1-based, 0 = absent) of the two sequences of each pair
-  int ka[2], kb[2];
-  int nseq = 0;
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    if (nl == 1) {
-      ka[p] = 1 + 2 * (lb * P + p);
-      kb[p] = ka[p] + 1;
-      if (ka[p] > Mx - 1) ka[p] = 0;
-      if (kb[p] > Mx - 1) kb[p] = 0;
-    } else {
-      ka[p] = 1 + lb * P + p;
-      if (ka[p] > Mx - 1) ka[p] = 0;
-      kb[p] = ka[p];
-    }
-    if (p >= P) ka[p] = kb[p] = 0;
-    if (ka[p]) nseq = p + 1;
-  }
-  T* cola[2];
-  T* colb[2];
-  double lxa[2], lxb[2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    cola[p] = w + (size_t)(ka[p] ? ka[p] - 1 : 0) * ny1;
-    colb[p] = w + ((nl == 2) ? mplane : 0) + (size_t)(kb[p] ? kb[p] - 1 : 0) * ny1;
-    lxa[p] = ka[p] ? lamx[ka[p] - 1] : -1.0;
-    lxb[p] = (kb[p] ? lamx[kb[p] - 1] : -1.0) - shift;
-  }
+  // the pair's columns (1-based); kb may be absent (one layer, Mx - 1 odd)
+  const int ka = nl == 1 ? 1 + 2 * lb : 1 + lb;
+  const int kb = nl == 1 ? ka + 1 : ka;
+  const bool has_b = kb <= Mx - 1;
+  T* cola = w + (size_t)(ka - 1) * ny1;
+  T* colb = w + (nl == 2 ? mplane : 0) + (size_t)((has_b ? kb : ka) - 1) * ny1;
+  const double lxa = lamx[ka - 1];
+  const double lxb = lamx[(has_b ? kb : ka) - 1] - shift;
 
-  load_twiddles(tw, twg + d.twc_off, d.ntw_c);
-  if (threadIdx.x < nseq) {
-    buf[threadIdx.x * LP + pad(0)] = {T(0), T(0)};
-    buf[threadIdx.x * LP + pad(My)] = {T(0), T(0)};
-  }
-  for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
+  T twx[kTw], twy[kTw];
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      if (p < nseq) {
-        const T a = ka[p] ? cola[p][l - 1] : T(0);
-        const T b = kb[p] ? colb[p][l - 1] : T(0);
-        buf[p * LP + pad(l)] = {a, b};
-        buf[p * LP + pad(2 * My - l)] = {-a, -b};
-      }
+  for (int q = 0; q < kTw; ++q) {
+    const int m = threadIdx.x + kThreads * q;
+    const cplx<T> z = twg[d.twc_off + (m < ntw ? m : 0)];
+    twx[q] = z.x;
+    twy[q] = z.y;
+  }
+  T va[kRowIter], vb[kRowIter];
+  double ly[kRowIter];
+#pragma unroll
+  for (int q = 0; q < kRowIter; ++q) {
+    const int l = min(1 + (int)threadIdx.x + kThreads * q, My - 1);
+    va[q] = cola[l - 1];
+    const T b = colb[l - 1];
+    vb[q] = has_b ? b : T(0);
+    ly[q] = lamy[l - 1];
+  }
+#pragma unroll
+  for (int q = 0; q < kTw; ++q) {
+    const int m = threadIdx.x + kThreads * q;
+    if (m < ntw) tw[m] = {twx[q], twy[q]};
+  }
+  if (threadIdx.x == 0) {
+    buf[pad(0)] = {T(0), T(0)};
+    buf[pad(My)] = {T(0), T(0)};
+  }
+#pragma unroll
+  for (int q = 0; q < kRowIter; ++q) {
+    const int l = 1 + threadIdx.x + kThreads * q;
+    if (l < My) {
+      buf[pad(l)] = {va[q], vb[q]};
+      buf[pad(2 * My - l)] = {-va[q], -vb[q]};
     }
   }
-  cplx<T>* Z = fft_run<T, LC>(buf, buf2, nseq, L, d.nst_c, d.stw_c, tw);
+  cplx<T>* Z = fft_run<T, LC>(buf, buf2, 1, L, d.nst_c, d.stw_c, tw);
   cplx<T>* Y = (Z == buf) ? buf2 : buf;
 
-  for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
-    const double ly = lamy[l - 1];
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      if (p < nseq) {
-        const cplx<T> z = Z[p * LP + pad(l)];
-        const T a = T(-0.5) * z.y * T(scale / (lxa[p] + ly));
-        const T b = T(0.5) * z.x * T(scale / (lxb[p] + ly));
-        Y[p * LP + pad(l)] = {a, b};
-        Y[p * LP + pad(2 * My - l)] = {-a, -b};
-      }
+  for (int q = 0; q < kRowIter; ++q) {
+    const int l = 1 + threadIdx.x + kThreads * q;
+    if (l < My) {
+      const cplx<T> z = Z[pad(l)];
+      const T a = T(-0.5) * z.y * T(scale / (lxa + ly[q]));
+      const T b = T(0.5) * z.x * T(scale / (lxb + ly[q]));
+      Y[pad(l)] = {a, b};
+      Y[pad(2 * My - l)] = {-a, -b};
     }
   }
-  if (threadIdx.x < nseq) {
-    Y[threadIdx.x * LP + pad(0)] = {T(0), T(0)};
-    Y[threadIdx.x * LP + pad(My)] = {T(0), T(0)};
+  if (threadIdx.x == 0) {
+    Y[pad(0)] = {T(0), T(0)};
+    Y[pad(My)] = {T(0), T(0)};
   }
-  const cplx<T>* R = fft_run<T, LC>(Y, Z, nseq, L, d.nst_c, d.stw_c, tw);
+  const cplx<T>* R = fft_run<T, LC>(Y, Z, 1, L, d.nst_c, d.stw_c, tw);
 
-  for (int l = 1 + threadIdx.x; l < My; l += kThreads) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      if (p < nseq) {
-        const cplx<T> z = R[p * LP + pad(l)];
-        if (ka[p]) cola[p][l - 1] = T(-0.5) * z.y;
-        if (kb[p]) colb[p][l - 1] = T(0.5) * z.x;
-      }
+  for (int q = 0; q < kRowIter; ++q) {
+    const int l = 1 + threadIdx.x + kThreads * q;
+    if (l < My) {
+      const cplx<T> z = R[pad(l)];
+      cola[l - 1] = T(-0.5) * z.y;
+      if (has_b) colb[l - 1] = T(0.5) * z.x;
     }
   }
 }
@@ -408,11 +431,19 @@ __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* _
 template <typename T>
 hipError_t Launch<T>::restrict_rowdst(const MemberDesc* md, const Group& g, const T* src, T* wt,
                                       const cplx<T>* tw, hipStream_t s) {
-#define CALL(LC)                                                                             \
-  hipLaunchKernelGGL((k_restrict_rowdst<T, LC>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
+#define CALL1(LC)                                                                               \
+  hipLaunchKernelGGL((k_restrict_rowdst<T, LC, 1>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
                      g.members, g.count, src, wt, tw)
-  CGP_BY_LENGTH(g.L, CALL)
-#undef CALL
+#define CALL2(LC)                                                                               \
+  hipLaunchKernelGGL((k_restrict_rowdst<T, LC, 2>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
+                     g.members, g.count, src, wt, tw)
+  if (g.nlayers == 1) {
+    CGP_BY_LENGTH(g.L, CALL1)
+  } else {
+    CGP_BY_LENGTH(g.L, CALL2)
+  }
+#undef CALL1
+#undef CALL2
   return hipGetLastError();
 }
 
@@ -443,7 +474,8 @@ hipError_t Launch<T>::prepare(size_t bytes) {
   const int b = (int)bytes;
   const void* fns[] = {
 #define FNS(LC)                                                      \
-  reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC>),          \
+  reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC, 1>),       \
+      reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC, 2>),   \
       reinterpret_cast<const void*>(&k_col_solve<T, LC>),            \
       reinterpret_cast<const void*>(&k_rowdst_prolong<T, LC>)
       FNS(0), FNS(256), FNS(512), FNS(1024), FNS(2048)

@@ -37,9 +37,8 @@ __global__ __launch_bounds__(kTileX* kTileY) void k_stencil_rk3(
     return;
   }
   const T dt = T(d.dt), a = T(a_), b = T(b_);
-  const T cj = T(1.0 / (12.0 * d.dx * d.dy));
-  const T cb = T(d.inv_ro / (3.0 * d.dx));
-  const T idx2 = T(1.0 / (d.dx * d.dx)), idy2 = T(1.0 / (d.dy * d.dy));
+  const T cj = T(d.cj), cb = T(d.cb);
+  const T idx2 = T(d.idx2), idy2 = T(d.idy2);
   const T nu = T(d.inv_re);
   const T* W = ws + d.field_off;
   const T* PS = psi + d.field_off;
@@ -110,9 +109,8 @@ __global__ __launch_bounds__(kTileX* kTileY) void k_adjoint_stencil(
     if (acc_mode == 0) acc[o] = 0.0;
     return;
   }
-  const double cj = 1.0 / (12.0 * d.dx * d.dy);
-  const double cb = d.inv_ro / (3.0 * d.dx);
-  const double idx2 = 1.0 / (d.dx * d.dx), idy2 = 1.0 / (d.dy * d.dy);
+  const double cj = d.cj, cb = d.cb;
+  const double idx2 = d.idx2, idy2 = d.idy2;
   const double bdt = b * d.dt;
   Nbr<double> mu = load_nbr_masked(lam_in, pitch, nx, ny, i, j);
   const double lc = mu.C;
