@@ -173,13 +173,14 @@ cgp_status cgp_ensemble_step(cgp_handle* h, void* omega_packed_dev,
  * workspace contents: pass 0 (restriction + x transform of omega_dev),
  * 1 (y transforms + eigenvalue divide), 2 (x transform + prolongation into
  * psi), 3 (Arakawa right-hand side + RK3 combine in the form of stage 2:
- * reads stage 1, psi, the forcing and omega_dev, writes stage 2) and 4 (the
+ * reads stage 1, psi, the forcing and omega_dev, writes stage 2), 4 (the
  * fused form of passes 2 and 3 that one-layer time steps use when every
- * member's coarse rows hold at most 512 intervals; 0 is reported for handles
- * without it).  Each pass is launched `reps` times back to back on `stream`
- * between two HIP events; ms_host[p] (5 doubles, host memory) receives the
- * mean milliseconds per launch.  Synchronises the stream.  omega_dev is only
- * read. */
+ * member's rows hold at most 512 intervals and 2^level <= 4) and 5 (pass 4
+ * followed by pass 0 of the next stage on its result, the form time steps
+ * launch); 0 is reported for 4 and 5 on handles without them.  Each pass is
+ * launched `reps` times back to back on `stream` between two HIP events;
+ * ms_host[p] (6 doubles, host memory) receives the mean milliseconds per
+ * launch.  Synchronises the stream.  omega_dev is only read. */
 cgp_status cgp_time_passes(cgp_handle* h, const void* omega_dev, const void* forcing_dev,
                            int32_t reps, double* ms_host, void* stream);
 

@@ -140,9 +140,10 @@ def cgp_ensemble_step(h, omega_packed, forcing_packed, nsteps=1, use_graph=True,
 
 
 def cgp_time_passes(h, omega, forcing, reps, stream=None):
-    """Mean ms per launch of passes A, B, C, D and the fused C + D pass (0 when
-    the handle has none); reps back-to-back launches each; synchronises."""
-    ms = (ctypes.c_double * 5)()
+    """Mean ms per launch of passes A, B, C, D, the fused C + D pass and the
+    fused pass with the next stage's pass A (0 for the last two when the handle
+    has none); reps back-to-back launches each; synchronises."""
+    ms = (ctypes.c_double * 6)()
     call("cgp_time_passes", h, _ptr(omega), _ptr(forcing), int(reps), ms,
          ctypes.c_void_p(stream_ptr(stream)))
     return list(ms)

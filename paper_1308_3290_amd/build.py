@@ -33,6 +33,10 @@ def compile_flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             # no packed FP32 instructions in device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # multiply-adds are fused only within one source expression, so
+            # that the same expression rounds the same way in every kernel it
+            # is inlined into (the fused pass and pass A must agree bit for bit)
+            "-ffp-contract=on",
             "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
 
 

@@ -35,6 +35,8 @@ struct MemberDesc {
   int stw_r[kMaxStages], stw_c[kMaxStages];  // stage words: radix, log2 span, table offset
   int ntw_r, ntw_c;                          // twiddle table sizes (complex values)
   int pa;               // pass A: sequences per block (1)
+  int a_first, a_rows;  // pass A, one layer: block b packs coarse rows a_first + b a_rows
+                        // (+1 when a_rows = 2; row 0, a wall, as 0), as the fused pass does
   int pb;               // pass B: sequences per block (1)
   int tj;               // pass C: coarse rows owned per block
   int pc;               // pass C: sequence pairs per block (derived from tj)
@@ -97,17 +99,19 @@ struct Launch {
   // pass A: restrict (level times) + forward x sine transform, src -> spectra
   static hipError_t restrict_rowdst(const MemberDesc* md, const Group& g, const T* src, T* wt,
                                     const cplx<T>* tw, hipStream_t s);
-  // pass B: y sine transform, eigenvalue divide, y sine transform (in place)
-  static hipError_t col_solve(const MemberDesc* md, const Group& g, T* wt, const cplx<T>* tw,
-                              const double* lam, hipStream_t s);
+  // pass B: y sine transform, eigenvalue divide, y sine transform, from the
+  // spectra of omega (win) to those of psi (wout)
+  static hipError_t col_solve(const MemberDesc* md, const Group& g, const T* win, T* wout,
+                              const cplx<T>* tw, const double* lam, hipStream_t s);
   // pass C: inverse x sine transform + prolongation; accumulate != 0 adds to dst
   static hipError_t rowdst_prolong(const MemberDesc* md, const Group& g, const T* wt, T* dst,
                                    int accumulate, const cplx<T>* tw, hipStream_t s);
   // allow the transform kernels up to `bytes` of dynamic LDS per block
   static hipError_t prepare(size_t bytes);
-  // passes C + D fused (one layer): x transform, prolongation into LDS,
-  // stencil + RK3 (g.L holds the group's coarsening factor)
-  static hipError_t prolong_stencil(const MemberDesc* md, const Group& g, const T* wt,
+  // passes C + D fused (one layer): x transform of the psi spectra wt,
+  // prolongation into LDS, stencil + RK3; with wnext != NULL also pass A of
+  // the next stage on the result (spectra into wnext)
+  static hipError_t prolong_stencil(const MemberDesc* md, const Group& g, const T* wt, T* wnext,
                                     const cplx<T>* tw, const T* ws, const T* forcing, const T* wn,
                                     T* out, double a, double b, hipStream_t s);
   static hipError_t prepare_fused(size_t bytes);

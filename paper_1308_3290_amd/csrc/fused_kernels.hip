@@ -1,7 +1,9 @@
 // Pass C + D fused (one layer): inverse x sine transform of the coarse
 // spectra (Sec. 4.3), bilinear prolongation (Sec. 3.1) into LDS, and the
 // Arakawa right-hand side with the TVD-RK3 stage combine (Sec. 4.1, 4.2), so
-// that the prolonged psi never travels through HBM.
+// that the prolonged psi never travels through HBM.  Optionally followed by
+// pass A of the next stage (restriction and forward x transform of the new
+// vorticity), which then needs no launch and no read of it from HBM.
 //
 // A block owns coarse rows j0 .. j0+TJ-1 and writes omega_{s+1} on the fine
 // rows C*j0 .. C*(j0+TJ)-1 (the last block also the top wall row).  The
@@ -24,39 +26,53 @@
 namespace cgp {
 
 // C: coarsening factor; TJ: coarse rows owned per block; LC: transform
-// length with a compile-time transform, or 0.
-template <typename T, int C, int TJ, int LC>
+// length with a compile-time transform, or 0.  NEXT: also restrict the new
+// vorticity of the block's coarse rows and transform it along x (pass A of
+// the next stage), which needs it on the C-1 fine rows below the block too;
+// those rows are computed here as well but not stored.
+template <typename T, int C, int TJ, int LC, bool NEXT>
 __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
-    const T* __restrict__ wt, const cplx<T>* __restrict__ twg, const T* __restrict__ ws,
-    const T* __restrict__ forcing, const T* __restrict__ wn, T* __restrict__ out, double a_,
-    double b_) {
+    const T* __restrict__ wt, T* __restrict__ wnext, const cplx<T>* __restrict__ twg,
+    const T* __restrict__ ws, const T* __restrict__ forcing, const T* __restrict__ wn,
+    T* __restrict__ out, double a_, double b_) {
   constexpr int NT = kFusedThreads;
-  constexpr int NR = C * TJ + 1;  // the most fine rows a block writes (+1: top wall row)
+  constexpr int NR = C * TJ + 1;      // the most own fine rows (+1: top wall row)
+  constexpr int E = NEXT ? C - 1 : 0;  // computed rows below the block
+  constexpr int NO = NR + E;          // the most computed rows
+  constexpr int NP = NO + 2;          // tile rows: computed rows and one on each side
+  constexpr int OFF = C - 1 - E;      // tile row u is fine row C*(j0-1) + OFF + u
   // twiddles per thread: (R-1) Ns summed over the stages, < L <= 1024
   constexpr int kTwPer = ((LC ? stage_plan(LC).ntw : 1023) + NT - 1) / NT;
   static_assert(kFusedMaxNx - 1 <= NT, "one spectral column and one fine column per thread");
-  constexpr int kWPer = ((NR + 2) * (kFusedMaxNx + 1) + NT - 1) / NT;
+  constexpr int kWPer = (NP * (kFusedMaxNx + 1) + NT - 1) / NT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int t = threadIdx.x;
   const int bid = xcd_contiguous(blockIdx.x, nblk);
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_CD, bid)];
   const int lb = bid - d.blk0[PASS_CD];
-  const int Mx = d.Mx, My = d.My, L = d.Lr, c = C;
+  const int Mx = d.Mx, My = d.My, L = d.Lr;
   const int nx = d.nx, ny = d.ny, pitch = nx + 1;
   const int LP = lpad(L);
   const int ntw = d.ntw_r;
 
+  // coarse rows j0-1 .. j0+TJ are synthesised in the global pairs (2m-1, 2m),
+  // so that every block that synthesises a row gets the same bits for it
   const int j0 = lb * TJ;
-  const int ilo = max(1, j0 - 1);
-  const int ihi = min(My - 1, j0 + TJ);
+  const int rlo = max(1, j0 - 1);
+  const int ilo = rlo - ((rlo & 1) ? 0 : 1);      // odd: first row of its pair
+  const int rhi = min(My - 1, j0 + TJ);
+  const int ihi = min(My - 1, rhi + (rhi & 1));   // even: last row of its pair
+                                                  // (My-1 odd: its partner is the wall)
   const int nint = ihi >= ilo ? ihi - ilo + 1 : 0;
   const int nseq = (nint + 1) / 2;
   const int last = (lb == d.nblk[PASS_CD] - 1);
-  const int R0 = c * j0;
-  const int R1 = last ? ny + 1 : c * (j0 + TJ);  // exclusive end of the output rows
-  const int nfr = R1 - R0;                       // output rows (<= NR)
-  const int nW = (nfr + 2) * pitch;              // vorticity tile: rows R0-1 .. R1
+  const int R0 = C * j0;
+  const int R1 = last ? ny + 1 : C * (j0 + TJ);  // exclusive end of the own rows
+  const int nfr = R1 - R0;                       // own rows (<= NR)
+  const int nrow = nfr + E;                      // computed rows: tile rows 1 .. nrow
+  const int RB0 = R0 - 1 - E;                    // fine row of tile row 0
+  const int nW = (nrow + 2) * pitch;
 
   // LDS: [ FFT buffers ] [ twiddles ] [ coarse psi rows ] [ vorticity tile ]
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
@@ -93,7 +109,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   const T* FF = forcing + d.field_off;
   const T* WN = wn + d.field_off;
   T* O = out + d.field_off;
-  const long long g0 = (long long)(R0 - 1) * pitch;
+  const long long g0 = (long long)RB0 * pitch;
   const long long gend = (long long)(ny + 1) * pitch;
   T wv[kWPer];
 #pragma unroll
@@ -104,17 +120,17 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     const T v = W[in ? g : 0];
     wv[q] = in ? v : T(0);
   }
-  // forcing and omega_n at the thread's column x = 1 + t, rows R0 + r
+  // forcing and omega_n at the thread's column x = 1 + t, computed rows
   const int x = 1 + t;
-  T fv[NR], nv[NR];
+  T fv[NO], nv[NO];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int rr = R0 + r;
-    const bool in = x < nx && r < nfr && rr >= 1 && rr < ny;
+  for (int u = 1; u <= NO; ++u) {
+    const int rr = RB0 + u;
+    const bool in = x < nx && u <= nrow && rr >= 1 && rr < ny;
     const size_t o = in ? (size_t)rr * pitch + x : 0;
     const T f = FF[o], n = WN[o];
-    fv[r] = in ? f : T(0);
-    nv[r] = in ? n : T(0);
+    fv[u - 1] = in ? f : T(0);
+    nv[u - 1] = in ? n : T(0);
   }
 
   // ---- twiddles and the two packed sequences (odd extension) into LDS
@@ -161,16 +177,19 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   }
   __syncthreads();
 
-  // ---- walls: columns 0 and nx of the output rows
+  // ---- walls: columns 0 and nx of the own rows
   if (t < nfr) O[(size_t)(R0 + t) * pitch] = T(0);
   else if (t >= 64 && t < 64 + nfr) O[(size_t)(R0 + t - 64) * pitch + nx] = T(0);
 
-  // ---- stencil + RK3 on fine rows R0 .. R1-1 (tile row q = fine row R0-1+q)
+  // ---- stencil + RK3 on the computed rows (tile row u = fine row RB0 + u)
   const T dt = T(d.dt), a = T(a_), b = T(b_);
   const T cj = T(d.cj), cb = T(d.cb);
   const T idx2 = T(d.idx2), idy2 = T(d.idy2);
   const T nu = T(d.inv_re);
   constexpr T kInvC2 = T(1) / T(C * C);
+  T res[NO];
+#pragma unroll
+  for (int u = 0; u < NO; ++u) res[u] = T(0);
   if (x < nx) {
     // coarse columns I0 .. I0+2 (clamped to the wall column Mx) cover the
     // fine columns x-1 .. x+1 for C >= 2; for C = 1 they are those columns
@@ -182,9 +201,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
 #pragma unroll
       for (int r = 0; r < TJ + 2; ++r) A[m][r] = psc[r * prow + I];
     }
-    // P[dx][q]: psi at fine column x-1+dx, tile row q (bilinear, Sec. 3.1;
-    // times C^2, scaled below)
-    T P[3][NR + 2];
+    // P[dx][u]: psi at fine column x-1+dx, tile row u (bilinear, Sec. 3.1)
+    T P[3][NP];
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
       const int xx = x - 1 + dx;
@@ -204,19 +222,20 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
         cv[r] = T(C - fx) * lo + T(fx) * hi;
       }
 #pragma unroll
-      for (int q = 0; q < NR + 2; ++q) {
-        // fine row R0-1+q = C*(j0-1) + (C-1+q): coarse row j0-1+jr, weight fy
-        const int u = C - 1 + q;
-        const int jr = u / C, fy = u - jr * C;
+      for (int u = 0; u < NP; ++u) {
+        // fine row C*(j0-1) + m: coarse row j0-1+jr, weight fy toward jr+1
+        // (rows past the last coarse row are never used; they are clamped)
+        const int m = OFF + u;
+        const int jr = m / C, fy = m - jr * C;
         const T top = jr + 1 < TJ + 2 ? cv[jr + 1 < TJ + 2 ? jr + 1 : TJ + 1] : T(0);
-        P[dx][q] = (T(C - fy) * cv[jr < TJ + 2 ? jr : TJ + 1] + T(fy) * top) * kInvC2;
+        P[dx][u] = (T(C - fy) * cv[jr < TJ + 2 ? jr : TJ + 1] + T(fy) * top) * kInvC2;
       }
     }
     const bool mw = x > 1, me = x < nx - 1;
-    auto wrow = [&](int q, T& w0, T& w1, T& w2) {
-      const int rr = R0 - 1 + q;
+    auto wrow = [&](int u, T& w0, T& w1, T& w2) {
+      const int rr = RB0 + u;
       const bool in = rr >= 1 && rr <= ny - 1;
-      const T* p = wtile + q * pitch + x;
+      const T* p = wtile + u * pitch + x;
       w0 = (in && mw) ? p[-1] : T(0);
       w1 = in ? p[0] : T(0);
       w2 = (in && me) ? p[1] : T(0);
@@ -225,30 +244,85 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     wrow(0, ws0, ws1, ws2);
     wrow(1, wc0, wc1, wc2);
 #pragma unroll
-    for (int q = 1; q <= NR; ++q) {
-      if (q > nfr) break;
+    for (int u = 1; u <= NO; ++u) {
+      if (u > nrow) break;
       T wn0, wn1, wn2;
-      wrow(q + 1, wn0, wn1, wn2);
-      const int rr = R0 - 1 + q;
+      wrow(u + 1, wn0, wn1, wn2);
+      const int rr = RB0 + u;
       T v = T(0);
-      if (rr != 0 && rr != ny) {
+      if (rr >= 1 && rr <= ny - 1) {
         Nbr<T> p, w;
-        p.C = P[1][q]; p.E = P[2][q]; p.W = P[0][q];
-        p.N = P[1][q + 1]; p.S = P[1][q - 1];
-        p.NE = P[2][q + 1]; p.NW = P[0][q + 1];
-        p.SE = P[2][q - 1]; p.SW = P[0][q - 1];
+        p.C = P[1][u]; p.E = P[2][u]; p.W = P[0][u];
+        p.N = P[1][u + 1]; p.S = P[1][u - 1];
+        p.NE = P[2][u + 1]; p.NW = P[0][u + 1];
+        p.SE = P[2][u - 1]; p.SW = P[0][u - 1];
         w.C = wc1; w.E = wc2; w.W = wc0;
         w.N = wn1; w.S = ws1;
         w.NE = wn2; w.NW = wn0;
         w.SE = ws2; w.SW = ws0;
         const T G =
-            -cj * arakawa12(p, w) - cb * beta3(p) + nu * lap5(w, idx2, idy2) + fv[q - 1];
+            -cj * arakawa12(p, w) - cb * beta3(p) + nu * lap5(w, idx2, idy2) + fv[u - 1];
         v = b * (w.C + dt * G);
-        if (a_ != 0.0) v += a * nv[q - 1];
+        if (a_ != 0.0) v += a * nv[u - 1];
       }
-      O[(size_t)rr * pitch + x] = v;
+      if (u > E) O[(size_t)rr * pitch + x] = v;
+      res[u - 1] = v;
       ws0 = wc0; ws1 = wc1; ws2 = wc2;
       wc0 = wn0; wc1 = wn1; wc2 = wn2;
+    }
+  }
+  if constexpr (NEXT) {
+    // ---- pass A of the next stage on the block's coarse rows j0 .. j0+TJ-1:
+    // their full-weighting stencils cover the computed rows R0-E .. R1-1
+    // (row k of rt = fine row R0-E+k = tile row k+1), Sec. 3.1 and 4.3
+    constexpr int NRT = C * (TJ + 1) - 1;
+    T* rt = wtile;
+    __syncthreads();  // every thread is done with wtile and psc
+    if (x < nx) {
+#pragma unroll
+      for (int k = 0; k < NRT; ++k) rt[k * pitch + x] = res[k];
+    }
+    if (t == 0) {
+      buf[pad(0)] = {T(0), T(0)};
+      buf[pad(Mx)] = {T(0), T(0)};
+    }
+    __syncthreads();
+    const int i = 1 + t;
+    if (i < Mx) {
+      // x-weighted sums of each fine row, then the y weights (as pass A)
+      T racc[NRT];
+#pragma unroll
+      for (int q = 0; q < NRT; ++q) {
+        const T* row = rt + q * pitch + C * i;
+        T acc = T(0);
+#pragma unroll
+        for (int dx = -(C - 1); dx <= C - 1; ++dx) acc += T(C - (dx < 0 ? -dx : dx)) * row[dx];
+        racc[q] = acc;
+      }
+      T v[2] = {T(0), T(0)};
+#pragma unroll
+      for (int r = 0; r < TJ; ++r) {
+        T acc = T(0);
+#pragma unroll
+        for (int dy = -(C - 1); dy <= C - 1; ++dy)
+          acc += T(C - (dy < 0 ? -dy : dy)) * racc[C * r + dy + (C - 1)];
+        v[r] = acc * (T(1) / T(C * C * C * C));
+      }
+      // packed as pass A packs them (the wall row 0 as 0), so that both give
+      // the same spectra bit for bit
+      const cplx<T> z = {j0 >= 1 ? v[0] : T(0), v[1]};
+      buf[pad(i)] = z;
+      buf[pad(2 * Mx - i)] = {-z.x, -z.y};
+    }
+    const cplx<T>* Z2 = fft_run<T, LC, NT>(buf, buf + LP, 1, L, d.nst_r, d.stw_r, tw);
+    if (i < Mx) {
+      const cplx<T> zk = Z2[pad(i)];
+      T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
+#pragma unroll
+      for (int r = 0; r < TJ; ++r) {
+        const int j = j0 + r;
+        if (j >= 1 && j <= My - 1) wo[j - 1] = r == 0 ? T(-0.5) * zk.y : T(0.5) * zk.x;
+      }
     }
   }
 }
@@ -256,24 +330,33 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
 // g.L = (c << 16) | transform length with a compile-time transform (or 0).
 template <typename T>
 hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, const T* wt,
-                                      const cplx<T>* tw, const T* ws, const T* forcing,
-                                      const T* wn, T* out, double a, double b, hipStream_t s) {
-#define LAUNCH(C, TJ, LC)                                                                     \
-  hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC>), dim3(g.nblk), dim3(kFusedThreads), g.lds, \
-                     s, md, g.members, g.count, g.nblk, wt, tw, ws, forcing, wn, out, a, b)
-#define BY_LEN(C, TJ)                         \
-  switch (g.L & 0xffff) {                     \
-    case 256: LAUNCH(C, TJ, 256); break;      \
-    case 512: LAUNCH(C, TJ, 512); break;      \
-    case 1024: LAUNCH(C, TJ, 1024); break;    \
-    default: LAUNCH(C, TJ, 0);                \
+                                      T* wnext, const cplx<T>* tw, const T* ws,
+                                      const T* forcing, const T* wn, T* out, double a, double b,
+                                      hipStream_t s) {
+#define LAUNCH(C, TJ, LC, NX)                                                                \
+  hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC, NX>), dim3(g.nblk), dim3(kFusedThreads), \
+                     g.lds, s, md, g.members, g.count, g.nblk, wt, wnext, tw, ws, forcing, wn, \
+                     out, a, b)
+#define BY_LEN(C, TJ, NX)                      \
+  switch (g.L & 0xffff) {                      \
+    case 256: LAUNCH(C, TJ, 256, NX); break;   \
+    case 512: LAUNCH(C, TJ, 512, NX); break;   \
+    case 1024: LAUNCH(C, TJ, 1024, NX); break; \
+    default: LAUNCH(C, TJ, 0, NX);             \
   }
-  switch (g.L >> 16) {
-    case 1: BY_LEN(1, 2); break;
-    case 2: BY_LEN(2, 2); break;
-    case 4: BY_LEN(4, 1); break;
-    default: return hipErrorInvalidValue;
+#define BY_C(NX)                       \
+  switch (g.L >> 16) {                 \
+    case 1: BY_LEN(1, 2, NX); break;   \
+    case 2: BY_LEN(2, 2, NX); break;   \
+    case 4: BY_LEN(4, 1, NX); break;   \
+    default: return hipErrorInvalidValue; \
   }
+  if (wnext) {
+    BY_C(true)
+  } else {
+    BY_C(false)
+  }
+#undef BY_C
 #undef BY_LEN
 #undef LAUNCH
   return hipGetLastError();
@@ -283,13 +366,15 @@ template <typename T>
 hipError_t Launch<T>::prepare_fused(size_t bytes) {
   const int b = (int)bytes;
   const void* fns[] = {
-#define FNS(C, TJ)                                                          \
-  reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 0>),           \
-      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 256>),     \
-      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 512>),     \
-      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 1024>)
+#define F1(C, TJ, NX)                                                         \
+  reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 0, NX>),         \
+      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 256, NX>),   \
+      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 512, NX>),   \
+      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 1024, NX>)
+#define FNS(C, TJ) F1(C, TJ, false), F1(C, TJ, true)
       FNS(1, 2), FNS(2, 2), FNS(4, 1)
 #undef FNS
+#undef F1
   };
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);

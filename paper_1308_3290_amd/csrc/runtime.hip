@@ -15,6 +15,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <tuple>
 #include <string>
 #include <utility>
 #include <vector>
@@ -102,8 +103,10 @@ cgp_status validate(const cgp_config* c) {
 }
 
 struct Layout {
-  size_t desc = 0, order = 0, tw = 0, lam = 0, wt = 0, psi = 0, st1 = 0, st2 = 0, diag = 0,
-         fin = 0, total = 0;
+  // wt: spectra of omega (pass A out, pass B in); wt2: spectra of psi (pass B
+  // out, pass C / fused pass in)
+  size_t desc = 0, order = 0, tw = 0, lam = 0, wt = 0, wt2 = 0, psi = 0, st1 = 0, st2 = 0,
+         diag = 0, fin = 0, total = 0;
   long long field_elems = 0;
 };
 
@@ -212,14 +215,20 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   }
   // A block transforms at most two sequences and at most 2048 complex values.
   auto pairs = [](int L) { return L <= 512 ? 2 : 1; };
-  // pass A: one complex sequence per block: a pair of coarse rows (one
-  // layer) or one coarse row's two modes
+  // fused C + D pass (one layer, rows of at most kFusedMaxNx intervals, c <= 4)
+  bool fusable = nl == 1;
+  for (const MemberDesc& d : plan->md) fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4;
+  // pass A: one complex sequence per block: coarse rows packed as the fused
+  // pass packs them when it computes the next stage's spectra (so that both
+  // give the same bits), else a pair of rows; two layers: one row's modes
   build_groups(plan->md, PASS_A, [](const MemberDesc& d) { return fft_special(d.Lr); },
                [&](MemberDesc& d, HostGroup&) {
                  d.pa = 1;
-                 const int rows = nl == 1 ? 2 : 1;
+                 d.a_rows = nl == 1 ? (fusable ? fused_tj(d.c) : 2) : 1;
+                 d.a_first = (nl == 1 && fusable && d.a_rows == 2) ? 0 : 1;
+                 const int nrows = d.My - d.a_first;
                  const size_t lds = ((size_t)2 * lpad(d.Lr) + d.ntw_r) * cs;
-                 return std::make_pair((d.My - 1 + rows - 1) / rows, lds);
+                 return std::make_pair((nrows + d.a_rows - 1) / d.a_rows, lds);
                },
                plan->groups[0]);
   // pass B: one complex sequence per block: a pair of spectral columns (one
@@ -248,19 +257,19 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     for (const HostGroup& g : plan->groups[p])
       if (g.lds > kMaxLds)
         return fail(CGP_ERR_UNSUPPORTED, "a transform pass needs more than 160 KiB LDS per block");
-  // fused C + D (one layer, rows of at most kFusedMaxNx intervals, c <= 4): a
-  // block owns fused_tj(c) coarse rows and synthesises the two neighbouring
-  // ones (at most two packed sequences); one launch per coarsening factor.
-  bool fusable = nl == 1;
-  for (const MemberDesc& d : plan->md) fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4;
+  // fused C + D: a block owns fused_tj(c) coarse rows and synthesises the
+  // two neighbouring ones (at most two packed sequences); one launch per
+  // coarsening factor and transform length.
   if (fusable) {
     build_groups(plan->md, PASS_CD,
                  [](const MemberDesc& d) { return (d.c << 16) | fft_special(d.Lr); },
                  [&](MemberDesc& d, HostGroup&) {
+                   // vorticity tile: own rows, c - 1 rows below them for the
+                   // next stage's restriction, one more on each side
                    const int tj = fused_tj(d.c), nr = fused_nr(d.c);
                    const size_t lds = ((size_t)4 * lpad(d.Lr) + d.ntw_r) * cs +
                                       ((size_t)(tj + 2) * (d.Mx + 1) +
-                                       (size_t)(nr + 2) * (d.nx + 1)) * es;
+                                       (size_t)(nr + 2 + d.c - 1) * (d.nx + 1)) * es;
                    return std::make_pair((d.My + tj - 1) / tj, lds);
                  },
                  plan->groups[3]);
@@ -281,6 +290,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   L.tw = off; off = align_up(off + (size_t)tw * 2 * es);
   L.lam = off; off = align_up(off + (size_t)lam * sizeof(double));
   L.wt = off; off = align_up(off + (size_t)wt * es);
+  L.wt2 = off; off = align_up(off + (size_t)wt * es);
   L.field_elems = fld;
   L.psi = off; off = align_up(off + (size_t)fld * es);
   L.st1 = off; off = align_up(off + (size_t)fld * es);
@@ -297,8 +307,9 @@ struct cgp_handle {
   Plan plan;
   char* ws = nullptr;
   std::vector<char> host_tables;  // kept alive until destroy (async upload source)
-  // graph cache: (omega, forcing) -> executable graph of one step
-  std::map<std::pair<const void*, const void*>, hipGraphExec_t> graphs;
+  // graph cache: (omega, forcing, rotation phase of the fused step) ->
+  // executable graph of one step
+  std::map<std::tuple<const void*, const void*, int>, hipGraphExec_t> graphs;
   int nm() const { return (int)plan.md.size(); }
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   const MemberDesc* d_md() const { return at<MemberDesc>(plan.lay.desc); }
@@ -322,12 +333,16 @@ hipError_t enqueue_pass(cgp_handle* h, int pass, const T* src, T* dst, int accum
   const Plan& p = h->plan;
   const cplx<T>* tw = h->at<cplx<T>>(p.lay.tw);
   T* wt = h->at<T>(p.lay.wt);
+  T* wt2 = h->at<T>(p.lay.wt2);
   for (int i = 0; i < h->ngroups(pass); ++i) {
     const Group g = h->group(pass, i);
     hipError_t e;
-    if (pass == 0) e = Launch<T>::restrict_rowdst(h->d_md(), g, src, wt, tw, s);
-    else if (pass == 1) e = Launch<T>::col_solve(h->d_md(), g, wt, tw, h->at<double>(p.lay.lam), s);
-    else e = Launch<T>::rowdst_prolong(h->d_md(), g, wt, dst, accumulate, tw, s);
+    if (pass == 0)
+      e = Launch<T>::restrict_rowdst(h->d_md(), g, src, wt, tw, s);
+    else if (pass == 1)
+      e = Launch<T>::col_solve(h->d_md(), g, wt, wt2, tw, h->at<double>(p.lay.lam), s);
+    else
+      e = Launch<T>::rowdst_prolong(h->d_md(), g, wt2, dst, accumulate, tw, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -341,23 +356,24 @@ hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hi
   return e;
 }
 
-// Fused pass C + D over every member: out = a wn + b (ws + dt G(ws, psi(ws))).
+// Fused pass C + D over every member: out = a wn + b (ws + dt G(ws, psi(ws)));
+// with `next`, also pass A on out (its spectra into wt for the next stage).
 template <typename T>
 hipError_t enqueue_fused(cgp_handle* h, const T* ws, const T* forcing, const T* wn, T* out,
-                         double a, double b, hipStream_t s) {
+                         double a, double b, bool next, hipStream_t s) {
   const Plan& p = h->plan;
   for (int i = 0; i < h->ngroups(3); ++i) {
-    hipError_t e = Launch<T>::prolong_stencil(h->d_md(), h->group(3, i), h->at<T>(p.lay.wt),
-                                              h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, a,
-                                              b, s);
+    hipError_t e = Launch<T>::prolong_stencil(
+        h->d_md(), h->group(3, i), h->at<T>(p.lay.wt2), next ? h->at<T>(p.lay.wt) : nullptr,
+        h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, a, b, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-// One CGPRK3 step: w1 -> stage 1 buffer, w2 -> stage 2 buffer, w_{n+1} -> omega.
-// psi0..psi2, when given, receive the stage stream functions (the unfused
-// passes run then).
+// One CGPRK3 step (unfused passes): w1 -> stage 1 buffer, w2 -> stage 2
+// buffer, w_{n+1} -> omega.  psi0..psi2, when given, receive the stage stream
+// functions.
 template <typename T>
 hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s,
                         T* st1 = nullptr, T* st2 = nullptr, T* psi0 = nullptr,
@@ -369,16 +385,7 @@ hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s
   T* psis[3] = {psi0 ? psi0 : pd, psi1 ? psi1 : pd, psi2 ? psi2 : pd};
   const T* src[3] = {omega, b1, b2};
   T* dst[3] = {b1, b2, omega};
-  const bool fused = p.fused && !psi0 && !psi1 && !psi2;
   for (int st = 0; st < 3; ++st) {
-    if (fused) {
-      hipError_t e = enqueue_pass<T>(h, 0, src[st], nullptr, 0, s);
-      if (e == hipSuccess) e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s);
-      if (e == hipSuccess)
-        e = enqueue_fused<T>(h, src[st], forcing, omega, dst[st], kRkA[st], kRkB[st], s);
-      if (e != hipSuccess) return e;
-      continue;
-    }
     hipError_t e = enqueue_solve<T>(h, src[st], psis[st], 0, s);
     if (e != hipSuccess) return e;
     e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), p.nblk_d, src[st], psis[st], forcing,
@@ -388,8 +395,34 @@ hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s
   return hipSuccess;
 }
 
-// reps back-to-back launches of pass p (3 = stencil, 4 = fused C + D, both in
-// their stage-2 form)
+// One CGPRK3 step with the fused pass.  Each stage is pass B and the fused
+// pass, which also leaves the spectra of its result for the next stage (the
+// spectra of the state must be in place on entry).  The fused pass reads the
+// vorticity of the stage input on rows of neighbouring blocks, so no stage
+// may overwrite a field it reads: the state rotates through bufs[0..2]
+// (omega and the two stage buffers) with period 3.  The state is in bufs[pos]
+// on entry and in bufs[(pos+1) % 3] on exit.
+template <typename T>
+hipError_t enqueue_step_fused(cgp_handle* h, T* omega, const T* forcing, int pos,
+                              hipStream_t s) {
+  const Plan& p = h->plan;
+  T* bufs[3] = {omega, h->at<T>(p.lay.st1), h->at<T>(p.lay.st2)};
+  T* S = bufs[pos];
+  T* X = bufs[(pos + 1) % 3];
+  T* Y = bufs[(pos + 2) % 3];
+  const T* src[3] = {S, X, Y};
+  T* dst[3] = {X, Y, X};
+  for (int st = 0; st < 3; ++st) {
+    hipError_t e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s);
+    if (e == hipSuccess)
+      e = enqueue_fused<T>(h, src[st], forcing, S, dst[st], kRkA[st], kRkB[st], true, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// reps back-to-back launches of pass p (3 = stencil, 4 = fused C + D, 5 =
+// fused C + D + next pass A, in their stage-2 form)
 template <typename T>
 hipError_t enqueue_pass_reps(cgp_handle* h, int p, const T* omega, const T* forcing, int reps,
                              hipStream_t s) {
@@ -403,7 +436,7 @@ hipError_t enqueue_pass_reps(cgp_handle* h, int p, const T* omega, const T* forc
     else if (p == 3)
       e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), pl.nblk_d, b1, pd, forcing, omega, b2,
                                  kRkA[1], kRkB[1], s);
-    else e = enqueue_fused<T>(h, b1, forcing, omega, b2, kRkA[1], kRkB[1], s);
+    else e = enqueue_fused<T>(h, b1, forcing, omega, b2, kRkA[1], kRkB[1], p == 5, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -507,32 +540,70 @@ cgp_status create_common(const cgp_config* cfgs, int count, void* ws, size_t byt
   return CGP_OK;
 }
 
+// Graph of one step for (omega, forcing, pos), captured on first use.
+template <typename T>
+cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, hipStream_t s,
+                      hipGraphExec_t* out) {
+  auto key = std::make_tuple(static_cast<const void*>(w), static_cast<const void*>(F), pos);
+  auto it = h->graphs.find(key);
+  if (it != h->graphs.end()) {
+    *out = it->second;
+    return CGP_OK;
+  }
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+  hipError_t e = h->plan.fused ? enqueue_step_fused<T>(h, w, F, pos, s) : enqueue_step<T>(h, w, F, s);
+  hipError_t e2 = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess) return hip_fail(e, "capture step");
+  if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+  h->graphs[key] = exec;
+  *out = exec;
+  return CGP_OK;
+}
+
 template <typename T>
 cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_out, int nsteps,
                      int use_graph, hipStream_t s) {
   T* w = static_cast<T*>(omega);
   const T* F = static_cast<const T*>(forcing);
-  if (use_graph && s != nullptr && nsteps > 0) {
-    auto key = std::make_pair(static_cast<const void*>(omega), forcing);
-    auto it = h->graphs.find(key);
-    hipGraphExec_t exec = nullptr;
-    if (it == h->graphs.end()) {
-      hipGraph_t g = nullptr;
-      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-      hipError_t e = enqueue_step<T>(h, w, F, s);
-      hipError_t e2 = hipStreamEndCapture(s, &g);
-      if (e != hipSuccess) return hip_fail(e, "capture step");
-      if (e2 != hipSuccess) return hip_fail(e2, "end capture");
-      e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-      h->graphs[key] = exec;
-    } else {
-      exec = it->second;
+  const bool graph = use_graph && s != nullptr;
+  if (!h->plan.fused) {
+    for (int n = 0; n < nsteps; ++n) {
+      if (graph) {
+        hipGraphExec_t exec = nullptr;
+        cgp_status st = step_graph<T>(h, w, F, 0, s, &exec);
+        if (st != CGP_OK) return st;
+        HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
+      } else {
+        HIP_TRY(enqueue_step<T>(h, w, F, s), "step launch");
+      }
     }
-    for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
-  } else {
-    for (int n = 0; n < nsteps; ++n) HIP_TRY(enqueue_step<T>(h, w, F, s), "step launch");
+  } else if (nsteps > 0) {
+    // spectra of omega, then steps rotating the state through omega and the
+    // stage buffers; the result is copied back to omega unless it is there
+    HIP_TRY(enqueue_pass<T>(h, 0, w, nullptr, 0, s), "pass A launch");
+    int pos = 0;
+    for (int n = 0; n < nsteps; ++n) {
+      if (graph) {
+        hipGraphExec_t exec = nullptr;
+        cgp_status st = step_graph<T>(h, w, F, pos, s, &exec);
+        if (st != CGP_OK) return st;
+        HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
+      } else {
+        HIP_TRY(enqueue_step_fused<T>(h, w, F, pos, s), "step launch");
+      }
+      pos = (pos + 1) % 3;
+    }
+    if (pos != 0) {
+      const T* from = h->at<T>(pos == 1 ? h->plan.lay.st1 : h->plan.lay.st2);
+      HIP_TRY(hipMemcpyAsync(w, from, (size_t)h->plan.lay.field_elems * sizeof(T),
+                             hipMemcpyDeviceToDevice, s),
+              "state copy");
+    }
   }
   if (psi_out) HIP_TRY(enqueue_solve<T>(h, w, static_cast<T*>(psi_out), 0, s), "psi launch");
   return CGP_OK;
@@ -668,10 +739,10 @@ cgp_status cgp_time_passes(cgp_handle* h, const void* omega, const void* forcing
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(CGP_ERR_DEVICE, "event create");
   cgp_status st = CGP_OK;
-  for (int p = 0; p < 5 && st == CGP_OK; ++p) {
-    if (p == 4 && !h->plan.fused) {
+  for (int p = 0; p < 6 && st == CGP_OK; ++p) {
+    if (p >= 4 && !h->plan.fused) {
       ms[p] = 0.0;
-      break;
+      continue;
     }
     hipError_t e = hipEventRecord(e0, s);
     if (e == hipSuccess)

@@ -41,15 +41,17 @@ __device__ __forceinline__ T restrict_generic(const T* __restrict__ f, int pitch
 // ---------------------------------------------------------------------------
 // Pass A.  A block restricts RB consecutive coarse rows starting at j0 (one
 // layer: RB = 2, packed as the real and imaginary parts of one complex
-// sequence; two layers: RB = 1, its barotropic and baroclinic combinations)
-// and transforms them along x.  The twiddles and every fine value of the
+// sequence, j0 = a_first + b a_rows, the second row absent when a_rows = 1
+// and row 0 read as 0; two layers: RB = 1, its barotropic and baroclinic
+// combinations) and transforms them along x.  The twiddles and every fine value of the
 // block are loaded before any is used: the loads are unconditional (a lane
 // without a column reads a valid neighbour), so that they are in flight
 // together.
 // ---------------------------------------------------------------------------
 // Restriction of coarse rows j0 .. j0+RB-1 at coarse column i, separably: the
 // x-weighted sums of the fine rows C j0-(C-1) .. C (j0+RB-1)+(C-1) first, then
-// the y weights.  Rows of absent coarse rows are clamped to the array.
+// the y weights.  Rows of absent coarse rows (the wall row 0, rows past
+// My-1) are clamped to the array; their values are discarded.
 template <typename T, int C, int RB>
 __device__ __forceinline__ void restrict_rows(const T* __restrict__ f, int pitch, int ny, int i,
                                               int j0, T* v) {
@@ -58,7 +60,7 @@ __device__ __forceinline__ void restrict_rows(const T* __restrict__ f, int pitch
   T racc[NF];
 #pragma unroll
   for (int q = 0; q < NF; ++q) {
-    const T* row = f + (size_t)min(fr0 + q, ny) * pitch + C * i;
+    const T* row = f + (size_t)max(0, min(fr0 + q, ny)) * pitch + C * i;
     T acc = T(0);
 #pragma unroll
     for (int dx = -(C - 1); dx <= C - 1; ++dx) acc += T(C - (dx < 0 ? -dx : dx)) * row[dx];
@@ -74,11 +76,12 @@ __device__ __forceinline__ void restrict_rows(const T* __restrict__ f, int pitch
   }
 }
 
+// keep: which of the one-layer pair's rows are present (bit 0: j0, bit 1: j0+1)
 template <typename T, int NL>
 __device__ __forceinline__ void put_rows(cplx<T>* buf, int Mx, int i, const T* v, const T* u,
-                                         T wbt1, T wbt2) {
+                                         T wbt1, T wbt2, int keep) {
   cplx<T> z;
-  if constexpr (NL == 1) z = {v[0], v[1]};
+  if constexpr (NL == 1) z = {(keep & 1) ? v[0] : T(0), (keep & 2) ? v[1] : T(0)};
   else z = {wbt1 * v[0] + wbt2 * u[0], v[0] - u[0]};  // (barotropic, baroclinic)
   buf[pad(i)] = z;
   buf[pad(2 * Mx - i)] = {-z.x, -z.y};
@@ -89,7 +92,7 @@ constexpr int kColIter = 4;  // Mx - 1 <= 1023
 
 template <typename T, int C, int NL>
 __device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __restrict__ f,
-                                               cplx<T>* buf, int j0) {
+                                               cplx<T>* buf, int j0, int keep) {
   constexpr int RB = NL == 1 ? 2 : 1;
   const int Mx = d.Mx, pitch = d.nx + 1, ny = d.ny;
   const size_t plane = (size_t)(ny + 1) * pitch;
@@ -107,7 +110,7 @@ __device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __r
 #pragma unroll
     for (int q = 0; q < kColIter; ++q) {
       const int i = 1 + threadIdx.x + kThreads * q;
-      if (i < Mx) put_rows<T, NL>(buf, Mx, i, v[q], u[q], wbt1, wbt2);
+      if (i < Mx) put_rows<T, NL>(buf, Mx, i, v[q], u[q], wbt1, wbt2, keep);
     }
   } else {
     const int c = d.c;
@@ -115,11 +118,11 @@ __device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __r
       T v[RB], u[RB];
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
-        const int j = min(j0 + r, d.My - 1);
+        const int j = max(1, min(j0 + r, d.My - 1));
         v[r] = restrict_generic<T>(f, pitch, c, i, j);
         u[r] = NL == 2 ? restrict_generic<T>(f + plane, pitch, c, i, j) : T(0);
       }
-      put_rows<T, NL>(buf, Mx, i, v, u, wbt1, wbt2);
+      put_rows<T, NL>(buf, Mx, i, v, u, wbt1, wbt2, keep);
     }
   }
 }
@@ -137,8 +140,9 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
   const int LP = lpad(L);
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + 2 * LP;
-  const int j0 = 1 + lb * RB;
-  const int nr = min(RB, My - j0);
+  const int j0 = NL == 1 ? d.a_first + lb * d.a_rows : 1 + lb;
+  // rows of the pair that exist and are interior (1 .. My-1)
+  const int keep = NL == 1 ? ((j0 >= 1 ? 1 : 0) | (d.a_rows == 2 && j0 + 1 <= My - 1 ? 2 : 0)) : 1;
 
   T twx[kTw], twy[kTw];
 #pragma unroll
@@ -154,10 +158,10 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
   }
   const T* f = src + d.field_off;
   switch (d.c) {
-    case 1: restrict_block<T, 1, NL>(d, f, buf, j0); break;
-    case 2: restrict_block<T, 2, NL>(d, f, buf, j0); break;
-    case 4: restrict_block<T, 4, NL>(d, f, buf, j0); break;
-    default: restrict_block<T, 0, NL>(d, f, buf, j0);
+    case 1: restrict_block<T, 1, NL>(d, f, buf, j0, keep); break;
+    case 2: restrict_block<T, 2, NL>(d, f, buf, j0, keep); break;
+    case 4: restrict_block<T, 4, NL>(d, f, buf, j0, keep); break;
+    default: restrict_block<T, 0, NL>(d, f, buf, j0, keep);
   }
 #pragma unroll
   for (int q = 0; q < kTw; ++q) {
@@ -171,10 +175,10 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
   for (int k = 1 + threadIdx.x; k < Mx; k += kThreads) {
     const cplx<T> zk = Z[pad(k)];
-    const size_t o = (size_t)(k - 1) * (My - 1) + (j0 - 1);
+    const long long o = (long long)(k - 1) * (My - 1) + (j0 - 1);  // row j0 (-1 if j0 = 0)
     if constexpr (NL == 1) {
-      w[o] = T(-0.5) * zk.y;
-      if (nr > 1) w[o + 1] = T(0.5) * zk.x;
+      if (keep & 1) w[o] = T(-0.5) * zk.y;
+      if (keep & 2) w[o + 1] = T(0.5) * zk.x;
     } else {
       w[o] = T(-0.5) * zk.y;
       w[mplane + o] = T(0.5) * zk.x;
@@ -186,12 +190,14 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
 // Pass B.  A block transforms one pair of coarse spectral columns (one layer:
 // columns k, k+1; two layers: the barotropic and baroclinic column k) along
 // y, multiplies by (2/Mx)(2/My)/lambda_kl (baroclinic: 1/(lambda_kl - F1 -
-// F2)), and transforms back.  Loads are batched as in pass A.
+// F2)), and transforms back, from the spectra of omega (win) to those of psi
+// (wout, same layout).  Loads are batched as in pass A.
 // ---------------------------------------------------------------------------
 template <typename T, int LC>
 __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __restrict__ md,
                                                         const int* __restrict__ grp, int ng,
-                                                        T* __restrict__ wt,
+                                                        const T* __restrict__ win,
+                                                        T* __restrict__ wout,
                                                         const cplx<T>* __restrict__ twg,
                                                         const double* __restrict__ lam) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -205,7 +211,6 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* buf2 = buf + LP;
   cplx<T>* tw = buf2 + LP;
-  T* w = wt + d.wt_off;
   const size_t mplane = (size_t)(Mx - 1) * (My - 1);
   const double* lamx = lam + d.lam_off;
   const double* lamy = lamx + (Mx - 1);
@@ -216,8 +221,10 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
   const int ka = nl == 1 ? 1 + 2 * lb : 1 + lb;
   const int kb = nl == 1 ? ka + 1 : ka;
   const bool has_b = kb <= Mx - 1;
-  T* cola = w + (size_t)(ka - 1) * ny1;
-  T* colb = w + (nl == 2 ? mplane : 0) + (size_t)((has_b ? kb : ka) - 1) * ny1;
+  const size_t offa = d.wt_off + (size_t)(ka - 1) * ny1;
+  const size_t offb = d.wt_off + (nl == 2 ? mplane : 0) + (size_t)((has_b ? kb : ka) - 1) * ny1;
+  const T* cola = win + offa;
+  const T* colb = win + offb;
   const double lxa = lamx[ka - 1];
   const double lxb = lamx[(has_b ? kb : ka) - 1] - shift;
 
@@ -281,8 +288,8 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
     const int l = 1 + threadIdx.x + kThreads * q;
     if (l < My) {
       const cplx<T> z = R[pad(l)];
-      cola[l - 1] = T(-0.5) * z.y;
-      if (has_b) colb[l - 1] = T(0.5) * z.x;
+      wout[offa + l - 1] = T(-0.5) * z.y;
+      if (has_b) wout[offb + l - 1] = T(0.5) * z.x;
     }
   }
 }
@@ -448,11 +455,11 @@ hipError_t Launch<T>::restrict_rowdst(const MemberDesc* md, const Group& g, cons
 }
 
 template <typename T>
-hipError_t Launch<T>::col_solve(const MemberDesc* md, const Group& g, T* wt, const cplx<T>* tw,
-                                const double* lam, hipStream_t s) {
+hipError_t Launch<T>::col_solve(const MemberDesc* md, const Group& g, const T* win, T* wout,
+                                const cplx<T>* tw, const double* lam, hipStream_t s) {
 #define CALL(LC)                                                                                \
   hipLaunchKernelGGL((k_col_solve<T, LC>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members, \
-                     g.count, wt, tw, lam)
+                     g.count, win, wout, tw, lam)
   CGP_BY_LENGTH(g.L, CALL)
 #undef CALL
   return hipGetLastError();

@@ -288,6 +288,39 @@ def test_steps_are_deterministic():
     assert torch.equal(a, c)
 
 
+@pytest.mark.parametrize("nx,ny", [(96, 192), (256, 512)])
+@pytest.mark.parametrize("level", [0, 1, 2])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_steps_split_over_calls_give_the_same_bits(nx, ny, level, dtype):
+    """Six steps in one call, in calls of 1, 2 and 3 steps, and through the
+    captured-graph path agree bit for bit: the spectra a fused step leaves for
+    the next one equal those the first step of a call computes itself, and the
+    rotation of the state through the stage buffers does not matter."""
+    from paper_1308_3290_amd.api import Ensemble, config_from_case
+    case = ci.make_case(nx, ny, level=level, dt=1e-4)
+    say(f"{nx}x{ny} level {level} {dtype}: 6 steps in one call vs 1+2+3 vs graph")
+    tdt = _tdt(dtype)
+    w0 = random_state(case, 21, 1e-2)
+    F = to_dev(ci.forcing_field(case), tdt)
+    b = _basin(case, dtype)
+    one = to_dev(w0, tdt)
+    b.step(one, F, nsteps=6)
+    split = to_dev(w0, tdt)
+    for n in (1, 2, 3):
+        b.step(split, F, nsteps=n)
+    ens = Ensemble([config_from_case(case, dtype)])
+    g = to_dev(w0, tdt).reshape(-1).contiguous()
+    Fg = F.reshape(-1).contiguous()
+    side = torch.cuda.Stream()  # graphs are captured on a non-default stream
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ens.step(g, Fg, nsteps=2, use_graph=True)
+        ens.step(g, Fg, nsteps=4, use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(one, split)
+    assert torch.equal(one.reshape(-1), g)
+
+
 # ----------------------------------------------------------------- ensemble
 def _members(dtype):
     sizes = [(64, 128, 1), (96, 192, 1), (32, 64, 1), (128, 256, 1), (48, 96, 1)]
@@ -313,8 +346,12 @@ def test_ensemble_matches_single_basins_and_oracle(dtype, use_graph):
     Fp = ens.pack(Fs)
     nsteps = 6
     # two calls: the graph is captured on the first and replayed on both
-    ens.step(W, Fp, nsteps=nsteps // 2, use_graph=use_graph)
-    ens.step(W, Fp, nsteps=nsteps - nsteps // 2, use_graph=use_graph)
+    # (graphs need a non-default stream)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ens.step(W, Fp, nsteps=nsteps // 2, use_graph=use_graph)
+        ens.step(W, Fp, nsteps=nsteps - nsteps // 2, use_graph=use_graph)
     torch.cuda.synchronize()
     tdt = _tdt(dtype)
     for m, c in enumerate(cases):
