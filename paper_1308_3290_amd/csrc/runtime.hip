@@ -540,7 +540,8 @@ cgp_status create_common(const cgp_config* cfgs, int count, void* ws, size_t byt
   return CGP_OK;
 }
 
-// Graph of one step for (omega, forcing, pos), captured on first use.
+// Graph of one step for (omega, forcing, pos), captured on first use; pos = 3
+// (fused handles): the three steps of a full rotation, pos 0 -> 0.
 template <typename T>
 cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, hipStream_t s,
                       hipGraphExec_t* out) {
@@ -552,7 +553,13 @@ cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, hipStream_t s,
   }
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-  hipError_t e = h->plan.fused ? enqueue_step_fused<T>(h, w, F, pos, s) : enqueue_step<T>(h, w, F, s);
+  hipError_t e = hipSuccess;
+  if (!h->plan.fused) {
+    e = enqueue_step<T>(h, w, F, s);
+  } else {
+    for (int q = (pos == 3 ? 0 : pos); q < (pos == 3 ? 3 : pos + 1) && e == hipSuccess; ++q)
+      e = enqueue_step_fused<T>(h, w, F, q, s);
+  }
   hipError_t e2 = hipStreamEndCapture(s, &g);
   if (e != hipSuccess) return hip_fail(e, "capture step");
   if (e2 != hipSuccess) return hip_fail(e2, "end capture");
@@ -587,16 +594,22 @@ cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_
     // stage buffers; the result is copied back to omega unless it is there
     HIP_TRY(enqueue_pass<T>(h, 0, w, nullptr, 0, s), "pass A launch");
     int pos = 0;
-    for (int n = 0; n < nsteps; ++n) {
+    for (int n = 0; n < nsteps;) {
       if (graph) {
+        // whole rotations as one graph, the rest step by step
+        const int q = (pos == 0 && nsteps - n >= 3) ? 3 : pos;
         hipGraphExec_t exec = nullptr;
-        cgp_status st = step_graph<T>(h, w, F, pos, s, &exec);
+        cgp_status st = step_graph<T>(h, w, F, q, s, &exec);
         if (st != CGP_OK) return st;
         HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
+        const int done = q == 3 ? 3 : 1;
+        n += done;
+        pos = (pos + done) % 3;
       } else {
         HIP_TRY(enqueue_step_fused<T>(h, w, F, pos, s), "step launch");
+        ++n;
+        pos = (pos + 1) % 3;
       }
-      pos = (pos + 1) % 3;
     }
     if (pos != 0) {
       const T* from = h->at<T>(pos == 1 ? h->plan.lay.st1 : h->plan.lay.st2);
