@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--only", default="", help="comma list: l0,l1,l2,timed (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration runs)")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
+                    help="print per-kernel launch statistics of a rocprofv3 --kernel-trace CSV "
+                         "as a markdown table and exit (no GPU needed)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) into "
                          "profiles/traffic_c1_l1.json and exit (no GPU needed)")
@@ -97,6 +100,24 @@ def summarize_pmc(fetch_csv, write_csv):
     print(json.dumps(out, indent=1))
 
 
+def summarize_trace(trace_csv):
+    """Launch count and duration statistics (us) per kernel of a kernel trace."""
+    import csv
+    import statistics
+    per = {}
+    for r in csv.DictReader(open(trace_csv)):
+        name = r["Kernel_Name"]
+        if "cgp::" in name:
+            name = name.split("cgp::")[1].split("(")[0]
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+        per.setdefault(name, []).append(dur)
+    print("| kernel | launches | mean us | median us | min us | max us |")
+    print("|---|---|---|---|---|---|")
+    for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        print(f"| {name} | {len(d)} | {statistics.mean(d):.2f} | {statistics.median(d):.2f} | "
+              f"{min(d):.2f} | {max(d):.2f} |")
+
+
 def pass_bytes(case, es):
     """Algorithmic bytes of one launch of each pass as timed by cgp_time_passes
     (fine node arrays with ring, coarse interior spectra); pass D in its
@@ -120,6 +141,9 @@ def source_hash():
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return
