@@ -109,11 +109,12 @@ struct Launch {
   // allow the transform kernels up to `bytes` of dynamic LDS per block
   static hipError_t prepare(size_t bytes);
   // passes C + D fused (one layer): x transform of the psi spectra wt,
-  // prolongation into LDS, stencil + RK3; with wnext != NULL also pass A of
-  // the next stage on the result (spectra into wnext)
+  // prolongation into registers, stencil + RK3; with wnext != NULL also pass
+  // A of the next stage on the result (spectra into wnext); with psi_out !=
+  // NULL the prolonged psi is stored too
   static hipError_t prolong_stencil(const MemberDesc* md, const Group& g, const T* wt, T* wnext,
                                     const cplx<T>* tw, const T* ws, const T* forcing, const T* wn,
-                                    T* out, double a, double b, hipStream_t s);
+                                    T* out, T* psi_out, double a, double b, hipStream_t s);
   static hipError_t prepare_fused(size_t bytes);
   // pass D: Arakawa right-hand side + TVD-RK3 stage combine
   static hipError_t stencil_rk3(const MemberDesc* md, int nm, int nblk, const T* ws,

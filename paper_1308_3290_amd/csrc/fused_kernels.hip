@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
     const T* __restrict__ wt, T* __restrict__ wnext, const cplx<T>* __restrict__ twg,
     const T* __restrict__ ws, const T* __restrict__ forcing, const T* __restrict__ wn,
-    T* __restrict__ out, double a_, double b_) {
+    T* __restrict__ out, T* __restrict__ psi_out, double a_, double b_) {
   constexpr int NT = kFusedThreads;
   constexpr int NR = C * TJ + 1;      // the most own fine rows (+1: top wall row)
   constexpr int E = NEXT ? C - 1 : 0;  // computed rows below the block
@@ -177,9 +177,15 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   }
   __syncthreads();
 
-  // ---- walls: columns 0 and nx of the own rows
-  if (t < nfr) O[(size_t)(R0 + t) * pitch] = T(0);
-  else if (t >= 64 && t < 64 + nfr) O[(size_t)(R0 + t - 64) * pitch + nx] = T(0);
+  // ---- walls: columns 0 and nx of the own rows (of psi_out too)
+  T* PO = psi_out ? psi_out + d.field_off : nullptr;
+  if (t < nfr) {
+    O[(size_t)(R0 + t) * pitch] = T(0);
+    if (PO) PO[(size_t)(R0 + t) * pitch] = T(0);
+  } else if (t >= 64 && t < 64 + nfr) {
+    O[(size_t)(R0 + t - 64) * pitch + nx] = T(0);
+    if (PO) PO[(size_t)(R0 + t - 64) * pitch + nx] = T(0);
+  }
 
   // ---- stencil + RK3 on the computed rows (tile row u = fine row RB0 + u)
   const T dt = T(d.dt), a = T(a_), b = T(b_);
@@ -265,7 +271,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
         v = b * (w.C + dt * G);
         if (a_ != 0.0) v += a * nv[u - 1];
       }
-      if (u > E) O[(size_t)rr * pitch + x] = v;
+      if (u > E) {
+        O[(size_t)rr * pitch + x] = v;
+        if (PO) PO[(size_t)rr * pitch + x] = P[1][u];  // the prolonged psi (0 on wall rows)
+      }
       res[u - 1] = v;
       ws0 = wc0; ws1 = wc1; ws2 = wc2;
       wc0 = wn0; wc1 = wn1; wc2 = wn2;
@@ -331,12 +340,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
 template <typename T>
 hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, const T* wt,
                                       T* wnext, const cplx<T>* tw, const T* ws,
-                                      const T* forcing, const T* wn, T* out, double a, double b,
-                                      hipStream_t s) {
+                                      const T* forcing, const T* wn, T* out, T* psi_out,
+                                      double a, double b, hipStream_t s) {
 #define LAUNCH(C, TJ, LC, NX)                                                                \
   hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC, NX>), dim3(g.nblk), dim3(kFusedThreads), \
                      g.lds, s, md, g.members, g.count, g.nblk, wt, wnext, tw, ws, forcing, wn, \
-                     out, a, b)
+                     out, psi_out, a, b)
 #define BY_LEN(C, TJ, NX)                      \
   switch (g.L & 0xffff) {                      \
     case 256: LAUNCH(C, TJ, 256, NX); break;   \

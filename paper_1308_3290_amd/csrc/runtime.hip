@@ -357,15 +357,16 @@ hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hi
 }
 
 // Fused pass C + D over every member: out = a wn + b (ws + dt G(ws, psi(ws)));
-// with `next`, also pass A on out (its spectra into wt for the next stage).
+// with `next`, also pass A on out (its spectra into wt for the next stage);
+// psi_out (optional) receives psi(ws).
 template <typename T>
 hipError_t enqueue_fused(cgp_handle* h, const T* ws, const T* forcing, const T* wn, T* out,
-                         double a, double b, bool next, hipStream_t s) {
+                         double a, double b, bool next, hipStream_t s, T* psi_out = nullptr) {
   const Plan& p = h->plan;
   for (int i = 0; i < h->ngroups(3); ++i) {
     hipError_t e = Launch<T>::prolong_stencil(
         h->d_md(), h->group(3, i), h->at<T>(p.lay.wt2), next ? h->at<T>(p.lay.wt) : nullptr,
-        h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, a, b, s);
+        h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, psi_out, a, b, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -416,6 +417,23 @@ hipError_t enqueue_step_fused(cgp_handle* h, T* omega, const T* forcing, int pos
     hipError_t e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s);
     if (e == hipSuccess)
       e = enqueue_fused<T>(h, src[st], forcing, S, dst[st], kRkA[st], kRkB[st], true, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// One fused step into explicit buffers (the adjoint's tape): stage inputs
+// w[0..2] (w[0] holds omega_n, and the spectra of w[0] must be in place),
+// stream functions psi[0..2], result wnext (distinct from all of them).
+template <typename T>
+hipError_t enqueue_step_tape(cgp_handle* h, T* const w[3], T* const psi[3], T* wnext,
+                             const T* forcing, hipStream_t s) {
+  T* dst[3] = {w[1], w[2], wnext};
+  for (int st = 0; st < 3; ++st) {
+    hipError_t e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s);
+    if (e == hipSuccess)
+      e = enqueue_fused<T>(h, w[st], forcing, w[0], dst[st], kRkA[st], kRkB[st], true, s,
+                           psi[st]);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -810,19 +828,30 @@ cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forc
   double* P = X2 + N;
   double* ACC = P + N;
   const double* F = static_cast<const double*>(forcing);
-  // forward recompute: step n reads w0(n) (a copy of the state) and leaves
-  // w_{n+1} in w0(n+1), or in X1 for the last step (not needed afterwards).
+  // forward recompute: step n reads w0(n) and leaves w_{n+1} in w0(n+1), or
+  // in X1 for the last step (not needed afterwards).
   HIP_TRY(hipMemcpyAsync(slot(0, 0), omega_n, N * sizeof(double), hipMemcpyDeviceToDevice, s),
           "tape copy");
-  for (int n = 0; n < nsteps; ++n) {
-    double* next = (n + 1 < nsteps) ? slot(n + 1, 0) : X1;
-    HIP_TRY(hipMemcpyAsync(next, slot(n, 0), N * sizeof(double), hipMemcpyDeviceToDevice, s),
-            "tape copy");
-    // enqueue_step updates its omega argument in place: run it on `next`
-    // (holding w_n) so that w0(n) stays intact.
-    HIP_TRY(enqueue_step<double>(h, next, F, s, slot(n, 1), slot(n, 2), slot(n, 3), slot(n, 4),
-                                 slot(n, 5)),
-            "forward recompute");
+  if (h->plan.fused) {
+    // the fused steps of the forward run, writing every stage into the tape
+    HIP_TRY(enqueue_pass<double>(h, 0, slot(0, 0), nullptr, 0, s), "forward recompute");
+    for (int n = 0; n < nsteps; ++n) {
+      double* const w[3] = {slot(n, 0), slot(n, 1), slot(n, 2)};
+      double* const ps[3] = {slot(n, 3), slot(n, 4), slot(n, 5)};
+      HIP_TRY(enqueue_step_tape<double>(h, w, ps, (n + 1 < nsteps) ? slot(n + 1, 0) : X1, F, s),
+              "forward recompute");
+    }
+  } else {
+    for (int n = 0; n < nsteps; ++n) {
+      double* next = (n + 1 < nsteps) ? slot(n + 1, 0) : X1;
+      HIP_TRY(hipMemcpyAsync(next, slot(n, 0), N * sizeof(double), hipMemcpyDeviceToDevice, s),
+              "tape copy");
+      // enqueue_step updates its omega argument in place: run it on `next`
+      // (holding w_n) so that w0(n) stays intact.
+      HIP_TRY(enqueue_step<double>(h, next, F, s, slot(n, 1), slot(n, 2), slot(n, 3),
+                                   slot(n, 4), slot(n, 5)),
+              "forward recompute");
+    }
   }
   // reverse sweep
   double* lam = static_cast<double*>(lambda);
