@@ -272,7 +272,10 @@ __host__ __device__ constexpr int tw_per_thread() {
 
 // Lengths with a compile-time transform (0: none).
 __host__ __device__ constexpr int fft_special(int L) {
-  return (L == 256 || L == 512 || L == 1024 || L == 2048) ? L : 0;
+  return (L == 128 || L == 256 || L == 384 || L == 512 || L == 768 || L == 1024 || L == 1536 ||
+          L == 2048)
+             ? L
+             : 0;
 }
 
 // Copy n twiddle values from global memory to LDS.

@@ -74,12 +74,16 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   const int RB0 = R0 - 1 - E;                    // fine row of tile row 0
   const int nW = (nrow + 2) * pitch;
 
-  // LDS: [ FFT buffers ] [ twiddles ] [ coarse psi rows ] [ vorticity tile ]
+  // LDS: [ FFT buffers | later the vorticity tile | later the restriction
+  // rows and the next transform's buffers ] [ twiddles ] [ coarse psi rows ].
+  // Sharing the first region keeps the block small enough for two blocks per
+  // CU when there are many (ensembles).
+  const int region = (max(4 * LP * (int)sizeof(cplx<T>), NP * pitch * (int)sizeof(T)) + 15) & ~15;
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = buf + 4 * LP;
+  T* wtile = reinterpret_cast<T*>(smem);
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + region);
   T* psc = reinterpret_cast<T*>(tw + ntw);
   const int prow = Mx + 1;
-  T* wtile = psc + (TJ + 2) * prow;
 
   // ---- issue the block's global loads.  They are unconditional (a lane
   // without an element reads element 0 of the same array and discards it), so
@@ -170,6 +174,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
       psc[r * prow + i] = v;
     }
   }
+  __syncthreads();  // the transform's output is consumed: the tile may overwrite it
 #pragma unroll
   for (int q = 0; q < kWPer; ++q) {
     const int e = t + NT * q;
@@ -291,12 +296,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
 #pragma unroll
       for (int k = 0; k < NRT; ++k) rt[k * pitch + x] = res[k];
     }
-    if (t == 0) {
-      buf[pad(0)] = {T(0), T(0)};
-      buf[pad(Mx)] = {T(0), T(0)};
-    }
     __syncthreads();
     const int i = 1 + t;
+    cplx<T> z = {T(0), T(0)};
     if (i < Mx) {
       // x-weighted sums of each fine row, then the y weights (as pass A)
       T racc[NRT];
@@ -319,9 +321,16 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
       }
       // packed as pass A packs them (the wall row 0 as 0), so that both give
       // the same spectra bit for bit
-      const cplx<T> z = {j0 >= 1 ? v[0] : T(0), v[1]};
+      z = {j0 >= 1 ? v[0] : T(0), v[1]};
+    }
+    __syncthreads();  // rt is read: the transform buffers may overwrite it
+    if (i < Mx) {
       buf[pad(i)] = z;
       buf[pad(2 * Mx - i)] = {-z.x, -z.y};
+    }
+    if (t == 0) {
+      buf[pad(0)] = {T(0), T(0)};
+      buf[pad(Mx)] = {T(0), T(0)};
     }
     const cplx<T>* Z2 = fft_run<T, LC, NT>(buf, buf + LP, 1, L, d.nst_r, d.stw_r, tw);
     if (i < Mx) {
@@ -346,18 +355,37 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
   hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC, NX>), dim3(g.nblk), dim3(kFusedThreads), \
                      g.lds, s, md, g.members, g.count, g.nblk, wt, wnext, tw, ws, forcing, wn, \
                      out, psi_out, a, b)
-#define BY_LEN(C, TJ, NX)                      \
+// rows hold at most kFusedMaxNx intervals, so c = 1, 2, 4 have transform
+// lengths of at most 1024, 512, 256
+#define BY_LEN1(NX)                            \
   switch (g.L & 0xffff) {                      \
-    case 256: LAUNCH(C, TJ, 256, NX); break;   \
-    case 512: LAUNCH(C, TJ, 512, NX); break;   \
-    case 1024: LAUNCH(C, TJ, 1024, NX); break; \
-    default: LAUNCH(C, TJ, 0, NX);             \
+    case 128: LAUNCH(1, 2, 128, NX); break;    \
+    case 256: LAUNCH(1, 2, 256, NX); break;    \
+    case 384: LAUNCH(1, 2, 384, NX); break;    \
+    case 512: LAUNCH(1, 2, 512, NX); break;    \
+    case 768: LAUNCH(1, 2, 768, NX); break;    \
+    case 1024: LAUNCH(1, 2, 1024, NX); break;  \
+    default: LAUNCH(1, 2, 0, NX);              \
   }
-#define BY_C(NX)                       \
-  switch (g.L >> 16) {                 \
-    case 1: BY_LEN(1, 2, NX); break;   \
-    case 2: BY_LEN(2, 2, NX); break;   \
-    case 4: BY_LEN(4, 1, NX); break;   \
+#define BY_LEN2(NX)                            \
+  switch (g.L & 0xffff) {                      \
+    case 128: LAUNCH(2, 2, 128, NX); break;    \
+    case 256: LAUNCH(2, 2, 256, NX); break;    \
+    case 384: LAUNCH(2, 2, 384, NX); break;    \
+    case 512: LAUNCH(2, 2, 512, NX); break;    \
+    default: LAUNCH(2, 2, 0, NX);              \
+  }
+#define BY_LEN4(NX)                            \
+  switch (g.L & 0xffff) {                      \
+    case 128: LAUNCH(4, 1, 128, NX); break;    \
+    case 256: LAUNCH(4, 1, 256, NX); break;    \
+    default: LAUNCH(4, 1, 0, NX);              \
+  }
+#define BY_C(NX)                          \
+  switch (g.L >> 16) {                    \
+    case 1: BY_LEN1(NX); break;           \
+    case 2: BY_LEN2(NX); break;           \
+    case 4: BY_LEN4(NX); break;           \
     default: return hipErrorInvalidValue; \
   }
   if (wnext) {
@@ -366,7 +394,9 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
     BY_C(false)
   }
 #undef BY_C
-#undef BY_LEN
+#undef BY_LEN1
+#undef BY_LEN2
+#undef BY_LEN4
 #undef LAUNCH
   return hipGetLastError();
 }
@@ -375,15 +405,12 @@ template <typename T>
 hipError_t Launch<T>::prepare_fused(size_t bytes) {
   const int b = (int)bytes;
   const void* fns[] = {
-#define F1(C, TJ, NX)                                                         \
-  reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 0, NX>),         \
-      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 256, NX>),   \
-      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 512, NX>),   \
-      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, 1024, NX>)
-#define FNS(C, TJ) F1(C, TJ, false), F1(C, TJ, true)
-      FNS(1, 2), FNS(2, 2), FNS(4, 1)
-#undef FNS
-#undef F1
+#define K(C, TJ, LC) reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, false>), \
+                     reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, true>)
+      K(1, 2, 0), K(1, 2, 128), K(1, 2, 256), K(1, 2, 384), K(1, 2, 512), K(1, 2, 768),
+      K(1, 2, 1024), K(2, 2, 0), K(2, 2, 128), K(2, 2, 256), K(2, 2, 384), K(2, 2, 512),
+      K(4, 1, 0), K(4, 1, 128), K(4, 1, 256)
+#undef K
   };
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);

@@ -266,10 +266,13 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                  [&](MemberDesc& d, HostGroup&) {
                    // vorticity tile: own rows, c - 1 rows below them for the
                    // next stage's restriction, one more on each side
+                   // (shares LDS with the transform buffers)
                    const int tj = fused_tj(d.c), nr = fused_nr(d.c);
-                   const size_t lds = ((size_t)4 * lpad(d.Lr) + d.ntw_r) * cs +
-                                      ((size_t)(tj + 2) * (d.Mx + 1) +
-                                       (size_t)(nr + 2 + d.c - 1) * (d.nx + 1)) * es;
+                   const size_t tile = (size_t)(nr + 2 + d.c - 1) * (d.nx + 1) * es;
+                   const size_t region =
+                       (std::max((size_t)4 * lpad(d.Lr) * cs, tile) + 15) & ~(size_t)15;
+                   const size_t lds = region + (size_t)d.ntw_r * cs +
+                                      (size_t)(tj + 2) * (d.Mx + 1) * es;
                    return std::make_pair((d.My + tj - 1) / tj, lds);
                  },
                  plan->groups[3]);

@@ -426,13 +426,17 @@ __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* _
 // ---------------------------------------------------------------------------
 // Launch the instantiation for the group's transform length (g.L: a length
 // with a compile-time transform, or 0 for the runtime engine).
-#define CGP_BY_LENGTH(LEN, CALL) \
-  switch (LEN) {                 \
-    case 256: CALL(256); break;  \
-    case 512: CALL(512); break;  \
+#define CGP_BY_LENGTH(LEN, CALL)  \
+  switch (LEN) {                  \
+    case 128: CALL(128); break;   \
+    case 256: CALL(256); break;   \
+    case 384: CALL(384); break;   \
+    case 512: CALL(512); break;   \
+    case 768: CALL(768); break;   \
     case 1024: CALL(1024); break; \
+    case 1536: CALL(1536); break; \
     case 2048: CALL(2048); break; \
-    default: CALL(0);            \
+    default: CALL(0);             \
   }
 
 template <typename T>
@@ -485,7 +489,7 @@ hipError_t Launch<T>::prepare(size_t bytes) {
       reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC, 2>),   \
       reinterpret_cast<const void*>(&k_col_solve<T, LC>),            \
       reinterpret_cast<const void*>(&k_rowdst_prolong<T, LC>)
-      FNS(0), FNS(256), FNS(512), FNS(1024), FNS(2048)
+      FNS(0), FNS(128), FNS(256), FNS(384), FNS(512), FNS(768), FNS(1024), FNS(1536), FNS(2048)
 #undef FNS
   };
   for (const void* f : fns) {
