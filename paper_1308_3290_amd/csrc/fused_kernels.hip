@@ -114,15 +114,27 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   const T* WN = wn + d.field_off;
   T* O = out + d.field_off;
   const long long g0 = (long long)RB0 * pitch;
-  const long long gend = (long long)(ny + 1) * pitch;
+  // Element e of the tile is tile row e / pitch, column e % pitch, tracked
+  // incrementally; the ring and the rows outside 1 .. ny-1 are stored as 0, so
+  // that the stencil reads the tile without masks.
   T wv[kWPer];
+  {
+    int er = t / pitch, ec = t - er * pitch;
+    const int dr = NT / pitch, dc = NT - dr * pitch;
 #pragma unroll
-  for (int q = 0; q < kWPer; ++q) {
-    const int e = t + NT * q;
-    const long long g = g0 + e;
-    const bool in = e < nW && g >= 0 && g < gend;
-    const T v = W[in ? g : 0];
-    wv[q] = in ? v : T(0);
+    for (int q = 0; q < kWPer; ++q) {
+      const int e = t + NT * q;
+      const int fr = RB0 + er;
+      const bool in = e < nW && fr >= 1 && fr <= ny - 1 && ec >= 1 && ec <= nx - 1;
+      const T v = W[in ? g0 + e : 0];
+      wv[q] = in ? v : T(0);
+      er += dr;
+      ec += dc;
+      if (ec >= pitch) {
+        ec -= pitch;
+        ++er;
+      }
+    }
   }
   // forcing and omega_n at the thread's column x = 1 + t, computed rows
   const int x = 1 + t;
@@ -202,35 +214,26 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
 #pragma unroll
   for (int u = 0; u < NO; ++u) res[u] = T(0);
   if (x < nx) {
-    // coarse columns I0 .. I0+2 (clamped to the wall column Mx) cover the
-    // fine columns x-1 .. x+1 for C >= 2; for C = 1 they are those columns
-    const int I0 = (x - 1) / C;
-    T A[3][TJ + 2];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      const int I = min(I0 + m, Mx);
-#pragma unroll
-      for (int r = 0; r < TJ + 2; ++r) A[m][r] = psc[r * prow + I];
-    }
-    // P[dx][u]: psi at fine column x-1+dx, tile row u (bilinear, Sec. 3.1)
+    // P[dx][u]: psi at fine column x-1+dx, tile row u (bilinear, Sec. 3.1):
+    // x weights (C - fx, fx)/C^2 on the coarse columns I, I+1 (I+1 clamped
+    // to the wall column Mx), then the compile-time y weights (C - fy, fy).
+    // The coarse rows are prow apart; prow is a constant when L is.
+    const int prow_c = LC ? LC / 2 + 1 : prow;
     T P[3][NP];
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-      const int xx = x - 1 + dx;
-      const int rel = xx / C - I0;  // 0 or 1 (0 .. 2 when C = 1)
-      const int fx = xx - (xx / C) * C;
+      const int xx = x - 1 + dx;  // 0 .. nx
       T cv[TJ + 2];
+      if constexpr (C == 1) {
 #pragma unroll
-      for (int r = 0; r < TJ + 2; ++r) {
-        T lo, hi;
-        if constexpr (C == 1) {
-          lo = dx == 0 ? A[0][r] : (dx == 1 ? A[1][r] : A[2][r]);
-          hi = T(0);
-        } else {
-          lo = rel == 0 ? A[0][r] : A[1][r];
-          hi = rel == 0 ? A[1][r] : A[2][r];
-        }
-        cv[r] = T(C - fx) * lo + T(fx) * hi;
+        for (int r = 0; r < TJ + 2; ++r) cv[r] = psc[r * prow_c + xx];
+      } else {
+        const int I = xx / C, fx = xx - I * C;
+        const T a0 = T(C - fx) * kInvC2, a1 = T(fx) * kInvC2;
+        const T* p0 = psc + I;
+        const T* p1 = psc + min(I + 1, Mx);
+#pragma unroll
+        for (int r = 0; r < TJ + 2; ++r) cv[r] = a0 * p0[r * prow_c] + a1 * p1[r * prow_c];
       }
 #pragma unroll
       for (int u = 0; u < NP; ++u) {
@@ -239,43 +242,31 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
         const int m = OFF + u;
         const int jr = m / C, fy = m - jr * C;
         const T top = jr + 1 < TJ + 2 ? cv[jr + 1 < TJ + 2 ? jr + 1 : TJ + 1] : T(0);
-        P[dx][u] = (T(C - fy) * cv[jr < TJ + 2 ? jr : TJ + 1] + T(fy) * top) * kInvC2;
+        P[dx][u] = T(C - fy) * cv[jr < TJ + 2 ? jr : TJ + 1] + T(fy) * top;
       }
     }
-    const bool mw = x > 1, me = x < nx - 1;
-    auto wrow = [&](int u, T& w0, T& w1, T& w2) {
-      const int rr = RB0 + u;
-      const bool in = rr >= 1 && rr <= ny - 1;
-      const T* p = wtile + u * pitch + x;
-      w0 = (in && mw) ? p[-1] : T(0);
-      w1 = in ? p[0] : T(0);
-      w2 = (in && me) ? p[1] : T(0);
-    };
-    T ws0, ws1, ws2, wc0, wc1, wc2;
-    wrow(0, ws0, ws1, ws2);
-    wrow(1, wc0, wc1, wc2);
+    // rows 1 .. NO-1 exist in every block (the last block's row NO is the top
+    // wall); rows below 1 (first block) are computed from zeros and dropped
+    const T* wt0 = wtile + x;
+    T ws0 = wt0[-1], ws1 = wt0[0], ws2 = wt0[1];
+    T wc0 = wt0[pitch - 1], wc1 = wt0[pitch], wc2 = wt0[pitch + 1];
 #pragma unroll
-    for (int u = 1; u <= NO; ++u) {
-      if (u > nrow) break;
-      T wn0, wn1, wn2;
-      wrow(u + 1, wn0, wn1, wn2);
+    for (int u = 1; u < NO; ++u) {
+      const T* wr = wt0 + (u + 1) * pitch;
+      const T wn0 = wr[-1], wn1 = wr[0], wn2 = wr[1];
       const int rr = RB0 + u;
-      T v = T(0);
-      if (rr >= 1 && rr <= ny - 1) {
-        Nbr<T> p, w;
-        p.C = P[1][u]; p.E = P[2][u]; p.W = P[0][u];
-        p.N = P[1][u + 1]; p.S = P[1][u - 1];
-        p.NE = P[2][u + 1]; p.NW = P[0][u + 1];
-        p.SE = P[2][u - 1]; p.SW = P[0][u - 1];
-        w.C = wc1; w.E = wc2; w.W = wc0;
-        w.N = wn1; w.S = ws1;
-        w.NE = wn2; w.NW = wn0;
-        w.SE = ws2; w.SW = ws0;
-        const T G =
-            -cj * arakawa12(p, w) - cb * beta3(p) + nu * lap5(w, idx2, idy2) + fv[u - 1];
-        v = b * (w.C + dt * G);
-        if (a_ != 0.0) v += a * nv[u - 1];
-      }
+      Nbr<T> p, w;
+      p.C = P[1][u]; p.E = P[2][u]; p.W = P[0][u];
+      p.N = P[1][u + 1]; p.S = P[1][u - 1];
+      p.NE = P[2][u + 1]; p.NW = P[0][u + 1];
+      p.SE = P[2][u - 1]; p.SW = P[0][u - 1];
+      w.C = wc1; w.E = wc2; w.W = wc0;
+      w.N = wn1; w.S = ws1;
+      w.NE = wn2; w.NW = wn0;
+      w.SE = ws2; w.SW = ws0;
+      const T G = -cj * arakawa12(p, w) - cb * beta3(p) + nu * lap5(w, idx2, idy2) + fv[u - 1];
+      T v = a * nv[u - 1] + b * (w.C + dt * G);  // a = 0 in stage 1
+      v = rr >= 1 ? v : T(0);
       if (u > E) {
         O[(size_t)rr * pitch + x] = v;
         if (PO) PO[(size_t)rr * pitch + x] = P[1][u];  // the prolonged psi (0 on wall rows)
@@ -283,6 +274,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
       res[u - 1] = v;
       ws0 = wc0; ws1 = wc1; ws2 = wc2;
       wc0 = wn0; wc1 = wn1; wc2 = wn2;
+    }
+    if (last) {  // the top wall row
+      O[(size_t)ny * pitch + x] = T(0);
+      if (PO) PO[(size_t)ny * pitch + x] = T(0);
     }
   }
   if constexpr (NEXT) {
