@@ -136,6 +136,15 @@ struct AdjLaunch {
                             const double* ws, const double* psi, double* lam_out,
                             double* psi_src, double* acc, double* gF, double a, double b,
                             int acc_mode, hipStream_t s);
+  // The same stage fused with the solve of the previous stage's source (its
+  // y-solved spectra wt2; NULL for the first stage of a sweep: lam_in = lin)
+  // and the restriction + x transform of this stage's source (into wnext).
+  // Blocks as the fused forward pass (group of pass CD).
+  static hipError_t fused(const MemberDesc* md, const Group& g, const double* wt2, double* wnext,
+                          const cplx<double>* tw, const double* lin, const double* ws,
+                          const double* psi, double* lout, double* acc, double* gF, double a,
+                          double b, int acc_mode, hipStream_t s);
+  static hipError_t prepare_fused(size_t bytes);
 };
 
 }  // namespace cgp

@@ -517,6 +517,7 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
     size_t lds_f = 0;
     for (const HostGroup& g : p.groups[3]) lds_f = std::max(lds_f, g.lds);
     HIP_TRY(Launch<T>::prepare_fused(lds_f), "LDS attribute (fused pass)");
+    if (p.dtype == CGP_F64) HIP_TRY(AdjLaunch::prepare_fused(lds_f), "LDS attribute (adjoint)");
   }
   HIP_TRY(hipMemcpyAsync(h->ws, h->host_tables.data(), L.wt, hipMemcpyHostToDevice, s),
           "table upload");
@@ -861,6 +862,30 @@ cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forc
   double* gF = static_cast<double*>(grad_forcing);
   const MemberDesc* md = h->d_md();
   const int nb = h->plan.nblk_d;
+  if (h->plan.fused) {
+    // each stage: the fused adjoint kernel (which finishes the previous
+    // stage's solve) and pass B on its source; pass C ends the sweep
+    double* wt = h->at<double>(h->plan.lay.wt);
+    double* wt2 = h->at<double>(h->plan.lay.wt2);
+    const cplx<double>* tw = h->at<cplx<double>>(h->plan.lay.tw);
+    bool prev = false;
+    for (int n = nsteps - 1; n >= 0; --n) {
+      const double* lin[3] = {X1, X2, lam};
+      double* lout[3] = {lam, X1, X2};
+      for (int st = 2; st >= 0; --st) {
+        const int mode = st == 2 ? 0 : (st == 1 ? 1 : 2);
+        for (int i = 0; i < h->ngroups(3); ++i)
+          HIP_TRY(AdjLaunch::fused(md, h->group(3, i), prev ? wt2 : nullptr, wt, tw, lin[st],
+                                   slot(n, st), slot(n, 3 + st), lout[st], ACC, gF, kRkA[st],
+                                   kRkB[st], mode, s),
+                  "adjoint stage");
+        HIP_TRY(enqueue_pass<double>(h, 1, nullptr, nullptr, 0, s), "adjoint solve");
+        prev = true;
+      }
+    }
+    HIP_TRY(enqueue_pass<double>(h, 2, nullptr, lam, 1, s), "adjoint solve");
+    return CGP_OK;
+  }
   for (int n = nsteps - 1; n >= 0; --n) {
     // stage 2: lam_3 = lam -> X2 ; stage 1: X2 -> X1 ; stage 0: X1 -> lam
     const double* lin[3] = {X1, X2, lam};
