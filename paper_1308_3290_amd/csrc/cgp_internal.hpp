@@ -116,6 +116,11 @@ struct Launch {
                                     const cplx<T>* tw, const T* ws, const T* forcing, const T* wn,
                                     T* out, T* psi_out, double a, double b, hipStream_t s);
   static hipError_t prepare_fused(size_t bytes);
+  // the same for two layers (mode recombination and split inside; c = 2, 4)
+  static hipError_t prolong_stencil2(const MemberDesc* md, const Group& g, const T* wt, T* wnext,
+                                     const cplx<T>* tw, const T* ws, const T* forcing,
+                                     const T* wn, T* out, double a, double b, hipStream_t s);
+  static hipError_t prepare_fused2(size_t bytes);
   // pass D: Arakawa right-hand side + TVD-RK3 stage combine
   static hipError_t stencil_rk3(const MemberDesc* md, int nm, int nblk, const T* ws,
                                 const T* psi, const T* forcing, const T* wn, T* out, double a,

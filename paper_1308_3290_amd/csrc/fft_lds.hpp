@@ -201,7 +201,7 @@ __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nseq, in
 // output o + r Ns is pad(o) + r lpad(Ns) (Ns a multiple of 8) or pad(o) + r Ns
 // (Ns R divides 8).
 // ---------------------------------------------------------------------------
-template <typename T, int L, int S, int NT>
+template <typename T, int L, int S, int NT, int MAXSEQ>
 __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int nseq,
                                          const cplx<T>* tw) {
   constexpr StagePlan P = stage_plan(L);
@@ -210,7 +210,7 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
   static_assert(LR % 8 == 0, "read offsets need L/R to be a multiple of 8");
   static_assert(NS % 8 == 0 || 8 % (NS * R) == 0, "write offsets need Ns % 8 == 0 or Ns R | 8");
   constexpr int WS = NS % 8 == 0 ? lpad(NS) : NS;
-  constexpr int Q = (2 * LR + NT - 1) / NT;  // nseq <= 2
+  constexpr int Q = (MAXSEQ * LR + NT - 1) / NT;  // nseq <= MAXSEQ
   const int nb = nseq * LR;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -238,15 +238,15 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
   __syncthreads();
 }
 
-template <typename T, int L, int S, int NT>
+template <typename T, int L, int S, int NT, int MAXSEQ>
 __device__ __forceinline__ cplx<T>* ct_stages(cplx<T>* a, cplx<T>* b, int nseq,
                                               const cplx<T>* tw) {
   constexpr StagePlan P = stage_plan(L);
   if constexpr (S == P.n) {
     return a;
   } else {
-    ct_stage<T, L, S, NT>(a, b, nseq, tw);
-    return ct_stages<T, L, S + 1, NT>(b, a, nseq, tw);
+    ct_stage<T, L, S, NT, MAXSEQ>(a, b, nseq, tw);
+    return ct_stages<T, L, S + 1, NT, MAXSEQ>(b, a, nseq, tw);
   }
 }
 
@@ -259,8 +259,17 @@ __device__ __forceinline__ cplx<T>* fft_run(cplx<T>* a, cplx<T>* b, int nseq, in
     return fft_lds<T, NT>(a, b, nseq, L, nst, words, tw);
   } else {
     __syncthreads();
-    return ct_stages<T, LC, 0, NT>(a, b, nseq, tw);
+    return ct_stages<T, LC, 0, NT, 2>(a, b, nseq, tw);
   }
+}
+
+// Compile-time transform of up to four sequences (L = LC), same contract.
+template <typename T, int LC, int NT>
+__device__ __forceinline__ cplx<T>* fft_run4(cplx<T>* a, cplx<T>* b, int nseq,
+                                             const cplx<T>* tw) {
+  static_assert(LC != 0, "four sequences need a compile-time length");
+  __syncthreads();
+  return ct_stages<T, LC, 0, NT, 4>(a, b, nseq, tw);
 }
 
 // Twiddle values a thread of NT prefetches for a transform of length LC (0:

@@ -215,9 +215,13 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   }
   // A block transforms at most two sequences and at most 2048 complex values.
   auto pairs = [](int L) { return L <= 512 ? 2 : 1; };
-  // fused C + D pass (one layer, rows of at most kFusedMaxNx intervals, c <= 4)
-  bool fusable = nl == 1;
-  for (const MemberDesc& d : plan->md) fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4;
+  // fused C + D pass (rows of at most kFusedMaxNx intervals; one layer:
+  // c <= 4; two layers: c = 2 or 4 and a compile-time transform length)
+  bool fusable = true;
+  for (const MemberDesc& d : plan->md) {
+    fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4;
+    if (nl == 2) fusable = fusable && d.c >= 2 && fft_special(d.Lr) != 0;
+  }
   // pass A: one complex sequence per block: coarse rows packed as the fused
   // pass packs them when it computes the next stage's spectra (so that both
   // give the same bits), else a pair of rows; two layers: one row's modes
@@ -264,15 +268,16 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     build_groups(plan->md, PASS_CD,
                  [](const MemberDesc& d) { return (d.c << 16) | fft_special(d.Lr); },
                  [&](MemberDesc& d, HostGroup&) {
-                   // vorticity tile: own rows, c - 1 rows below them for the
-                   // next stage's restriction, one more on each side
-                   // (shares LDS with the transform buffers)
+                   // vorticity tile(s): own rows, c - 1 rows below them for
+                   // the next stage's restriction, one more on each side
+                   // (shares LDS with the transform buffers: two sequences
+                   // per block for one layer, tj + 2 for two)
                    const int tj = fused_tj(d.c), nr = fused_nr(d.c);
-                   const size_t tile = (size_t)(nr + 2 + d.c - 1) * (d.nx + 1) * es;
-                   const size_t region =
-                       (std::max((size_t)4 * lpad(d.Lr) * cs, tile) + 15) & ~(size_t)15;
+                   const size_t tile = (size_t)nl * (nr + 2 + d.c - 1) * (d.nx + 1) * es;
+                   const size_t fft = (size_t)(nl == 1 ? 4 : 8) * lpad(d.Lr) * cs;
+                   const size_t region = (std::max(fft, tile) + 15) & ~(size_t)15;
                    const size_t lds = region + (size_t)d.ntw_r * cs +
-                                      (size_t)(tj + 2) * (d.Mx + 1) * es;
+                                      (size_t)nl * (tj + 2) * (d.Mx + 1) * es;
                    return std::make_pair((d.My + tj - 1) / tj, lds);
                  },
                  plan->groups[3]);
@@ -367,9 +372,15 @@ hipError_t enqueue_fused(cgp_handle* h, const T* ws, const T* forcing, const T* 
                          double a, double b, bool next, hipStream_t s, T* psi_out = nullptr) {
   const Plan& p = h->plan;
   for (int i = 0; i < h->ngroups(3); ++i) {
-    hipError_t e = Launch<T>::prolong_stencil(
-        h->d_md(), h->group(3, i), h->at<T>(p.lay.wt2), next ? h->at<T>(p.lay.wt) : nullptr,
-        h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, psi_out, a, b, s);
+    T* wnext = next ? h->at<T>(p.lay.wt) : nullptr;
+    hipError_t e =
+        p.nlayers == 1
+            ? Launch<T>::prolong_stencil(h->d_md(), h->group(3, i), h->at<T>(p.lay.wt2), wnext,
+                                         h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, psi_out,
+                                         a, b, s)
+            : Launch<T>::prolong_stencil2(h->d_md(), h->group(3, i), h->at<T>(p.lay.wt2), wnext,
+                                          h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, a, b,
+                                          s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -516,8 +527,13 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
   if (p.fused) {
     size_t lds_f = 0;
     for (const HostGroup& g : p.groups[3]) lds_f = std::max(lds_f, g.lds);
-    HIP_TRY(Launch<T>::prepare_fused(lds_f), "LDS attribute (fused pass)");
-    if (p.dtype == CGP_F64) HIP_TRY(AdjLaunch::prepare_fused(lds_f), "LDS attribute (adjoint)");
+    if (p.nlayers == 1) {
+      HIP_TRY(Launch<T>::prepare_fused(lds_f), "LDS attribute (fused pass)");
+      if (p.dtype == CGP_F64)
+        HIP_TRY(AdjLaunch::prepare_fused(lds_f), "LDS attribute (adjoint)");
+    } else {
+      HIP_TRY(Launch<T>::prepare_fused2(lds_f), "LDS attribute (fused pass)");
+    }
   }
   HIP_TRY(hipMemcpyAsync(h->ws, h->host_tables.data(), L.wt, hipMemcpyHostToDevice, s),
           "table upload");

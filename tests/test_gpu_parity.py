@@ -153,12 +153,16 @@ def test_ragged_and_radix3_trajectories(nx, ny, level):
     assert errs.max() < TOL64
 
 
-@pytest.mark.parametrize("level", [0, 1, 2])
-def test_two_layer_trajectory_fp64(level):
+# 64x128: the unfused two-layer passes; 128x256 / 256x128 / 384x192 (coarse
+# rows of 64, 64 and 192 intervals, transforms of 128 and 384): the fused
+# two-layer stage kernel
+@pytest.mark.parametrize("nx,ny,level", [(64, 128, 0), (64, 128, 1), (64, 128, 2),
+                                         (128, 256, 1), (256, 128, 2), (384, 192, 1)])
+def test_two_layer_trajectory_fp64(nx, ny, level):
     c2 = ci.case_c2(level)
-    case = ci.make_case(64, 128, level=level, nlayers=2, f1=c2.f1, f2=c2.f2, drag=c2.drag,
+    case = ci.make_case(nx, ny, level=level, nlayers=2, f1=c2.f1, f2=c2.f2, drag=c2.drag,
                         dt=2.5e-5)
-    say(f"two-layer 64x128 level {level}, 50 steps FP64")
+    say(f"two-layer {nx}x{ny} level {level}, 50 steps FP64")
     rng = np.random.default_rng(c2.seed)
     Q0 = ci.initial_field(case, rng)
     F = ci.forcing_field(case)
@@ -288,17 +292,23 @@ def test_steps_are_deterministic():
     assert torch.equal(a, c)
 
 
-@pytest.mark.parametrize("nx,ny", [(96, 192), (256, 512)])
-@pytest.mark.parametrize("level", [0, 1, 2])
+@pytest.mark.parametrize("nx,ny,level,layers", [
+    (96, 192, 0, 1), (96, 192, 1, 1), (96, 192, 2, 1), (256, 512, 0, 1), (256, 512, 1, 1),
+    (256, 512, 2, 1), (256, 512, 1, 2), (256, 512, 2, 2)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_steps_split_over_calls_give_the_same_bits(nx, ny, level, dtype):
+def test_steps_split_over_calls_give_the_same_bits(nx, ny, level, layers, dtype):
     """Six steps in one call, in calls of 1, 2 and 3 steps, and through the
     captured-graph path agree bit for bit: the spectra a fused step leaves for
     the next one equal those the first step of a call computes itself, and the
     rotation of the state through the stage buffers does not matter."""
     from paper_1308_3290_amd.api import Ensemble, config_from_case
-    case = ci.make_case(nx, ny, level=level, dt=1e-4)
-    say(f"{nx}x{ny} level {level} {dtype}: 6 steps in one call vs 1+2+3 vs graph")
+    if layers == 2:
+        c2 = ci.case_c2(level)
+        case = ci.make_case(nx, ny, level=level, nlayers=2, f1=c2.f1, f2=c2.f2, drag=c2.drag,
+                            dt=2.5e-5)
+    else:
+        case = ci.make_case(nx, ny, level=level, dt=1e-4)
+    say(f"{nx}x{ny} level {level} layers {layers} {dtype}: 6 steps in one call vs 1+2+3 vs graph")
     tdt = _tdt(dtype)
     w0 = random_state(case, 21, 1e-2)
     F = to_dev(ci.forcing_field(case), tdt)
@@ -311,6 +321,8 @@ def test_steps_split_over_calls_give_the_same_bits(nx, ny, level, dtype):
     ens = Ensemble([config_from_case(case, dtype)])
     g = to_dev(w0, tdt).reshape(-1).contiguous()
     Fg = F.reshape(-1).contiguous()
+    if layers == 2:  # packed ensemble fields hold both layers (layer 2 forcing unused)
+        Fg = torch.cat([Fg, torch.zeros_like(Fg)])
     side = torch.cuda.Stream()  # graphs are captured on a non-default stream
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
