@@ -261,7 +261,7 @@ def main():
         del b, w, F
     # ---------------------------------------------------------------- adjoint ratio
     adj = None
-    if not args.no_adjoint and not only:
+    if not args.no_adjoint and (not only or "adj" in only):
         p = ci.adjoint_c4()
         c = p.case
         b = api.Basin(api.config_from_case(c), device=dev)

@@ -1,5 +1,5 @@
 // Reverse sweep of the adjoint CGP step, one RK3 stage per launch (one layer,
-// FP64), fused like the forward stage kernel.  With mu = b dt lam_in:
+// FP64, coarsening 2 or 4), fused like the forward stage kernel.  With mu = b dt lam_in:
 //   lam_in  = lin + P L^-1 R src_prev  (the previous stage's source, solved:
 //             its y-solved spectra are transformed back along x here and
 //             prolonged in registers, Sec. 3.1 and 4.3; absent for the first
@@ -298,7 +298,6 @@ hipError_t AdjLaunch::fused(const MemberDesc* md, const Group& g, const double* 
   }
 #define BY_C(PV)                          \
   switch (g.L >> 16) {                    \
-    case 1: BY_LEN(1, 2, PV); break;      \
     case 2: BY_LEN(2, 2, PV); break;      \
     case 4: BY_LEN(4, 1, PV); break;      \
     default: return hipErrorInvalidValue; \
@@ -319,8 +318,8 @@ hipError_t AdjLaunch::prepare_fused(size_t bytes) {
   const void* fns[] = {
 #define K(C, TJ, LC) reinterpret_cast<const void*>(&k_adjoint_fused<C, TJ, LC, false>), \
                      reinterpret_cast<const void*>(&k_adjoint_fused<C, TJ, LC, true>)
-      K(1, 2, 0), K(1, 2, 128), K(1, 2, 256), K(1, 2, 512), K(2, 2, 0), K(2, 2, 128),
-      K(2, 2, 256), K(2, 2, 512), K(4, 1, 0), K(4, 1, 128), K(4, 1, 256), K(4, 1, 512)
+      K(2, 2, 0), K(2, 2, 128), K(2, 2, 256), K(2, 2, 512), K(4, 1, 0), K(4, 1, 128),
+      K(4, 1, 256), K(4, 1, 512)
 #undef K
   };
   for (const void* f : fns) {

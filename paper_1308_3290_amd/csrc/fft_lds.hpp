@@ -103,7 +103,7 @@ __device__ __forceinline__ void fft_stage(const cplx<T>* in, cplx<T>* out, int n
   for (int q = 0; q < MAXB; ++q) {
     const int b = threadIdx.x + NT * q;
     if (b < nb) {
-      const int p = b >= LR ? 1 : 0;
+      const int p = b / LR;
       const int j = b - p * LR;
       const int k = j & (ns - 1);
       const cplx<T>* src = in + p * LP;
@@ -166,8 +166,9 @@ __host__ __device__ constexpr StagePlan stage_plan(int L) {
   return p;
 }
 
-// Forward DFT of nseq (1 or 2) sequences of length L held back to back in
-// buffer a (LDS, padded layout); b is scratch of the same size.  Returns the
+// Forward DFT of nseq sequences of length L held back to back in buffer a
+// (LDS, padded layout; nseq L <= 2048 for 256 threads, <= 3072 for 512); b
+// is scratch of the same size.  Returns the
 // buffer holding the result.  Every thread of the block (NT threads) must
 // call it; it begins and ends with a barrier.
 template <typename T, int NT = kThreads>
@@ -270,6 +271,18 @@ __device__ __forceinline__ cplx<T>* fft_run4(cplx<T>* a, cplx<T>* b, int nseq,
   static_assert(LC != 0, "four sequences need a compile-time length");
   __syncthreads();
   return ct_stages<T, LC, 0, NT, 4>(a, b, nseq, tw);
+}
+
+// Up to MAXSEQ sequences, compile-time length or (LC = 0) the runtime engine.
+template <typename T, int LC, int NT, int MAXSEQ>
+__device__ __forceinline__ cplx<T>* fft_runn(cplx<T>* a, cplx<T>* b, int nseq, int L, int nst,
+                                             const int* words, const cplx<T>* tw) {
+  if constexpr (LC == 0) {
+    return fft_lds<T, NT>(a, b, nseq, L, nst, words, tw);
+  } else {
+    __syncthreads();
+    return ct_stages<T, LC, 0, NT, MAXSEQ>(a, b, nseq, tw);
+  }
 }
 
 // Twiddle values a thread of NT prefetches for a transform of length LC (0:

@@ -42,6 +42,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   constexpr int NO = NR + E;          // the most computed rows
   constexpr int NP = NO + 2;          // tile rows: computed rows and one on each side
   constexpr int OFF = C - 1 - E;      // tile row u is fine row C*(j0-1) + OFF + u
+  constexpr int NSQ = fused_nseq(TJ);  // complex sequences of the inverse transform
+  constexpr int NQ = (TJ + 1) / 2;     // complex sequences of the next stage's transform
   // twiddles per thread: (R-1) Ns summed over the stages, < L <= 1024
   constexpr int kTwPer = ((LC ? stage_plan(LC).ntw : 1023) + NT - 1) / NT;
   static_assert(kFusedMaxNx - 1 <= NT, "one spectral column and one fine column per thread");
@@ -78,7 +80,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   // rows and the next transform's buffers ] [ twiddles ] [ coarse psi rows ].
   // Sharing the first region keeps the block small enough for two blocks per
   // CU when there are many (ensembles).
-  const int region = (max(4 * LP * (int)sizeof(cplx<T>), NP * pitch * (int)sizeof(T)) + 15) & ~15;
+  const int region =
+      (max(2 * NSQ * LP * (int)sizeof(cplx<T>), NP * pitch * (int)sizeof(T)) + 15) & ~15;
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   T* wtile = reinterpret_cast<T*>(smem);
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + region);
@@ -98,12 +101,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     twy[q] = z.y;
   }
   const T* w = wt + d.wt_off;
-  T sv[4];
+  T sv[2 * NSQ];
   {
     const int k = 1 + t;
     const size_t cbase = (size_t)(k - 1) * (My - 1) + (ilo - 1);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 2 * NSQ; ++r) {
       const bool in = k < Mx && r < nint;
       const T v = w[in ? cbase + r : 0];
       sv[r] = in ? v : T(0);
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   if (1 + t < Mx) {
     const int k = 1 + t;
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < NSQ; ++p) {
       if (p < nseq) {
         const cplx<T> z = {sv[2 * p], sv[2 * p + 1]};
         buf[p * LP + pad(k)] = z;
@@ -170,7 +173,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
       }
     }
   }
-  const cplx<T>* Z = fft_run<T, LC, NT>(buf, buf + 2 * LP, nseq, L, d.nst_r, d.stw_r, tw);
+  const cplx<T>* Z =
+      fft_runn<T, LC, NT, NSQ>(buf, buf + NSQ * LP, nseq, L, d.nst_r, d.stw_r, tw);
 
   // ---- coarse psi rows J = j0-1 .. j0+TJ (zero walls) into psc
   for (int i = t; i <= Mx; i += NT) {
@@ -293,7 +297,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     }
     __syncthreads();
     const int i = 1 + t;
-    cplx<T> z = {T(0), T(0)};
+    cplx<T> z[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) z[q] = {T(0), T(0)};
     if (i < Mx) {
       // x-weighted sums of each fine row, then the y weights (as pass A)
       T racc[NRT];
@@ -305,7 +311,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
         for (int dx = -(C - 1); dx <= C - 1; ++dx) acc += T(C - (dx < 0 ? -dx : dx)) * row[dx];
         racc[q] = acc;
       }
-      T v[2] = {T(0), T(0)};
+      T v[2 * NQ];
+#pragma unroll
+      for (int r = 0; r < 2 * NQ; ++r) v[r] = T(0);
 #pragma unroll
       for (int r = 0; r < TJ; ++r) {
         T acc = T(0);
@@ -314,27 +322,33 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
           acc += T(C - (dy < 0 ? -dy : dy)) * racc[C * r + dy + (C - 1)];
         v[r] = acc * (T(1) / T(C * C * C * C));
       }
-      // packed as pass A packs them (the wall row 0 as 0), so that both give
-      // the same spectra bit for bit
-      z = {j0 >= 1 ? v[0] : T(0), v[1]};
+      // packed as pass A packs them (rows in pairs (2m, 2m+1), the wall row 0
+      // as 0), so that both give the same spectra bit for bit
+      if (j0 == 0) v[0] = T(0);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) z[q] = {v[2 * q], v[2 * q + 1]};
     }
     __syncthreads();  // rt is read: the transform buffers may overwrite it
     if (i < Mx) {
-      buf[pad(i)] = z;
-      buf[pad(2 * Mx - i)] = {-z.x, -z.y};
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        buf[q * LP + pad(i)] = z[q];
+        buf[q * LP + pad(2 * Mx - i)] = {-z[q].x, -z[q].y};
+      }
     }
-    if (t == 0) {
-      buf[pad(0)] = {T(0), T(0)};
-      buf[pad(Mx)] = {T(0), T(0)};
+    if (t < NQ) {
+      buf[t * LP + pad(0)] = {T(0), T(0)};
+      buf[t * LP + pad(Mx)] = {T(0), T(0)};
     }
-    const cplx<T>* Z2 = fft_run<T, LC, NT>(buf, buf + LP, 1, L, d.nst_r, d.stw_r, tw);
+    const cplx<T>* Z2 = fft_runn<T, LC, NT, (NQ > 2 ? 4 : 2)>(buf, buf + NQ * LP, NQ, L, d.nst_r,
+                                                              d.stw_r, tw);
     if (i < Mx) {
-      const cplx<T> zk = Z2[pad(i)];
       T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
 #pragma unroll
       for (int r = 0; r < TJ; ++r) {
         const int j = j0 + r;
-        if (j >= 1 && j <= My - 1) wo[j - 1] = r == 0 ? T(-0.5) * zk.y : T(0.5) * zk.x;
+        const cplx<T> zk = Z2[(r >> 1) * LP + pad(i)];
+        if (j >= 1 && j <= My - 1) wo[j - 1] = (r & 1) ? T(0.5) * zk.x : T(-0.5) * zk.y;
       }
     }
   }
@@ -354,13 +368,13 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
 // lengths of at most 1024, 512, 256
 #define BY_LEN1(NX)                            \
   switch (g.L & 0xffff) {                      \
-    case 128: LAUNCH(1, 2, 128, NX); break;    \
-    case 256: LAUNCH(1, 2, 256, NX); break;    \
-    case 384: LAUNCH(1, 2, 384, NX); break;    \
-    case 512: LAUNCH(1, 2, 512, NX); break;    \
-    case 768: LAUNCH(1, 2, 768, NX); break;    \
-    case 1024: LAUNCH(1, 2, 1024, NX); break;  \
-    default: LAUNCH(1, 2, 0, NX);              \
+    case 128: LAUNCH(1, 4, 128, NX); break;    \
+    case 256: LAUNCH(1, 4, 256, NX); break;    \
+    case 384: LAUNCH(1, 4, 384, NX); break;    \
+    case 512: LAUNCH(1, 4, 512, NX); break;    \
+    case 768: LAUNCH(1, 4, 768, NX); break;    \
+    case 1024: LAUNCH(1, 4, 1024, NX); break;  \
+    default: LAUNCH(1, 4, 0, NX);              \
   }
 #define BY_LEN2(NX)                            \
   switch (g.L & 0xffff) {                      \
@@ -402,8 +416,8 @@ hipError_t Launch<T>::prepare_fused(size_t bytes) {
   const void* fns[] = {
 #define K(C, TJ, LC) reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, false>), \
                      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, true>)
-      K(1, 2, 0), K(1, 2, 128), K(1, 2, 256), K(1, 2, 384), K(1, 2, 512), K(1, 2, 768),
-      K(1, 2, 1024), K(2, 2, 0), K(2, 2, 128), K(2, 2, 256), K(2, 2, 384), K(2, 2, 512),
+      K(1, 4, 0), K(1, 4, 128), K(1, 4, 256), K(1, 4, 384), K(1, 4, 512), K(1, 4, 768),
+      K(1, 4, 1024), K(2, 2, 0), K(2, 2, 128), K(2, 2, 256), K(2, 2, 384), K(2, 2, 512),
       K(4, 1, 0), K(4, 1, 128), K(4, 1, 256)
 #undef K
   };

@@ -228,7 +228,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   build_groups(plan->md, PASS_A, [](const MemberDesc& d) { return fft_special(d.Lr); },
                [&](MemberDesc& d, HostGroup&) {
                  d.pa = 1;
-                 d.a_rows = nl == 1 ? (fusable ? fused_tj(d.c) : 2) : 1;
+                 d.a_rows = nl == 1 ? (fusable && fused_tj(d.c) == 1 ? 1 : 2) : 1;
                  d.a_first = (nl == 1 && fusable && d.a_rows == 2) ? 0 : 1;
                  const int nrows = d.My - d.a_first;
                  const size_t lds = ((size_t)2 * lpad(d.Lr) + d.ntw_r) * cs;
@@ -274,7 +274,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                    // per block for one layer, tj + 2 for two)
                    const int tj = fused_tj(d.c), nr = fused_nr(d.c);
                    const size_t tile = (size_t)nl * (nr + 2 + d.c - 1) * (d.nx + 1) * es;
-                   const size_t fft = (size_t)(nl == 1 ? 4 : 8) * lpad(d.Lr) * cs;
+                   const size_t fft =
+                       (size_t)(nl == 1 ? 2 * fused_nseq(tj) : 8) * lpad(d.Lr) * cs;
                    const size_t region = (std::max(fft, tile) + 15) & ~(size_t)15;
                    const size_t lds = region + (size_t)d.ntw_r * cs +
                                       (size_t)nl * (tj + 2) * (d.Mx + 1) * es;
@@ -878,7 +879,7 @@ cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forc
   double* gF = static_cast<double*>(grad_forcing);
   const MemberDesc* md = h->d_md();
   const int nb = h->plan.nblk_d;
-  if (h->plan.fused) {
+  if (h->plan.fused && d.c >= 2) {
     // each stage: the fused adjoint kernel (which finishes the previous
     // stage's solve) and pass B on its source; pass C ends the sweep
     double* wt = h->at<double>(h->plan.lay.wt);
