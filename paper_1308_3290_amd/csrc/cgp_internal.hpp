@@ -62,6 +62,21 @@ struct cplx {
   T x, y;
 };
 
+// Two consecutive elements at an address aligned to one element, moved by one
+// memory instruction (the target allows unaligned vector accesses).
+template <typename T>
+struct UPairOf;
+template <>
+struct UPairOf<double> {
+  typedef double type __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <>
+struct UPairOf<float> {
+  typedef float type __attribute__((ext_vector_type(2), aligned(4)));
+};
+template <typename T>
+using upair = typename UPairOf<T>::type;
+
 // Locate the member owning block `b` of the stencil pass (members are laid
 // out in order in its grid).
 __device__ inline int find_member(const MemberDesc* md, int nm, int p, int b) {
@@ -74,9 +89,11 @@ __device__ inline int find_member(const MemberDesc* md, int nm, int p, int b) {
 }
 
 // Locate the member of group `grp` (ng members, ordered by first block)
-// owning block `b` of pass `p`.
+// owning block `b` of pass `p`.  A group of one member m is passed as
+// ng = -(m + 1): the kernel then needs no load to find it.
 __device__ __forceinline__ int group_member(const MemberDesc* md, const int* grp, int ng, int p,
                                            int b) {
+  if (ng < 0) return -ng - 1;
   int lo = 0, hi = ng - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -89,7 +106,7 @@ __device__ __forceinline__ int group_member(const MemberDesc* md, const int* grp
 struct Group {
   int L;               // transform length with a compile-time transform, or 0
                        // (fused C + D pass: (c << 16) | that length)
-  int count;           // members in the group
+  int count;           // members in the group; one member m is encoded as -(m + 1)
   const int* members;  // device array of the group's member indices
   int nblk, threads;  // threads = kThreads
   size_t lds;

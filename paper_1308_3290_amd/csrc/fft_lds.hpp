@@ -9,9 +9,14 @@
 // The transform is its own inverse up to 2/n, so the same routine serves
 // the analysis and the synthesis sums of Sec. 4.3.
 //
-// The DFT is a Stockham autosort FFT over radices 8, 4 and 2, with the
+// The DFT is a Stockham autosort FFT over radices 8, 4 and 2 with the
 // radix-3 stage of L = 3*2^k placed last, so that the span Ns of every stage
-// is a power of two and all index arithmetic is shifts and masks.  At a stage
+// is a power of two and all index arithmetic is shifts and masks.  Lengths
+// up to 512 use radix 4 (one radix-8 or radix-2 stage first when the power
+// of two is odd): a block then has L/4 butterflies per sequence in flight,
+// enough to occupy its four SIMDs.  Longer transforms have enough
+// butterflies at radix 8, which needs fewer stages (each stage moves the
+// whole sequence through LDS once).  At a stage
 // of radix R, butterfly j reads x[j + r L/R], twiddles element r by
 // w_L^(r (j mod Ns) L/(Ns R)), takes an R-point DFT and writes
 // y[(j div Ns) Ns R + (j mod Ns) + r Ns].  Stages ping-pong between two LDS
@@ -129,9 +134,11 @@ __host__ __device__ constexpr int stage_word(int R, int lns, int two) {
   return R | (lns << 4) | (two << 9);
 }
 
-// Stage plan of a complex FFT of length L = 2^k or 3*2^k: radix 8 while
-// possible, then 4, then 2, the radix 3 last, so that every stage's span Ns
-// (the product of the earlier radices) is a power of two.  Stage s has radix
+// Stage plan of a complex FFT of length L = 2^k or 3*2^k.  L <= 512: for odd
+// k one radix-8 stage first (radix 2 when k = 1), then radix 4.  L >= 1024:
+// radix 8 while possible, then 4, then 2.  The radix 3 comes last, so that
+// every stage's span Ns (the product of the earlier radices) is a power of
+// two.  The first stage has no twiddles (Ns = 1).  Stage s has radix
 // R[s], span 2^lns[s] and its twiddle table ((R-1) x Ns values) at off[s];
 // ntw is the total table size.  Shared by the host (tables, stage words) and
 // the compile-time transforms below.
@@ -142,19 +149,24 @@ struct StagePlan {
 
 __host__ __device__ constexpr StagePlan stage_plan(int L) {
   StagePlan p{};
-  int rest = L, ns = 1, lg = 0;
-  const int radix[3] = {8, 4, 2}, lgr[3] = {3, 2, 1};
-  for (int i = 0; i < 3; ++i) {
-    while (rest % radix[i] == 0 && p.n < kMaxStages) {
-      p.R[p.n] = radix[i];
-      p.lns[p.n] = lg;
-      p.off[p.n] = p.ntw;
-      p.ntw += (radix[i] - 1) * ns;
-      ns *= radix[i];
-      lg += lgr[i];
-      rest /= radix[i];
-      ++p.n;
-    }
+  int rest = L, ns = 1, lg = 0, e = 0;
+  while (rest % 2 == 0) {
+    rest /= 2;
+    ++e;
+  }
+  const bool wide = L >= 1024;
+  while (e > 0 && p.n < kMaxStages) {
+    // log2 of this stage's radix
+    const int lr = wide ? (e >= 3 ? 3 : e) : ((e & 1) ? (e >= 3 ? 3 : 1) : 2);
+    const int R = 1 << lr;
+    p.R[p.n] = R;
+    p.lns[p.n] = lg;
+    p.off[p.n] = p.ntw;
+    p.ntw += (R - 1) * ns;
+    ns *= R;
+    lg += lr;
+    e -= lr;
+    ++p.n;
   }
   if (rest == 3 && p.n < kMaxStages) {
     p.R[p.n] = 3;
@@ -199,8 +211,9 @@ __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nseq, in
 // and twiddle offsets are constants, so that every LDS address of a butterfly
 // is a per-thread base plus an immediate offset: the padded index of
 // j + r L/R is pad(j) + r lpad(L/R) (L/R is a multiple of 8), and that of the
-// output o + r Ns is pad(o) + r lpad(Ns) (Ns a multiple of 8) or pad(o) + r Ns
-// (Ns R divides 8).
+// output o + r Ns is pad(o) + r Ns + floor(r Ns / 8).  The latter holds for
+// every power-of-two span: o is a multiple of Ns R plus k < Ns, so o + r Ns
+// crosses a multiple of 8 exactly where r Ns does.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int S, int NT, int MAXSEQ>
 __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int nseq,
@@ -209,8 +222,7 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
   constexpr int R = P.R[S], LNS = P.lns[S], NS = 1 << LNS, OFF = P.off[S];
   constexpr int LR = L / R, LP = lpad(L), RS = lpad(LR);
   static_assert(LR % 8 == 0, "read offsets need L/R to be a multiple of 8");
-  static_assert(NS % 8 == 0 || 8 % (NS * R) == 0, "write offsets need Ns % 8 == 0 or Ns R | 8");
-  constexpr int WS = NS % 8 == 0 ? lpad(NS) : NS;
+  static_assert((NS & (NS - 1)) == 0, "write offsets need a power-of-two span");
   constexpr int Q = (MAXSEQ * LR + NT - 1) / NT;  // nseq <= MAXSEQ
   const int nb = nseq * LR;
 #pragma unroll
@@ -233,7 +245,7 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
       const int o = ((j >> LNS) << LNS) * R + k;
       cplx<T>* dst = out + p * LP + pad(o);
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * WS] = v[r];
+      for (int r = 0; r < R; ++r) dst[r * NS + ((r * NS) >> 3)] = v[r];
     }
   }
   __syncthreads();

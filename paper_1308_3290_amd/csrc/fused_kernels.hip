@@ -88,10 +88,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   T* psc = reinterpret_cast<T*>(tw + ntw);
   const int prow = Mx + 1;
 
-  // ---- issue the block's global loads.  They are unconditional (a lane
-  // without an element reads element 0 of the same array and discards it), so
-  // that they sit in one basic block and the transform below waits only for
-  // the twiddles and spectra, not for the loads issued after them.
+  // ---- global loads are unconditional (a lane without an element reads
+  // element 0 of the same array and discards it), so that they sit in one
+  // basic block.  The transform's twiddles and spectra come first.
   T twx[kTwPer], twy[kTwPer];
 #pragma unroll
   for (int q = 0; q < kTwPer; ++q) {
@@ -100,16 +99,45 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     twx[q] = z.x;
     twy[q] = z.y;
   }
+  // Spectra: row pair p of column k (rows ilo+2p, ilo+2p+1, consecutive in
+  // the column) is one load; item c = (k-1) NSQ + p, so that neighbouring
+  // lanes read neighbouring pairs.  A pair whose second row is the wall row
+  // My is read one element lower, which keeps the load inside the column.
   const T* w = wt + d.wt_off;
-  T sv[2 * NSQ];
-  {
-    const int k = 1 + t;
-    const size_t cbase = (size_t)(k - 1) * (My - 1) + (ilo - 1);
+  constexpr int kPairs = ((kFusedMaxNx / C - 1) * NSQ + NT - 1) / NT;
+  upair<T> sp[kPairs];
 #pragma unroll
-    for (int r = 0; r < 2 * NSQ; ++r) {
-      const bool in = k < Mx && r < nint;
-      const T v = w[in ? cbase + r : 0];
-      sv[r] = in ? v : T(0);
+  for (int q = 0; q < kPairs; ++q) {
+    const int c = t + NT * q;
+    const int k = 1 + c / NSQ, p = c - (k - 1) * NSQ;
+    const int r0 = ilo + 2 * p;
+    const bool in = k < Mx && p < nseq;
+    const bool top = r0 + 1 > My - 1;
+    const size_t e = (size_t)(k - 1) * (My - 1) + (r0 - 1) - (top ? 1 : 0);
+    const upair<T> v = *reinterpret_cast<const upair<T>*>(w + (in ? e : 0));
+    upair<T> z;
+    z.x = in ? (top ? v.y : v.x) : T(0);
+    z.y = in && !top ? v.y : T(0);
+    sp[q] = z;
+  }
+  // ---- twiddles and the two packed sequences (odd extension) into LDS
+#pragma unroll
+  for (int q = 0; q < kTwPer; ++q) {
+    const int m = t + NT * q;
+    if (m < ntw) tw[m] = {twx[q], twy[q]};
+  }
+  if (t < nseq) {
+    buf[t * LP + pad(0)] = {T(0), T(0)};
+    buf[t * LP + pad(Mx)] = {T(0), T(0)};
+  }
+#pragma unroll
+  for (int q = 0; q < kPairs; ++q) {
+    const int c = t + NT * q;
+    const int k = 1 + c / NSQ, p = c - (k - 1) * NSQ;
+    if (k < Mx && p < nseq) {
+      const cplx<T> z = {sp[q].x, sp[q].y};
+      buf[p * LP + pad(k)] = z;
+      buf[p * LP + pad(2 * Mx - k)] = {-z.x, -z.y};
     }
   }
   const T* W = ws + d.field_off;
@@ -117,6 +145,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   const T* WN = wn + d.field_off;
   T* O = out + d.field_off;
   const long long g0 = (long long)RB0 * pitch;
+  // ---- the stencil's inputs, issued once the transform's inputs are in
+  // LDS: they arrive while the transform runs.
   // Element e of the tile is tile row e / pitch, column e % pitch, tracked
   // incrementally; the ring and the rows outside 1 .. ny-1 are stored as 0, so
   // that the stencil reads the tile without masks.
@@ -152,27 +182,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     nv[u - 1] = in ? n : T(0);
   }
 
-  // ---- twiddles and the two packed sequences (odd extension) into LDS
-#pragma unroll
-  for (int q = 0; q < kTwPer; ++q) {
-    const int m = t + NT * q;
-    if (m < ntw) tw[m] = {twx[q], twy[q]};
-  }
-  if (t < nseq) {
-    buf[t * LP + pad(0)] = {T(0), T(0)};
-    buf[t * LP + pad(Mx)] = {T(0), T(0)};
-  }
-  if (1 + t < Mx) {
-    const int k = 1 + t;
-#pragma unroll
-    for (int p = 0; p < NSQ; ++p) {
-      if (p < nseq) {
-        const cplx<T> z = {sv[2 * p], sv[2 * p + 1]};
-        buf[p * LP + pad(k)] = z;
-        buf[p * LP + pad(2 * Mx - k)] = {-z.x, -z.y};
-      }
-    }
-  }
   const cplx<T>* Z =
       fft_runn<T, LC, NT, NSQ>(buf, buf + NSQ * LP, nseq, L, d.nst_r, d.stw_r, tw);
 
@@ -343,12 +352,22 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     const cplx<T>* Z2 = fft_runn<T, LC, NT, (NQ > 2 ? 4 : 2)>(buf, buf + NQ * LP, NQ, L, d.nst_r,
                                                               d.stw_r, tw);
     if (i < Mx) {
+      // rows j0+2q, j0+2q+1 are consecutive in column i: one store per pair
       T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
 #pragma unroll
-      for (int r = 0; r < TJ; ++r) {
-        const int j = j0 + r;
-        const cplx<T> zk = Z2[(r >> 1) * LP + pad(i)];
-        if (j >= 1 && j <= My - 1) wo[j - 1] = (r & 1) ? T(0.5) * zk.x : T(-0.5) * zk.y;
+      for (int q = 0; q < NQ; ++q) {
+        const int j = j0 + 2 * q;
+        const cplx<T> zk = Z2[q * LP + pad(i)];
+        const T v0 = T(-0.5) * zk.y, v1 = T(0.5) * zk.x;
+        if (2 * q + 1 < TJ && j >= 1 && j + 1 <= My - 1) {
+          upair<T> pr;
+          pr.x = v0;
+          pr.y = v1;
+          *reinterpret_cast<upair<T>*>(wo + j - 1) = pr;
+        } else {
+          if (j >= 1 && j <= My - 1) wo[j - 1] = v0;
+          if (2 * q + 1 < TJ && j + 1 <= My - 1) wo[j] = v1;
+        }
       }
     }
   }

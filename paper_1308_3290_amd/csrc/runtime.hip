@@ -324,7 +324,8 @@ struct cgp_handle {
   const MemberDesc* d_md() const { return at<MemberDesc>(plan.lay.desc); }
   Group group(int pass, int i) const {
     const HostGroup& g = plan.groups[pass][i];
-    return Group{g.L,   (int)g.members.size(), at<int>(plan.lay.order) + g.order_off, g.nblk,
+    const int count = g.members.size() == 1 ? -(g.members[0] + 1) : (int)g.members.size();
+    return Group{g.L,   count, at<int>(plan.lay.order) + g.order_off, g.nblk,
                  kThreads, g.lds, plan.nlayers};
   }
   int ngroups(int pass) const { return (int)plan.groups[pass].size(); }
