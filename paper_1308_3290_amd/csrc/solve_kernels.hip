@@ -193,6 +193,17 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
 // F2)), and transforms back, from the spectra of omega (win) to those of psi
 // (wout, same layout).  Loads are batched as in pass A.
 // ---------------------------------------------------------------------------
+// 1/x for the eigenvalues (negative, far from the overflow and subnormal
+// ranges): the hardware estimate refined by two Newton steps
+// r <- r + r (1 - x r), within an ulp or two of the quotient, at a third of
+// the instructions of a full IEEE division.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 template <typename T, int LC>
 __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __restrict__ md,
                                                         const int* __restrict__ grp, int ng,
@@ -271,8 +282,8 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
     const int l = 1 + threadIdx.x + kThreads * q;
     if (l < My) {
       const cplx<T> z = Z[pad(l)];
-      const T a = T(-0.5) * z.y * T(scale / (lxa + ly[q]));
-      const T b = T(0.5) * z.x * T(scale / (lxb + ly[q]));
+      const T a = T(-0.5) * z.y * T(scale * recip(lxa + ly[q]));
+      const T b = T(0.5) * z.x * T(scale * recip(lxb + ly[q]));
       Y[pad(l)] = {a, b};
       Y[pad(2 * My - l)] = {-a, -b};
     }
