@@ -132,15 +132,19 @@ def step(omega, forcing, grid: Grid, level: int, phys: Physics, dt: float,
 
 
 def step_two_layer(Q, forcing, grid: Grid, level: int, phys: Physics, dt: float,
-                   route: str = "dst"):
+                   route: str = "dst", return_stages: bool = False):
     """One CGPRK3 step of the two-layer model."""
     Qn = zero_ring(Q)
     F = np.asarray(forcing, dtype=np.float64)
     w = Qn
+    stages = []
     for s in range(3):
         psi = cgp_psi_two_layer(w, grid, level, phys, route)
+        stages.append((w, psi))
         g = rhs_two_layer(w, psi, F, grid, phys)
         w = zero_ring(RK3_A[s] * Qn + RK3_B[s] * (w + dt * g))
+    if return_stages:
+        return w, stages
     return w
 
 
