@@ -58,6 +58,7 @@ class Case:
     f2: float = 0.0
     drag: float = 0.0
     dt: float = 1e-4
+    cfl: float = 0.0      # CFL number of the adaptive step (Sec. 4.2); 0: fixed dt
     nsteps: int = 1
     seed: int = 0
     dtype: str = "f64"

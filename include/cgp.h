@@ -82,7 +82,15 @@ typedef struct cgp_config {
   double lx, ly, y0;   /* basin [0, lx] x [y0, y0 + ly] */
   double inv_re, inv_ro;
   double f1, f2, drag; /* two-layer coefficients, ignored for one layer */
-  double dt;           /* fixed time step */
+  double dt;           /* time step; with cfl > 0 the largest (and first) step */
+  double cfl;          /* CFL number c of Sec. 4.2: 0 keeps dt fixed; c > 0 adapts
+                        * the step: after every step, the next step's size is
+                        * min(dt, c min(dx, dy) / max |grad psi|), the maximum of
+                        * |d psi/dx| and |d psi/dy| (centred differences at the
+                        * interior nodes, every layer) taken on the prolonged psi
+                        * of the step's third stage (dt itself when that maximum
+                        * is 0).  The step state lives in the workspace, so that
+                        * a run split over calls takes the same steps. */
 } cgp_config;
 
 typedef struct cgp_handle cgp_handle;
@@ -109,6 +117,12 @@ cgp_status cgp_destroy(cgp_handle* h);
  * psi = P^l L_c^-1 R^l omega of the final state.  nsteps >= 0. */
 cgp_status cgp_step(cgp_handle* h, void* omega_dev, const void* forcing_dev,
                     void* psi_out_dev, int32_t nsteps, void* stream);
+
+/* Step state: out_dev[2m] = the dt of member m's latest step (the configured
+ * dt before the first step), out_dev[2m+1] = the model time its steps have
+ * advanced since cgp_create (m = 0 for a single basin).  out_dev holds
+ * 2 * members doubles (device memory), written on `stream`. */
+cgp_status cgp_time_state(cgp_handle* h, double* out_dev, void* stream);
 
 /* The CGP elliptic map alone: psi_dev = P^l L_c^-1 R^l omega_dev
  * (Sec. 3 steps (ii)-(iv); for two layers the coupled solve of Sec. 4.3).
@@ -139,7 +153,9 @@ cgp_status cgp_check_finite(cgp_handle* h, const void* field_dev, int64_t count,
  * in plain sums).  The tape holds the recomputed stage states.
  * ---------------------------------------------------------------------- */
 
-/* Bytes of device tape cgp_adjoint_step needs for a segment of nsteps. */
+/* Bytes of device tape cgp_adjoint_step needs for a segment of nsteps.
+ * The adjoint differentiates steps of fixed size: cfl must be 0
+ * (CGP_ERR_UNSUPPORTED otherwise, here and in cgp_adjoint_step). */
 cgp_status cgp_tape_size(const cgp_config* cfg, int32_t nsteps, size_t* bytes);
 
 /* Reverse sweep over one segment of nsteps >= 1 steps that starts from the

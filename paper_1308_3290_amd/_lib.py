@@ -23,7 +23,7 @@ class cgp_config(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
                 ("y0", ctypes.c_double), ("inv_re", ctypes.c_double),
                 ("inv_ro", ctypes.c_double), ("f1", ctypes.c_double), ("f2", ctypes.c_double),
-                ("drag", ctypes.c_double), ("dt", ctypes.c_double)]
+                ("drag", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double)]
 
 
 class CGPError(RuntimeError):
@@ -45,6 +45,7 @@ SIGNATURES = {
     "cgp_destroy": (_I32, [_P]),
     "cgp_step": (_I32, [_P, _P, _P, _P, _I32, _P]),
     "cgp_solve": (_I32, [_P, _P, _P, _P]),
+    "cgp_time_state": (_I32, [_P, _P, _P]),
     "cgp_diagnostics": (_I32, [_P, _P, _P, _P, _P]),
     "cgp_check_finite": (_I32, [_P, _P, _I64, _P, _P]),
     "cgp_tape_size": (_I32, [_CFG, _I32, ctypes.POINTER(_SZ)]),

@@ -21,18 +21,19 @@ _TORCH_DTYPE = {CGP_F32: torch.float32, CGP_F64: torch.float64}
 
 
 def make_config(nx, ny, level=0, nlayers=1, dtype="f64", lx=1.0, ly=2.0, y0=-1.0,
-                inv_re=1.0, inv_ro=0.0, f1=0.0, f2=0.0, drag=0.0, dt=1e-4) -> cgp_config:
+                inv_re=1.0, inv_ro=0.0, f1=0.0, f2=0.0, drag=0.0, dt=1e-4,
+                cfl=0.0) -> cgp_config:
     dt_code = {"f64": CGP_F64, "f32": CGP_F32}.get(dtype, dtype)  # ints pass through
     return cgp_config(nx=nx, ny=ny, level=level, nlayers=nlayers, dtype=dt_code, reserved=0,
                       lx=lx, ly=ly, y0=y0, inv_re=inv_re, inv_ro=inv_ro, f1=f1, f2=f2,
-                      drag=drag, dt=dt)
+                      drag=drag, dt=dt, cfl=cfl)
 
 
 def config_from_case(case, dtype: Optional[str] = None) -> cgp_config:
     """cgp_config of a cgp_inputs.Case."""
     return make_config(case.nx, case.ny, case.level, case.nlayers, dtype or case.dtype, case.lx,
                        case.ly, case.y0, case.inv_re, case.inv_ro, case.f1, case.f2, case.drag,
-                       case.dt)
+                       case.dt, case.cfl)
 
 
 def stream_ptr(stream=None) -> int:
@@ -76,6 +77,11 @@ def cgp_destroy(h):
 def cgp_step(h, omega, forcing, psi_out=None, nsteps=1, stream=None):
     call("cgp_step", h, _ptr(omega), _ptr(forcing), _ptr(psi_out), int(nsteps),
          ctypes.c_void_p(stream_ptr(stream)))
+
+
+def cgp_time_state(h, out, stream=None):
+    """out (FP64 device tensor, 2 per member) <- (dt of the latest step, model time)."""
+    call("cgp_time_state", h, _ptr(out), ctypes.c_void_p(stream_ptr(stream)))
 
 
 def cgp_solve(h, omega, psi, stream=None):
@@ -205,6 +211,12 @@ class Basin:
         cgp_check_finite(self.handle, field, flag, stream)
         return flag
 
+    def time_state(self, stream=None):
+        """FP64 device tensor [dt of the latest step, model time advanced]."""
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        cgp_time_state(self.handle, out, stream)
+        return out
+
     def tape(self, nsteps):
         n = cgp_tape_size(self.cfg, nsteps)
         return torch.empty(n // 8, dtype=torch.float64, device=self.device)
@@ -258,6 +270,13 @@ class Ensemble:
         _check_tensor(forcing_packed, self.dtype, self.total, "forcing_packed")
         cgp_ensemble_step(self.handle, omega_packed, forcing_packed, nsteps, use_graph, stream)
         return omega_packed
+
+    def time_state(self, stream=None):
+        """FP64 device tensor (members, 2): dt of each member's latest step and
+        its model time advanced."""
+        out = torch.empty((len(self.cfgs), 2), dtype=torch.float64, device=self.device)
+        cgp_time_state(self.handle, out, stream)
+        return out
 
     def close(self):
         if self.handle is not None:

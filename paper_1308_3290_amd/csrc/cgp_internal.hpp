@@ -55,7 +55,96 @@ struct MemberDesc {
   double delta;         // barotropic weight f2/(f1+f2) (0.5 if f1 = f2 = 0)
   // stencil coefficients: 1/(12 dx dy), inv_ro/(3 dx), 1/dx^2, 1/dy^2
   double cj, cb, idx2, idy2;
+  // step size (Sec. 4.2): cfl = 0 keeps dt; cfl > 0 adapts it.  The member's
+  // step state sits at cfl_off in the step-state region (see StepCtl); the
+  // last stage of a step leaves kVmaxSlots maxima per block of its launch
+  // (npart blocks)
+  double cfl, hmin;
+  long long cfl_off;
+  int npart;
 };
+
+// Per-wave maxima one block of a stage kernel leaves (512 threads at most).
+constexpr int kVmaxSlots = 8;
+
+// Step-size state, per member at md.cfl_off of a double region:
+// [0] the dt of the current (latest) step, [1] the model time advanced so far,
+// [2 .. 2 + npart kVmaxSlots) the largest |d psi/dx|, |d psi/dy| (centred
+// differences, interior nodes) seen by each wave of the last stage of the
+// latest step.  Pass B of a step's first stage turns these into that step's
+// dt: min(dt, cfl min(dx, dy) / max) (dt itself when the max is 0); the
+// stage kernels read it.
+struct StepCtl {
+  double* w;  // the region; NULL: fixed dt from the descriptor, no maxima
+  int last;   // the launch is the last stage of a step: leave the maxima
+};
+
+// The dt a stage kernel applies.
+template <typename T>
+__device__ __forceinline__ T stage_dt(const MemberDesc& d, const StepCtl& c) {
+  return (c.w != nullptr && d.cfl > 0) ? T(c.w[d.cfl_off]) : T(d.dt);
+}
+
+// Whether a stage launch leaves the velocity maxima for member d.
+__device__ __forceinline__ bool wants_vmax(const MemberDesc& d, const StepCtl& c) {
+  return c.w != nullptr && c.last && d.cfl > 0;
+}
+
+// Store the wave's largest scaled velocity max(mx / hx, my / hy) (mx, my:
+// the largest differences of psi along x and y the lane saw, hx, hy the
+// spacings they span) in slot (lb, wave) of member d.  Every lane of the wave
+// must call it.
+__device__ __forceinline__ void put_vmax(const MemberDesc& d, const StepCtl& c, int lb, double mx,
+                                         double my, double hx, double hy) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o));
+    my = fmax(my, __shfl_xor(my, o));
+  }
+  if ((threadIdx.x & 63) == 0)
+    c.w[d.cfl_off + 2 + (long long)lb * kVmaxSlots + (threadIdx.x >> 6)] = fmax(mx / hx, my / hy);
+}
+
+// The velocity maxima of a fused stage block, from its coarse psi rows in
+// LDS (psc row r = coarse row j0-1+r, r = 0..TJ+1, columns 0..Mx, zero walls)
+// instead of the prolonged fine psi: bilinear interpolation is linear in
+// each coarse cell, so for C >= 2 the fine centred difference at a node
+// inside a cell is that cell's slope, at a coarse node the mean of two
+// slopes, and on fine rows (columns) between coarse ones a convex
+// combination of the slopes of the neighbouring coarse rows (columns).  The
+// largest fine centred difference is therefore the largest coarse cell slope:
+// x on the interior coarse rows, y on the interior coarse columns, each
+// spanning C dx (C dy).  For C = 1 the fine grid is the coarse one (centred
+// differences over 2 dx, 2 dy).  Each block takes its own coarse rows j0 ..
+// j0+TJ-1 (the y slopes of the cells above them); two layers pass both
+// layers' rows (psc2 != NULL).  Every thread calls it.
+template <typename T, int C, int TJ, int NT>
+__device__ __forceinline__ void put_vmax_coarse(const MemberDesc& d, const StepCtl& ctl, int lb,
+                                                const T* psc, const T* psc2, int prow, int j0) {
+  const int Mx = d.Mx, My = d.My;
+  double mx = 0.0, my = 0.0;
+  for (int l = 0; l < (psc2 ? 2 : 1); ++l) {
+    const T* P = l ? psc2 : psc;
+    for (int I = threadIdx.x; I < Mx; I += NT) {
+#pragma unroll
+      for (int r = 1; r <= TJ; ++r) {
+        const int J = j0 - 1 + r;
+        const T* row = P + r * prow;
+        if constexpr (C == 1) {
+          if (J >= 1 && J <= My - 1 && I >= 1) {
+            mx = fmax(mx, (double)fabs(row[I + 1] - row[I - 1]));
+            my = fmax(my, (double)fabs(row[prow + I] - row[I - prow]));
+          }
+        } else {
+          if (J >= 1 && J <= My - 1) mx = fmax(mx, (double)fabs(row[I + 1] - row[I]));
+          if (J <= My - 1 && I >= 1) my = fmax(my, (double)fabs(row[prow + I] - row[I]));
+        }
+      }
+    }
+  }
+  const double k = C == 1 ? 2.0 : (double)C;
+  put_vmax(d, ctl, lb, mx, my, k * d.dx, k * d.dy);
+}
 
 template <typename T>
 struct cplx {
@@ -121,8 +210,11 @@ struct Launch {
                                     const cplx<T>* tw, hipStream_t s);
   // pass B: y sine transform, eigenvalue divide, y sine transform, from the
   // spectra of omega (win) to those of psi (wout)
+  // With ctl != NULL (the first stage of a step) the member's first block
+  // also sets the step's dt in the step state.
   static hipError_t col_solve(const MemberDesc* md, const Group& g, const T* win, T* wout,
-                              const cplx<T>* tw, const double* lam, hipStream_t s);
+                              const cplx<T>* tw, const double* lam, double* ctl,
+                              hipStream_t s);
   // pass C: inverse x sine transform + prolongation; accumulate != 0 adds to dst
   static hipError_t rowdst_prolong(const MemberDesc* md, const Group& g, const T* wt, T* dst,
                                    int accumulate, const cplx<T>* tw, hipStream_t s);
@@ -134,23 +226,29 @@ struct Launch {
   // NULL the prolonged psi is stored too
   static hipError_t prolong_stencil(const MemberDesc* md, const Group& g, const T* wt, T* wnext,
                                     const cplx<T>* tw, const T* ws, const T* forcing, const T* wn,
-                                    T* out, T* psi_out, double a, double b, hipStream_t s);
+                                    T* out, T* psi_out, double a, double b, StepCtl ctl,
+                                    hipStream_t s);
   static hipError_t prepare_fused(size_t bytes);
   // the same for two layers (mode recombination and split inside; c = 2, 4)
   static hipError_t prolong_stencil2(const MemberDesc* md, const Group& g, const T* wt, T* wnext,
                                      const cplx<T>* tw, const T* ws, const T* forcing,
-                                     const T* wn, T* out, double a, double b, hipStream_t s);
+                                     const T* wn, T* out, double a, double b, StepCtl ctl,
+                                     hipStream_t s);
   static hipError_t prepare_fused2(size_t bytes);
   // pass D: Arakawa right-hand side + TVD-RK3 stage combine
   static hipError_t stencil_rk3(const MemberDesc* md, int nm, int nblk, const T* ws,
                                 const T* psi, const T* forcing, const T* wn, T* out, double a,
-                                double b, hipStream_t s);
+                                double b, StepCtl ctl, hipStream_t s);
   // diagnostics partial sums (2 per layer per block) + ordered final sum
   static hipError_t diagnostics(const MemberDesc* md, const T* w, const T* psi, double* partial,
                                 int nblk, double* out, hipStream_t s);
   static hipError_t check_finite(const T* f, long long n, int* partial, int nblk, int* flag,
                                  hipStream_t s);
 };
+
+// out[2m], out[2m+1] = dt of the latest step and model time of member m.
+hipError_t time_state(const MemberDesc* md, int nm, const double* ctl, double* out,
+                      hipStream_t s);
 
 // Adjoint kernels (FP64 only).
 struct AdjLaunch {

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
     const T* __restrict__ wt, T* __restrict__ wnext, const cplx<T>* __restrict__ twg,
     const T* __restrict__ ws, const T* __restrict__ forcing, const T* __restrict__ wn,
-    T* __restrict__ out, double a_, double b_) {
+    T* __restrict__ out, double a_, double b_, StepCtl ctl) {
   static_assert(C >= 2 && LC != 0, "two layers: coarsening 2 or 4, compile-time length");
   constexpr int NT = kFusedThreads;
   constexpr int NR = C * TJ + 1;      // the most own fine rows (+1: top wall row)
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
   }
 
   // ---- both layers' right-hand sides and RK3 on the computed rows
-  const T dt = T(d.dt), a = T(a_), b = T(b_);
+  const T dt = stage_dt<T>(d, ctl), a = T(a_), b = T(b_);
   const T cj = T(d.cj), cb = T(d.cb);
   const T idx2 = T(d.idx2), idy2 = T(d.idy2);
   const T nu = T(d.inv_re);
@@ -277,6 +277,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
       O[plane + (size_t)ny * pitch + x] = T(0);
     }
   }
+  // last stage of an adaptive step: the velocity maxima for the next dt
+  if (wants_vmax(d, ctl)) put_vmax_coarse<T, C, TJ, NT>(d, ctl, lb, psc1, psc2, PROW, j0);
   if constexpr (NEXT) {
     // ---- pass A of the next stage on the block's coarse rows j0 .. j0+TJ-1
     // (row k of rt = fine row R0-E+k = tile row k+1), as pass A computes it
@@ -353,11 +355,11 @@ template <typename T>
 hipError_t Launch<T>::prolong_stencil2(const MemberDesc* md, const Group& g, const T* wt,
                                        T* wnext, const cplx<T>* tw, const T* ws,
                                        const T* forcing, const T* wn, T* out, double a, double b,
-                                       hipStream_t s) {
+                                       StepCtl ctl, hipStream_t s) {
 #define LAUNCH(C, TJ, LC, NX)                                                                  \
   hipLaunchKernelGGL((k_prolong_stencil2<T, C, TJ, LC, NX>), dim3(g.nblk), dim3(kFusedThreads), \
                      g.lds, s, md, g.members, g.count, g.nblk, wt, wnext, tw, ws, forcing, wn,  \
-                     out, a, b)
+                     out, a, b, ctl)
 #define BY_C(NX)                                                  \
   switch (g.L) {                                                  \
     case (2 << 16) | 128: LAUNCH(2, 2, 128, NX); break;           \

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
     const T* __restrict__ wt, T* __restrict__ wnext, const cplx<T>* __restrict__ twg,
     const T* __restrict__ ws, const T* __restrict__ forcing, const T* __restrict__ wn,
-    T* __restrict__ out, T* __restrict__ psi_out, double a_, double b_) {
+    T* __restrict__ out, T* __restrict__ psi_out, double a_, double b_, StepCtl ctl) {
   constexpr int NT = kFusedThreads;
   constexpr int NR = C * TJ + 1;      // the most own fine rows (+1: top wall row)
   constexpr int E = NEXT ? C - 1 : 0;  // computed rows below the block
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   }
 
   // ---- stencil + RK3 on the computed rows (tile row u = fine row RB0 + u)
-  const T dt = T(d.dt), a = T(a_), b = T(b_);
+  const T dt = stage_dt<T>(d, ctl), a = T(a_), b = T(b_);
   const T cj = T(d.cj), cb = T(d.cb);
   const T idx2 = T(d.idx2), idy2 = T(d.idy2);
   const T nu = T(d.inv_re);
@@ -293,6 +293,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
       if (PO) PO[(size_t)ny * pitch + x] = T(0);
     }
   }
+  // last stage of an adaptive step: the velocity maxima for the next dt
+  if (wants_vmax(d, ctl)) put_vmax_coarse<T, C, TJ, NT>(d, ctl, lb, psc, nullptr, prow, j0);
   if constexpr (NEXT) {
     // ---- pass A of the next stage on the block's coarse rows j0 .. j0+TJ-1:
     // their full-weighting stencils cover the computed rows R0-E .. R1-1
@@ -378,11 +380,11 @@ template <typename T>
 hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, const T* wt,
                                       T* wnext, const cplx<T>* tw, const T* ws,
                                       const T* forcing, const T* wn, T* out, T* psi_out,
-                                      double a, double b, hipStream_t s) {
+                                      double a, double b, StepCtl ctl, hipStream_t s) {
 #define LAUNCH(C, TJ, LC, NX)                                                                \
   hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC, NX>), dim3(g.nblk), dim3(kFusedThreads), \
                      g.lds, s, md, g.members, g.count, g.nblk, wt, wnext, tw, ws, forcing, wn, \
-                     out, psi_out, a, b)
+                     out, psi_out, a, b, ctl)
 // rows hold at most kFusedMaxNx intervals, so c = 1, 2, 4 have transform
 // lengths of at most 1024, 512, 256
 #define BY_LEN1(NX)                            \

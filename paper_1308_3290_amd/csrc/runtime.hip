@@ -93,20 +93,22 @@ cgp_status validate(const cgp_config* c) {
     return fail(CGP_ERR_UNSUPPORTED, "coarse size above 1024");
   if (c->nlayers == 2 && f > 1 && Mx > 512)
     return fail(CGP_ERR_UNSUPPORTED, "two-layer coarse rows above 512 with coarsening");
-  const double vals[] = {c->lx, c->ly, c->y0, c->inv_re, c->inv_ro, c->f1, c->f2, c->drag, c->dt};
+  const double vals[] = {c->lx, c->ly, c->y0, c->inv_re, c->inv_ro, c->f1, c->f2, c->drag, c->dt,
+                         c->cfl};
   for (double v : vals)
     if (!std::isfinite(v)) return fail(CGP_ERR_INVALID, "non-finite coefficient");
   if (!(c->lx > 0) || !(c->ly > 0)) return fail(CGP_ERR_INVALID, "lx, ly must be > 0");
   if (c->inv_re < 0 || c->f1 < 0 || c->f2 < 0 || c->drag < 0)
     return fail(CGP_ERR_INVALID, "inv_re, f1, f2, drag must be >= 0");
+  if (c->cfl < 0) return fail(CGP_ERR_INVALID, "cfl must be >= 0 (0: fixed dt)");
   return CGP_OK;
 }
 
 struct Layout {
   // wt: spectra of omega (pass A out, pass B in); wt2: spectra of psi (pass B
   // out, pass C / fused pass in)
-  size_t desc = 0, order = 0, tw = 0, lam = 0, wt = 0, wt2 = 0, psi = 0, st1 = 0, st2 = 0,
-         diag = 0, fin = 0, total = 0;
+  size_t desc = 0, order = 0, tw = 0, lam = 0, ctl = 0, wt = 0, wt2 = 0, psi = 0, st1 = 0,
+         st2 = 0, diag = 0, fin = 0, total = 0;
   long long field_elems = 0;
 };
 
@@ -204,6 +206,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     d.f2 = nl == 2 ? c.f2 : 0.0;
     d.drag = nl == 2 ? c.drag : 0.0;
     d.dt = c.dt;
+    d.cfl = c.cfl;
+    d.hmin = std::min(c.lx / c.nx, c.ly / c.ny);
     d.delta = (d.f1 + d.f2 > 0) ? d.f2 / (d.f1 + d.f2) : 0.5;
     d.cj = 1.0 / (12.0 * d.dx * d.dy);
     d.cb = d.inv_ro / (3.0 * d.dx);
@@ -216,10 +220,12 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   // A block transforms at most two sequences and at most 2048 complex values.
   auto pairs = [](int L) { return L <= 512 ? 2 : 1; };
   // fused C + D pass (rows of at most kFusedMaxNx intervals; one layer:
-  // c <= 4; two layers: c = 2 or 4 and a compile-time transform length)
+  // c <= 4; two layers: c = 2 or 4 and a compile-time transform length).
+  // Its last block owns exactly fused_tj(c) coarse rows, so the coarse row
+  // count must be a multiple of that (only My = 6 at c = 1 is not).
   bool fusable = true;
   for (const MemberDesc& d : plan->md) {
-    fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4;
+    fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4 && d.My % fused_tj(d.c) == 0;
     if (nl == 2) fusable = fusable && d.c >= 2 && fft_special(d.Lr) != 0;
   }
   // pass A: one complex sequence per block: coarse rows packed as the fused
@@ -298,6 +304,15 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     }
   L.tw = off; off = align_up(off + (size_t)tw * 2 * es);
   L.lam = off; off = align_up(off + (size_t)lam * sizeof(double));
+  // step-size state: per member [dt, time, kVmaxSlots maxima per block of
+  // the stage launch]
+  long long ctl = 0;
+  for (MemberDesc& d : plan->md) {
+    d.npart = plan->fused ? d.nblk[PASS_CD] : d.nblk[PASS_D];
+    d.cfl_off = ctl;
+    ctl += 2 + (long long)d.npart * kVmaxSlots;
+  }
+  L.ctl = off; off = align_up(off + (size_t)ctl * sizeof(double));
   L.wt = off; off = align_up(off + (size_t)wt * es);
   L.wt2 = off; off = align_up(off + (size_t)wt * es);
   L.field_elems = fld;
@@ -337,9 +352,10 @@ const double kRkA[3] = {0.0, 0.75, 1.0 / 3.0};
 const double kRkB[3] = {1.0, 0.25, 2.0 / 3.0};
 
 // One pass of the coarse solve (0: A, 1: B, 2: C) over every member.
+// ctl (pass B of a step's first stage): the step state, whose dt is set.
 template <typename T>
 hipError_t enqueue_pass(cgp_handle* h, int pass, const T* src, T* dst, int accumulate,
-                        hipStream_t s) {
+                        hipStream_t s, double* ctl = nullptr) {
   const Plan& p = h->plan;
   const cplx<T>* tw = h->at<cplx<T>>(p.lay.tw);
   T* wt = h->at<T>(p.lay.wt);
@@ -350,7 +366,7 @@ hipError_t enqueue_pass(cgp_handle* h, int pass, const T* src, T* dst, int accum
     if (pass == 0)
       e = Launch<T>::restrict_rowdst(h->d_md(), g, src, wt, tw, s);
     else if (pass == 1)
-      e = Launch<T>::col_solve(h->d_md(), g, wt, wt2, tw, h->at<double>(p.lay.lam), s);
+      e = Launch<T>::col_solve(h->d_md(), g, wt, wt2, tw, h->at<double>(p.lay.lam), ctl, s);
     else
       e = Launch<T>::rowdst_prolong(h->d_md(), g, wt2, dst, accumulate, tw, s);
     if (e != hipSuccess) return e;
@@ -359,9 +375,10 @@ hipError_t enqueue_pass(cgp_handle* h, int pass, const T* src, T* dst, int accum
 }
 
 template <typename T>
-hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hipStream_t s) {
+hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hipStream_t s,
+                         double* ctl = nullptr) {
   hipError_t e = enqueue_pass<T>(h, 0, src, nullptr, 0, s);
-  if (e == hipSuccess) e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s);
+  if (e == hipSuccess) e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s, ctl);
   if (e == hipSuccess) e = enqueue_pass<T>(h, 2, nullptr, dst, accumulate, s);
   return e;
 }
@@ -371,7 +388,8 @@ hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hi
 // psi_out (optional) receives psi(ws).
 template <typename T>
 hipError_t enqueue_fused(cgp_handle* h, const T* ws, const T* forcing, const T* wn, T* out,
-                         double a, double b, bool next, hipStream_t s, T* psi_out = nullptr) {
+                         double a, double b, bool next, hipStream_t s, T* psi_out = nullptr,
+                         StepCtl ctl = StepCtl{nullptr, 0}) {
   const Plan& p = h->plan;
   for (int i = 0; i < h->ngroups(3); ++i) {
     T* wnext = next ? h->at<T>(p.lay.wt) : nullptr;
@@ -379,10 +397,10 @@ hipError_t enqueue_fused(cgp_handle* h, const T* ws, const T* forcing, const T* 
         p.nlayers == 1
             ? Launch<T>::prolong_stencil(h->d_md(), h->group(3, i), h->at<T>(p.lay.wt2), wnext,
                                          h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, psi_out,
-                                         a, b, s)
+                                         a, b, ctl, s)
             : Launch<T>::prolong_stencil2(h->d_md(), h->group(3, i), h->at<T>(p.lay.wt2), wnext,
                                           h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, a, b,
-                                          s);
+                                          ctl, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -396,17 +414,19 @@ hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s
                         T* st1 = nullptr, T* st2 = nullptr, T* psi0 = nullptr,
                         T* psi1 = nullptr, T* psi2 = nullptr) {
   const Plan& p = h->plan;
+  const bool tape = st1 != nullptr;  // the adjoint's recomputation: fixed dt
   T* b1 = st1 ? st1 : h->at<T>(p.lay.st1);
   T* b2 = st2 ? st2 : h->at<T>(p.lay.st2);
   T* pd = h->at<T>(p.lay.psi);
   T* psis[3] = {psi0 ? psi0 : pd, psi1 ? psi1 : pd, psi2 ? psi2 : pd};
   const T* src[3] = {omega, b1, b2};
   T* dst[3] = {b1, b2, omega};
+  double* ctl = tape ? nullptr : h->at<double>(p.lay.ctl);
   for (int st = 0; st < 3; ++st) {
-    hipError_t e = enqueue_solve<T>(h, src[st], psis[st], 0, s);
+    hipError_t e = enqueue_solve<T>(h, src[st], psis[st], 0, s, st == 0 ? ctl : nullptr);
     if (e != hipSuccess) return e;
     e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), p.nblk_d, src[st], psis[st], forcing,
-                               omega, dst[st], kRkA[st], kRkB[st], s);
+                               omega, dst[st], kRkA[st], kRkB[st], StepCtl{ctl, st == 2}, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -429,10 +449,12 @@ hipError_t enqueue_step_fused(cgp_handle* h, T* omega, const T* forcing, int pos
   T* Y = bufs[(pos + 2) % 3];
   const T* src[3] = {S, X, Y};
   T* dst[3] = {X, Y, X};
+  double* ctl = h->at<double>(p.lay.ctl);
   for (int st = 0; st < 3; ++st) {
-    hipError_t e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s);
+    hipError_t e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s, st == 0 ? ctl : nullptr);
     if (e == hipSuccess)
-      e = enqueue_fused<T>(h, src[st], forcing, S, dst[st], kRkA[st], kRkB[st], true, s);
+      e = enqueue_fused<T>(h, src[st], forcing, S, dst[st], kRkA[st], kRkB[st], true, s,
+                           nullptr, StepCtl{ctl, st == 2});
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -469,7 +491,7 @@ hipError_t enqueue_pass_reps(cgp_handle* h, int p, const T* omega, const T* forc
     if (p < 3) e = enqueue_pass<T>(h, p, omega, pd, 0, s);
     else if (p == 3)
       e = Launch<T>::stencil_rk3(h->d_md(), h->nm(), pl.nblk_d, b1, pd, forcing, omega, b2,
-                                 kRkA[1], kRkB[1], s);
+                                 kRkA[1], kRkB[1], StepCtl{nullptr, 0}, s);
     else e = enqueue_fused<T>(h, b1, forcing, omega, b2, kRkA[1], kRkB[1], p == 5, s);
     if (e != hipSuccess) return e;
   }
@@ -480,7 +502,7 @@ template <typename T>
 cgp_status create_tables(cgp_handle* h, hipStream_t s) {
   const Plan& p = h->plan;
   const Layout& L = p.lay;
-  // host image of [desc][tw][lam]
+  // host image of [desc][order][tw][lam][step state]
   h->host_tables.assign(L.wt, 0);
   std::memcpy(h->host_tables.data() + L.desc, p.md.data(), sizeof(MemberDesc) * p.md.size());
   int* order = reinterpret_cast<int*>(h->host_tables.data() + L.order);
@@ -522,6 +544,9 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
       ly[l - 1] = -4.0 * sn * sn / (hy * hy);
     }
   }
+  // step state: dt of the latest step = the configured dt, time 0, maxima 0
+  double* ctl = reinterpret_cast<double*>(h->host_tables.data() + L.ctl);
+  for (const MemberDesc& d : p.md) ctl[d.cfl_off] = d.dt;
   size_t lds_max = 0;
   for (int pass = 0; pass < 3; ++pass)
     for (const HostGroup& g : p.groups[pass]) lds_max = std::max(lds_max, g.lds);
@@ -821,10 +846,21 @@ cgp_status cgp_time_passes(cgp_handle* h, const void* omega, const void* forcing
 // each): per step s of the segment the stage states w0 w1 w2 and psi0 psi1
 // psi2 (6 arrays), then four work arrays X1 X2 P ACC.
 // ---------------------------------------------------------------------------
+cgp_status cgp_time_state(cgp_handle* h, double* out, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!out) return fail(CGP_ERR_INVALID, "out is NULL");
+  HIP_TRY(time_state(h->d_md(), h->nm(), h->at<double>(h->plan.lay.ctl), out,
+                     static_cast<hipStream_t>(stream)),
+          "time state launch");
+  return CGP_OK;
+}
+
 cgp_status cgp_tape_size(const cgp_config* cfg, int32_t nsteps, size_t* bytes) {
   cgp_status st = validate(cfg);
   if (st != CGP_OK) return st;
   if (!bytes || nsteps < 1) return fail(CGP_ERR_INVALID, "bad argument");
+  if (cfg->cfl > 0)
+    return fail(CGP_ERR_UNSUPPORTED, "the adjoint needs a fixed dt (cfl = 0)");
   const size_t N = (size_t)(cfg->nx + 1) * (cfg->ny + 1);
   *bytes = (6 * (size_t)nsteps + 4) * N * sizeof(double);
   return CGP_OK;
@@ -836,6 +872,8 @@ cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forc
   if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
   if (h->nm() != 1 || h->plan.nlayers != 1 || h->plan.dtype != CGP_F64)
     return fail(CGP_ERR_UNSUPPORTED, "adjoint needs a one-layer FP64 single-basin handle");
+  if (h->plan.md[0].cfl > 0)
+    return fail(CGP_ERR_UNSUPPORTED, "the adjoint needs a fixed dt (cfl = 0)");
   if (!omega_n || !forcing || !lambda || !grad_forcing || !tape || nsteps < 1)
     return fail(CGP_ERR_INVALID, "bad argument");
   const MemberDesc& d = h->plan.md[0];

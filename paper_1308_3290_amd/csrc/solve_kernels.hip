@@ -210,7 +210,8 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
                                                         const T* __restrict__ win,
                                                         T* __restrict__ wout,
                                                         const cplx<T>* __restrict__ twg,
-                                                        const double* __restrict__ lam) {
+                                                        const double* __restrict__ lam,
+                                                        double* __restrict__ ctl) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int kTw = tw_per_thread<LC, kThreads>();
   constexpr int kRowIter = 4;  // My - 1 <= 1023
@@ -301,6 +302,29 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
       const cplx<T> z = R[pad(l)];
       wout[offa + l - 1] = T(-0.5) * z.y;
       if (has_b) wout[offb + l - 1] = T(0.5) * z.x;
+    }
+  }
+  if (ctl != nullptr && lb == 0) {
+    // first stage of a step: the member's dt for this step (Sec. 4.2) from
+    // the velocity maxima the previous step's last stage left (0 before the
+    // first step: dt itself)
+    double* st = ctl + d.cfl_off;
+    double m = 0.0;
+    if (d.cfl > 0) {
+      const int n = d.npart * kVmaxSlots;
+      for (int i = threadIdx.x; i < n; i += kThreads) m = fmax(m, st[2 + i]);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+      double* red = reinterpret_cast<double*>(tw);  // the twiddles are read no more
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int i = 1; i < kThreads / 64; ++i) m = fmax(m, red[i]);
+    }
+    if (threadIdx.x == 0) {
+      const double dt = m > 0 ? fmin(d.dt, d.cfl * d.hmin / m) : d.dt;
+      st[0] = dt;
+      st[1] += dt;
     }
   }
 }
@@ -471,10 +495,11 @@ hipError_t Launch<T>::restrict_rowdst(const MemberDesc* md, const Group& g, cons
 
 template <typename T>
 hipError_t Launch<T>::col_solve(const MemberDesc* md, const Group& g, const T* win, T* wout,
-                                const cplx<T>* tw, const double* lam, hipStream_t s) {
+                                const cplx<T>* tw, const double* lam, double* ctl,
+                                hipStream_t s) {
 #define CALL(LC)                                                                                \
   hipLaunchKernelGGL((k_col_solve<T, LC>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members, \
-                     g.count, win, wout, tw, lam)
+                     g.count, win, wout, tw, lam, ctl)
   CGP_BY_LENGTH(g.L, CALL)
 #undef CALL
   return hipGetLastError();

@@ -18,7 +18,7 @@ template <typename T>
 __global__ __launch_bounds__(kTileX* kTileY) void k_stencil_rk3(
     const MemberDesc* __restrict__ md, int nm, const T* __restrict__ ws, const T* __restrict__ psi,
     const T* __restrict__ forcing, const T* __restrict__ wn, T* __restrict__ out, double a_,
-    double b_) {
+    double b_, StepCtl ctl) {
   const int m = find_member(md, nm, PASS_D, blockIdx.x);
   const MemberDesc& d = md[m];
   const int lb = blockIdx.x - d.blk0[PASS_D];
@@ -27,60 +27,72 @@ __global__ __launch_bounds__(kTileX* kTileY) void k_stencil_rk3(
   const int by = lb / tiles_x, bx = lb - by * tiles_x;
   const int i = bx * kTileX + (threadIdx.x & (kTileX - 1));
   const int j = by * kTileY + (threadIdx.x / kTileX);
-  if (i > nx || j > ny) return;
-  const size_t plane = (size_t)(ny + 1) * pitch;
-  const size_t o = d.field_off + (size_t)j * pitch + i;
-  const int nl = d.nlayers;
-  if (i == 0 || j == 0 || i == nx || j == ny) {
-    out[o] = T(0);
-    if (nl == 2) out[o + plane] = T(0);
-    return;
-  }
-  const T dt = T(d.dt), a = T(a_), b = T(b_);
-  const T cj = T(d.cj), cb = T(d.cb);
-  const T idx2 = T(d.idx2), idy2 = T(d.idy2);
-  const T nu = T(d.inv_re);
-  const T* W = ws + d.field_off;
-  const T* PS = psi + d.field_off;
-  if (nl == 1) {
-    const Nbr<T> p = load_nbr(PS, pitch, i, j);
-    const Nbr<T> q = load_nbr_masked(W, pitch, nx, ny, i, j);
-    const T G = -cj * arakawa12(p, q) - cb * beta3(p) + nu * lap5(q, idx2, idy2) +
-                forcing[o];
-    T v = b * (q.C + dt * G);
-    if (a_ != 0.0) v += a * wn[o];
-    out[o] = v;
-  } else {
-    const T F1 = T(d.f1), F2 = T(d.f2), drag = T(d.drag);
-    const Nbr<T> p1 = load_nbr(PS, pitch, i, j);
-    const Nbr<T> p2 = load_nbr(PS + plane, pitch, i, j);
-    const Nbr<T> q1 = load_nbr_masked(W, pitch, nx, ny, i, j);
-    const Nbr<T> q2 = load_nbr_masked(W + plane, pitch, nx, ny, i, j);
-    // zeta_i = Q_i - F_i (psi_j - psi_i) on the 5-point cross (zero on walls)
-    Nbr<T> z1, z2;
-    z1.C = q1.C - F1 * (p2.C - p1.C);
-    z1.E = q1.E - F1 * (p2.E - p1.E);
-    z1.W = q1.W - F1 * (p2.W - p1.W);
-    z1.N = q1.N - F1 * (p2.N - p1.N);
-    z1.S = q1.S - F1 * (p2.S - p1.S);
-    z2.C = q2.C - F2 * (p1.C - p2.C);
-    z2.E = q2.E - F2 * (p1.E - p2.E);
-    z2.W = q2.W - F2 * (p1.W - p2.W);
-    z2.N = q2.N - F2 * (p1.N - p2.N);
-    z2.S = q2.S - F2 * (p1.S - p2.S);
-    const T G1 = -cj * arakawa12(p1, q1) - cb * beta3(p1) + nu * lap5(z1, idx2, idy2) +
-                 forcing[o];
-    const T G2 = -cj * arakawa12(p2, q2) - cb * beta3(p2) + nu * lap5(z2, idx2, idy2) -
-                 drag * z2.C;
-    T v1 = b * (q1.C + dt * G1);
-    T v2 = b * (q2.C + dt * G2);
-    if (a_ != 0.0) {
-      v1 += a * wn[o];
-      v2 += a * wn[o + plane];
+  const bool track = wants_vmax(d, ctl);  // last stage of an adaptive step
+  double vmx = 0.0, vmy = 0.0;
+  if (i <= nx && j <= ny) {
+    const size_t plane = (size_t)(ny + 1) * pitch;
+    const size_t o = d.field_off + (size_t)j * pitch + i;
+    const int nl = d.nlayers;
+    if (i == 0 || j == 0 || i == nx || j == ny) {
+      out[o] = T(0);
+      if (nl == 2) out[o + plane] = T(0);
+    } else {
+      const T dt = stage_dt<T>(d, ctl), a = T(a_), b = T(b_);
+      const T cj = T(d.cj), cb = T(d.cb);
+      const T idx2 = T(d.idx2), idy2 = T(d.idy2);
+      const T nu = T(d.inv_re);
+      const T* W = ws + d.field_off;
+      const T* PS = psi + d.field_off;
+      if (nl == 1) {
+        const Nbr<T> p = load_nbr(PS, pitch, i, j);
+        const Nbr<T> q = load_nbr_masked(W, pitch, nx, ny, i, j);
+        const T G = -cj * arakawa12(p, q) - cb * beta3(p) + nu * lap5(q, idx2, idy2) +
+                    forcing[o];
+        T v = b * (q.C + dt * G);
+        if (a_ != 0.0) v += a * wn[o];
+        out[o] = v;
+        if (track) {
+          vmx = (double)fabs(p.E - p.W);
+          vmy = (double)fabs(p.N - p.S);
+        }
+      } else {
+        const T F1 = T(d.f1), F2 = T(d.f2), drag = T(d.drag);
+        const Nbr<T> p1 = load_nbr(PS, pitch, i, j);
+        const Nbr<T> p2 = load_nbr(PS + plane, pitch, i, j);
+        const Nbr<T> q1 = load_nbr_masked(W, pitch, nx, ny, i, j);
+        const Nbr<T> q2 = load_nbr_masked(W + plane, pitch, nx, ny, i, j);
+        // zeta_i = Q_i - F_i (psi_j - psi_i) on the 5-point cross (zero on walls)
+        Nbr<T> z1, z2;
+        z1.C = q1.C - F1 * (p2.C - p1.C);
+        z1.E = q1.E - F1 * (p2.E - p1.E);
+        z1.W = q1.W - F1 * (p2.W - p1.W);
+        z1.N = q1.N - F1 * (p2.N - p1.N);
+        z1.S = q1.S - F1 * (p2.S - p1.S);
+        z2.C = q2.C - F2 * (p1.C - p2.C);
+        z2.E = q2.E - F2 * (p1.E - p2.E);
+        z2.W = q2.W - F2 * (p1.W - p2.W);
+        z2.N = q2.N - F2 * (p1.N - p2.N);
+        z2.S = q2.S - F2 * (p1.S - p2.S);
+        const T G1 = -cj * arakawa12(p1, q1) - cb * beta3(p1) + nu * lap5(z1, idx2, idy2) +
+                     forcing[o];
+        const T G2 = -cj * arakawa12(p2, q2) - cb * beta3(p2) + nu * lap5(z2, idx2, idy2) -
+                     drag * z2.C;
+        T v1 = b * (q1.C + dt * G1);
+        T v2 = b * (q2.C + dt * G2);
+        if (a_ != 0.0) {
+          v1 += a * wn[o];
+          v2 += a * wn[o + plane];
+        }
+        out[o] = v1;
+        out[o + plane] = v2;
+        if (track) {
+          vmx = (double)fmax(fabs(p1.E - p1.W), fabs(p2.E - p2.W));
+          vmy = (double)fmax(fabs(p1.N - p1.S), fabs(p2.N - p2.S));
+        }
+      }
     }
-    out[o] = v1;
-    out[o + plane] = v2;
   }
+  if (track) put_vmax(d, ctl, lb, vmx, vmy, 2.0 * d.dx, 2.0 * d.dy);
 }
 
 // ---------------------------------------------------------------------------
@@ -232,9 +244,24 @@ __global__ void k_finite_final(const int* __restrict__ partial, int nblk, int* _
 template <typename T>
 hipError_t Launch<T>::stencil_rk3(const MemberDesc* md, int nm, int nblk, const T* ws,
                                   const T* psi, const T* forcing, const T* wn, T* out, double a,
-                                  double b, hipStream_t s) {
+                                  double b, StepCtl ctl, hipStream_t s) {
   hipLaunchKernelGGL(k_stencil_rk3<T>, dim3(nblk), dim3(kTileX * kTileY), 0, s, md, nm, ws, psi,
-                     forcing, wn, out, a, b);
+                     forcing, wn, out, a, b, ctl);
+  return hipGetLastError();
+}
+
+__global__ void k_time_state(const MemberDesc* __restrict__ md, int nm,
+                             const double* __restrict__ ctl, double* __restrict__ out) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < nm) {
+    out[2 * m] = ctl[md[m].cfl_off];
+    out[2 * m + 1] = ctl[md[m].cfl_off + 1];
+  }
+}
+
+hipError_t time_state(const MemberDesc* md, int nm, const double* ctl, double* out,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_time_state, dim3((nm + 255) / 256), dim3(256), 0, s, md, nm, ctl, out);
   return hipGetLastError();
 }
 

@@ -140,9 +140,12 @@ def test_c0_physics_100_steps_fp32(level):
 
 # (512, 32, 0): the fused transform + stencil pass at its widest rows (512
 # intervals, transforms of 1024 complex values); (1024, 64, 1), (1024, 48, 0):
-# rows too wide for it, the unfused one-layer step.
+# rows too wide for it, the unfused one-layer step.  (8, 6, 0): 6 coarse rows,
+# not a multiple of the 4 a fused block owns at c = 1 (unfused); (24, 12, 0)
+# and (16, 12, 1): the smallest fused grids (3 blocks).
 @pytest.mark.parametrize("nx,ny,level", [(96, 192, 1), (48, 96, 0), (192, 96, 2),
-                                         (512, 32, 0), (1024, 64, 1), (1024, 48, 0)])
+                                         (512, 32, 0), (1024, 64, 1), (1024, 48, 0),
+                                         (8, 6, 0), (24, 12, 0), (16, 12, 1)])
 def test_ragged_and_radix3_trajectories(nx, ny, level):
     case = ci.make_case(nx, ny, level=level, dt=1e-4)
     say(f"{nx}x{ny} level {level}, 30 steps FP64")
