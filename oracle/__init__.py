@@ -18,6 +18,7 @@ Modules
   elliptic    sine-transform Poisson / two-layer solves (Sec. 4.3), three routes
   model       right-hand sides, the CGP elliptic map, CGPRK3 step (Sec. 3.2, 4.2)
   cfl         adaptive CFL step size (Sec. 4.2) and the adaptive trajectory
+  statistics  time means over a window of a long run (Sec. 5.1)
   diagnostics basin energy (eq. 26) and enstrophy
   adjoint     tangent-linear and adjoint of the one-layer CGP step; loss gradient
   params      nondimensional parameters from Tables 1 and 2
@@ -29,4 +30,4 @@ against closed forms, invariants, special cases or printed values, except the
 absolute long-run trajectories, which the paper prints nowhere (parity
 unpinned beyond the operator pins that compose them).
 """
-from . import grid, operators, transfer, elliptic, model, cfl, diagnostics, adjoint, params  # noqa: F401
+from . import grid, operators, transfer, elliptic, model, cfl, statistics, diagnostics, adjoint, params  # noqa: F401

@@ -45,8 +45,9 @@ def cfl_dt(psi, grid: Grid, cfl: float, dt_max: float) -> float:
 def run_adaptive(omega0, forcing, grid: Grid, level: int, phys: model.Physics, cfl: float,
                  dt_max: float, nsteps: int, nlayers: int = 1, route: str = "dst",
                  callback=None):
-    """Advance nsteps with adaptive steps.  Returns (state, list of the dt of every
-    step).  callback(n, state, dt) after every step if given."""
+    """Advance nsteps with adaptive steps (cfl <= 0: every step dt_max).  Returns
+    (state, list of the dt of every step).  callback(n, state, dt) after every
+    step if given."""
     w = np.array(omega0, dtype=np.float64)
     dt = dt_max
     dts = []
@@ -59,5 +60,5 @@ def run_adaptive(omega0, forcing, grid: Grid, level: int, phys: model.Physics, c
         dts.append(dt)
         if callback is not None:
             callback(n + 1, w, dt)
-        dt = cfl_dt(stages[2][1], grid, cfl, dt_max)
+        dt = cfl_dt(stages[2][1], grid, cfl, dt_max) if cfl > 0 else dt_max
     return w, dts

@@ -105,3 +105,43 @@ def test_adaptive_steps_follow_the_third_stage_psi():
         w = w_next
     # the steps really adapt (the cap binds only at the start of the spin-up)
     assert len(set(dts[1:])) > 3 and min(dts) < 0.5 * dt_max
+
+
+# ------------------------------------------------------------------ time means (Sec. 5.1)
+def test_time_mean_of_psi_is_the_mean_of_the_per_step_psi():
+    # brute force: average A(omega_n) step by step; the oracle maps the mean
+    # of omega once (A is linear)
+    from oracle import statistics
+    g, phys, w0, F, level = _small()
+    c, dt_max = 0.002, 1e-3
+    mean_w, mean_psi, tsum, _ = statistics.time_mean(w0, F, g, level, phys, c, dt_max, 3, 5)
+    acc_w = np.zeros_like(w0)
+    acc_p = np.zeros_like(w0)
+    t = 0.0
+
+    def cb(n, w, dt):
+        nonlocal t
+        if n > 3:
+            acc_w[...] += dt * w
+            acc_p[...] += dt * model.cgp_psi(w, g, level)
+            t += dt
+
+    cfl.run_adaptive(w0, F, g, level, phys, c, dt_max, 8, callback=cb)
+    assert tsum == pytest.approx(t, rel=1e-15)
+    np.testing.assert_allclose(mean_w, acc_w / t, rtol=0, atol=1e-13 * np.abs(acc_w / t).max())
+    np.testing.assert_allclose(mean_psi, acc_p / t, rtol=0, atol=1e-12 * np.abs(acc_p / t).max())
+
+
+def test_time_mean_with_fixed_steps_is_the_plain_average():
+    from oracle import statistics
+    g, phys, w0, F, level = _small()
+    states = []
+    mean_w, _, tsum, _ = statistics.time_mean(w0, F, g, level, phys, 0.0, 1e-4, 2, 4)
+    w = np.array(w0, dtype=np.float64)
+    for n in range(6):
+        w = model.step(w, F, g, level, phys, 1e-4)
+        if n >= 2:
+            states.append(w)
+    assert tsum == pytest.approx(4e-4, rel=1e-14)
+    np.testing.assert_allclose(mean_w, np.mean(states, axis=0), rtol=0,
+                               atol=1e-13 * np.abs(mean_w).max())
