@@ -124,6 +124,25 @@ cgp_status cgp_step(cgp_handle* h, void* omega_dev, const void* forcing_dev,
  * 2 * members doubles (device memory), written on `stream`. */
 cgp_status cgp_time_state(cgp_handle* h, double* out_dev, void* stream);
 
+/* cgp_step (without psi_out) that also adds, after every step, dt * omega of
+ * the new state to sum_dev (FP64, the handle's field layout; dt of that step):
+ * the time integral of omega over the steps, from which the time mean of
+ * omega, and by linearity of the elliptic map that of psi, follow (the
+ * statistics of the paper's long runs, Sec. 5.1).  Works for ensembles too
+ * (packed fields).  use_graph != 0 replays captured graphs of the steps and
+ * their sums (on a non-default stream). */
+cgp_status cgp_step_mean(cgp_handle* h, void* omega_dev, const void* forcing_dev, int32_t nsteps,
+                         double* sum_dev, int32_t use_graph, void* stream);
+
+/* Running sums for time means (the statistics of the paper's long runs,
+ * Sec. 5.1): sum_dev[k] += weight * w_m * field_dev[k] for every element k
+ * of the handle's field layout (all members and layers, packed as
+ * cgp_step's fields), in FP64 whatever the handle's dtype; w_m is the dt of
+ * member m's latest step when times_dt != 0 (a time-weighted sum), else 1.
+ * sum_dev holds that many doubles (device memory). */
+cgp_status cgp_accumulate(cgp_handle* h, const void* field_dev, double* sum_dev, double weight,
+                          int32_t times_dt, void* stream);
+
 /* The CGP elliptic map alone: psi_dev = P^l L_c^-1 R^l omega_dev
  * (Sec. 3 steps (ii)-(iv); for two layers the coupled solve of Sec. 4.3).
  * Arrays [L][ny+1][nx+1]. */

@@ -46,6 +46,8 @@ SIGNATURES = {
     "cgp_step": (_I32, [_P, _P, _P, _P, _I32, _P]),
     "cgp_solve": (_I32, [_P, _P, _P, _P]),
     "cgp_time_state": (_I32, [_P, _P, _P]),
+    "cgp_accumulate": (_I32, [_P, _P, _P, ctypes.c_double, _I32, _P]),
+    "cgp_step_mean": (_I32, [_P, _P, _P, _I32, _P, _I32, _P]),
     "cgp_diagnostics": (_I32, [_P, _P, _P, _P, _P]),
     "cgp_check_finite": (_I32, [_P, _P, _I64, _P, _P]),
     "cgp_tape_size": (_I32, [_CFG, _I32, ctypes.POINTER(_SZ)]),

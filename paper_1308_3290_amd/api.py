@@ -84,6 +84,17 @@ def cgp_time_state(h, out, stream=None):
     call("cgp_time_state", h, _ptr(out), ctypes.c_void_p(stream_ptr(stream)))
 
 
+def cgp_step_mean(h, omega, forcing, nsteps, total, use_graph=True, stream=None):
+    call("cgp_step_mean", h, _ptr(omega), _ptr(forcing), int(nsteps), _ptr(total),
+         int(bool(use_graph)), ctypes.c_void_p(stream_ptr(stream)))
+
+
+def cgp_accumulate(h, field, total, weight=1.0, times_dt=False, stream=None):
+    """total (FP64 device tensor, the handle's field layout) += weight [* dt] * field."""
+    call("cgp_accumulate", h, _ptr(field), _ptr(total), float(weight), int(bool(times_dt)),
+         ctypes.c_void_p(stream_ptr(stream)))
+
+
 def cgp_solve(h, omega, psi, stream=None):
     call("cgp_solve", h, _ptr(omega), _ptr(psi), ctypes.c_void_p(stream_ptr(stream)))
 
@@ -216,6 +227,23 @@ class Basin:
         out = torch.empty(2, dtype=torch.float64, device=self.device)
         cgp_time_state(self.handle, out, stream)
         return out
+
+    def step_mean(self, omega, forcing, nsteps, total, use_graph=True, stream=None):
+        """nsteps steps; after each, total (FP64, the field's shape) += dt * omega."""
+        self._chk(omega, "omega")
+        self._chk(forcing, "forcing", (self.cfg.ny + 1) * (self.cfg.nx + 1))
+        if total.dtype != torch.float64 or total.numel() != self.numel or not total.is_cuda:
+            raise CGPError(_lib.CGP_ERR_INVALID, "total must be an FP64 device tensor of the field")
+        cgp_step_mean(self.handle, omega, forcing, nsteps, total, use_graph, stream)
+        return omega
+
+    def accumulate(self, field, total, weight=1.0, times_dt=False, stream=None):
+        """total (FP64, the field's shape) += weight [* dt of the latest step] * field."""
+        self._chk(field, "field")
+        if total.dtype != torch.float64 or total.numel() != self.numel or not total.is_cuda:
+            raise CGPError(_lib.CGP_ERR_INVALID, "total must be an FP64 device tensor of the field")
+        cgp_accumulate(self.handle, field, total, weight, times_dt, stream)
+        return total
 
     def tape(self, nsteps):
         n = cgp_tape_size(self.cfg, nsteps)

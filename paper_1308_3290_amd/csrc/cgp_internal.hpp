@@ -244,6 +244,10 @@ struct Launch {
                                 int nblk, double* out, hipStream_t s);
   static hipError_t check_finite(const T* f, long long n, int* partial, int nblk, int* flag,
                                  hipStream_t s);
+  // sum[k] += weight * w_m * f[k] (FP64) over the n packed field elements of
+  // the nm members, w_m = the dt of member m's latest step (ctl != NULL) or 1
+  static hipError_t accumulate(const MemberDesc* md, int nm, const T* f, long long n,
+                               double* sum, double weight, const double* ctl, hipStream_t s);
 };
 
 // out[2m], out[2m+1] = dt of the latest step and model time of member m.

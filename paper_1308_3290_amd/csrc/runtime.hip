@@ -331,9 +331,9 @@ struct cgp_handle {
   Plan plan;
   char* ws = nullptr;
   std::vector<char> host_tables;  // kept alive until destroy (async upload source)
-  // graph cache: (omega, forcing, rotation phase of the fused step) ->
-  // executable graph of one step
-  std::map<std::tuple<const void*, const void*, int>, hipGraphExec_t> graphs;
+  // graph cache: (omega, forcing, rotation phase of the fused step, running
+  // sum of cgp_step_mean or NULL) -> executable graph of one step
+  std::map<std::tuple<const void*, const void*, int, const void*>, hipGraphExec_t> graphs;
   int nm() const { return (int)plan.md.size(); }
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   const MemberDesc* d_md() const { return at<MemberDesc>(plan.lay.desc); }
@@ -605,12 +605,28 @@ cgp_status create_common(const cgp_config* cfgs, int count, void* ws, size_t byt
   return CGP_OK;
 }
 
-// Graph of one step for (omega, forcing, pos), captured on first use; pos = 3
-// (fused handles): the three steps of a full rotation, pos 0 -> 0.
+// sum += dt * (state after a step), over the handle's field layout.
 template <typename T>
-cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, hipStream_t s,
+hipError_t enqueue_mean(cgp_handle* h, const T* state, double* sum, hipStream_t s) {
+  return Launch<T>::accumulate(h->d_md(), h->nm(), state, h->plan.lay.field_elems, sum, 1.0,
+                               h->at<double>(h->plan.lay.ctl), s);
+}
+
+// The state buffer of a fused step that started at rotation phase pos.
+template <typename T>
+T* fused_state_after(cgp_handle* h, T* w, int pos) {
+  const int q = (pos + 1) % 3;
+  return q == 0 ? w : h->at<T>(q == 1 ? h->plan.lay.st1 : h->plan.lay.st2);
+}
+
+// Graph of one step for (omega, forcing, pos, sum), captured on first use;
+// pos = 3 (fused handles): the three steps of a full rotation, pos 0 -> 0;
+// sum != NULL: each step followed by its time-weighted accumulation.
+template <typename T>
+cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, double* sum, hipStream_t s,
                       hipGraphExec_t* out) {
-  auto key = std::make_tuple(static_cast<const void*>(w), static_cast<const void*>(F), pos);
+  auto key = std::make_tuple(static_cast<const void*>(w), static_cast<const void*>(F), pos,
+                             static_cast<const void*>(sum));
   auto it = h->graphs.find(key);
   if (it != h->graphs.end()) {
     *out = it->second;
@@ -621,9 +637,12 @@ cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, hipStream_t s,
   hipError_t e = hipSuccess;
   if (!h->plan.fused) {
     e = enqueue_step<T>(h, w, F, s);
+    if (e == hipSuccess && sum) e = enqueue_mean<T>(h, w, sum, s);
   } else {
-    for (int q = (pos == 3 ? 0 : pos); q < (pos == 3 ? 3 : pos + 1) && e == hipSuccess; ++q)
+    for (int q = (pos == 3 ? 0 : pos); q < (pos == 3 ? 3 : pos + 1) && e == hipSuccess; ++q) {
       e = enqueue_step_fused<T>(h, w, F, q, s);
+      if (e == hipSuccess && sum) e = enqueue_mean<T>(h, fused_state_after<T>(h, w, q), sum, s);
+    }
   }
   hipError_t e2 = hipStreamEndCapture(s, &g);
   if (e != hipSuccess) return hip_fail(e, "capture step");
@@ -639,7 +658,7 @@ cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, hipStream_t s,
 
 template <typename T>
 cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_out, int nsteps,
-                     int use_graph, hipStream_t s) {
+                     int use_graph, hipStream_t s, double* sum = nullptr) {
   T* w = static_cast<T*>(omega);
   const T* F = static_cast<const T*>(forcing);
   const bool graph = use_graph && s != nullptr;
@@ -647,11 +666,12 @@ cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_
     for (int n = 0; n < nsteps; ++n) {
       if (graph) {
         hipGraphExec_t exec = nullptr;
-        cgp_status st = step_graph<T>(h, w, F, 0, s, &exec);
+        cgp_status st = step_graph<T>(h, w, F, 0, sum, s, &exec);
         if (st != CGP_OK) return st;
         HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
       } else {
         HIP_TRY(enqueue_step<T>(h, w, F, s), "step launch");
+        if (sum) HIP_TRY(enqueue_mean<T>(h, w, sum, s), "accumulate launch");
       }
     }
   } else if (nsteps > 0) {
@@ -664,7 +684,7 @@ cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_
         // whole rotations as one graph, the rest step by step
         const int q = (pos == 0 && nsteps - n >= 3) ? 3 : pos;
         hipGraphExec_t exec = nullptr;
-        cgp_status st = step_graph<T>(h, w, F, q, s, &exec);
+        cgp_status st = step_graph<T>(h, w, F, q, sum, s, &exec);
         if (st != CGP_OK) return st;
         HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
         const int done = q == 3 ? 3 : 1;
@@ -672,6 +692,8 @@ cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_
         pos = (pos + done) % 3;
       } else {
         HIP_TRY(enqueue_step_fused<T>(h, w, F, pos, s), "step launch");
+        if (sum) HIP_TRY(enqueue_mean<T>(h, fused_state_after<T>(h, w, pos), sum, s),
+                         "accumulate launch");
         ++n;
         pos = (pos + 1) % 3;
       }
@@ -762,6 +784,17 @@ cgp_status cgp_step(cgp_handle* h, void* omega, const void* forcing, void* psi_o
              : step_impl<float>(h, omega, forcing, psi_out, nsteps, 0, s);
 }
 
+cgp_status cgp_step_mean(cgp_handle* h, void* omega, const void* forcing, int32_t nsteps,
+                         double* sum, int32_t use_graph, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!omega || !forcing || !sum) return fail(CGP_ERR_INVALID, "omega, forcing or sum is NULL");
+  if (nsteps < 0) return fail(CGP_ERR_INVALID, "nsteps < 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return h->plan.dtype == CGP_F64
+             ? step_impl<double>(h, omega, forcing, nullptr, nsteps, use_graph, s, sum)
+             : step_impl<float>(h, omega, forcing, nullptr, nsteps, use_graph, s, sum);
+}
+
 cgp_status cgp_solve(cgp_handle* h, const void* omega, void* psi, void* stream) {
   if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
   if (!omega || !psi) return fail(CGP_ERR_INVALID, "omega or psi is NULL");
@@ -805,6 +838,25 @@ cgp_status cgp_check_finite(cgp_handle* h, const void* field, int64_t count, int
                      : Launch<float>::check_finite(static_cast<const float*>(field), count, part,
                                                    kFiniteBlocks, flag, s);
   if (e != hipSuccess) return hip_fail(e, "finite-check launch");
+  return CGP_OK;
+}
+
+cgp_status cgp_accumulate(cgp_handle* h, const void* field, double* sum, double weight,
+                          int32_t times_dt, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!field || !sum) return fail(CGP_ERR_INVALID, "bad argument");
+  if (!std::isfinite(weight)) return fail(CGP_ERR_INVALID, "non-finite weight");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double* ctl = times_dt ? h->at<double>(h->plan.lay.ctl) : nullptr;
+  const long long n = h->plan.lay.field_elems;
+  hipError_t e = h->plan.dtype == CGP_F64
+                     ? Launch<double>::accumulate(h->d_md(), h->nm(),
+                                                  static_cast<const double*>(field), n, sum,
+                                                  weight, ctl, s)
+                     : Launch<float>::accumulate(h->d_md(), h->nm(),
+                                                 static_cast<const float*>(field), n, sum, weight,
+                                                 ctl, s);
+  if (e != hipSuccess) return hip_fail(e, "accumulate launch");
   return CGP_OK;
 }
 

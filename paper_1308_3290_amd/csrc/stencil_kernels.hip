@@ -273,6 +273,37 @@ hipError_t Launch<T>::diagnostics(const MemberDesc* md, const T* w, const T* psi
   return hipGetLastError();
 }
 
+// Running sums of a packed field (time means of the statistics workloads).
+template <typename T>
+__global__ __launch_bounds__(256) void k_accumulate(const MemberDesc* __restrict__ md, int nm,
+                                                    const T* __restrict__ f, long long n,
+                                                    double* __restrict__ sum, double weight,
+                                                    const double* __restrict__ ctl) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    double w = weight;
+    if (ctl != nullptr) {
+      int lo = 0, hi = nm - 1;  // the member holding element k
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (md[mid].field_off <= k) lo = mid; else hi = mid - 1;
+      }
+      w *= ctl[md[lo].cfl_off];
+    }
+    sum[k] += w * (double)f[k];
+  }
+}
+
+template <typename T>
+hipError_t Launch<T>::accumulate(const MemberDesc* md, int nm, const T* f, long long n,
+                                 double* sum, double weight, const double* ctl, hipStream_t s) {
+  const long long want = (n + 255) / 256;
+  const int nblk = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+  hipLaunchKernelGGL(k_accumulate<T>, dim3(nblk), dim3(256), 0, s, md, nm, f, n, sum, weight,
+                     ctl);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t Launch<T>::check_finite(const T* f, long long n, int* partial, int nblk, int* flag,
                                    hipStream_t s) {

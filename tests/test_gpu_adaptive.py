@@ -145,3 +145,85 @@ def test_ensemble_mixes_adaptive_and_fixed_members():
         assert torch.equal(st[m], ts), m
     assert float(st[1][0]) == 1e-4 and float(st[1][1]) == pytest.approx(1e-3, rel=1e-14)
     assert float(st[0][0]) < 1e-3
+
+
+# ----------------------------------------------------------------- time means (Sec. 5.1)
+def test_accumulate_matches_numpy():
+    from paper_1308_3290_amd.api import Basin, config_from_case
+    case = _case(64, 128, 1, 1, 0.01)
+    b = Basin(config_from_case(case))
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(case.shape)
+    s0 = rng.standard_normal(case.shape)
+    total = to_dev(s0)
+    b.accumulate(to_dev(f), total, weight=0.3)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(to_np(total), s0 + 0.3 * f, rtol=1e-15, atol=1e-15)
+    # times_dt: the weight times the dt of the latest step (the configured dt
+    # before any step)
+    b.accumulate(to_dev(f), total, weight=2.0, times_dt=True)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(to_np(total), s0 + 0.3 * f + 2.0 * case.dt * f, rtol=1e-14,
+                               atol=1e-14)
+
+
+@pytest.mark.parametrize("nx,ny,level,layers", [(64, 128, 1, 1), (64, 128, 0, 1),
+                                                (128, 256, 1, 2)])
+def test_step_mean_matches_oracle_time_mean(nx, ny, level, layers):
+    from oracle import statistics as ost
+    from paper_1308_3290_amd.api import Basin, config_from_case
+    case = _case(nx, ny, level, layers, 0.01 if layers == 1 else 0.003)
+    say(f"time mean {nx}x{ny} level {level} layers {layers}: 5 + 12 adaptive steps")
+    g, phys = oracle_setup(case)
+    w0 = random_state(case, 11, 1e-2)
+    F = ci.forcing_field(case)
+    mw_ref, mp_ref, tsum_ref, _ = ost.time_mean(w0, F, g, level, phys, case.cfl, case.dt, 5, 12,
+                                                nlayers=layers)
+    means = []
+    for use_graph in (False, True):
+        b = Basin(config_from_case(case))
+        w = to_dev(w0)
+        Fd = to_dev(F)
+        total = torch.zeros_like(w)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            b.step(w, Fd, nsteps=5, stream=side)
+            t0 = b.time_state(side)[1].clone()
+            b.step_mean(w, Fd, 12, total, use_graph=use_graph, stream=side)
+            t1 = b.time_state(side)[1].clone()
+        torch.cuda.synchronize()
+        tsum = float(t1 - t0)
+        mw = to_np(total) / tsum
+        mp = to_np(b.solve(to_dev(mw)))
+        means.append(total)
+        assert tsum == pytest.approx(tsum_ref, rel=1e-12)
+        assert rel_l2(mw, mw_ref) < TOL64 and rel_l2(mp, mp_ref) < TOL64
+    assert torch.equal(means[0], means[1])  # graphs and direct launches agree
+
+
+def test_long_run_driver_matches_oracle():
+    """The statistics driver (spin-up, averaging window, energy history) on a
+    short horizon, against the oracle's time mean over the same steps."""
+    from oracle import statistics as ost
+    from paper_1308_3290_amd.api import Basin, config_from_case
+    from paper_1308_3290_amd.statistics import long_run
+    case = _case(64, 128, 1, 1, 0.01)
+    g, phys = oracle_setup(case)
+    w0 = random_state(case, 12, 1e-2)
+    F = ci.forcing_field(case)
+    b = Basin(config_from_case(case))
+    w = to_dev(w0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        r = long_run(b, w, to_dev(F), t_spin=0.004, t_end=0.012, chunk=5, stream=side)
+    say(f"long run: {r['steps_spin']} + {r['steps_avg']} steps, window {r['t0']:.4g}..{r['t1']:.4g}")
+    assert r["steps_spin"] > 0 and r["steps_avg"] > 0 and r["t1"] >= 0.012
+    mw_ref, mp_ref, tsum_ref, w_ref = ost.time_mean(w0, F, g, 1, phys, case.cfl, case.dt,
+                                                    r["steps_spin"], r["steps_avg"])
+    assert (r["t1"] - r["t0"]) == pytest.approx(tsum_ref, rel=1e-12)
+    assert rel_l2(r["mean_omega"], mw_ref) < TOL64 and rel_l2(r["mean_psi"], mp_ref) < TOL64
+    assert rel_l2(to_np(w), w_ref) < TOL64
+    n = (r["steps_spin"] + r["steps_avg"]) // 5 + 1
+    assert r["energy"].shape == (n, 1) and np.all(np.diff(r["times"]) > 0)
