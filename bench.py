@@ -292,7 +292,7 @@ def main():
     # ---------------------------------------------------------------- extras
     extras = {}
     if args.extras:
-        # --only may pick extras too: two_layer, fp32, ens
+        # --only may pick extras too: two_layer, l3, adaptive, fp32, ens
         want = (lambda k: not only or k in only)
         for lv in (1, 0, 2):
             if not want("two_layer"):
@@ -300,6 +300,15 @@ def main():
             case = ci.case_c2(lv)
             ms, finite, *_ = timed_run(case, steps=min(K, 500))
             extras[f"two_layer_l{lv}"] = case.points * min(K, 500) / (ms * 1e-3) / 1e6
+        if want("l3"):  # three levels of coarsening (64x128 solve)
+            case = ci.case_c1(3)
+            ms, finite, *_ = timed_run(case, steps=min(K, 500))
+            extras["cgp8_l3"] = case.points * min(K, 500) / (ms * 1e-3) / 1e6
+        if want("adaptive"):  # the step size of Sec. 4.2 (CFL 0.5, capped at dt)
+            case = ci.case_c1(1)
+            case.cfl = 0.5
+            ms, finite, *_ = timed_run(case)
+            extras["adaptive_l1"] = case.points * K / (ms * 1e-3) / 1e6
         for lv in (1, 0):
             if not want("fp32"):
                 break

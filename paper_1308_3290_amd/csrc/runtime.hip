@@ -129,6 +129,10 @@ struct Plan {
   int nblk_d = 0;                    // pass D: one launch over every member
   int dtype = CGP_F64, nlayers = 1;
   bool fused = false;                // time steps use the fused C + D pass
+  // member chains of the fused step: (pass B group, fused group) pairs with
+  // the same members; the chains of a step are independent, so a captured
+  // step runs them on separate streams (ensembles of several sizes)
+  std::vector<std::pair<int, int>> chains;
 };
 
 constexpr int kGenericThreads = 256;
@@ -322,6 +326,14 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   L.diag = off; off = align_up(off + (size_t)kDiagBlocks * 2 * 3 * sizeof(double));
   L.fin = off; off = align_up(off + (size_t)kFiniteBlocks * sizeof(int));
   L.total = off;
+  if (plan->fused && plan->groups[1].size() == plan->groups[3].size() &&
+      plan->groups[3].size() > 1) {
+    for (size_t i = 0; i < plan->groups[3].size(); ++i)
+      for (size_t j = 0; j < plan->groups[1].size(); ++j)
+        if (plan->groups[1][j].members == plan->groups[3][i].members)
+          plan->chains.emplace_back((int)j, (int)i);
+    if (plan->chains.size() != plan->groups[3].size()) plan->chains.clear();
+  }
   return CGP_OK;
 }
 
@@ -334,6 +346,9 @@ struct cgp_handle {
   // graph cache: (omega, forcing, rotation phase of the fused step, running
   // sum of cgp_step_mean or NULL) -> executable graph of one step
   std::map<std::tuple<const void*, const void*, int, const void*>, hipGraphExec_t> graphs;
+  // side streams and events of chained graph captures (made on first use)
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> events;
   int nm() const { return (int)plan.md.size(); }
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   const MemberDesc* d_md() const { return at<MemberDesc>(plan.lay.desc); }
@@ -353,14 +368,16 @@ const double kRkB[3] = {1.0, 0.25, 2.0 / 3.0};
 
 // One pass of the coarse solve (0: A, 1: B, 2: C) over every member.
 // ctl (pass B of a step's first stage): the step state, whose dt is set.
+// only >= 0: that group of the pass alone.
 template <typename T>
 hipError_t enqueue_pass(cgp_handle* h, int pass, const T* src, T* dst, int accumulate,
-                        hipStream_t s, double* ctl = nullptr) {
+                        hipStream_t s, double* ctl = nullptr, int only = -1) {
   const Plan& p = h->plan;
   const cplx<T>* tw = h->at<cplx<T>>(p.lay.tw);
   T* wt = h->at<T>(p.lay.wt);
   T* wt2 = h->at<T>(p.lay.wt2);
   for (int i = 0; i < h->ngroups(pass); ++i) {
+    if (only >= 0 && i != only) continue;
     const Group g = h->group(pass, i);
     hipError_t e;
     if (pass == 0)
@@ -389,9 +406,10 @@ hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hi
 template <typename T>
 hipError_t enqueue_fused(cgp_handle* h, const T* ws, const T* forcing, const T* wn, T* out,
                          double a, double b, bool next, hipStream_t s, T* psi_out = nullptr,
-                         StepCtl ctl = StepCtl{nullptr, 0}) {
+                         StepCtl ctl = StepCtl{nullptr, 0}, int only = -1) {
   const Plan& p = h->plan;
   for (int i = 0; i < h->ngroups(3); ++i) {
+    if (only >= 0 && i != only) continue;
     T* wnext = next ? h->at<T>(p.lay.wt) : nullptr;
     hipError_t e =
         p.nlayers == 1
@@ -441,7 +459,7 @@ hipError_t enqueue_step(cgp_handle* h, T* omega, const T* forcing, hipStream_t s
 // on entry and in bufs[(pos+1) % 3] on exit.
 template <typename T>
 hipError_t enqueue_step_fused(cgp_handle* h, T* omega, const T* forcing, int pos,
-                              hipStream_t s) {
+                              hipStream_t s, int chain = -1) {
   const Plan& p = h->plan;
   T* bufs[3] = {omega, h->at<T>(p.lay.st1), h->at<T>(p.lay.st2)};
   T* S = bufs[pos];
@@ -450,11 +468,13 @@ hipError_t enqueue_step_fused(cgp_handle* h, T* omega, const T* forcing, int pos
   const T* src[3] = {S, X, Y};
   T* dst[3] = {X, Y, X};
   double* ctl = h->at<double>(p.lay.ctl);
+  const int gb = chain >= 0 ? p.chains[chain].first : -1;
+  const int gf = chain >= 0 ? p.chains[chain].second : -1;
   for (int st = 0; st < 3; ++st) {
-    hipError_t e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s, st == 0 ? ctl : nullptr);
+    hipError_t e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s, st == 0 ? ctl : nullptr, gb);
     if (e == hipSuccess)
       e = enqueue_fused<T>(h, src[st], forcing, S, dst[st], kRkA[st], kRkB[st], true, s,
-                           nullptr, StepCtl{ctl, st == 2});
+                           nullptr, StepCtl{ctl, st == 2}, gf);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -632,14 +652,41 @@ cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, double* sum, hip
     *out = it->second;
     return CGP_OK;
   }
+  const size_t nch = h->plan.chains.size();
+  if (h->plan.fused && nch > 1 && !sum && h->side.size() + 1 < nch) {
+    // side streams (default priority) and fork / join events, made once
+    while (h->side.size() + 1 < nch) {
+      hipStream_t st = nullptr;
+      HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "side stream");
+      h->side.push_back(st);
+    }
+    while (h->events.size() < nch) {
+      hipEvent_t ev = nullptr;
+      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+      h->events.push_back(ev);
+    }
+  }
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
   hipError_t e = hipSuccess;
+  const int q0 = pos == 3 ? 0 : pos, q1 = pos == 3 ? 3 : pos + 1;
   if (!h->plan.fused) {
     e = enqueue_step<T>(h, w, F, s);
     if (e == hipSuccess && sum) e = enqueue_mean<T>(h, w, sum, s);
+  } else if (nch > 1 && !sum) {
+    // independent member chains forked onto side streams and joined back
+    const int nc = (int)nch;
+    hipEvent_t* ev = h->events.data();
+    e = hipEventRecord(ev[0], s);
+    for (int k = 0; k < nc && e == hipSuccess; ++k) {
+      hipStream_t sk = k == 0 ? s : h->side[k - 1];
+      if (k > 0) e = hipStreamWaitEvent(sk, ev[0], 0);
+      for (int q = q0; q < q1 && e == hipSuccess; ++q) e = enqueue_step_fused<T>(h, w, F, q, sk, k);
+      if (k > 0 && e == hipSuccess) e = hipEventRecord(ev[k], sk);
+    }
+    for (int k = 1; k < nc && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, ev[k], 0);
   } else {
-    for (int q = (pos == 3 ? 0 : pos); q < (pos == 3 ? 3 : pos + 1) && e == hipSuccess; ++q) {
+    for (int q = q0; q < q1 && e == hipSuccess; ++q) {
       e = enqueue_step_fused<T>(h, w, F, q, s);
       if (e == hipSuccess && sum) e = enqueue_mean<T>(h, fused_state_after<T>(h, w, q), sum, s);
     }
@@ -757,6 +804,8 @@ cgp_status cgp_ensemble_create(const cgp_config* members, int32_t count, void* w
 cgp_status cgp_destroy(cgp_handle* h) {
   if (!h) return CGP_OK;
   for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (hipStream_t st : h->side) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
   delete h;
   return CGP_OK;
 }

@@ -121,19 +121,25 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=250)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--control-seed", type=int, default=None,
+                    help="also run level 0 from another initial state (this seed) and report "
+                         "its differences from the first level-0 run: the sampling spread of "
+                         "the time means")
     args = ap.parse_args(argv)
     p = EXPERIMENTS[args.exp]
     nx, ny = args.nx, args.ny
     y = -1.0 + np.arange(ny + 1) * (2.0 / ny)
     F = np.broadcast_to((np.sin(np.pi * y) / p["ro"])[:, None], (ny + 1, nx + 1)).copy()
     tdt = torch.float64 if args.dtype == "f64" else torch.float32
-    rng = np.random.default_rng(args.seed)
-    w0 = np.zeros((ny + 1, nx + 1))
-    w0[1:-1, 1:-1] = 1e-3 * rng.standard_normal((ny - 1, nx - 1))
     dev = torch.device("cuda:0")
     side = torch.cuda.Stream()  # graphs are captured on a non-default stream
     ref = None
-    for lv in args.levels:
+    runs = [(lv, args.seed) for lv in args.levels]
+    if args.control_seed is not None:
+        runs.append((0, args.control_seed))
+    for lv, seed in runs:
+        w0 = np.zeros((ny + 1, nx + 1))
+        w0[1:-1, 1:-1] = 1e-3 * np.random.default_rng(seed).standard_normal((ny - 1, nx - 1))
         cfg = make_config(nx, ny, level=lv, dtype=args.dtype, inv_re=1.0 / p["re"],
                           inv_ro=1.0 / p["ro"], dt=args.dt_max, cfl=args.cfl)
         b = Basin(cfg, device=dev)
@@ -152,7 +158,7 @@ def main(argv=None):
                          progress=progress)
         q = p["ro"] * r["mean_omega"] + y[:, None]
         sel = r["times"] >= r["t0"]
-        out = dict(experiment=args.exp, grid=f"{nx}x{ny}", level=lv,
+        out = dict(experiment=args.exp, grid=f"{nx}x{ny}", level=lv, seed=seed,
                    elliptic_grid=f"{nx >> lv}x{ny >> lv}", cfl=args.cfl, dt_max=args.dt_max,
                    t_window=[round(r["t0"], 4), round(r["t1"], 4)],
                    steps=r["steps_spin"] + r["steps_avg"], wall_s=round(r["wall_s"], 2),

@@ -46,6 +46,7 @@ def _tdt(dtype):
 SOLVE_CASES = [
     (64, 128, 0), (64, 128, 1), (64, 128, 2), (96, 192, 1), (48, 96, 0), (128, 64, 1),
     (16, 16, 2), (192, 384, 2), (512, 1024, 1), (512, 1024, 2), (512, 1024, 0),
+    (64, 128, 3), (512, 1024, 3),  # three levels of coarsening (c = 8)
 ]
 
 
@@ -145,7 +146,7 @@ def test_c0_physics_100_steps_fp32(level):
 # and (16, 12, 1): the smallest fused grids (3 blocks).
 @pytest.mark.parametrize("nx,ny,level", [(96, 192, 1), (48, 96, 0), (192, 96, 2),
                                          (512, 32, 0), (1024, 64, 1), (1024, 48, 0),
-                                         (8, 6, 0), (24, 12, 0), (16, 12, 1)])
+                                         (8, 6, 0), (24, 12, 0), (16, 12, 1), (256, 512, 3)])
 def test_ragged_and_radix3_trajectories(nx, ny, level):
     case = ci.make_case(nx, ny, level=level, dt=1e-4)
     say(f"{nx}x{ny} level {level}, 30 steps FP64")
@@ -160,7 +161,8 @@ def test_ragged_and_radix3_trajectories(nx, ny, level):
 # rows of 64, 64 and 192 intervals, transforms of 128 and 384): the fused
 # two-layer stage kernel
 @pytest.mark.parametrize("nx,ny,level", [(64, 128, 0), (64, 128, 1), (64, 128, 2),
-                                         (128, 256, 1), (256, 128, 2), (384, 192, 1)])
+                                         (128, 256, 1), (256, 128, 2), (384, 192, 1),
+                                         (128, 256, 3)])
 def test_two_layer_trajectory_fp64(nx, ny, level):
     c2 = ci.case_c2(level)
     case = ci.make_case(nx, ny, level=level, nlayers=2, f1=c2.f1, f2=c2.f2, drag=c2.drag,
@@ -382,6 +384,36 @@ def test_ensemble_matches_single_basins_and_oracle(dtype, use_graph):
         err = rel_l2(to_np(got), w_or)
         say(f"  member {m} {c.nx}x{c.ny}: rel L2 vs oracle {err:.3e}")
         assert err < (TOL64 if dtype == "f64" else TOL32)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_chained_ensemble_graph_matches_single_basins(dtype):
+    """Members of three sizes with compile-time transform lengths: each size is
+    one chain of pass B and fused launches, and a captured step runs the
+    chains on separate streams.  Every member must equal its single-basin
+    run bit for bit, over 7 steps (a rotation graph plus single steps)."""
+    from paper_1308_3290_amd.api import Ensemble, config_from_case
+    sizes = [(128, 256), (256, 512), (128, 256), (384, 768), (256, 512)]
+    cases = [ci.make_case(nx, ny, level=1, inv_re=1.0 / (300 + 50 * k), dt=2.5e-5, dtype=dtype)
+             for k, (nx, ny) in enumerate(sizes)]
+    rng = np.random.default_rng(44)
+    w0s = [ci.initial_field(c, rng, 1e-2) for c in cases]
+    Fs = [ci.forcing_field(c) for c in cases]
+    ens = Ensemble([config_from_case(c) for c in cases])
+    W = ens.pack(w0s)
+    Fp = ens.pack(Fs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ens.step(W, Fp, nsteps=4, use_graph=True)
+        ens.step(W, Fp, nsteps=3, use_graph=True)
+    torch.cuda.synchronize()
+    tdt = _tdt(dtype)
+    for m, c in enumerate(cases):
+        b = _basin(c, dtype)
+        ws = to_dev(w0s[m], tdt)
+        b.step(ws, to_dev(Fs[m], tdt), nsteps=7)
+        assert torch.equal(ens.member_view(W, m), ws), f"member {m} differs"
 
 
 # ----------------------------------------------------------------- adjoint
