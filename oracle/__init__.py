@@ -16,6 +16,7 @@ Modules
               and exact transposes of every 9-point operator (scatter form)
   transfer    full-weighting restriction and bilinear prolongation (Sec. 3.1)
   elliptic    sine-transform Poisson / two-layer solves (Sec. 4.3), three routes
+  multigrid   V-cycle multigrid for the coarse Poisson problem (CGP's black box)
   model       right-hand sides, the CGP elliptic map, CGPRK3 step (Sec. 3.2, 4.2)
   cfl         adaptive CFL step size (Sec. 4.2) and the adaptive trajectory
   statistics  time means over a window of a long run (Sec. 5.1)
@@ -30,4 +31,4 @@ against closed forms, invariants, special cases or printed values, except the
 absolute long-run trajectories, which the paper prints nowhere (parity
 unpinned beyond the operator pins that compose them).
 """
-from . import grid, operators, transfer, elliptic, model, cfl, statistics, diagnostics, adjoint, params  # noqa: F401
+from . import grid, operators, transfer, elliptic, multigrid, model, cfl, statistics, diagnostics, adjoint, params  # noqa: F401

@@ -16,6 +16,8 @@ Three independent routes reach the same unique discrete solution:
   'dense'  the sums written out as dense sine matrices (O(n^2) per line)
   'dst'    scipy.fft.dst type I (a library sine transform; dst1 = 2 * S)
   'sparse' scipy.sparse LU of the assembled 5-point matrix (no transform)
+and, as an iterative black box for CGP, 'mg<N>': N multigrid V-cycles
+(multigrid.py; one layer).
 """
 from __future__ import annotations
 
@@ -85,6 +87,9 @@ def laplacian_matrix(nx: int, ny: int, dx: float, dy: float):
 def poisson(r: np.ndarray, dx: float, dy: float, route: str = "dst") -> np.ndarray:
     """psi with Delta_h psi = r at interior nodes, psi = 0 on the ring."""
     ny, nx = r.shape[0] - 1, r.shape[1] - 1
+    if route.startswith("mg"):  # "mg<N>": N multigrid V-cycles (multigrid.py)
+        from . import multigrid
+        return multigrid.poisson_mg(r, dx, dy, int(route[2:]))
     if route == "sparse":
         A = laplacian_matrix(nx, ny, dx, dy)
         sol = scipy.sparse.linalg.splu(A).solve(r[1:-1, 1:-1].ravel())
