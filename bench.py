@@ -292,7 +292,7 @@ def main():
     # ---------------------------------------------------------------- extras
     extras = {}
     if args.extras:
-        # --only may pick extras too: two_layer, l3, adaptive, fp32, ens
+        # --only may pick extras too: two_layer, l3, mg, adaptive, fp32, ens
         want = (lambda k: not only or k in only)
         for lv in (1, 0, 2):
             if not want("two_layer"):
@@ -304,6 +304,12 @@ def main():
             case = ci.case_c1(3)
             ms, finite, *_ = timed_run(case, steps=min(K, 500))
             extras["cgp8_l3"] = case.points * min(K, 500) / (ms * 1e-3) / 1e6
+        if want("mg"):  # the multigrid coarse solver (12 V-cycles) at levels 0, 1, 2
+            for lv in (0, 1, 2):
+                case = ci.case_c1(lv)
+                case.solver = 1
+                ms, finite, *_ = timed_run(case, steps=20, warm=2)
+                extras[f"multigrid_l{lv}"] = case.points * 20 / (ms * 1e-3) / 1e6
         if want("adaptive"):  # the step size of Sec. 4.2 (CFL 0.5, capped at dt)
             case = ci.case_c1(1)
             case.cfl = 0.5

@@ -59,6 +59,8 @@ class Case:
     drag: float = 0.0
     dt: float = 1e-4
     cfl: float = 0.0      # CFL number of the adaptive step (Sec. 4.2); 0: fixed dt
+    solver: int = 0       # coarse solver: 0 sine transform, 1 multigrid V-cycles
+    mg_cycles: int = 0    # V-cycles per solve (0: the library default)
     nsteps: int = 1
     seed: int = 0
     dtype: str = "f64"

@@ -91,6 +91,13 @@ typedef struct cgp_config {
                         * of the step's third stage (dt itself when that maximum
                         * is 0).  The step state lives in the workspace, so that
                         * a run split over calls takes the same steps. */
+  int32_t solver;      /* coarse elliptic solver: 0 = sine transform (Sec. 4.3, exact);
+                        * 1 = multigrid V(2,2) cycles (red-black Gauss-Seidel,
+                        * full weighting, bilinear interpolation, exact coarsest
+                        * grid), an iterative black box under CGP: one layer,
+                        * single basin, no adjoint */
+  int32_t mg_cycles;   /* V-cycles per solve with solver 1 (0: 12; each cycle cuts
+                        * the residual about tenfold) */
 } cgp_config;
 
 typedef struct cgp_handle cgp_handle;

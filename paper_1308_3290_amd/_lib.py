@@ -23,7 +23,8 @@ class cgp_config(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
                 ("y0", ctypes.c_double), ("inv_re", ctypes.c_double),
                 ("inv_ro", ctypes.c_double), ("f1", ctypes.c_double), ("f2", ctypes.c_double),
-                ("drag", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double)]
+                ("drag", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("solver", ctypes.c_int32), ("mg_cycles", ctypes.c_int32)]
 
 
 class CGPError(RuntimeError):

@@ -22,18 +22,18 @@ _TORCH_DTYPE = {CGP_F32: torch.float32, CGP_F64: torch.float64}
 
 def make_config(nx, ny, level=0, nlayers=1, dtype="f64", lx=1.0, ly=2.0, y0=-1.0,
                 inv_re=1.0, inv_ro=0.0, f1=0.0, f2=0.0, drag=0.0, dt=1e-4,
-                cfl=0.0) -> cgp_config:
+                cfl=0.0, solver=0, mg_cycles=0) -> cgp_config:
     dt_code = {"f64": CGP_F64, "f32": CGP_F32}.get(dtype, dtype)  # ints pass through
     return cgp_config(nx=nx, ny=ny, level=level, nlayers=nlayers, dtype=dt_code, reserved=0,
                       lx=lx, ly=ly, y0=y0, inv_re=inv_re, inv_ro=inv_ro, f1=f1, f2=f2,
-                      drag=drag, dt=dt, cfl=cfl)
+                      drag=drag, dt=dt, cfl=cfl, solver=solver, mg_cycles=mg_cycles)
 
 
 def config_from_case(case, dtype: Optional[str] = None) -> cgp_config:
     """cgp_config of a cgp_inputs.Case."""
     return make_config(case.nx, case.ny, case.level, case.nlayers, dtype or case.dtype, case.lx,
                        case.ly, case.y0, case.inv_re, case.inv_ro, case.f1, case.f2, case.drag,
-                       case.dt, case.cfl)
+                       case.dt, case.cfl, case.solver, case.mg_cycles)
 
 
 def stream_ptr(stream=None) -> int:

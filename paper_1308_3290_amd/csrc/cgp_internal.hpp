@@ -79,6 +79,31 @@ struct StepCtl {
   int last;   // the launch is the last stage of a step: leave the maxima
 };
 
+// First stage of a step: member d's dt for the step (Sec. 4.2) from the
+// velocity maxima the previous step's last stage left (0 before the first
+// step: dt itself), and the model time.  Every thread of the block (NT
+// threads) calls it; red is LDS scratch of NT / 64 doubles.
+template <int NT>
+__device__ __forceinline__ void update_step_dt(const MemberDesc& d, double* ctl, double* red) {
+  double* st = ctl + d.cfl_off;
+  double m = 0.0;
+  if (d.cfl > 0) {
+    const int n = d.npart * kVmaxSlots;
+    for (int i = threadIdx.x; i < n; i += NT) m = fmax(m, st[2 + i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int i = 1; i < NT / 64; ++i) m = fmax(m, red[i]);
+  }
+  if (threadIdx.x == 0) {
+    const double dt = m > 0 ? fmin(d.dt, d.cfl * d.hmin / m) : d.dt;
+    st[0] = dt;
+    st[1] += dt;
+  }
+}
+
 // The dt a stage kernel applies.
 template <typename T>
 __device__ __forceinline__ T stage_dt(const MemberDesc& d, const StepCtl& c) {
@@ -249,6 +274,32 @@ struct Launch {
   static hipError_t accumulate(const MemberDesc* md, int nm, const T* f, long long n,
                                double* sum, double weight, const double* ctl, hipStream_t s);
 };
+
+// Multigrid V-cycle operations on one level (an nx x ny interval node array
+// with a zero ring), one launch each.
+template <typename T>
+struct MgLaunch {
+  // f0 = R^l w (coarse node array of nx/c x ny/c intervals, zero ring)
+  static hipError_t restrict_field(const T* w, int nx, int ny, int c, T* f0, hipStream_t s);
+  // half sweep of red-black Gauss-Seidel for Lap_h u = f on nodes i + j = color (mod 2)
+  static hipError_t smooth(T* u, const T* f, int nx, int ny, double dx, double dy, int color,
+                           hipStream_t s);
+  // fc (nx/2 x ny/2 intervals) = full weighting of f - Lap_h u
+  static hipError_t residual_restrict(const T* u, const T* f, int nx, int ny, double dx,
+                                      double dy, T* fc, hipStream_t s);
+  // u += bilinear interpolation of uc (nx/2 x ny/2 intervals)
+  static hipError_t prolong_add(const T* uc, int nx, int ny, T* u, hipStream_t s);
+  // u = minv f on the nb interior nodes of the coarsest grid
+  static hipError_t bottom(const double* minv, int nb, const T* f, int nx, T* u, hipStream_t s);
+  // psi (fine, nx x ny) (+)= P^l uc
+  static hipError_t prolong_field(const T* uc, int nx, int ny, int c, T* psi, int accumulate,
+                                  hipStream_t s);
+  static hipError_t fill_zero(T* a, long long n, hipStream_t s);
+};
+
+// The step size of every member (the first stage of a step on handles whose
+// steps launch no pass B).
+hipError_t step_ctl(const MemberDesc* md, int nm, double* ctl, hipStream_t s);
 
 // out[2m], out[2m+1] = dt of the latest step and model time of member m.
 hipError_t time_state(const MemberDesc* md, int nm, const double* ctl, double* out,

@@ -101,14 +101,18 @@ cgp_status validate(const cgp_config* c) {
   if (c->inv_re < 0 || c->f1 < 0 || c->f2 < 0 || c->drag < 0)
     return fail(CGP_ERR_INVALID, "inv_re, f1, f2, drag must be >= 0");
   if (c->cfl < 0) return fail(CGP_ERR_INVALID, "cfl must be >= 0 (0: fixed dt)");
+  if (c->solver != 0 && c->solver != 1)
+    return fail(CGP_ERR_INVALID, "solver must be 0 (sine transform) or 1 (multigrid)");
+  if (c->mg_cycles < 0 || c->mg_cycles > 1000)
+    return fail(CGP_ERR_INVALID, "mg_cycles must be in 0..1000");
   return CGP_OK;
 }
 
 struct Layout {
   // wt: spectra of omega (pass A out, pass B in); wt2: spectra of psi (pass B
   // out, pass C / fused pass in)
-  size_t desc = 0, order = 0, tw = 0, lam = 0, ctl = 0, wt = 0, wt2 = 0, psi = 0, st1 = 0,
-         st2 = 0, diag = 0, fin = 0, total = 0;
+  size_t desc = 0, order = 0, tw = 0, lam = 0, ctl = 0, mgm = 0, wt = 0, wt2 = 0, psi = 0,
+         st1 = 0, st2 = 0, diag = 0, fin = 0, mg = 0, total = 0;
   long long field_elems = 0;
 };
 
@@ -122,8 +126,21 @@ struct HostGroup {
   int order_off = 0;         // offset of the member list in the order region (ints)
 };
 
+// One level of the multigrid solver: an nx x ny interval grid (spacings dx,
+// dy) with its correction u and right-hand side f (element offsets in the
+// multigrid region).
+struct MgLevel {
+  int nx = 0, ny = 0;
+  double dx = 0, dy = 0;
+  long long u = 0, f = 0;
+};
+
 struct Plan {
   std::vector<MemberDesc> md;
+  int solver = 0;                    // 0: sine transform, 1: multigrid
+  int mg_cycles = 0;
+  std::vector<MgLevel> mg;           // finest (the coarse CGP grid) first
+  int mg_nb = 0;                     // unknowns of the coarsest grid
   Layout lay;
   std::vector<HostGroup> groups[4];  // passes A, B, C and the fused C + D pass
   int nblk_d = 0;                    // pass D: one launch over every member
@@ -181,6 +198,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     if (st != CGP_OK) return st;
     if (c.dtype != dtype || c.nlayers != nl)
       return fail(CGP_ERR_INVALID, "all members must share dtype and nlayers");
+    if (c.solver != cfgs[0].solver)
+      return fail(CGP_ERR_INVALID, "all members must share the coarse solver");
     MemberDesc& d = plan->md[m];
     d.nx = c.nx;
     d.ny = c.ny;
@@ -227,7 +246,31 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   // c <= 4; two layers: c = 2 or 4 and a compile-time transform length).
   // Its last block owns exactly fused_tj(c) coarse rows, so the coarse row
   // count must be a multiple of that (only My = 6 at c = 1 is not).
-  bool fusable = true;
+  // multigrid (one layer, single basin): levels from the coarse CGP grid
+  // down to the coarsest (an odd interval count or one below 8)
+  plan->solver = cfgs[0].solver;
+  if (plan->solver == 1) {
+    if (count != 1 || nl != 1)
+      return fail(CGP_ERR_UNSUPPORTED, "the multigrid solver takes one layer, single basin");
+    const MemberDesc& d = plan->md[0];
+    plan->mg_cycles = cfgs[0].mg_cycles > 0 ? cfgs[0].mg_cycles : 12;
+    int gx = d.Mx, gy = d.My;
+    double hx = d.dx * d.c, hy = d.dy * d.c;
+    long long off = 0;
+    for (;;) {
+      MgLevel lv;
+      lv.nx = gx; lv.ny = gy; lv.dx = hx; lv.dy = hy;
+      lv.u = off; off += (long long)(gx + 1) * (gy + 1);
+      lv.f = off; off += (long long)(gx + 1) * (gy + 1);
+      plan->mg.push_back(lv);
+      if (gx % 2 || gy % 2 || gx < 8 || gy < 8) break;
+      gx /= 2; gy /= 2; hx *= 2; hy *= 2;
+    }
+    plan->mg_nb = (gx - 1) * (gy - 1);
+    if (plan->mg_nb > 1024)
+      return fail(CGP_ERR_UNSUPPORTED, "multigrid coarsest grid %dx%d too large", gx, gy);
+  }
+  bool fusable = plan->solver == 0;
   for (const MemberDesc& d : plan->md) {
     fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4 && d.My % fused_tj(d.c) == 0;
     if (nl == 2) fusable = fusable && d.c >= 2 && fft_special(d.Lr) != 0;
@@ -317,6 +360,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     ctl += 2 + (long long)d.npart * kVmaxSlots;
   }
   L.ctl = off; off = align_up(off + (size_t)ctl * sizeof(double));
+  L.mgm = off; off = align_up(off + (size_t)plan->mg_nb * plan->mg_nb * sizeof(double));
   L.wt = off; off = align_up(off + (size_t)wt * es);
   L.wt2 = off; off = align_up(off + (size_t)wt * es);
   L.field_elems = fld;
@@ -325,6 +369,9 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   L.st2 = off; off = align_up(off + (size_t)fld * es);
   L.diag = off; off = align_up(off + (size_t)kDiagBlocks * 2 * 3 * sizeof(double));
   L.fin = off; off = align_up(off + (size_t)kFiniteBlocks * sizeof(int));
+  long long mg_elems = 0;
+  for (const MgLevel& lv : plan->mg) mg_elems += 2LL * (lv.nx + 1) * (lv.ny + 1);
+  L.mg = off; off = align_up(off + (size_t)mg_elems * es);
   L.total = off;
   if (plan->fused && plan->groups[1].size() == plan->groups[3].size() &&
       plan->groups[3].size() > 1) {
@@ -391,9 +438,59 @@ hipError_t enqueue_pass(cgp_handle* h, int pass, const T* src, T* dst, int accum
   return hipSuccess;
 }
 
+// One multigrid V(2,2) cycle from level k (the correction u_k of the
+// right-hand side f_k; coarser levels' u zeroed before use).
+template <typename T>
+hipError_t mg_vcycle(cgp_handle* h, int k, hipStream_t s) {
+  const Plan& p = h->plan;
+  T* base = h->at<T>(p.lay.mg);
+  const MgLevel& lv = p.mg[k];
+  T* u = base + lv.u;
+  T* f = base + lv.f;
+  if (k + 1 == (int)p.mg.size())
+    return MgLaunch<T>::bottom(h->at<double>(p.lay.mgm), p.mg_nb, f, lv.nx, u, s);
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < 2 && e == hipSuccess; ++q) {  // pre-smoothing: red, black
+    e = MgLaunch<T>::smooth(u, f, lv.nx, lv.ny, lv.dx, lv.dy, 0, s);
+    if (e == hipSuccess) e = MgLaunch<T>::smooth(u, f, lv.nx, lv.ny, lv.dx, lv.dy, 1, s);
+  }
+  const MgLevel& cl = p.mg[k + 1];
+  if (e == hipSuccess)
+    e = MgLaunch<T>::residual_restrict(u, f, lv.nx, lv.ny, lv.dx, lv.dy, base + cl.f, s);
+  if (e == hipSuccess)
+    e = MgLaunch<T>::fill_zero(base + cl.u, (long long)(cl.nx + 1) * (cl.ny + 1), s);
+  if (e == hipSuccess) e = mg_vcycle<T>(h, k + 1, s);
+  if (e == hipSuccess) e = MgLaunch<T>::prolong_add(base + cl.u, lv.nx, lv.ny, u, s);
+  for (int q = 0; q < 2 && e == hipSuccess; ++q) {  // post-smoothing: black, red
+    e = MgLaunch<T>::smooth(u, f, lv.nx, lv.ny, lv.dx, lv.dy, 1, s);
+    if (e == hipSuccess) e = MgLaunch<T>::smooth(u, f, lv.nx, lv.ny, lv.dx, lv.dy, 0, s);
+  }
+  return e;
+}
+
+// psi (+)= P^l A_c^-1 R^l omega with the multigrid coarse solve (single basin).
+template <typename T>
+hipError_t enqueue_solve_mg(cgp_handle* h, const T* src, T* dst, int accumulate, hipStream_t s,
+                            double* ctl) {
+  const Plan& p = h->plan;
+  const MemberDesc& d = p.md[0];
+  T* base = h->at<T>(p.lay.mg);
+  const MgLevel& l0 = p.mg[0];
+  hipError_t e = MgLaunch<T>::restrict_field(src + d.field_off, d.nx, d.ny, d.c, base + l0.f, s);
+  if (e == hipSuccess)
+    e = MgLaunch<T>::fill_zero(base + l0.u, (long long)(l0.nx + 1) * (l0.ny + 1), s);
+  for (int cyc = 0; cyc < p.mg_cycles && e == hipSuccess; ++cyc) e = mg_vcycle<T>(h, 0, s);
+  if (e == hipSuccess)
+    e = MgLaunch<T>::prolong_field(base + l0.u, d.nx, d.ny, d.c, dst + d.field_off, accumulate,
+                                   s);
+  if (e == hipSuccess && ctl) e = step_ctl(h->d_md(), h->nm(), ctl, s);
+  return e;
+}
+
 template <typename T>
 hipError_t enqueue_solve(cgp_handle* h, const T* src, T* dst, int accumulate, hipStream_t s,
                          double* ctl = nullptr) {
+  if (h->plan.solver == 1) return enqueue_solve_mg<T>(h, src, dst, accumulate, s, ctl);
   hipError_t e = enqueue_pass<T>(h, 0, src, nullptr, 0, s);
   if (e == hipSuccess) e = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s, ctl);
   if (e == hipSuccess) e = enqueue_pass<T>(h, 2, nullptr, dst, accumulate, s);
@@ -567,6 +664,48 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
   // step state: dt of the latest step = the configured dt, time 0, maxima 0
   double* ctl = reinterpret_cast<double*>(h->host_tables.data() + L.ctl);
   for (const MemberDesc& d : p.md) ctl[d.cfl_off] = d.dt;
+  // multigrid: inverse of the coarsest grid's 5-point matrix (Gauss-Jordan
+  // with partial pivoting, FP64; the matrix is symmetric negative definite)
+  if (p.solver == 1) {
+    const MgLevel& b = p.mg.back();
+    const int n = p.mg_nb, n1 = b.nx - 1;
+    const double ax = 1.0 / (b.dx * b.dx), ay = 1.0 / (b.dy * b.dy);
+    std::vector<double> A((size_t)n * n, 0.0), X((size_t)n * n, 0.0);
+    for (int k = 0; k < n; ++k) {
+      const int i = k % n1, j = k / n1;
+      A[(size_t)k * n + k] = -2.0 * ax - 2.0 * ay;
+      if (i > 0) A[(size_t)k * n + k - 1] = ax;
+      if (i < n1 - 1) A[(size_t)k * n + k + 1] = ax;
+      if (j > 0) A[(size_t)k * n + k - n1] = ay;
+      if (j < b.ny - 2) A[(size_t)k * n + k + n1] = ay;
+      X[(size_t)k * n + k] = 1.0;
+    }
+    for (int col = 0; col < n; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < n; ++r)
+        if (std::fabs(A[(size_t)r * n + col]) > std::fabs(A[(size_t)piv * n + col])) piv = r;
+      if (piv != col)
+        for (int q = 0; q < n; ++q) {
+          std::swap(A[(size_t)piv * n + q], A[(size_t)col * n + q]);
+          std::swap(X[(size_t)piv * n + q], X[(size_t)col * n + q]);
+        }
+      const double inv = 1.0 / A[(size_t)col * n + col];
+      for (int q = 0; q < n; ++q) {
+        A[(size_t)col * n + q] *= inv;
+        X[(size_t)col * n + q] *= inv;
+      }
+      for (int r = 0; r < n; ++r) {
+        if (r == col) continue;
+        const double fct = A[(size_t)r * n + col];
+        if (fct == 0.0) continue;
+        for (int q = 0; q < n; ++q) {
+          A[(size_t)r * n + q] -= fct * A[(size_t)col * n + q];
+          X[(size_t)r * n + q] -= fct * X[(size_t)col * n + q];
+        }
+      }
+    }
+    std::memcpy(h->host_tables.data() + L.mgm, X.data(), X.size() * sizeof(double));
+  }
   size_t lds_max = 0;
   for (int pass = 0; pass < 3; ++pass)
     for (const HostGroup& g : p.groups[pass]) lds_max = std::max(lds_max, g.lds);
@@ -913,6 +1052,8 @@ cgp_status cgp_time_passes(cgp_handle* h, const void* omega, const void* forcing
                            double* ms, void* stream) {
   if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
   if (!omega || !forcing || !ms || reps < 1) return fail(CGP_ERR_INVALID, "bad argument");
+  if (h->plan.solver != 0)
+    return fail(CGP_ERR_UNSUPPORTED, "pass timing needs the sine-transform solver");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -962,6 +1103,8 @@ cgp_status cgp_tape_size(const cgp_config* cfg, int32_t nsteps, size_t* bytes) {
   if (!bytes || nsteps < 1) return fail(CGP_ERR_INVALID, "bad argument");
   if (cfg->cfl > 0)
     return fail(CGP_ERR_UNSUPPORTED, "the adjoint needs a fixed dt (cfl = 0)");
+  if (cfg->solver != 0)
+    return fail(CGP_ERR_UNSUPPORTED, "the adjoint needs the sine-transform solver");
   const size_t N = (size_t)(cfg->nx + 1) * (cfg->ny + 1);
   *bytes = (6 * (size_t)nsteps + 4) * N * sizeof(double);
   return CGP_OK;
@@ -975,6 +1118,8 @@ cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forc
     return fail(CGP_ERR_UNSUPPORTED, "adjoint needs a one-layer FP64 single-basin handle");
   if (h->plan.md[0].cfl > 0)
     return fail(CGP_ERR_UNSUPPORTED, "the adjoint needs a fixed dt (cfl = 0)");
+  if (h->plan.solver != 0)
+    return fail(CGP_ERR_UNSUPPORTED, "the adjoint needs the sine-transform solver");
   if (!omega_n || !forcing || !lambda || !grad_forcing || !tape || nsteps < 1)
     return fail(CGP_ERR_INVALID, "bad argument");
   const MemberDesc& d = h->plan.md[0];

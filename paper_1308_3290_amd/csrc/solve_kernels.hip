@@ -304,29 +304,9 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
       if (has_b) wout[offb + l - 1] = T(0.5) * z.x;
     }
   }
-  if (ctl != nullptr && lb == 0) {
-    // first stage of a step: the member's dt for this step (Sec. 4.2) from
-    // the velocity maxima the previous step's last stage left (0 before the
-    // first step: dt itself)
-    double* st = ctl + d.cfl_off;
-    double m = 0.0;
-    if (d.cfl > 0) {
-      const int n = d.npart * kVmaxSlots;
-      for (int i = threadIdx.x; i < n; i += kThreads) m = fmax(m, st[2 + i]);
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-      double* red = reinterpret_cast<double*>(tw);  // the twiddles are read no more
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-      __syncthreads();
-      if (threadIdx.x == 0)
-        for (int i = 1; i < kThreads / 64; ++i) m = fmax(m, red[i]);
-    }
-    if (threadIdx.x == 0) {
-      const double dt = m > 0 ? fmin(d.dt, d.cfl * d.hmin / m) : d.dt;
-      st[0] = dt;
-      st[1] += dt;
-    }
-  }
+  // first stage of a step: the member's dt (the twiddles are read no more)
+  if (ctl != nullptr && lb == 0)
+    update_step_dt<kThreads>(d, ctl, reinterpret_cast<double*>(tw));
 }
 
 // ---------------------------------------------------------------------------

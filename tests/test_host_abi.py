@@ -119,3 +119,30 @@ def test_adaptive_step_config_and_fixed_step_adjoint():
     lib = _lib.load()
     out = ctypes.c_void_p()
     assert lib.cgp_time_state(None, out, None) == _lib.CGP_ERR_INVALID
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(solver=2), 1),
+    (dict(solver=1, mg_cycles=-1), 1),
+    (dict(solver=1, mg_cycles=5000), 1),
+    (dict(solver=1, nlayers=2, f1=2000, f2=500), 2),   # multigrid: one layer only
+])
+def test_multigrid_config_validation(kw, status):
+    from paper_1308_3290_amd.api import CGPError, cgp_workspace_size
+    with pytest.raises(CGPError) as e:
+        cgp_workspace_size(_cfg(**kw))
+    assert e.value.status == status
+
+
+def test_multigrid_workspace_and_limits():
+    from paper_1308_3290_amd.api import (CGPError, cgp_ensemble_workspace_size, cgp_tape_size,
+                                         cgp_workspace_size)
+    assert cgp_workspace_size(_cfg(solver=1)) > cgp_workspace_size(_cfg())
+    with pytest.raises(CGPError) as e:
+        cgp_tape_size(_cfg(solver=1), 10)
+    assert e.value.status == 2
+    with pytest.raises(CGPError) as e:  # single basin only
+        cgp_ensemble_workspace_size([_cfg(solver=1), _cfg(solver=1)])
+    assert e.value.status == 2
+    with pytest.raises(CGPError):       # members share the solver
+        cgp_ensemble_workspace_size([_cfg(solver=1), _cfg()])
