@@ -8,17 +8,19 @@
 // A block owns coarse rows j0 .. j0+TJ-1 and writes omega_{s+1} on the fine
 // rows C*j0 .. C*(j0+TJ)-1 (the last block also the top wall row).  The
 // stencil on those rows needs psi on one more fine row above and below, i.e.
-// the coarse rows j0-1 .. j0+TJ, which the block synthesises itself (at most
-// four rows: two complex sequences) and keeps in LDS.  Each thread then owns
-// fine columns and interpolates psi at its column and both neighbours for all
-// of the block's rows in registers; the row weights are compile-time
-// constants.
+// the coarse rows j0-1 .. j0+TJ, which the block synthesises itself (TJ + 2
+// rows in at most (TJ + 3)/2 complex sequences) and keeps in LDS.  Each
+// thread then owns a fine column and interpolates psi at its column and both
+// neighbours for all of the block's rows in registers; the row weights are
+// compile-time constants.  The step size comes from the step state (adaptive
+// steps, Sec. 4.2); the last stage of a step leaves the velocity maxima of
+// the block's coarse psi rows for the next step's size.
 //
-// Latency: a block is the only one on its CU, so its phases do not overlap
-// with other blocks.  Every global load of the block is therefore issued at
-// the start: the twiddles and spectra first (the transform waits for them
-// only), then the vorticity rows, the forcing and omega_n, which arrive while
-// the transform runs.  Rows are at most kFusedMaxNx + 1 nodes wide.
+// Latency: a single basin has one block per CU, so a block's phases do not
+// overlap with other blocks.  The twiddles and spectra are loaded first (the
+// transform waits for them only); once they are in LDS the vorticity rows,
+// the forcing and omega_n are issued, and they arrive while the transform
+// runs.  Rows are at most kFusedMaxNx + 1 nodes wide.
 #include "cgp_internal.hpp"
 #include "fft_lds.hpp"
 #include "stencil.hpp"
