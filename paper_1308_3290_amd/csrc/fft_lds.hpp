@@ -11,12 +11,13 @@
 //
 // The DFT is a Stockham autosort FFT over radices 8, 4 and 2 with the
 // radix-3 stage of L = 3*2^k placed last, so that the span Ns of every stage
-// is a power of two and all index arithmetic is shifts and masks.  Lengths
-// up to 512 use radix 4 (one radix-8 or radix-2 stage first when the power
+// is a power of two and all index arithmetic is shifts and masks.  Shorter
+// transforms use radix 4 (one radix-8 or radix-2 stage first when the power
 // of two is odd): a block then has L/4 butterflies per sequence in flight,
-// enough to occupy its four SIMDs.  Longer transforms have enough
+// enough to occupy its four SIMDs.  Long enough ones have enough
 // butterflies at radix 8, which needs fewer stages (each stage moves the
-// whole sequence through LDS once).  At a stage
+// whole sequence through LDS once); where that starts depends on the
+// sequences per block (stage_plan).  At a stage
 // of radix R, butterfly j reads x[j + r L/R], twiddles element r by
 // w_L^(r (j mod Ns) L/(Ns R)), takes an R-point DFT and writes
 // y[(j div Ns) Ns R + (j mod Ns) + r Ns].  Stages ping-pong between two LDS
@@ -134,27 +135,34 @@ __host__ __device__ constexpr int stage_word(int R, int lns, int two) {
   return R | (lns << 4) | (two << 9);
 }
 
-// Stage plan of a complex FFT of length L = 2^k or 3*2^k.  L <= 512: for odd
-// k one radix-8 stage first (radix 2 when k = 1), then radix 4.  L >= 1024:
+// Stage plan of a complex FFT of length L = 2^k or 3*2^k.  L < wide: for odd
+// k one radix-8 stage first (radix 2 when k = 1), then radix 4.  L >= wide:
 // radix 8 while possible, then 4, then 2.  The radix 3 comes last, so that
 // every stage's span Ns (the product of the earlier radices) is a power of
-// two.  The first stage has no twiddles (Ns = 1).  Stage s has radix
-// R[s], span 2^lns[s] and its twiddle table ((R-1) x Ns values) at off[s];
-// ntw is the total table size.  Shared by the host (tables, stage words) and
-// the compile-time transforms below.
+// two.  `wide` is where a block has enough radix-8 butterflies per stage to
+// keep its four SIMDs busy: kWideRows for the row transforms (two or three
+// sequences per 512-thread block), kWideCols for the column transform (one
+// sequence per 256-thread block: L/8 >= 256 from L = 2048 on).  The first
+// stage has no twiddles (Ns = 1).  Stage s has radix R[s], span 2^lns[s] and
+// its twiddle table ((R-1) x Ns values) at off[s]; ntw is the total table
+// size.  Shared by the host (tables, stage words) and the compile-time
+// transforms below.
 struct StagePlan {
   int n = 0, ntw = 0;
   int R[kMaxStages] = {}, lns[kMaxStages] = {}, off[kMaxStages] = {};
 };
 
-__host__ __device__ constexpr StagePlan stage_plan(int L) {
+constexpr int kWideRows = 1024;
+constexpr int kWideCols = 2048;
+
+__host__ __device__ constexpr StagePlan stage_plan(int L, int wide_from = kWideRows) {
   StagePlan p{};
   int rest = L, ns = 1, lg = 0, e = 0;
   while (rest % 2 == 0) {
     rest /= 2;
     ++e;
   }
-  const bool wide = L >= 1024;
+  const bool wide = L >= wide_from;
   while (e > 0 && p.n < kMaxStages) {
     // log2 of this stage's radix
     const int lr = wide ? (e >= 3 ? 3 : e) : ((e & 1) ? (e >= 3 ? 3 : 1) : 2);
@@ -215,10 +223,10 @@ __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nseq, in
 // every power-of-two span: o is a multiple of Ns R plus k < Ns, so o + r Ns
 // crosses a multiple of 8 exactly where r Ns does.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int S, int NT, int MAXSEQ>
+template <typename T, int L, int S, int NT, int MAXSEQ, int WF>
 __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int nseq,
                                          const cplx<T>* tw) {
-  constexpr StagePlan P = stage_plan(L);
+  constexpr StagePlan P = stage_plan(L, WF);
   constexpr int R = P.R[S], LNS = P.lns[S], NS = 1 << LNS, OFF = P.off[S];
   constexpr int LR = L / R, LP = lpad(L), RS = lpad(LR);
   static_assert(LR % 8 == 0, "read offsets need L/R to be a multiple of 8");
@@ -251,28 +259,95 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
   __syncthreads();
 }
 
-template <typename T, int L, int S, int NT, int MAXSEQ>
-__device__ __forceinline__ cplx<T>* ct_stages(cplx<T>* a, cplx<T>* b, int nseq,
-                                              const cplx<T>* tw) {
-  constexpr StagePlan P = stage_plan(L);
-  if constexpr (S == P.n) {
+// Stages S .. SEND-1, ping-ponging between a and b; returns the buffer that
+// holds the output of stage SEND-1 (a when S == SEND).
+template <typename T, int L, int S, int SEND, int NT, int MAXSEQ, int WF>
+__device__ __forceinline__ cplx<T>* ct_stage_range(cplx<T>* a, cplx<T>* b, int nseq,
+                                                   const cplx<T>* tw) {
+  if constexpr (S == SEND) {
     return a;
   } else {
-    ct_stage<T, L, S, NT, MAXSEQ>(a, b, nseq, tw);
-    return ct_stages<T, L, S + 1, NT, MAXSEQ>(b, a, nseq, tw);
+    ct_stage<T, L, S, NT, MAXSEQ, WF>(a, b, nseq, tw);
+    return ct_stage_range<T, L, S + 1, SEND, NT, MAXSEQ, WF>(b, a, nseq, tw);
   }
 }
 
+template <typename T, int L, int S, int NT, int MAXSEQ, int WF>
+__device__ __forceinline__ cplx<T>* ct_stages(cplx<T>* a, cplx<T>* b, int nseq,
+                                              const cplx<T>* tw) {
+  return ct_stage_range<T, L, S, stage_plan(L, WF).n, NT, MAXSEQ, WF>(a, b, nseq, tw);
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time transforms whose last stage hands its outputs to a store
+// callable instead of writing LDS, e.g. straight to global memory or into
+// another LDS buffer with a pointwise map: that saves the LDS pass and the
+// barrier of a separate copy.  st(p, m, v, q, r) receives output m of
+// sequence p; it is output r of the thread's q-th butterfly of the last
+// stage, m = j + r L/R for that butterfly's index j < L/R.  The last stage
+// ends without a barrier.
+// ---------------------------------------------------------------------------
+template <typename T, int L, int NT, int MAXSEQ, int WF, class St>
+__device__ __forceinline__ void ct_stage_last(const cplx<T>* in, int nseq, const cplx<T>* tw,
+                                              St&& st) {
+  constexpr StagePlan P = stage_plan(L, WF);
+  constexpr int S = P.n - 1;
+  constexpr int R = P.R[S], NS = 1 << P.lns[S], OFF = P.off[S];
+  constexpr int LR = L / R, LP = lpad(L), RS = lpad(LR);
+  static_assert(LR == NS, "the last stage spans the whole sequence");
+  static_assert(LR % 8 == 0, "read offsets need L/R to be a multiple of 8");
+  constexpr int Q = (MAXSEQ * LR + NT - 1) / NT;
+  const int nb = nseq * LR;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int b = threadIdx.x + NT * q;
+    if (b < nb) {
+      const int p = b / LR;
+      const int j = b - p * LR;  // = j mod Ns
+      const cplx<T>* src = in + p * LP + pad(j);
+      cplx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = src[r * RS];
+      const cplx<T>* t = tw + OFF + j;
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * NS]);
+      small_dft<T, R>(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) st(p, j + r * NS, v[r], q, r);
+    }
+  }
+}
+
+// Whether the last stage of ct_run_to reads buffer a (else b): the n - 1
+// stages before it ping-pong from a.
+template <int L, int WF>
+__host__ __device__ constexpr bool ct_last_reads_a() {
+  return ((stage_plan(L, WF).n - 1) & 1) == 0;
+}
+
+// Input in LDS buffer a (as fft_run, which it matches bit for bit), last
+// stage to st.
+template <typename T, int LC, int NT, int MAXSEQ, int WF, class St>
+__device__ __forceinline__ void ct_run_to(St&& st, cplx<T>* a, cplx<T>* b, int nseq,
+                                          const cplx<T>* tw) {
+  constexpr int N = stage_plan(LC, WF).n;
+  static_assert(N >= 2, "the last stage follows at least one LDS stage");
+  __syncthreads();
+  const cplx<T>* x = ct_stage_range<T, LC, 0, N - 1, NT, MAXSEQ, WF>(a, b, nseq, tw);
+  ct_stage_last<T, LC, NT, MAXSEQ, WF>(x, nseq, tw, st);
+}
+
 // Forward DFT with the contract of fft_lds; LC = 0 selects the runtime
-// engine (any supported length), otherwise L must equal LC.
-template <typename T, int LC, int NT = kThreads>
+// engine (any supported length), otherwise L must equal LC and the stage
+// plan is stage_plan(LC, WF) (the host builds the twiddles of the same plan).
+template <typename T, int LC, int NT = kThreads, int WF = kWideRows>
 __device__ __forceinline__ cplx<T>* fft_run(cplx<T>* a, cplx<T>* b, int nseq, int L, int nst,
                                             const int* words, const cplx<T>* tw) {
   if constexpr (LC == 0) {
     return fft_lds<T, NT>(a, b, nseq, L, nst, words, tw);
   } else {
     __syncthreads();
-    return ct_stages<T, LC, 0, NT, 2>(a, b, nseq, tw);
+    return ct_stages<T, LC, 0, NT, 2, WF>(a, b, nseq, tw);
   }
 }
 
@@ -282,7 +357,7 @@ __device__ __forceinline__ cplx<T>* fft_run4(cplx<T>* a, cplx<T>* b, int nseq,
                                              const cplx<T>* tw) {
   static_assert(LC != 0, "four sequences need a compile-time length");
   __syncthreads();
-  return ct_stages<T, LC, 0, NT, 4>(a, b, nseq, tw);
+  return ct_stages<T, LC, 0, NT, 4, kWideRows>(a, b, nseq, tw);
 }
 
 // Up to MAXSEQ sequences, compile-time length or (LC = 0) the runtime engine.
@@ -293,15 +368,15 @@ __device__ __forceinline__ cplx<T>* fft_runn(cplx<T>* a, cplx<T>* b, int nseq, i
     return fft_lds<T, NT>(a, b, nseq, L, nst, words, tw);
   } else {
     __syncthreads();
-    return ct_stages<T, LC, 0, NT, MAXSEQ>(a, b, nseq, tw);
+    return ct_stages<T, LC, 0, NT, MAXSEQ, kWideRows>(a, b, nseq, tw);
   }
 }
 
 // Twiddle values a thread of NT prefetches for a transform of length LC (0:
 // any supported length, L <= 2048).
-template <int LC, int NT>
+template <int LC, int NT, int WF = kWideRows>
 __host__ __device__ constexpr int tw_per_thread() {
-  return ((LC ? stage_plan(LC).ntw : 2047) + NT - 1) / NT;
+  return ((LC ? stage_plan(LC, WF).ntw : 2047) + NT - 1) / NT;
 }
 
 // Lengths with a compile-time transform (0: none).

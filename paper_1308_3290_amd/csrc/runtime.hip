@@ -65,8 +65,8 @@ bool pow2_or_3pow2(int n) {
 
 // Stage words of the runtime transform (see stage_plan); returns the stage
 // count and the twiddle table size in *ntw.
-int plan_stages(int L, int* words, int* ntw) {
-  const StagePlan p = stage_plan(L);
+int plan_stages(int L, int wide_from, int* words, int* ntw) {
+  const StagePlan p = stage_plan(L, wide_from);
   for (int s = 0; s < p.n; ++s) words[s] = stage_word(p.R[s], p.lns[s], p.off[s]);
   *ntw = p.ntw;
   return p.n;
@@ -209,8 +209,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     d.nlayers = nl;
     d.Lr = 2 * d.Mx;
     d.Lc = 2 * d.My;
-    d.nst_r = plan_stages(d.Lr, d.stw_r, &d.ntw_r);
-    d.nst_c = plan_stages(d.Lc, d.stw_c, &d.ntw_c);
+    d.nst_r = plan_stages(d.Lr, kWideRows, d.stw_r, &d.ntw_r);
+    d.nst_c = plan_stages(d.Lc, kWideCols, d.stw_c, &d.ntw_c);
     d.field_off = fld;
     fld += (long long)nl * (c.ny + 1) * (c.nx + 1);
     d.wt_off = wt;

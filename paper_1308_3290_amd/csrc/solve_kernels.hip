@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
                                                         const double* __restrict__ lam,
                                                         double* __restrict__ ctl) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int kTw = tw_per_thread<LC, kThreads>();
+  constexpr int kTw = tw_per_thread<LC, kThreads, kWideCols>();
   constexpr int kRowIter = 4;  // My - 1 <= 1023
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_B, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_B];
@@ -275,33 +275,70 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
       buf[pad(2 * My - l)] = {-va[q], -vb[q]};
     }
   }
-  cplx<T>* Z = fft_run<T, LC>(buf, buf2, 1, L, d.nst_c, d.stw_c, tw);
-  cplx<T>* Y = (Z == buf) ? buf2 : buf;
-
+  if constexpr (LC != 0) {
+    // Compile-time transform: the last stage of the forward transform divides
+    // by the eigenvalues and writes the synthesis input, and the last stage of
+    // the inverse stores the result (no separate LDS passes for either).
+    constexpr StagePlan P = stage_plan(LC, kWideCols);
+    constexpr int RL = P.R[P.n - 1], NSL = LC / RL;
+    constexpr int QL = (NSL + kThreads - 1) / kThreads;
+    // lambda_y at the outputs m = j + r L/R of the thread's last-stage butterflies
+    double lyl[QL][RL];
 #pragma unroll
-  for (int q = 0; q < kRowIter; ++q) {
-    const int l = 1 + threadIdx.x + kThreads * q;
-    if (l < My) {
-      const cplx<T> z = Z[pad(l)];
-      const T a = T(-0.5) * z.y * T(scale * recip(lxa + ly[q]));
-      const T b = T(0.5) * z.x * T(scale * recip(lxb + ly[q]));
-      Y[pad(l)] = {a, b};
-      Y[pad(2 * My - l)] = {-a, -b};
+    for (int q = 0; q < QL; ++q)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int m = (int)threadIdx.x + kThreads * q + r * NSL;
+        lyl[q][r] = lamy[min(max(m, 1), My - 1) - 1];
+      }
+    constexpr bool kLastA = ct_last_reads_a<LC, kWideCols>();
+    cplx<T>* Y = kLastA ? buf2 : buf;
+    auto divide = [&](int, int m, cplx<T> z, int q, int r) {
+      if (m >= 1 && m < My) {
+        const T a = T(-0.5) * z.y * T(scale * recip(lxa + lyl[q][r]));
+        const T b = T(0.5) * z.x * T(scale * recip(lxb + lyl[q][r]));
+        Y[pad(m)] = {a, b};
+        Y[pad(2 * My - m)] = {-a, -b};
+      } else if (m == 0 || m == My) {
+        Y[pad(m)] = {T(0), T(0)};
+      }
+    };
+    ct_run_to<T, LC, kThreads, 1, kWideCols>(divide, buf, buf2, 1, tw);
+    auto store = [&](int, int m, cplx<T> z, int, int) {
+      if (m >= 1 && m < My) {
+        wout[offa + m - 1] = T(-0.5) * z.y;
+        if (has_b) wout[offb + m - 1] = T(0.5) * z.x;
+      }
+    };
+    ct_run_to<T, LC, kThreads, 1, kWideCols>(store, Y, kLastA ? buf : buf2, 1, tw);
+    if (ctl != nullptr && lb == 0) __syncthreads();  // other waves may still read twiddles
+  } else {
+    cplx<T>* Z = fft_run<T, LC, kThreads, kWideCols>(buf, buf2, 1, L, d.nst_c, d.stw_c, tw);
+    cplx<T>* Y = (Z == buf) ? buf2 : buf;
+#pragma unroll
+    for (int q = 0; q < kRowIter; ++q) {
+      const int l = 1 + threadIdx.x + kThreads * q;
+      if (l < My) {
+        const cplx<T> z = Z[pad(l)];
+        const T a = T(-0.5) * z.y * T(scale * recip(lxa + ly[q]));
+        const T b = T(0.5) * z.x * T(scale * recip(lxb + ly[q]));
+        Y[pad(l)] = {a, b};
+        Y[pad(2 * My - l)] = {-a, -b};
+      }
     }
-  }
-  if (threadIdx.x == 0) {
-    Y[pad(0)] = {T(0), T(0)};
-    Y[pad(My)] = {T(0), T(0)};
-  }
-  const cplx<T>* R = fft_run<T, LC>(Y, Z, 1, L, d.nst_c, d.stw_c, tw);
-
+    if (threadIdx.x == 0) {
+      Y[pad(0)] = {T(0), T(0)};
+      Y[pad(My)] = {T(0), T(0)};
+    }
+    const cplx<T>* R = fft_run<T, LC, kThreads, kWideCols>(Y, Z, 1, L, d.nst_c, d.stw_c, tw);
 #pragma unroll
-  for (int q = 0; q < kRowIter; ++q) {
-    const int l = 1 + threadIdx.x + kThreads * q;
-    if (l < My) {
-      const cplx<T> z = R[pad(l)];
-      wout[offa + l - 1] = T(-0.5) * z.y;
-      if (has_b) wout[offb + l - 1] = T(0.5) * z.x;
+    for (int q = 0; q < kRowIter; ++q) {
+      const int l = 1 + threadIdx.x + kThreads * q;
+      if (l < My) {
+        const cplx<T> z = R[pad(l)];
+        wout[offa + l - 1] = T(-0.5) * z.y;
+        if (has_b) wout[offb + l - 1] = T(0.5) * z.x;
+      }
     }
   }
   // first stage of a step: the member's dt (the twiddles are read no more)
