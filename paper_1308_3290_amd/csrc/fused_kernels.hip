@@ -18,14 +18,43 @@
 //
 // Latency: a single basin has one block per CU, so a block's phases do not
 // overlap with other blocks.  The twiddles and spectra are loaded first (the
-// transform waits for them only); once they are in LDS the vorticity rows,
-// the forcing and omega_n are issued, and they arrive while the transform
-// runs.  Rows are at most kFusedMaxNx + 1 nodes wide.
+// transform waits for them only); once they are in LDS the forcing and
+// omega_n are issued, and they arrive while the transform runs.  The
+// vorticity rows are issued with the spectra at c = 2 (measured faster, for
+// single basins and ensembles, at no extra registers) and with the forcing
+// at c = 1 and 4 (measured faster there).  Rows are at most kFusedMaxNx + 1
+// nodes wide.
 #include "cgp_internal.hpp"
 #include "fft_lds.hpp"
 #include "stencil.hpp"
 
 namespace cgp {
+
+// Vorticity tile rows of a block (KW elements per thread; element e of the
+// tile is tile row e / pitch, column e % pitch, tracked incrementally); the
+// ring and the rows outside 1 .. ny-1 are stored as 0, so that the stencil
+// reads the tile without masks.
+template <typename T, int NT, int KW>
+__device__ __forceinline__ void load_tile(const T* __restrict__ W, long long g0, int nW, int RB0,
+                                          int pitch, int nx, int ny, T (&wv)[KW]) {
+  const int t = threadIdx.x;
+  int er = t / pitch, ec = t - er * pitch;
+  const int dr = NT / pitch, dc = NT - dr * pitch;
+#pragma unroll
+  for (int q = 0; q < KW; ++q) {
+    const int e = t + NT * q;
+    const int fr = RB0 + er;
+    const bool in = e < nW && fr >= 1 && fr <= ny - 1 && ec >= 1 && ec <= nx - 1;
+    const T v = W[in ? g0 + e : 0];
+    wv[q] = in ? v : T(0);
+    er += dr;
+    ec += dc;
+    if (ec >= pitch) {
+      ec -= pitch;
+      ++er;
+    }
+  }
+}
 
 // C: coarsening factor; TJ: coarse rows owned per block; LC: transform
 // length with a compile-time transform, or 0.  NEXT: also restrict the new
@@ -122,6 +151,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
     z.y = in && !top ? v.y : T(0);
     sp[q] = z;
   }
+  constexpr bool kEarlyTile = C == 2;
+  T wv[kWPer];
+  if constexpr (kEarlyTile)
+    load_tile<T, NT, kWPer>(ws + d.field_off, (long long)RB0 * pitch, nW, RB0, pitch, nx, ny, wv);
   // ---- twiddles and the two packed sequences (odd extension) into LDS
 #pragma unroll
   for (int q = 0; q < kTwPer; ++q) {
@@ -148,29 +181,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
   T* O = out + d.field_off;
   const long long g0 = (long long)RB0 * pitch;
   // ---- the stencil's inputs, issued once the transform's inputs are in
-  // LDS: they arrive while the transform runs.
-  // Element e of the tile is tile row e / pitch, column e % pitch, tracked
-  // incrementally; the ring and the rows outside 1 .. ny-1 are stored as 0, so
-  // that the stencil reads the tile without masks.
-  T wv[kWPer];
-  {
-    int er = t / pitch, ec = t - er * pitch;
-    const int dr = NT / pitch, dc = NT - dr * pitch;
-#pragma unroll
-    for (int q = 0; q < kWPer; ++q) {
-      const int e = t + NT * q;
-      const int fr = RB0 + er;
-      const bool in = e < nW && fr >= 1 && fr <= ny - 1 && ec >= 1 && ec <= nx - 1;
-      const T v = W[in ? g0 + e : 0];
-      wv[q] = in ? v : T(0);
-      er += dr;
-      ec += dc;
-      if (ec >= pitch) {
-        ec -= pitch;
-        ++er;
-      }
-    }
-  }
+  // LDS: they arrive while the transform runs
+  if constexpr (!kEarlyTile) load_tile<T, NT, kWPer>(W, g0, nW, RB0, pitch, nx, ny, wv);
   // forcing and omega_n at the thread's column x = 1 + t, computed rows
   const int x = 1 + t;
   T fv[NO], nv[NO];
