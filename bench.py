@@ -204,16 +204,18 @@ def main():
         if only and f"l{lv}" not in only:
             continue
         case = ci.case_c1(lv)
-        ms, finite, ens, w, Fp = timed_run(case)
-        rate = case.points * K / (ms * 1e-3) / 1e6
-        rates[lv] = dict(ms=ms, rate=rate, finite=finite)
-        log(f"512x1024 FP64 level {lv}: {ms / K * 1e3:.1f} us/step, {rate:.0f} Mpoint-steps/s"
-            f" (finite={finite})")
-        if lv == 1:
-            ms_direct, _, _, _, _ = timed_run(case, use_graph=False, steps=min(K, 200), warm=5)
-            rates["direct"] = case.points * min(K, 200) / (ms_direct * 1e-3) / 1e6
-            log(f"  without graph: {ms_direct / min(K, 200) * 1e3:.1f} us/step")
-        del ens, w, Fp
+        # the same K steps as captured-graph replays and as direct launches;
+        # the faster of the two is the level's rate (both are library modes)
+        by_mode = {}
+        for mode in ("graph", "direct"):
+            ms, finite, ens, w, Fp = timed_run(case, use_graph=mode == "graph")
+            by_mode[mode] = dict(ms=ms, rate=case.points * K / (ms * 1e-3) / 1e6, finite=finite,
+                                 launch=mode)
+            log(f"512x1024 FP64 level {lv} ({mode}): {ms / K * 1e3:.1f} us/step, "
+                f"{by_mode[mode]['rate']:.0f} Mpoint-steps/s (finite={finite})")
+            del ens, w, Fp
+        rates[lv] = max(by_mode.values(), key=lambda r: r["rate"])
+        rates[lv]["modes"] = {m: round(r["rate"], 1) for m, r in by_mode.items()}
     # ---------------------------------------------------------------- per-pass roofline
     roof = None
     if not only or "timed" in only:
@@ -390,15 +392,17 @@ def main():
         "config": {"workload": "single-layer barotropic QG, 512x1024 fine grid, FP64, "
                                "CGP factor 2 (256x512 sine-transform solve), Re 450, Ro 0.0036, "
                                "dt 2.5e-5, seeded omega0", "global_batch": 1, "seq_len": None,
-                   "parallelism": "single GPU", "launch": "hipGraph replay of one step"},
+                   "parallelism": "single GPU",
+                   "launch": ("hipGraph replays of a 3-step rotation" if rates[1]["launch"] == "graph"
+                              else "direct launches") if 1 in rates else None},
         "full_grid_value": round(rates[0]["rate"], 1) if 0 in rates else None,
         "cgp4_value": round(rates[2]["rate"], 1) if 2 in rates else None,
         "speedup_cgp2_vs_full": round(rates[1]["rate"] / rates[0]["rate"], 3)
         if 0 in rates and 1 in rates else None,
         "speedup_cgp4_vs_full": round(rates[2]["rate"] / rates[0]["rate"], 3)
         if 0 in rates and 2 in rates else None,
-        "no_graph_value": round(rates["direct"], 1) if "direct" in rates else None,
-        "all_finite": all(v["finite"] for k, v in rates.items() if k != "direct"),
+        "launch_modes": rates[1]["modes"] if 1 in rates else None,
+        "all_finite": all(v["finite"] for v in rates.values()),
         "adjoint_forward_ratio": round(adj["ratio"], 3) if adj else None,
         "adjoint": adj,
         "roofline": roof,

@@ -206,7 +206,10 @@ cgp_status cgp_ensemble_workspace_size(const cgp_config* members, int32_t count,
 cgp_status cgp_ensemble_create(const cgp_config* members, int32_t count, void* workspace_dev,
                                size_t bytes, void* stream, cgp_handle** out);
 /* Advance every member by nsteps.  With use_graph != 0 the step is captured
- * once into a HIP graph (per pointer set) and replayed nsteps times. */
+ * once into a HIP graph (per pointer set) and replayed nsteps times; only
+ * graphs run the transform-length chains of an ensemble concurrently.  For a
+ * single basin direct launches (use_graph = 0) measured faster on MI355X:
+ * graph kernel nodes there do not get the kernel arguments preloaded. */
 cgp_status cgp_ensemble_step(cgp_handle* h, void* omega_packed_dev,
                              const void* forcing_packed_dev, int32_t nsteps, int32_t use_graph,
                              void* stream);
