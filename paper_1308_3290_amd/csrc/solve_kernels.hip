@@ -217,7 +217,9 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
   constexpr int kRowIter = 4;  // My - 1 <= 1023
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_B, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_B];
-  const int Mx = d.Mx, My = d.My, L = d.Lc, nl = d.nlayers, ntw = d.ntw_c;
+  // a compile-time transform length fixes the column length (Lc = 2 My)
+  const int Mx = d.Mx, My = LC ? LC / 2 : d.My, L = LC ? LC : d.Lc, nl = d.nlayers;
+  const int ntw = d.ntw_c;
   const int ny1 = My - 1;
   const int LP = lpad(L);
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
