@@ -41,8 +41,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_adjoint_fused(
   const int bid = xcd_contiguous(blockIdx.x, nblk);
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_CD, bid)];
   const int lb = bid - d.blk0[PASS_CD];
-  const int Mx = d.Mx, My = d.My, L = d.Lr;
-  const int nx = d.nx, ny = d.ny, pitch = nx + 1;
+  // a compile-time transform length fixes the row sizes (Lr = 2 Mx, nx = C Mx)
+  const int Mx = LC ? LC / 2 : d.Mx, My = d.My, L = LC ? LC : d.Lr;
+  const int nx = LC ? C * (LC / 2) : d.nx, ny = d.ny, pitch = nx + 1;
   const int LP = lpad(L);
   const int ntw = d.ntw_r;
   const int j0 = lb * TJ;

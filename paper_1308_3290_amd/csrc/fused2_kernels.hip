@@ -44,7 +44,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_CD, bid)];
   const int lb = bid - d.blk0[PASS_CD];
   const int My = d.My;
-  const int nx = d.nx, ny = d.ny, pitch = nx + 1;
+  // the transform length fixes the row sizes (Lr = 2 Mx, nx = C Mx)
+  const int nx = C * (LC / 2), ny = d.ny, pitch = nx + 1;
   const size_t plane = (size_t)(ny + 1) * pitch;
   constexpr int LP = lpad(LC);
   const int ntw = d.ntw_r;

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
   constexpr int kTw = tw_per_thread<LC, kThreads>();
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_A, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_A];
-  const int Mx = d.Mx, My = d.My, L = d.Lr, ntw = d.ntw_r;
+  const int Mx = LC ? LC / 2 : d.Mx, My = d.My, L = LC ? LC : d.Lr, ntw = d.ntw_r;
   const int LP = lpad(L);
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + 2 * LP;
@@ -364,7 +364,8 @@ __global__ __launch_bounds__(kThreads) void k_rowdst_prolong(const MemberDesc* _
   extern __shared__ __align__(16) unsigned char smem[];
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_C, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_C];
-  const int Mx = d.Mx, My = d.My, L = d.Lr, c = d.c, nl = d.nlayers, TJ = d.tj, P = d.pc;
+  const int Mx = LC ? LC / 2 : d.Mx, My = d.My, L = LC ? LC : d.Lr, c = d.c, nl = d.nlayers;
+  const int TJ = d.tj, P = d.pc;
   const int nx = d.nx, ny = d.ny, pitch = nx + 1;
   const size_t plane = (size_t)(ny + 1) * pitch;
   const int LP = lpad(L);
