@@ -272,7 +272,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
         const int m = OFF + u;
         const int jr = m / C, fy = m - jr * C;
         const T top = jr + 1 < TJ + 2 ? cv[jr + 1 < TJ + 2 ? jr + 1 : TJ + 1] : T(0);
-        P[dx][u] = T(C - fy) * cv[jr < TJ + 2 ? jr : TJ + 1] + T(fy) * top;
+        const T on = T(C - fy) * cv[jr < TJ + 2 ? jr : TJ + 1];
+        P[dx][u] = fy == 0 ? on : on + T(fy) * top;  // fy is a constant here
       }
     }
     // rows 1 .. NO-1 exist in every block (the last block's row NO is the top
