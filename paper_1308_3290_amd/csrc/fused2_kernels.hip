@@ -70,7 +70,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
   T* psc1 = reinterpret_cast<T*>(tw + ntw);
   T* psc2 = psc1 + NS * PROW;
 
-  // ---- issue the block's global loads (unconditional; see the one-layer pass)
+  // ---- global loads (unconditional; see the one-layer pass): twiddles,
+  // spectra and the vorticity tiles first, then (once the transform's inputs
+  // are in LDS) forcing and omega_n, which arrive while the transform runs
   T twx[kTwPer], twy[kTwPer];
 #pragma unroll
   for (int q = 0; q < kTwPer; ++q) {
@@ -119,19 +121,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
       }
     }
   }
-  const int x = 1 + t;
-  T fv[NO], nv1[NO], nv2[NO];
-#pragma unroll
-  for (int u = 1; u <= NO; ++u) {
-    const int rr = RB0 + u;
-    const bool in = x < nx && u <= nrow && rr >= 1 && rr < ny;
-    const size_t o = in ? (size_t)rr * pitch + x : 0;
-    const T f = FF[o], n1 = WN[o], n2 = WN[plane + o];
-    fv[u - 1] = in ? f : T(0);
-    nv1[u - 1] = in ? n1 : T(0);
-    nv2[u - 1] = in ? n2 : T(0);
-  }
-
   // ---- twiddles and the NS row sequences (odd extension) into LDS
 #pragma unroll
   for (int q = 0; q < kTwPer; ++q) {
@@ -150,6 +139,19 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
       buf[r * LP + pad(2 * MX - k)] = {-sbt[r], -sbc[r]};
     }
   }
+  const int x = 1 + t;
+  T fv[NO], nv1[NO], nv2[NO];
+#pragma unroll
+  for (int u = 1; u <= NO; ++u) {
+    const int rr = RB0 + u;
+    const bool in = x < nx && u <= nrow && rr >= 1 && rr < ny;
+    const size_t o = in ? (size_t)rr * pitch + x : 0;
+    const T f = FF[o], n1 = WN[o], n2 = WN[plane + o];
+    fv[u - 1] = in ? f : T(0);
+    nv1[u - 1] = in ? n1 : T(0);
+    nv2[u - 1] = in ? n2 : T(0);
+  }
+
   const cplx<T>* Z = fft_run4<T, LC, NT>(buf, buf + 4 * LP, NS, tw);
 
   // ---- coarse psi of both layers, rows j0-1 .. j0+TJ (zero walls)

@@ -61,8 +61,14 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ W, long long g0,
 // vorticity of the block's coarse rows and transform it along x (pass A of
 // the next stage), which needs it on the C-1 fine rows below the block too;
 // those rows are computed here as well but not stored.
+// Waves per SIMD the register allocation must allow: four (two blocks per
+// CU, which ensembles of many blocks need) where that fits without spills.
+__host__ __device__ constexpr int fused_waves_per_simd(int c, int lc) {
+  return (c <= 2 && lc != 0) ? 4 : 2;
+}
+
 template <typename T, int C, int TJ, int LC, bool NEXT>
-__global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil(
+__global__ __launch_bounds__(kFusedThreads, fused_waves_per_simd(C, LC)) void k_prolong_stencil(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
     const T* __restrict__ wt, T* __restrict__ wnext, const cplx<T>* __restrict__ twg,
     const T* __restrict__ ws, const T* __restrict__ forcing, const T* __restrict__ wn,
