@@ -260,7 +260,27 @@ def main():
                 "traffic": traffic, "alg_bytes_per_launch": by[dom],
                 "us_per_launch": round(ms[i] * 1e3, 2)}
         result["passes"] = passes
-        del b, w, F
+        # diagnostics (E and Z per layer, eq. 26): outside the time step, timed
+        # on their own over the same fields; they read psi and omega once
+        psi = b.solve(w)
+        ez = torch.empty(2, dtype=torch.float64, device=dev)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(5):
+                api.cgp_diagnostics(b.handle, w, psi, ez, s)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(200):
+                api.cgp_diagnostics(b.handle, w, psi, ez, s)
+            e1.record(s)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 200
+        dbytes = 2 * w.numel() * 8
+        result["diagnostics"] = {"us_per_call": round(us, 2), "alg_bytes_per_call": dbytes,
+                                 "achieved_GBs": round(dbytes / (us * 1e-6) / 1e9, 1)}
+        log(f"diagnostics: {us:.1f} us per call ({dbytes / (us * 1e-6) / 1e9:.0f} GB/s)")
+        del b, w, F, psi
     # ---------------------------------------------------------------- adjoint ratio
     adj = None
     if not args.no_adjoint and (not only or "adj" in only):
@@ -412,6 +432,8 @@ def main():
         out["extras"] = {k: round(v, 1) for k, v in extras.items()}
     if "passes" in result:
         out["passes"] = result["passes"]
+    if "diagnostics" in result:
+        out["diagnostics"] = result["diagnostics"]
     print(json.dumps(out), flush=True)
 
 

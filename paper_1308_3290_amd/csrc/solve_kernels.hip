@@ -191,7 +191,9 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
 // columns k, k+1; two layers: the barotropic and baroclinic column k) along
 // y, multiplies by (2/Mx)(2/My)/lambda_kl (baroclinic: 1/(lambda_kl - F1 -
 // F2)), and transforms back, from the spectra of omega (win) to those of psi
-// (wout, same layout).  Loads are batched as in pass A.
+// (wout, same layout).  Loads are batched as in pass A.  The transforms use
+// the column plan (stage_plan(L, kWideCols)): one sequence per 256-thread
+// block has enough butterflies for radix 8 only from L = 2048 on.
 // ---------------------------------------------------------------------------
 // 1/x for the eigenvalues (negative, far from the overflow and subnormal
 // ranges): the hardware estimate refined by two Newton steps
