@@ -255,10 +255,28 @@ def main():
             base = kernel_names[dom].split("<")[0]
             if t.get("source_hash") == source_hash() and base in t.get("kernels", {}):
                 traffic = t["kernels"][base]["hbm_bytes_per_launch"]
+        # achievable HBM bandwidth: 1 GiB read + 1 GiB written by a device
+        # copy and by an elementwise kernel, the better of the two
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        best = 0.0
+        for op in (lambda: dst.copy_(src), lambda: torch.mul(src, 1.0, out=dst)):
+            for _ in range(3):
+                op()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                op()
+            e1.record()
+            torch.cuda.synchronize()
+            best = max(best, 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+        del src, dst
+        log(f"achievable HBM bandwidth (1 GiB copy): {best:.0f} GB/s")
         roof = {"bound": "hbm", "kernel": kernel_names[dom], "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic, "alg_bytes_per_launch": by[dom],
-                "us_per_launch": round(ms[i] * 1e3, 2)}
+                "us_per_launch": round(ms[i] * 1e3, 2),
+                "achievable_copy": round(best, 1), "frac_of_achievable": round(achieved / best, 4)}
         result["passes"] = passes
         # diagnostics (E and Z per layer, eq. 26): outside the time step, timed
         # on their own over the same fields; they read psi and omega once

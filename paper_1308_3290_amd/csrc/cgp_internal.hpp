@@ -20,6 +20,7 @@ enum Pass { PASS_A = 0, PASS_B = 1, PASS_C = 2, PASS_D = 3, PASS_CD = 4, NUM_PAS
 // fused_nr(c) fine rows.
 constexpr int kFusedMaxNx = 512;
 constexpr int kFusedThreads = 512;  // threads per block of the fused pass
+constexpr int kDiagBlocks = 2048;   // most blocks (partial sums) of the diagnostics
 __host__ __device__ constexpr int fused_tj(int c) { return c >= 4 ? 1 : (c == 2 ? 2 : 4); }
 __host__ __device__ constexpr int fused_nr(int c) { return c * fused_tj(c) + 1; }
 // complex sequences the fused one-layer pass transforms at most: the coarse

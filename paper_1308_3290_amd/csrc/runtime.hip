@@ -51,7 +51,6 @@ cgp_status hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int kDiagBlocks = 64;
 constexpr int kFiniteBlocks = 256;
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
@@ -1003,13 +1002,15 @@ cgp_status cgp_diagnostics(cgp_handle* h, const void* omega, const void* psi, do
   if (!omega || !psi || !out) return fail(CGP_ERR_INVALID, "NULL pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   double* part = h->at<double>(h->plan.lay.diag);
+  // one node row per block where that fits in kDiagBlocks blocks
+  const int nblk = std::min(kDiagBlocks, h->plan.md[0].ny + 1);
   hipError_t e = h->plan.dtype == CGP_F64
                      ? Launch<double>::diagnostics(h->d_md(), static_cast<const double*>(omega),
-                                                   static_cast<const double*>(psi), part,
-                                                   kDiagBlocks, out, s)
+                                                   static_cast<const double*>(psi), part, nblk,
+                                                   out, s)
                      : Launch<float>::diagnostics(h->d_md(), static_cast<const float*>(omega),
-                                                  static_cast<const float*>(psi), part,
-                                                  kDiagBlocks, out, s);
+                                                  static_cast<const float*>(psi), part, nblk,
+                                                  out, s);
   if (e != hipSuccess) return hip_fail(e, "diagnostics launch");
   return CGP_OK;
 }

@@ -140,77 +140,98 @@ __global__ __launch_bounds__(kTileX* kTileY) void k_adjoint_stencil(
 }
 
 // ---------------------------------------------------------------------------
-// Diagnostics.  Block b sums rows j = b, b + nblk, ... of member 0 in a fixed
-// order: per layer the x-link energy, y-link energy and enstrophy terms.
+// Diagnostics (eq. 26).  Per layer the x-link energy, y-link energy and
+// enstrophy sums.  Block b takes the node rows b, b + nblk, ... (one row per
+// block on most grids), thread t the columns t, t + 256, ...; the sums are
+// reduced in a fixed order (wave butterflies, then the four waves, then the
+// blocks in index order), so a call gives the same bits every time.
 // ---------------------------------------------------------------------------
+// Sums of v[0..5] over the block's 256 threads in a fixed order (wave
+// butterflies, then the four waves in order); sum k is returned in thread k.
+__device__ __forceinline__ double block_sums6(double (&v)[6], double (*red)[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[threadIdx.x >> 6][k] = v[k];
+  }
+  __syncthreads();
+  const int k = threadIdx.x < 6 ? threadIdx.x : 0;
+  return ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_diag_partial(const MemberDesc* __restrict__ md,
                                                       const T* __restrict__ w,
                                                       const T* __restrict__ psi,
                                                       double* __restrict__ partial) {
-  __shared__ double red[3][256];
+  __shared__ double red[4][6];
   const MemberDesc& d = md[0];
-  const int nx = d.nx, ny = d.ny, pitch = nx + 1;
-  const size_t plane = (size_t)(ny + 1) * pitch;
+  const int nx = d.nx, ny = d.ny, pitch = nx + 1, nl = d.nlayers;
+  const size_t n = (size_t)(ny + 1) * pitch;
   const double idx = 1.0 / d.dx, idy = 1.0 / d.dy;
-  for (int l = 0; l < d.nlayers; ++l) {
-    const T* P = psi + l * plane;
-    const T* Q = w + l * plane;
-    double ex = 0.0, ey = 0.0, z = 0.0;
-    for (int j = blockIdx.x; j <= ny; j += gridDim.x) {
-      for (int i = threadIdx.x; i <= nx; i += blockDim.x) {
-        const size_t o = (size_t)j * pitch + i;
-        const double pc = (double)P[o];
-        if (j >= 1 && j <= ny - 1 && i <= nx - 1) {
-          const double g = ((double)P[o + 1] - pc) * idx;
-          ex += g * g;
-        }
-        if (j <= ny - 1 && i >= 1 && i <= nx - 1) {
-          const double g = ((double)P[o + pitch] - pc) * idy;
-          ey += g * g;
-        }
-        if (j >= 1 && j <= ny - 1 && i >= 1 && i <= nx - 1) {
-          const double q = (double)Q[o];
-          z += q * q;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // layer l: ex, ey, z at 3 l
+  for (int j = blockIdx.x; j <= ny; j += gridDim.x) {
+    const bool rowin = j >= 1 && j <= ny - 1;
+    for (int i = threadIdx.x; i <= nx; i += 256) {
+      const size_t e = (size_t)j * pitch + i;
+      const bool xl = rowin && i <= nx - 1;                  // link (i, j) - (i+1, j)
+      const bool yl = j <= ny - 1 && i >= 1 && i <= nx - 1;  // link (i, j) - (i, j+1)
+      const bool in = rowin && i >= 1 && i <= nx - 1;
+      const size_t ex1 = xl ? e + 1 : e, ey1 = yl ? e + pitch : e;
+#pragma unroll
+      for (int l = 0; l < 2; ++l) {
+        if (l < nl) {
+          const T* P = psi + l * n;
+          const double pc = (double)P[e], pe = (double)P[ex1], pn = (double)P[ey1];
+          const double q = (double)w[l * n + e];
+          const double gx = (pe - pc) * idx, gy = (pn - pc) * idy;
+          acc[3 * l] += xl ? gx * gx : 0.0;
+          acc[3 * l + 1] += yl ? gy * gy : 0.0;
+          acc[3 * l + 2] += in ? q * q : 0.0;
         }
       }
     }
-    red[0][threadIdx.x] = ex;
-    red[1][threadIdx.x] = ey;
-    red[2][threadIdx.x] = z;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) {
-        red[0][threadIdx.x] += red[0][threadIdx.x + s];
-        red[1][threadIdx.x] += red[1][threadIdx.x + s];
-        red[2][threadIdx.x] += red[2][threadIdx.x + s];
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      partial[(blockIdx.x * 2 + l) * 3 + 0] = red[0][0];
-      partial[(blockIdx.x * 2 + l) * 3 + 1] = red[1][0];
-      partial[(blockIdx.x * 2 + l) * 3 + 2] = red[2][0];
-    }
-    __syncthreads();
   }
+  const double v = block_sums6(acc, red);
+  if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = v;
 }
 
-__global__ void k_diag_final(const MemberDesc* __restrict__ md, const double* __restrict__ partial,
-                             int nblk, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_diag_final(const MemberDesc* __restrict__ md,
+                                                    const double* __restrict__ partial, int nblk,
+                                                    double* __restrict__ out) {
+  __shared__ double red[4][6];
+  constexpr int kPer = kDiagBlocks / 256;  // partials per thread and sum
   const MemberDesc& d = md[0];
-  const int l = threadIdx.x;
-  if (l >= d.nlayers) return;
-  double ex = 0.0, ey = 0.0, z = 0.0;
-  for (int b = 0; b < nblk; ++b) {
-    ex += partial[(b * 2 + l) * 3 + 0];
-    ey += partial[(b * 2 + l) * 3 + 1];
-    z += partial[(b * 2 + l) * 3 + 2];
-  }
   const double area = (double)d.nx * d.dx * (double)d.ny * d.dy;
   const double f = d.dx * d.dy / (2.0 * area);
-  out[2 * l] = f * (ex + ey);
-  out[2 * l + 1] = f * z;
+  double v[6][kPer];  // all loads first, then the sums in a fixed order
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int b = threadIdx.x + 256 * q;
+      const double x = partial[(b < nblk ? b : 0) * 6 + k];
+      v[k][q] = b < nblk ? x : 0.0;
+    }
+  double sum[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    sum[k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) sum[k] += v[k][q];
+  }
+  const double tot = block_sums6(sum, red);  // total k in thread k
+  __shared__ double t6[6];
+  if (threadIdx.x < 6) t6[threadIdx.x] = tot;
+  __syncthreads();
+  if (threadIdx.x < d.nlayers) {
+    const int l = threadIdx.x;
+    out[2 * l] = f * (t6[3 * l] + t6[3 * l + 1]);
+    out[2 * l + 1] = f * t6[3 * l + 2];
+  }
 }
 
 template <typename T>
@@ -269,7 +290,7 @@ template <typename T>
 hipError_t Launch<T>::diagnostics(const MemberDesc* md, const T* w, const T* psi, double* partial,
                                   int nblk, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_diag_partial<T>, dim3(nblk), dim3(256), 0, s, md, w, psi, partial);
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, md, partial, nblk, out);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, md, partial, nblk, out);
   return hipGetLastError();
 }
 

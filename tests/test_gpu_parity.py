@@ -209,6 +209,8 @@ def test_c1_full_size_steps(level):
     say(f"  E gpu {diag[0]:.12e} oracle {E:.12e}; Z gpu {diag[1]:.12e} oracle {Z:.12e}")
     assert abs(diag[0] - E) < 1e-11 * abs(E)
     assert abs(diag[1] - Z) < 1e-12 * abs(Z)
+    # the reduction order is fixed: the same bits on every call
+    assert np.array_equal(to_np(b.diagnostics(wd, psi)), diag)
 
 
 @pytest.mark.parametrize("level", [1, 2])
