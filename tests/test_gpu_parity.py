@@ -47,6 +47,7 @@ SOLVE_CASES = [
     (64, 128, 0), (64, 128, 1), (64, 128, 2), (96, 192, 1), (48, 96, 0), (128, 64, 1),
     (16, 16, 2), (192, 384, 2), (512, 1024, 1), (512, 1024, 2), (512, 1024, 0),
     (64, 128, 3), (512, 1024, 3),  # three levels of coarsening (c = 8)
+    (64, 768, 0), (96, 1536, 1),  # column transforms of 1536 points (radix 3 last)
 ]
 
 
@@ -146,7 +147,8 @@ def test_c0_physics_100_steps_fp32(level):
 # and (16, 12, 1): the smallest fused grids (3 blocks).
 @pytest.mark.parametrize("nx,ny,level", [(96, 192, 1), (48, 96, 0), (192, 96, 2),
                                          (512, 32, 0), (1024, 64, 1), (1024, 48, 0),
-                                         (8, 6, 0), (24, 12, 0), (16, 12, 1), (256, 512, 3)])
+                                         (8, 6, 0), (24, 12, 0), (16, 12, 1), (256, 512, 3),
+                                         (64, 768, 0)])
 def test_ragged_and_radix3_trajectories(nx, ny, level):
     case = ci.make_case(nx, ny, level=level, dt=1e-4)
     say(f"{nx}x{ny} level {level}, 30 steps FP64")
@@ -162,7 +164,7 @@ def test_ragged_and_radix3_trajectories(nx, ny, level):
 # two-layer stage kernel
 @pytest.mark.parametrize("nx,ny,level", [(64, 128, 0), (64, 128, 1), (64, 128, 2),
                                          (128, 256, 1), (256, 128, 2), (384, 192, 1),
-                                         (128, 256, 3)])
+                                         (128, 256, 3), (128, 1536, 1)])
 def test_two_layer_trajectory_fp64(nx, ny, level):
     c2 = ci.case_c2(level)
     case = ci.make_case(nx, ny, level=level, nlayers=2, f1=c2.f1, f2=c2.f2, drag=c2.drag,
