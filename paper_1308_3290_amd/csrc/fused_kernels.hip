@@ -21,9 +21,8 @@
 // transform waits for them only); once they are in LDS the forcing and
 // omega_n are issued, and they arrive while the transform runs.  The
 // vorticity rows are issued with the spectra at c = 2 (measured faster, for
-// single basins and ensembles, at no extra registers) and with the forcing
-// at c = 1 and 4 (measured faster there).  Rows are at most kFusedMaxNx + 1
-// nodes wide.
+// single basins and ensembles) and with the forcing at c = 1 and 4
+// (measured faster there).  Rows are at most kFusedMaxNx + 1 nodes wide.
 #include "cgp_internal.hpp"
 #include "fft_lds.hpp"
 #include "stencil.hpp"
@@ -56,17 +55,17 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ W, long long g0,
   }
 }
 
-// C: coarsening factor; TJ: coarse rows owned per block; LC: transform
-// length with a compile-time transform, or 0.  NEXT: also restrict the new
-// vorticity of the block's coarse rows and transform it along x (pass A of
-// the next stage), which needs it on the C-1 fine rows below the block too;
-// those rows are computed here as well but not stored.
 // Waves per SIMD the register allocation must allow: four (two blocks per
 // CU, which ensembles of many blocks need) where that fits without spills.
 __host__ __device__ constexpr int fused_waves_per_simd(int c, int lc) {
   return (c <= 2 && lc != 0) ? 4 : 2;
 }
 
+// C: coarsening factor; TJ: coarse rows owned per block; LC: transform
+// length with a compile-time transform, or 0.  NEXT: also restrict the new
+// vorticity of the block's coarse rows and transform it along x (pass A of
+// the next stage), which needs it on the C-1 fine rows below the block too;
+// those rows are computed here as well but not stored.
 template <typename T, int C, int TJ, int LC, bool NEXT>
 __global__ __launch_bounds__(kFusedThreads, fused_waves_per_simd(C, LC)) void k_prolong_stencil(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
