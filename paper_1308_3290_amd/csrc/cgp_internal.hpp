@@ -16,13 +16,17 @@ constexpr int kTileY = 4;
 enum Pass { PASS_A = 0, PASS_B = 1, PASS_C = 2, PASS_D = 3, PASS_CD = 4, NUM_PASSES = 5 };
 
 // Fused C + D pass: rows of at most kFusedMaxNx intervals, coarsening
-// factors 1, 2 and 4; a block owns fused_tj(c) coarse rows and writes at most
-// fused_nr(c) fine rows.
+// factors 1, 2 and 4; a block owns fused_tj(c, layers) coarse rows and writes
+// at most fused_nr(c, layers) fine rows.  Two layers at c = 1: one coarse
+// row per block (the block's three sequences of up to 1024 points fill the
+// LDS).
 constexpr int kFusedMaxNx = 512;
 constexpr int kFusedThreads = 512;  // threads per block of the fused pass
 constexpr int kDiagBlocks = 2048;   // most blocks (partial sums) of the diagnostics
-__host__ __device__ constexpr int fused_tj(int c) { return c >= 4 ? 1 : (c == 2 ? 2 : 4); }
-__host__ __device__ constexpr int fused_nr(int c) { return c * fused_tj(c) + 1; }
+__host__ __device__ constexpr int fused_tj(int c, int nl = 1) {
+  return c >= 4 ? 1 : (c == 2 ? 2 : (nl == 2 ? 1 : 4));
+}
+__host__ __device__ constexpr int fused_nr(int c, int nl = 1) { return c * fused_tj(c, nl) + 1; }
 // complex sequences the fused one-layer pass transforms at most: the coarse
 // rows j0-1 .. j0+TJ in whole pairs (2m-1, 2m)
 __host__ __device__ constexpr int fused_nseq(int tj) { return (tj + 3) / 2; }

@@ -11,7 +11,8 @@
 //   3. with NEXT, restricts both new layers on its coarse rows, forms the
 //      modes delta Q_1 + (1 - delta) Q_2 and Q_1 - Q_2, and transforms them
 //      along x (one sequence per row), exactly as pass A does.
-// Coarsening factors 2 and 4, transform lengths with a compile-time engine.
+// Coarsening factors 1, 2 and 4 (at c = 1 the transfers are identities and a
+// block owns one coarse row), transform lengths with a compile-time engine.
 #include "cgp_internal.hpp"
 #include "fft_lds.hpp"
 #include "stencil.hpp"
@@ -24,7 +25,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
     const T* __restrict__ wt, T* __restrict__ wnext, const cplx<T>* __restrict__ twg,
     const T* __restrict__ ws, const T* __restrict__ forcing, const T* __restrict__ wn,
     T* __restrict__ out, double a_, double b_, StepCtl ctl) {
-  static_assert(C >= 2 && LC != 0, "two layers: coarsening 2 or 4, compile-time length");
+  static_assert(LC != 0, "two layers: compile-time transform length");
   constexpr int NT = kFusedThreads;
   constexpr int NR = C * TJ + 1;      // the most own fine rows (+1: top wall row)
   constexpr int E = NEXT ? C - 1 : 0;  // computed rows below the block
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
   // LDS: [ transform buffers | the two vorticity tiles | restriction rows and
   // the next transform's buffers ] [ twiddles ] [ coarse psi rows, 2 layers ]
   const int region =
-      (max(8 * LP * (int)sizeof(cplx<T>), 2 * NP * pitch * (int)sizeof(T)) + 15) & ~15;
+      (max(2 * NS * LP * (int)sizeof(cplx<T>), 2 * NP * pitch * (int)sizeof(T)) + 15) & ~15;
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   T* tile1 = reinterpret_cast<T*>(smem);
   T* tile2 = tile1 + NP * pitch;
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
     nv2[u - 1] = in ? n2 : T(0);
   }
 
-  const cplx<T>* Z = fft_run4<T, LC, NT>(buf, buf + 4 * LP, NS, tw);
+  const cplx<T>* Z = fft_run4<T, LC, NT>(buf, buf + NS * LP, NS, tw);
 
   // ---- coarse psi of both layers, rows j0-1 .. j0+TJ (zero walls)
   const T wbc1 = T(1.0 - d.delta), wbc2 = T(d.delta);
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
       buf[t * LP + pad(0)] = {T(0), T(0)};
       buf[t * LP + pad(MX)] = {T(0), T(0)};
     }
-    const cplx<T>* Z2 = fft_run4<T, LC, NT>(buf, buf + 2 * LP, TJ, tw);
+    const cplx<T>* Z2 = fft_run4<T, LC, NT>(buf, buf + TJ * LP, TJ, tw);
     if (i < MX) {
       T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
 #pragma unroll
@@ -365,6 +366,12 @@ hipError_t Launch<T>::prolong_stencil2(const MemberDesc* md, const Group& g, con
                      out, a, b, ctl)
 #define BY_C(NX)                                                  \
   switch (g.L) {                                                  \
+    case (1 << 16) | 128: LAUNCH(1, 1, 128, NX); break;           \
+    case (1 << 16) | 256: LAUNCH(1, 1, 256, NX); break;           \
+    case (1 << 16) | 384: LAUNCH(1, 1, 384, NX); break;           \
+    case (1 << 16) | 512: LAUNCH(1, 1, 512, NX); break;           \
+    case (1 << 16) | 768: LAUNCH(1, 1, 768, NX); break;           \
+    case (1 << 16) | 1024: LAUNCH(1, 1, 1024, NX); break;         \
     case (2 << 16) | 128: LAUNCH(2, 2, 128, NX); break;           \
     case (2 << 16) | 256: LAUNCH(2, 2, 256, NX); break;           \
     case (2 << 16) | 384: LAUNCH(2, 2, 384, NX); break;           \
@@ -389,6 +396,7 @@ hipError_t Launch<T>::prepare_fused2(size_t bytes) {
   const void* fns[] = {
 #define K(C, TJ, LC) reinterpret_cast<const void*>(&k_prolong_stencil2<T, C, TJ, LC, false>), \
                      reinterpret_cast<const void*>(&k_prolong_stencil2<T, C, TJ, LC, true>)
+      K(1, 1, 128), K(1, 1, 256), K(1, 1, 384), K(1, 1, 512), K(1, 1, 768), K(1, 1, 1024),
       K(2, 2, 128), K(2, 2, 256), K(2, 2, 384), K(2, 2, 512), K(4, 1, 128), K(4, 1, 256)
 #undef K
   };

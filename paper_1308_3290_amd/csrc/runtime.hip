@@ -241,10 +241,10 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   }
   // A block transforms at most two sequences and at most 2048 complex values.
   auto pairs = [](int L) { return L <= 512 ? 2 : 1; };
-  // fused C + D pass (rows of at most kFusedMaxNx intervals; one layer:
-  // c <= 4; two layers: c = 2 or 4 and a compile-time transform length).
-  // Its last block owns exactly fused_tj(c) coarse rows, so the coarse row
-  // count must be a multiple of that (only My = 6 at c = 1 is not).
+  // fused C + D pass (rows of at most kFusedMaxNx intervals, c <= 4; two
+  // layers: a compile-time transform length).  Its last block owns exactly
+  // fused_tj(c, layers) coarse rows, so the coarse row count must be a
+  // multiple of that (only My = 6 at c = 1, one layer, is not).
   // multigrid (one layer, single basin): levels from the coarse CGP grid
   // down to the coarsest (an odd interval count or one below 8)
   plan->solver = cfgs[0].solver;
@@ -271,8 +271,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   }
   bool fusable = plan->solver == 0;
   for (const MemberDesc& d : plan->md) {
-    fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4 && d.My % fused_tj(d.c) == 0;
-    if (nl == 2) fusable = fusable && d.c >= 2 && fft_special(d.Lr) != 0;
+    fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4 && d.My % fused_tj(d.c, nl) == 0;
+    if (nl == 2) fusable = fusable && fft_special(d.Lr) != 0;
   }
   // pass A: one complex sequence per block: coarse rows packed as the fused
   // pass packs them when it computes the next stage's spectra (so that both
@@ -324,10 +324,10 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                    // the next stage's restriction, one more on each side
                    // (shares LDS with the transform buffers: two sequences
                    // per block for one layer, tj + 2 for two)
-                   const int tj = fused_tj(d.c), nr = fused_nr(d.c);
+                   const int tj = fused_tj(d.c, nl), nr = fused_nr(d.c, nl);
                    const size_t tile = (size_t)nl * (nr + 2 + d.c - 1) * (d.nx + 1) * es;
                    const size_t fft =
-                       (size_t)(nl == 1 ? 2 * fused_nseq(tj) : 8) * lpad(d.Lr) * cs;
+                       (size_t)2 * (nl == 1 ? fused_nseq(tj) : tj + 2) * lpad(d.Lr) * cs;
                    const size_t region = (std::max(fft, tile) + 15) & ~(size_t)15;
                    const size_t lds = region + (size_t)d.ntw_r * cs +
                                       (size_t)nl * (tj + 2) * (d.Mx + 1) * es;

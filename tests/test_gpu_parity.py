@@ -215,7 +215,7 @@ def test_c1_full_size_steps(level):
     assert np.array_equal(to_np(b.diagnostics(wd, psi)), diag)
 
 
-@pytest.mark.parametrize("level", [1, 2])
+@pytest.mark.parametrize("level", [0, 1, 2])
 def test_c2_full_size_two_layer_steps(level):
     case = ci.case_c2(level)
     say(f"c2 512x1024 two-layer level {level}: 2 steps FP64")
