@@ -59,10 +59,11 @@ def _run(case, nsteps, dtype="f64"):
 
 # fused one-layer step at c = 2, 1, 4; (1024, 64, 1): rows too wide for the
 # fused kernel (unfused passes); two layers: (64, 128, 1) unfused, (128, 256, 1)
-# the fused two-layer kernel
+# and (64, 128, 0) the fused two-layer kernel at c = 2 and 1
 @pytest.mark.parametrize("nx,ny,level,layers,c", [
     (64, 128, 1, 1, 0.01), (64, 128, 0, 1, 0.01), (64, 128, 2, 1, 0.01),
-    (1024, 64, 1, 1, 0.01), (64, 128, 1, 2, 0.003), (128, 256, 1, 2, 0.003)])
+    (1024, 64, 1, 1, 0.01), (64, 128, 1, 2, 0.003), (128, 256, 1, 2, 0.003),
+    (64, 128, 0, 2, 0.003)])
 def test_adaptive_trajectory_matches_oracle(nx, ny, level, layers, c):
     case = _case(nx, ny, level, layers, c)
     say(f"adaptive {nx}x{ny} level {level} layers {layers} cfl {c}: 30 steps FP64")
