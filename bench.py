@@ -59,9 +59,10 @@ def parse():
 COPY_BYTES = 256 << 20
 
 
-def summarize_pmc(fetch_csv, write_csv):
+def summarize_pmc(fetch_csv, write_csv, out_path=None):
     """HBM bytes per dispatch of each CGP kernel from FETCH_SIZE / WRITE_SIZE (KiB),
-    each scaled so that the plain copy of COPY_BYTES reads and writes exactly that."""
+    each scaled so that the plain copy of COPY_BYTES reads and writes exactly that;
+    written to out_path (default profiles/traffic_c1_l1.json)."""
     import csv
     import statistics
 
@@ -95,7 +96,7 @@ def summarize_pmc(fetch_csv, write_csv):
         wb = write.get(name, 0.0) * 1024.0 * sw
         out["kernels"][short] = {"fetch_bytes": fb, "write_bytes": wb,
                                  "hbm_bytes_per_launch": fb + wb}
-    path = os.path.join(ROOT, "profiles", "traffic_c1_l1.json")
+    path = out_path or os.path.join(ROOT, "profiles", "traffic_c1_l1.json")
     json.dump(out, open(path, "w"), indent=1)
     print(json.dumps(out, indent=1))
 

@@ -1,0 +1,70 @@
+"""Host-side checks of bench.py's contract and helpers (no GPU)."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+import cgp_inputs as ci  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_algorithmic_bytes_of_the_512x1024_step():
+    # per launch at l = 1: fused pass 4 fine fields + 2 spectra, pass B 2 spectra
+    by = bench.pass_bytes(ci.case_c1(1), 8)
+    fine, coarse = 513 * 1025 * 8, 255 * 511 * 8
+    assert by["CDA"] == 4 * fine + 2 * coarse == 18911280
+    assert by["B"] == 2 * coarse
+    assert by["A"] == fine + coarse
+
+
+def _write_csv(path, rows, fields):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        w.writerows(rows)
+
+
+def test_trace_summary_statistics(tmp_path, capsys):
+    rows = [{"Kernel_Name": "void cgp::k_col_solve<double, 1024>(x)", "Start_Timestamp": s,
+             "End_Timestamp": s + d} for s, d in ((0, 5000), (10000, 7000), (20000, 6000))]
+    p = tmp_path / "trace.csv"
+    _write_csv(p, rows, ["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+    bench.summarize_trace(str(p))
+    out = capsys.readouterr().out.splitlines()
+    assert out[2] == "| k_col_solve<double, 1024> | 3 | 6.00 | 6.00 | 5.00 | 7.00 |"
+
+
+def test_pmc_summary_scales_by_the_copy(tmp_path):
+    copy_kib = bench.COPY_BYTES / 1024.0
+    fields = ["Kernel_Name", "Dispatch_Id", "Counter_Name", "Counter_Value"]
+    fetch = [{"Kernel_Name": "MulFunctor copy", "Dispatch_Id": 1, "Counter_Name": "FETCH_SIZE",
+              "Counter_Value": copy_kib / 2},  # the counter sees half of the copy's reads
+             {"Kernel_Name": "cgp::k_col_solve<double, 1024>(x)", "Dispatch_Id": 2,
+              "Counter_Name": "FETCH_SIZE", "Counter_Value": 1000.0}]
+    write = [{"Kernel_Name": "MulFunctor copy", "Dispatch_Id": 1, "Counter_Name": "WRITE_SIZE",
+              "Counter_Value": copy_kib},
+             {"Kernel_Name": "cgp::k_col_solve<double, 1024>(x)", "Dispatch_Id": 2,
+              "Counter_Name": "WRITE_SIZE", "Counter_Value": 500.0}]
+    pf, pw, out = tmp_path / "f.csv", tmp_path / "w.csv", tmp_path / "traffic.json"
+    _write_csv(pf, fetch, fields)
+    _write_csv(pw, write, fields)
+    bench.summarize_pmc(str(pf), str(pw), out_path=str(out))
+    t = json.load(open(out))
+    assert t["scale_fetch"] == pytest.approx(2.0) and t["scale_write"] == pytest.approx(1.0)
+    k = t["kernels"]["k_col_solve"]
+    assert k["fetch_bytes"] == pytest.approx(2000.0 * 1024)
+    assert k["hbm_bytes_per_launch"] == pytest.approx(2500.0 * 1024)
+    assert t["source_hash"] == bench.source_hash()
