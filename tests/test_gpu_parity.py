@@ -159,12 +159,14 @@ def test_ragged_and_radix3_trajectories(nx, ny, level):
     assert errs.max() < TOL64
 
 
-# 64x128: the unfused two-layer passes; 128x256 / 256x128 / 384x192 (coarse
-# rows of 64, 64 and 192 intervals, transforms of 128 and 384): the fused
-# two-layer stage kernel
+# 64x128 at l = 1, 2 (transforms of 64 and 32 points): the unfused two-layer
+# passes; 128x256 / 256x128 / 384x192 at l >= 1 (transforms of 128 and 384)
+# and 64x128 / 192x96 / 384x192 at l = 0 (c = 1: transforms of 128, 384 and
+# 768): the fused two-layer stage kernel
 @pytest.mark.parametrize("nx,ny,level", [(64, 128, 0), (64, 128, 1), (64, 128, 2),
                                          (128, 256, 1), (256, 128, 2), (384, 192, 1),
-                                         (128, 256, 3), (128, 1536, 1)])
+                                         (128, 256, 3), (128, 1536, 1),
+                                         (192, 96, 0), (384, 192, 0)])
 def test_two_layer_trajectory_fp64(nx, ny, level):
     c2 = ci.case_c2(level)
     case = ci.make_case(nx, ny, level=level, nlayers=2, f1=c2.f1, f2=c2.f2, drag=c2.drag,
