@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
                     help="print per-kernel launch statistics of a rocprofv3 --kernel-trace CSV "
                          "as a markdown table and exit (no GPU needed)")
+    ap.add_argument("--trace-tail", type=int, default=0, metavar="N",
+                    help="with --summarize-trace: statistics over each kernel's last N launches "
+                         "(the cgp_time_passes launches that end a --only timed run)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) into "
                          "profiles/traffic_c1_l1.json and exit (no GPU needed)")
@@ -101,8 +104,9 @@ def summarize_pmc(fetch_csv, write_csv, out_path=None):
     print(json.dumps(out, indent=1))
 
 
-def summarize_trace(trace_csv):
-    """Launch count and duration statistics (us) per kernel of a kernel trace."""
+def summarize_trace(trace_csv, tail=0):
+    """Launch count and duration statistics (us) per kernel of a kernel trace
+    (tail > 0: over each kernel's last `tail` launches in start order)."""
     import csv
     import statistics
     per = {}
@@ -110,8 +114,9 @@ def summarize_trace(trace_csv):
         name = r["Kernel_Name"]
         if "cgp::" in name:
             name = name.split("cgp::")[1].split("(")[0]
-        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
-        per.setdefault(name, []).append(dur)
+        start = int(r["Start_Timestamp"])
+        per.setdefault(name, []).append((start, (int(r["End_Timestamp"]) - start) / 1000.0))
+    per = {k: [d for _, d in sorted(v)][-tail if tail > 0 else 0:] for k, v in per.items()}
     print("| kernel | launches | mean us | median us | min us | max us |")
     print("|---|---|---|---|---|---|")
     for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
@@ -143,7 +148,7 @@ def source_hash():
 def main():
     args = parse()
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace)
+        summarize_trace(args.summarize_trace, args.trace_tail)
         return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
