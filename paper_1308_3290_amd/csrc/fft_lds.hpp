@@ -223,7 +223,48 @@ __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nseq, in
 // every power-of-two span: o is a multiple of Ns R plus k < Ns, so o + r Ns
 // crosses a multiple of 8 exactly where r Ns does.
 // ---------------------------------------------------------------------------
+// Twiddles in registers (RT = true below): a thread loads, once, the R-1
+// twiddles of each of its butterflies of every stage after the first, so
+// that the stages read no twiddle table from LDS (and the block needs no LDS
+// for it).  reg_tw_base(s) is where stage s's values start in the thread's
+// array, reg_tw_count() its length.
+template <int L, int NT, int MAXSEQ, int WF>
+__host__ __device__ constexpr int reg_tw_base(int s) {
+  const StagePlan P = stage_plan(L, WF);
+  int n = 0;
+  for (int u = 1; u < s; ++u) n += ((MAXSEQ * (L / P.R[u]) + NT - 1) / NT) * (P.R[u] - 1);
+  return n;
+}
+template <int L, int NT, int MAXSEQ, int WF>
+__host__ __device__ constexpr int reg_tw_count() {
+  return reg_tw_base<L, NT, MAXSEQ, WF>(stage_plan(L, WF).n);
+}
+
+// Loads stages S .. n-1 of the register twiddles from the stage tables tab
+// (global memory, the layout the LDS tables have).
 template <typename T, int L, int S, int NT, int MAXSEQ, int WF>
+__device__ __forceinline__ void reg_tw_load(cplx<T>* v, const cplx<T>* __restrict__ tab,
+                                            int nseq) {
+  constexpr StagePlan P = stage_plan(L, WF);
+  if constexpr (S < P.n) {
+    constexpr int R = P.R[S], NS = 1 << P.lns[S], OFF = P.off[S], LR = L / R;
+    constexpr int Q = (MAXSEQ * LR + NT - 1) / NT;
+    constexpr int BASE = reg_tw_base<L, NT, MAXSEQ, WF>(S);
+    const int nb = nseq * LR;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int b = threadIdx.x + NT * q;
+      const int bb = b < nb ? b : 0;
+      const int j = bb - (bb / LR) * LR;
+      const int k = j & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[BASE + q * (R - 1) + r - 1] = tab[OFF + (r - 1) * NS + k];
+    }
+    reg_tw_load<T, L, S + 1, NT, MAXSEQ, WF>(v, tab, nseq);
+  }
+}
+
+template <typename T, int L, int S, int NT, int MAXSEQ, int WF, bool RT = false>
 __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int nseq,
                                          const cplx<T>* tw) {
   constexpr StagePlan P = stage_plan(L, WF);
@@ -245,9 +286,15 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = src[r * RS];
       if constexpr (NS > 1) {
-        const cplx<T>* t = tw + OFF + k;
+        if constexpr (RT) {
+          constexpr int BASE = reg_tw_base<L, NT, MAXSEQ, WF>(S);
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * NS]);
+          for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[BASE + q * (R - 1) + r - 1]);
+        } else {
+          const cplx<T>* t = tw + OFF + k;
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * NS]);
+        }
       }
       small_dft<T, R>(v);
       const int o = ((j >> LNS) << LNS) * R + k;
@@ -261,14 +308,14 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
 
 // Stages S .. SEND-1, ping-ponging between a and b; returns the buffer that
 // holds the output of stage SEND-1 (a when S == SEND).
-template <typename T, int L, int S, int SEND, int NT, int MAXSEQ, int WF>
+template <typename T, int L, int S, int SEND, int NT, int MAXSEQ, int WF, bool RT = false>
 __device__ __forceinline__ cplx<T>* ct_stage_range(cplx<T>* a, cplx<T>* b, int nseq,
                                                    const cplx<T>* tw) {
   if constexpr (S == SEND) {
     return a;
   } else {
-    ct_stage<T, L, S, NT, MAXSEQ, WF>(a, b, nseq, tw);
-    return ct_stage_range<T, L, S + 1, SEND, NT, MAXSEQ, WF>(b, a, nseq, tw);
+    ct_stage<T, L, S, NT, MAXSEQ, WF, RT>(a, b, nseq, tw);
+    return ct_stage_range<T, L, S + 1, SEND, NT, MAXSEQ, WF, RT>(b, a, nseq, tw);
   }
 }
 
@@ -287,7 +334,7 @@ __device__ __forceinline__ cplx<T>* ct_stages(cplx<T>* a, cplx<T>* b, int nseq,
 // stage, m = j + r L/R for that butterfly's index j < L/R.  The last stage
 // ends without a barrier.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int NT, int MAXSEQ, int WF, class St>
+template <typename T, int L, int NT, int MAXSEQ, int WF, bool RT, class St>
 __device__ __forceinline__ void ct_stage_last(const cplx<T>* in, int nseq, const cplx<T>* tw,
                                               St&& st) {
   constexpr StagePlan P = stage_plan(L, WF);
@@ -308,9 +355,15 @@ __device__ __forceinline__ void ct_stage_last(const cplx<T>* in, int nseq, const
       cplx<T> v[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = src[r * RS];
-      const cplx<T>* t = tw + OFF + j;
+      if constexpr (RT) {
+        constexpr int BASE = reg_tw_base<L, NT, MAXSEQ, WF>(S);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * NS]);
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[BASE + q * (R - 1) + r - 1]);
+      } else {
+        const cplx<T>* t = tw + OFF + j;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * NS]);
+      }
       small_dft<T, R>(v);
 #pragma unroll
       for (int r = 0; r < R; ++r) st(p, j + r * NS, v[r], q, r);
@@ -326,15 +379,16 @@ __host__ __device__ constexpr bool ct_last_reads_a() {
 }
 
 // Input in LDS buffer a (as fft_run, which it matches bit for bit), last
-// stage to st.
-template <typename T, int LC, int NT, int MAXSEQ, int WF, class St>
+// stage to st.  RT: tw is the thread's register twiddles (reg_tw_load), else
+// the LDS tables.
+template <typename T, int LC, int NT, int MAXSEQ, int WF, bool RT = false, class St>
 __device__ __forceinline__ void ct_run_to(St&& st, cplx<T>* a, cplx<T>* b, int nseq,
                                           const cplx<T>* tw) {
   constexpr int N = stage_plan(LC, WF).n;
   static_assert(N >= 2, "the last stage follows at least one LDS stage");
   __syncthreads();
-  const cplx<T>* x = ct_stage_range<T, LC, 0, N - 1, NT, MAXSEQ, WF>(a, b, nseq, tw);
-  ct_stage_last<T, LC, NT, MAXSEQ, WF>(x, nseq, tw, st);
+  const cplx<T>* x = ct_stage_range<T, LC, 0, N - 1, NT, MAXSEQ, WF, RT>(a, b, nseq, tw);
+  ct_stage_last<T, LC, NT, MAXSEQ, WF, RT>(x, nseq, tw, st);
 }
 
 // Forward DFT with the contract of fft_lds; LC = 0 selects the runtime

@@ -293,7 +293,10 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                [&](MemberDesc& d, HostGroup&) {
                  d.pb = 1;
                  const int cols = nl == 1 ? 2 : 1;
-                 const size_t lds = ((size_t)2 * lpad(d.Lc) + d.ntw_c) * cs;
+                 // two transform buffers; the twiddle table only for the
+                 // runtime engine (compile-time lengths keep them in registers)
+                 const size_t lds =
+                     ((size_t)2 * lpad(d.Lc) + (fft_special(d.Lc) ? 0 : d.ntw_c)) * cs;
                  return std::make_pair((d.Mx - 1 + cols - 1) / cols, lds);
                },
                plan->groups[1]);

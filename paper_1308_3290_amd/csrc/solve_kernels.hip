@@ -215,7 +215,12 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
                                                         const double* __restrict__ lam,
                                                         double* __restrict__ ctl) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int kTw = tw_per_thread<LC, kThreads, kWideCols>();
+  __shared__ double red[kThreads / 64];  // step-size reduction
+  // twiddles: with a compile-time length each thread keeps the ones of its
+  // own butterflies in registers (no LDS table), else the block stages the
+  // table in LDS
+  constexpr int kTw = LC ? 1 : tw_per_thread<LC, kThreads, kWideCols>();
+  constexpr int kRegTw = LC ? reg_tw_count<LC, kThreads, 1, kWideCols>() : 1;
   constexpr int kRowIter = 4;  // My - 1 <= 1023
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_B, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_B];
@@ -245,12 +250,17 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
   const double lxb = lamx[(has_b ? kb : ka) - 1] - shift;
 
   T twx[kTw], twy[kTw];
+  cplx<T> rtw[kRegTw];
+  if constexpr (LC != 0) {
+    reg_tw_load<T, LC, 1, kThreads, 1, kWideCols>(rtw, twg + d.twc_off, 1);
+  } else {
 #pragma unroll
-  for (int q = 0; q < kTw; ++q) {
-    const int m = threadIdx.x + kThreads * q;
-    const cplx<T> z = twg[d.twc_off + (m < ntw ? m : 0)];
-    twx[q] = z.x;
-    twy[q] = z.y;
+    for (int q = 0; q < kTw; ++q) {
+      const int m = threadIdx.x + kThreads * q;
+      const cplx<T> z = twg[d.twc_off + (m < ntw ? m : 0)];
+      twx[q] = z.x;
+      twy[q] = z.y;
+    }
   }
   T va[kRowIter], vb[kRowIter];
   double ly[kRowIter];
@@ -262,10 +272,12 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
     vb[q] = has_b ? b : T(0);
     ly[q] = lamy[l - 1];
   }
+  if constexpr (LC == 0) {
 #pragma unroll
-  for (int q = 0; q < kTw; ++q) {
-    const int m = threadIdx.x + kThreads * q;
-    if (m < ntw) tw[m] = {twx[q], twy[q]};
+    for (int q = 0; q < kTw; ++q) {
+      const int m = threadIdx.x + kThreads * q;
+      if (m < ntw) tw[m] = {twx[q], twy[q]};
+    }
   }
   if (threadIdx.x == 0) {
     buf[pad(0)] = {T(0), T(0)};
@@ -307,15 +319,14 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
         Y[pad(m)] = {T(0), T(0)};
       }
     };
-    ct_run_to<T, LC, kThreads, 1, kWideCols>(divide, buf, buf2, 1, tw);
+    ct_run_to<T, LC, kThreads, 1, kWideCols, true>(divide, buf, buf2, 1, rtw);
     auto store = [&](int, int m, cplx<T> z, int, int) {
       if (m >= 1 && m < My) {
         wout[offa + m - 1] = T(-0.5) * z.y;
         if (has_b) wout[offb + m - 1] = T(0.5) * z.x;
       }
     };
-    ct_run_to<T, LC, kThreads, 1, kWideCols>(store, Y, kLastA ? buf : buf2, 1, tw);
-    if (ctl != nullptr && lb == 0) __syncthreads();  // other waves may still read twiddles
+    ct_run_to<T, LC, kThreads, 1, kWideCols, true>(store, Y, kLastA ? buf : buf2, 1, rtw);
   } else {
     cplx<T>* Z = fft_run<T, LC, kThreads, kWideCols>(buf, buf2, 1, L, d.nst_c, d.stw_c, tw);
     cplx<T>* Y = (Z == buf) ? buf2 : buf;
@@ -345,9 +356,8 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
       }
     }
   }
-  // first stage of a step: the member's dt (the twiddles are read no more)
-  if (ctl != nullptr && lb == 0)
-    update_step_dt<kThreads>(d, ctl, reinterpret_cast<double*>(tw));
+  // first stage of a step: the member's dt
+  if (ctl != nullptr && lb == 0) update_step_dt<kThreads>(d, ctl, red);
 }
 
 // ---------------------------------------------------------------------------
