@@ -16,10 +16,10 @@ constexpr int kTileY = 4;
 enum Pass { PASS_A = 0, PASS_B = 1, PASS_C = 2, PASS_D = 3, PASS_CD = 4, NUM_PASSES = 5 };
 
 // Fused C + D pass: rows of at most kFusedMaxNx intervals, coarsening
-// factors 1, 2 and 4; a block owns fused_tj(c, layers) coarse rows and writes
-// at most fused_nr(c, layers) fine rows.  Two layers at c = 1: one coarse
-// row per block (the block's three sequences of up to 1024 points fill the
-// LDS).
+// factors 1, 2, 4 and 8 (two layers: 1, 2 and 4); a block owns
+// fused_tj(c, layers) coarse rows and writes at most fused_nr(c, layers) fine
+// rows.  Two layers at c = 1: one coarse row per block (the block's three
+// sequences of up to 1024 points fill the LDS).
 constexpr int kFusedMaxNx = 512;
 constexpr int kFusedThreads = 512;  // threads per block of the fused pass
 constexpr int kDiagBlocks = 2048;   // most blocks (partial sums) of the diagnostics

@@ -408,8 +408,8 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
   hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC, NX>), dim3(g.nblk), dim3(kFusedThreads), \
                      g.lds, s, md, g.members, g.count, g.nblk, wt, wnext, tw, ws, forcing, wn, \
                      out, psi_out, a, b, ctl)
-// rows hold at most kFusedMaxNx intervals, so c = 1, 2, 4 have transform
-// lengths of at most 1024, 512, 256
+// rows hold at most kFusedMaxNx intervals, so c = 1, 2, 4, 8 have transform
+// lengths of at most 1024, 512, 256, 128
 #define BY_LEN1(NX)                            \
   switch (g.L & 0xffff) {                      \
     case 128: LAUNCH(1, 4, 128, NX); break;    \
@@ -434,11 +434,17 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
     case 256: LAUNCH(4, 1, 256, NX); break;    \
     default: LAUNCH(4, 1, 0, NX);              \
   }
+#define BY_LEN8(NX)                            \
+  switch (g.L & 0xffff) {                      \
+    case 128: LAUNCH(8, 1, 128, NX); break;    \
+    default: LAUNCH(8, 1, 0, NX);              \
+  }
 #define BY_C(NX)                          \
   switch (g.L >> 16) {                    \
     case 1: BY_LEN1(NX); break;           \
     case 2: BY_LEN2(NX); break;           \
     case 4: BY_LEN4(NX); break;           \
+    case 8: BY_LEN8(NX); break;           \
     default: return hipErrorInvalidValue; \
   }
   if (wnext) {
@@ -450,6 +456,7 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
 #undef BY_LEN1
 #undef BY_LEN2
 #undef BY_LEN4
+#undef BY_LEN8
 #undef LAUNCH
   return hipGetLastError();
 }
@@ -462,7 +469,7 @@ hipError_t Launch<T>::prepare_fused(size_t bytes) {
                      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, true>)
       K(1, 4, 0), K(1, 4, 128), K(1, 4, 256), K(1, 4, 384), K(1, 4, 512), K(1, 4, 768),
       K(1, 4, 1024), K(2, 2, 0), K(2, 2, 128), K(2, 2, 256), K(2, 2, 384), K(2, 2, 512),
-      K(4, 1, 0), K(4, 1, 128), K(4, 1, 256)
+      K(4, 1, 0), K(4, 1, 128), K(4, 1, 256), K(8, 1, 0), K(8, 1, 128)
 #undef K
   };
   for (const void* f : fns) {

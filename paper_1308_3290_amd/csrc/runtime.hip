@@ -241,8 +241,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   }
   // A block transforms at most two sequences and at most 2048 complex values.
   auto pairs = [](int L) { return L <= 512 ? 2 : 1; };
-  // fused C + D pass (rows of at most kFusedMaxNx intervals, c <= 4; two
-  // layers: a compile-time transform length).  Its last block owns exactly
+  // fused C + D pass (rows of at most kFusedMaxNx intervals, c <= 8; two
+  // layers: c <= 4 and a compile-time transform length).  Its last block owns exactly
   // fused_tj(c, layers) coarse rows, so the coarse row count must be a
   // multiple of that (only My = 6 at c = 1, one layer, is not).
   // multigrid (one layer, single basin): levels from the coarse CGP grid
@@ -271,7 +271,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   }
   bool fusable = plan->solver == 0;
   for (const MemberDesc& d : plan->md) {
-    fusable = fusable && d.nx <= kFusedMaxNx && d.c <= 4 && d.My % fused_tj(d.c, nl) == 0;
+    fusable = fusable && d.nx <= kFusedMaxNx && d.c <= (nl == 1 ? 8 : 4) &&
+              d.My % fused_tj(d.c, nl) == 0;
     if (nl == 2) fusable = fusable && fft_special(d.Lr) != 0;
   }
   // pass A: one complex sequence per block: coarse rows packed as the fused
@@ -1168,7 +1169,7 @@ cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forc
   double* gF = static_cast<double*>(grad_forcing);
   const MemberDesc* md = h->d_md();
   const int nb = h->plan.nblk_d;
-  if (h->plan.fused && d.c >= 2) {
+  if (h->plan.fused && d.c >= 2 && d.c <= 4) {
     // each stage: the fused adjoint kernel (which finishes the previous
     // stage's solve) and pass B on its source; pass C ends the sweep
     double* wt = h->at<double>(h->plan.lay.wt);

@@ -161,6 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     case 1: restrict_block<T, 1, NL>(d, f, buf, j0, keep); break;
     case 2: restrict_block<T, 2, NL>(d, f, buf, j0, keep); break;
     case 4: restrict_block<T, 4, NL>(d, f, buf, j0, keep); break;
+    case 8: restrict_block<T, 8, NL>(d, f, buf, j0, keep); break;
     default: restrict_block<T, 0, NL>(d, f, buf, j0, keep);
   }
 #pragma unroll

@@ -57,12 +57,12 @@ def _run(case, nsteps, dtype="f64"):
     return np.array(errs), np.array(gdts), np.array(dts), t
 
 
-# fused one-layer step at c = 2, 1, 4; (1024, 64, 1): rows too wide for the
+# fused one-layer step at c = 2, 1, 4, 8; (1024, 64, 1): rows too wide for the
 # fused kernel (unfused passes); two layers: (64, 128, 1) unfused, (128, 256, 1)
 # and (64, 128, 0) the fused two-layer kernel at c = 2 and 1
 @pytest.mark.parametrize("nx,ny,level,layers,c", [
     (64, 128, 1, 1, 0.01), (64, 128, 0, 1, 0.01), (64, 128, 2, 1, 0.01),
-    (1024, 64, 1, 1, 0.01), (64, 128, 1, 2, 0.003), (128, 256, 1, 2, 0.003),
+    (512, 256, 3, 1, 0.01), (1024, 64, 1, 1, 0.01), (64, 128, 1, 2, 0.003), (128, 256, 1, 2, 0.003),
     (64, 128, 0, 2, 0.003)])
 def test_adaptive_trajectory_matches_oracle(nx, ny, level, layers, c):
     case = _case(nx, ny, level, layers, c)

@@ -144,11 +144,13 @@ def test_c0_physics_100_steps_fp32(level):
 # intervals, transforms of 1024 complex values); (1024, 64, 1), (1024, 48, 0):
 # rows too wide for it, the unfused one-layer step.  (8, 6, 0): 6 coarse rows,
 # not a multiple of the 4 a fused block owns at c = 1 (unfused); (24, 12, 0)
-# and (16, 12, 1): the smallest fused grids (3 blocks).
+# and (16, 12, 1): the smallest fused grids (3 blocks).  c = 8: (256, 512, 3)
+# the fused pass with a runtime transform length (64 points), (512, 256, 3)
+# with the compile-time 128-point one, (1024, 64, 3) the unfused passes.
 @pytest.mark.parametrize("nx,ny,level", [(96, 192, 1), (48, 96, 0), (192, 96, 2),
                                          (512, 32, 0), (1024, 64, 1), (1024, 48, 0),
                                          (8, 6, 0), (24, 12, 0), (16, 12, 1), (256, 512, 3),
-                                         (64, 768, 0)])
+                                         (512, 256, 3), (1024, 64, 3), (64, 768, 0)])
 def test_ragged_and_radix3_trajectories(nx, ny, level):
     case = ci.make_case(nx, ny, level=level, dt=1e-4)
     say(f"{nx}x{ny} level {level}, 30 steps FP64")
@@ -191,7 +193,7 @@ def test_two_layer_trajectory_fp32():
     assert errs.max() < TOL32
 
 
-@pytest.mark.parametrize("level", [0, 1, 2])
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
 def test_c1_full_size_steps(level):
     """The 512 x 1024 workload itself, in the bench's launch configuration."""
     case = ci.case_c1(level)
@@ -305,7 +307,7 @@ def test_steps_are_deterministic():
 
 @pytest.mark.parametrize("nx,ny,level,layers", [
     (96, 192, 0, 1), (96, 192, 1, 1), (96, 192, 2, 1), (256, 512, 0, 1), (256, 512, 1, 1),
-    (256, 512, 2, 1), (256, 512, 1, 2), (256, 512, 2, 2)])
+    (256, 512, 2, 1), (512, 256, 3, 1), (256, 512, 1, 2), (256, 512, 2, 2)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_steps_split_over_calls_give_the_same_bits(nx, ny, level, layers, dtype):
     """Six steps in one call, in calls of 1, 2 and 3 steps, and through the
@@ -446,7 +448,7 @@ def test_adjoint_segment_matches_oracle():
     assert e1 < 1e-11 and e2 < 1e-11
 
 
-@pytest.mark.parametrize("level", [0, 1, 2])
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
 def test_adjoint_dot_product_with_oracle_tlm(level):
     case = ci.make_case(64, 128, level=level, dt=1e-4)
     g, phys = oracle_setup(case)
