@@ -282,6 +282,19 @@ struct Launch {
 
 // Multigrid V-cycle operations on one level (an nx x ny interval node array
 // with a zero ring), one launch each.
+// The lowest levels of a V-cycle run in one block with every level's u and f
+// in LDS (u_k at off[k], f_k right after it): at most kMgTailLevels levels
+// and kMgTailLds bytes.
+constexpr int kMgTailLevels = 8;
+constexpr int kMgTailThreads = 1024;
+constexpr size_t kMgTailLds = 64 * 1024;
+template <typename T>
+struct MgTail {
+  int nlev = 0;
+  int nx[kMgTailLevels] = {}, ny[kMgTailLevels] = {}, off[kMgTailLevels] = {};
+  T ax[kMgTailLevels] = {}, ay[kMgTailLevels] = {}, inv_d[kMgTailLevels] = {};
+};
+
 template <typename T>
 struct MgLaunch {
   // f0 = R^l w (coarse node array of nx/c x ny/c intervals, zero ring)
@@ -289,9 +302,9 @@ struct MgLaunch {
   // half sweep of red-black Gauss-Seidel for Lap_h u = f on nodes i + j = color (mod 2)
   static hipError_t smooth(T* u, const T* f, int nx, int ny, double dx, double dy, int color,
                            hipStream_t s);
-  // fc (nx/2 x ny/2 intervals) = full weighting of f - Lap_h u
+  // fc (nx/2 x ny/2 intervals) = full weighting of f - Lap_h u; uc = 0 (same size)
   static hipError_t residual_restrict(const T* u, const T* f, int nx, int ny, double dx,
-                                      double dy, T* fc, hipStream_t s);
+                                      double dy, T* fc, T* uc, hipStream_t s);
   // u += bilinear interpolation of uc (nx/2 x ny/2 intervals)
   static hipError_t prolong_add(const T* uc, int nx, int ny, T* u, hipStream_t s);
   // u = minv f on the nb interior nodes of the coarsest grid
@@ -300,6 +313,10 @@ struct MgLaunch {
   static hipError_t prolong_field(const T* uc, int nx, int ny, int c, T* psi, int accumulate,
                                   hipStream_t s);
   static hipError_t fill_zero(T* a, long long n, hipStream_t s);
+  // the rest of a V-cycle from level t.nx[0] x t.ny[0] down, in one block:
+  // u0, f0 that level's arrays (u0 read unless zero_u, written back)
+  static hipError_t tail(const MgTail<T>& t, T* u0, const T* f0, int zero_u, const double* minv,
+                         int nb, hipStream_t s);
 };
 
 // The step size of every member (the first stage of a step on handles whose

@@ -6,7 +6,9 @@
 // bilinear interpolation of the correction (the Sec. 3.1 operators),
 // coarsening while both interval counts are even and at least 8, and the
 // coarsest grid solved exactly by its dense inverse (built on the host in
-// FP64).  One kernel per operation and level; node arrays with a zero ring.
+// FP64).  One kernel per operation and level on the finer levels; the
+// lowest levels run in one block (k_mg_tail), with the same arithmetic
+// (shared helpers below) in the same order.  Node arrays with a zero ring.
 #include <hip/hip_runtime.h>
 
 #include "cgp_internal.hpp"
@@ -39,14 +41,11 @@ __global__ __launch_bounds__(256) void k_mg_restrict_field(const T* __restrict__
   f0[k] = v;
 }
 
-// One half sweep of Gauss-Seidel on the interior nodes of one colour:
-// u = (ax (uE + uW) + ay (uN + uS) - f) / (2 ax + 2 ay).
+// Gauss-Seidel update of interior node k (row-major over the interior) if it
+// has the given colour: u = (ax (uE + uW) + ay (uN + uS) - f) / (2 ax + 2 ay).
 template <typename T>
-__global__ __launch_bounds__(256) void k_mg_smooth(T* __restrict__ u, const T* __restrict__ f,
-                                                   int nx, int ny, T ax, T ay, T inv_d,
-                                                   int color) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (nx - 1) * (ny - 1)) return;
+__device__ __forceinline__ void mg_gs_node(T* u, const T* f, int nx, int k, T ax, T ay,
+                                           T inv_d, int color) {
   const int j = 1 + k / (nx - 1), i = 1 + k % (nx - 1);
   if (((i + j) & 1) != color) return;
   const int p = nx + 1;
@@ -54,16 +53,13 @@ __global__ __launch_bounds__(256) void k_mg_smooth(T* __restrict__ u, const T* _
   u[o] = (ax * (u[o + 1] + u[o - 1]) + ay * (u[o + p] + u[o - p]) - f[o]) * inv_d;
 }
 
-// fc = full weighting of the residual f - Lap_h u (each coarse interior node
-// evaluates the residual at its nine fine nodes), 0 on the coarse ring.
+// Full weighting of the residual f - Lap_h u at coarse node k of the
+// (nx/2 + 1) x (ny/2 + 1) array (the residual at its nine fine nodes), 0 on
+// the coarse ring.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mg_residual_restrict(const T* __restrict__ u,
-                                                              const T* __restrict__ f, int nx,
-                                                              int ny, T ax, T ay,
-                                                              T* __restrict__ fc) {
+__device__ __forceinline__ T mg_resid_fw(const T* u, const T* f, int nx, int ny, int k, T ax,
+                                         T ay) {
   const int nxc = nx / 2, nyc = ny / 2;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (nxc + 1) * (nyc + 1)) return;
   const int J = k / (nxc + 1), I = k - J * (nxc + 1);
   T v = T(0);
   if (I >= 1 && I <= nxc - 1 && J >= 1 && J <= nyc - 1) {
@@ -81,15 +77,14 @@ __global__ __launch_bounds__(256) void k_mg_residual_restrict(const T* __restric
     }
     v = acc / T(16);
   }
-  fc[k] = v;
+  return v;
 }
 
-// u += bilinear interpolation of the coarse correction uc at fine interior nodes.
+// Bilinear interpolation of the coarse correction uc at fine interior node k
+// (row-major over the interior of the nx x ny grid); returns the node's
+// offset in the fine array.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mg_prolong_add(const T* __restrict__ uc, int nx, int ny,
-                                                        T* __restrict__ u) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (nx - 1) * (ny - 1)) return;
+__device__ __forceinline__ T mg_prolong_node(const T* uc, int nx, int k, size_t& o) {
   const int j = 1 + k / (nx - 1), i = 1 + k % (nx - 1);
   const int pc = nx / 2 + 1;
   const int I = i >> 1, J = j >> 1;
@@ -99,7 +94,56 @@ __global__ __launch_bounds__(256) void k_mg_prolong_add(const T* __restrict__ uc
   else if (!(j & 1)) v = T(0.5) * (c0[0] + c0[1]);
   else if (!(i & 1)) v = T(0.5) * (c0[0] + c0[pc]);
   else v = T(0.25) * (c0[0] + c0[1] + c0[pc] + c0[pc + 1]);
-  u[(size_t)j * (nx + 1) + i] += v;
+  o = (size_t)j * (nx + 1) + i;
+  return v;
+}
+
+// Row k of the coarsest grid's dense inverse times f (interior nodes
+// row-major), accumulated in FP64.
+template <typename T>
+__device__ __forceinline__ T mg_bottom_row(const double* minv, int nb, const T* f, int nx,
+                                           int k) {
+  const int n1 = nx - 1, p = nx + 1;
+  const double* row = minv + (size_t)k * nb;
+  double s = 0.0;
+  for (int m = 0; m < nb; ++m) s += row[m] * (double)f[(size_t)(1 + m / n1) * p + 1 + m % n1];
+  return T(s);
+}
+
+// One half sweep of Gauss-Seidel on the interior nodes of one colour.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_smooth(T* __restrict__ u, const T* __restrict__ f,
+                                                   int nx, int ny, T ax, T ay, T inv_d,
+                                                   int color) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (nx - 1) * (ny - 1)) return;
+  mg_gs_node(u, f, nx, k, ax, ay, inv_d, color);
+}
+
+// fc = full weighting of the residual f - Lap_h u (each coarse interior node
+// evaluates the residual at its nine fine nodes), 0 on the coarse ring; the
+// coarse correction uc starts from zero.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_residual_restrict(const T* __restrict__ u,
+                                                              const T* __restrict__ f, int nx,
+                                                              int ny, T ax, T ay,
+                                                              T* __restrict__ fc,
+                                                              T* __restrict__ uc) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (nx / 2 + 1) * (ny / 2 + 1)) return;
+  fc[k] = mg_resid_fw(u, f, nx, ny, k, ax, ay);
+  uc[k] = T(0);
+}
+
+// u += bilinear interpolation of the coarse correction uc at fine interior nodes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_prolong_add(const T* __restrict__ uc, int nx, int ny,
+                                                        T* __restrict__ u) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (nx - 1) * (ny - 1)) return;
+  size_t o;
+  const T v = mg_prolong_node(uc, nx, k, o);
+  u[o] += v;
 }
 
 // Coarsest grid: u = A^-1 f on the nb interior nodes (row-major), A^-1 dense
@@ -110,11 +154,8 @@ __global__ __launch_bounds__(256) void k_mg_bottom(const double* __restrict__ mi
                                                    T* __restrict__ u) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nb) return;
-  const int n1 = nx - 1, p = nx + 1;
-  const double* row = minv + (size_t)k * nb;
-  double s = 0.0;
-  for (int m = 0; m < nb; ++m) s += row[m] * (double)f[(size_t)(1 + m / n1) * p + 1 + m % n1];
-  u[(size_t)(1 + k / n1) * p + 1 + k % n1] = T(s);
+  const int n1 = nx - 1;
+  u[(size_t)(1 + k / n1) * (nx + 1) + 1 + k % n1] = mg_bottom_row(minv, nb, f, nx, k);
 }
 
 // psi = P^l uc at every fine node: bilinear from the c-spaced coarse nodes
@@ -134,6 +175,76 @@ __global__ __launch_bounds__(256) void k_mg_prolong_field(const T* __restrict__ 
                a * g * uc[(size_t)J1 * pc + I] + b * g * uc[(size_t)J1 * pc + I1]) /
               (T(c) * T(c));
   psi[k] = accumulate ? psi[k] + v : v;
+}
+
+// The V-cycle from level 0 of t down to the coarsest, in one block: the
+// same pre-smoothing (red, black, red, black), residual restriction, zeroed
+// coarse correction, bottom solve, prolongation and post-smoothing (black,
+// red, black, red) as the per-level kernels, with a barrier after each step.
+template <typename T>
+__global__ __launch_bounds__(kMgTailThreads) void k_mg_tail(MgTail<T> t, T* __restrict__ u0,
+                                                            const T* __restrict__ f0, int zero_u,
+                                                            const double* __restrict__ minv,
+                                                            int nb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  constexpr int NT = kMgTailThreads;
+  const int tid = threadIdx.x;
+  auto nodes = [&](int l) { return (t.nx[l] + 1) * (t.ny[l] + 1); };
+  const int n0 = nodes(0);
+  for (int k = tid; k < n0; k += NT) {
+    lds[t.off[0] + k] = zero_u ? T(0) : u0[k];
+    lds[t.off[0] + n0 + k] = f0[k];
+  }
+  __syncthreads();
+  auto half_sweep = [&](int l, int color) {
+    T* u = lds + t.off[l];
+    const T* f = u + nodes(l);
+    const int ni = (t.nx[l] - 1) * (t.ny[l] - 1);
+    for (int k = tid; k < ni; k += NT)
+      mg_gs_node(u, f, t.nx[l], k, t.ax[l], t.ay[l], t.inv_d[l], color);
+    __syncthreads();
+  };
+  const int top = t.nlev - 1;
+  for (int l = 0; l < top; ++l) {
+    for (int q = 0; q < 2; ++q) {
+      half_sweep(l, 0);
+      half_sweep(l, 1);
+    }
+    const T* u = lds + t.off[l];
+    const T* f = u + nodes(l);
+    T* uc = lds + t.off[l + 1];
+    T* fc = uc + nodes(l + 1);
+    for (int k = tid; k < nodes(l + 1); k += NT) {
+      fc[k] = mg_resid_fw(u, f, t.nx[l], t.ny[l], k, t.ax[l], t.ay[l]);
+      uc[k] = T(0);
+    }
+    __syncthreads();
+  }
+  {
+    T* u = lds + t.off[top];
+    const int n1 = t.nx[top] - 1;
+    for (int k = tid; k < nb; k += NT)
+      u[(size_t)(1 + k / n1) * (t.nx[top] + 1) + 1 + k % n1] =
+          mg_bottom_row(minv, nb, u + nodes(top), t.nx[top], k);
+    __syncthreads();
+  }
+  for (int l = top - 1; l >= 0; --l) {
+    T* u = lds + t.off[l];
+    const T* uc = lds + t.off[l + 1];
+    const int ni = (t.nx[l] - 1) * (t.ny[l] - 1);
+    for (int k = tid; k < ni; k += NT) {
+      size_t o;
+      const T v = mg_prolong_node(uc, t.nx[l], k, o);
+      u[o] += v;
+    }
+    __syncthreads();
+    for (int q = 0; q < 2; ++q) {
+      half_sweep(l, 1);
+      half_sweep(l, 0);
+    }
+  }
+  for (int k = tid; k < n0; k += NT) u0[k] = lds[t.off[0] + k];
 }
 
 template <typename T>
@@ -172,10 +283,10 @@ hipError_t MgLaunch<T>::smooth(T* u, const T* f, int nx, int ny, double dx, doub
 
 template <typename T>
 hipError_t MgLaunch<T>::residual_restrict(const T* u, const T* f, int nx, int ny, double dx,
-                                          double dy, T* fc, hipStream_t s) {
+                                          double dy, T* fc, T* uc, hipStream_t s) {
   hipLaunchKernelGGL(k_mg_residual_restrict<T>,
                      grid_for((long long)(nx / 2 + 1) * (ny / 2 + 1)), dim3(256), 0, s, u, f, nx,
-                     ny, T(1.0 / (dx * dx)), T(1.0 / (dy * dy)), fc);
+                     ny, T(1.0 / (dx * dx)), T(1.0 / (dy * dy)), fc, uc);
   return hipGetLastError();
 }
 
@@ -198,6 +309,18 @@ hipError_t MgLaunch<T>::prolong_field(const T* uc, int nx, int ny, int c, T* psi
                                       int accumulate, hipStream_t s) {
   hipLaunchKernelGGL(k_mg_prolong_field<T>, grid_for((long long)(nx + 1) * (ny + 1)), dim3(256),
                      0, s, uc, nx, ny, c, psi, accumulate);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t MgLaunch<T>::tail(const MgTail<T>& t, T* u0, const T* f0, int zero_u,
+                             const double* minv, int nb, hipStream_t s) {
+  const int last = t.nlev - 1;
+  const size_t lds = ((size_t)t.off[last] + 2 * (size_t)(t.nx[last] + 1) * (t.ny[last] + 1)) *
+                     sizeof(T);
+  if (t.nlev < 1 || t.nlev > kMgTailLevels || lds > kMgTailLds) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(kMgTailThreads), lds, s, t, u0, f0, zero_u, minv,
+                     nb);
   return hipGetLastError();
 }
 

@@ -140,6 +140,7 @@ struct Plan {
   int mg_cycles = 0;
   std::vector<MgLevel> mg;           // finest (the coarse CGP grid) first
   int mg_nb = 0;                     // unknowns of the coarsest grid
+  int mg_tail = 0;                   // first level of the one-block tail (mg.size(): none)
   Layout lay;
   std::vector<HostGroup> groups[4];  // passes A, B, C and the fused C + D pass
   int nblk_d = 0;                    // pass D: one launch over every member
@@ -268,6 +269,15 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     plan->mg_nb = (gx - 1) * (gy - 1);
     if (plan->mg_nb > 1024)
       return fail(CGP_ERR_UNSUPPORTED, "multigrid coarsest grid %dx%d too large", gx, gy);
+    // the lowest levels whose u and f fit kMgTailLds run in one block
+    const int nlv = (int)plan->mg.size();
+    size_t tail_bytes = 0;
+    plan->mg_tail = nlv;
+    for (int k = nlv - 1; k >= 0 && nlv - k <= kMgTailLevels; --k) {
+      tail_bytes += 2 * (size_t)(plan->mg[k].nx + 1) * (plan->mg[k].ny + 1) * es;
+      if (tail_bytes > kMgTailLds) break;
+      plan->mg_tail = k;
+    }
   }
   bool fusable = plan->solver == 0;
   for (const MemberDesc& d : plan->md) {
@@ -450,6 +460,24 @@ hipError_t mg_vcycle(cgp_handle* h, int k, hipStream_t s) {
   const MgLevel& lv = p.mg[k];
   T* u = base + lv.u;
   T* f = base + lv.f;
+  if (k == p.mg_tail) {  // this level and the coarser ones in one block
+    MgTail<T> t;
+    t.nlev = (int)p.mg.size() - k;
+    int off = 0;
+    for (int l = 0; l < t.nlev; ++l) {
+      const MgLevel& m = p.mg[k + l];
+      const double ax = 1.0 / (m.dx * m.dx), ay = 1.0 / (m.dy * m.dy);
+      t.nx[l] = m.nx;
+      t.ny[l] = m.ny;
+      t.off[l] = off;
+      t.ax[l] = T(ax);
+      t.ay[l] = T(ay);
+      t.inv_d[l] = T(1.0 / (2.0 * ax + 2.0 * ay));
+      off += 2 * (m.nx + 1) * (m.ny + 1);
+    }
+    // below the top level the correction starts from zero
+    return MgLaunch<T>::tail(t, u, f, k > 0 ? 1 : 0, h->at<double>(p.lay.mgm), p.mg_nb, s);
+  }
   if (k + 1 == (int)p.mg.size())
     return MgLaunch<T>::bottom(h->at<double>(p.lay.mgm), p.mg_nb, f, lv.nx, u, s);
   hipError_t e = hipSuccess;
@@ -459,9 +487,8 @@ hipError_t mg_vcycle(cgp_handle* h, int k, hipStream_t s) {
   }
   const MgLevel& cl = p.mg[k + 1];
   if (e == hipSuccess)
-    e = MgLaunch<T>::residual_restrict(u, f, lv.nx, lv.ny, lv.dx, lv.dy, base + cl.f, s);
-  if (e == hipSuccess)
-    e = MgLaunch<T>::fill_zero(base + cl.u, (long long)(cl.nx + 1) * (cl.ny + 1), s);
+    e = MgLaunch<T>::residual_restrict(u, f, lv.nx, lv.ny, lv.dx, lv.dy, base + cl.f,
+                                       base + cl.u, s);
   if (e == hipSuccess) e = mg_vcycle<T>(h, k + 1, s);
   if (e == hipSuccess) e = MgLaunch<T>::prolong_add(base + cl.u, lv.nx, lv.ny, u, s);
   for (int q = 0; q < 2 && e == hipSuccess; ++q) {  // post-smoothing: black, red
