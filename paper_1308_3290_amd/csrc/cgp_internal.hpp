@@ -259,7 +259,7 @@ struct Launch {
                                     T* out, T* psi_out, double a, double b, StepCtl ctl,
                                     hipStream_t s);
   static hipError_t prepare_fused(size_t bytes);
-  // the same for two layers (mode recombination and split inside; c = 2, 4)
+  // the same for two layers (mode recombination and split inside; c = 1, 2, 4)
   static hipError_t prolong_stencil2(const MemberDesc* md, const Group& g, const T* wt, T* wnext,
                                      const cplx<T>* tw, const T* ws, const T* forcing,
                                      const T* wn, T* out, double a, double b, StepCtl ctl,

@@ -21,8 +21,9 @@
 // transform waits for them only); once they are in LDS the forcing and
 // omega_n are issued, and they arrive while the transform runs.  The
 // vorticity rows are issued with the spectra at c = 2 (measured faster, for
-// single basins and ensembles) and with the forcing at c = 1 and 4
-// (measured faster there).  Rows are at most kFusedMaxNx + 1 nodes wide.
+// single basins and ensembles) and with the forcing at c = 1, 4 and 8
+// (measured faster at c = 1 and 4).  Rows are at most kFusedMaxNx + 1 nodes
+// wide.
 #include "cgp_internal.hpp"
 #include "fft_lds.hpp"
 #include "stencil.hpp"

@@ -243,9 +243,9 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   // A block transforms at most two sequences and at most 2048 complex values.
   auto pairs = [](int L) { return L <= 512 ? 2 : 1; };
   // fused C + D pass (rows of at most kFusedMaxNx intervals, c <= 8; two
-  // layers: c <= 4 and a compile-time transform length).  Its last block owns exactly
-  // fused_tj(c, layers) coarse rows, so the coarse row count must be a
-  // multiple of that (only My = 6 at c = 1, one layer, is not).
+  // layers: c <= 4 and a compile-time transform length).  Its last block
+  // owns exactly fused_tj(c, layers) coarse rows, so the coarse row count
+  // must be a multiple of that (only My = 6 at c = 1, one layer, is not).
   // multigrid (one layer, single basin): levels from the coarse CGP grid
   // down to the coarsest (an odd interval count or one below 8)
   plan->solver = cfgs[0].solver;
@@ -1157,7 +1157,8 @@ cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forc
   const MemberDesc& d = h->plan.md[0];
   const size_t N = (size_t)(d.nx + 1) * (d.ny + 1);
   const size_t need = (6 * (size_t)nsteps + 4) * N * sizeof(double);
-  if (tape_bytes < need) return fail(CGP_ERR_INVALID, "tape too small: %zu < %zu", tape_bytes, need);
+  if (tape_bytes < need)
+    return fail(CGP_ERR_INVALID, "tape too small: %zu < %zu", tape_bytes, need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   double* tp = static_cast<double*>(tape);
   auto slot = [&](int n, int k) { return tp + ((size_t)n * 6 + k) * N; };
