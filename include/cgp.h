@@ -220,7 +220,7 @@ cgp_status cgp_ensemble_step(cgp_handle* h, void* omega_packed_dev,
  * psi), 3 (Arakawa right-hand side + RK3 combine in the form of stage 2:
  * reads stage 1, psi, the forcing and omega_dev, writes stage 2), 4 (the
  * fused form of passes 2 and 3 that one-layer time steps use when every
- * member's rows hold at most 512 intervals and 2^level <= 4) and 5 (pass 4
+ * member's rows hold at most 512 intervals and 2^level <= 8) and 5 (pass 4
  * followed by pass 0 of the next stage on its result, the form time steps
  * launch); 0 is reported for 4 and 5 on handles without them.  Each pass is
  * launched `reps` times back to back on `stream` between two HIP events;
