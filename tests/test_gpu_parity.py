@@ -424,6 +424,44 @@ def test_chained_ensemble_graph_matches_single_basins(dtype):
         assert torch.equal(ens.member_view(W, m), ws), f"member {m} differs"
 
 
+def test_ensemble_of_mixed_coarsening_factors():
+    """Members at c = 1, 2, 4 and 8 (compile-time transform lengths of 128 and
+    256 points and runtime ones of 64 and 96) in one ensemble: the fused pass
+    runs one launch per (c, length) group; every member equals its
+    single-basin run bit for bit over graph replays and follows the oracle."""
+    from paper_1308_3290_amd.api import Ensemble, config_from_case
+    sizes = [(128, 256, 0), (128, 256, 1), (256, 512, 2), (512, 256, 3), (256, 512, 3),
+             (96, 192, 1)]
+    cases = [ci.make_case(nx, ny, level=lv, inv_re=1.0 / (300 + 60 * k), dt=1e-4)
+             for k, (nx, ny, lv) in enumerate(sizes)]
+    say("ensemble of levels 0, 1, 2, 3: 5 steps, graph replays")
+    rng = np.random.default_rng(55)
+    w0s = [ci.initial_field(c, rng, 1e-2) for c in cases]
+    Fs = [ci.forcing_field(c) for c in cases]
+    ens = Ensemble([config_from_case(c) for c in cases])
+    W = ens.pack(w0s)
+    Fp = ens.pack(Fs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ens.step(W, Fp, nsteps=3, use_graph=True)
+        ens.step(W, Fp, nsteps=2, use_graph=True)
+    torch.cuda.synchronize()
+    for m, c in enumerate(cases):
+        b = _basin(c)
+        ws = to_dev(w0s[m])
+        b.step(ws, to_dev(Fs[m]), nsteps=5)
+        got = ens.member_view(W, m)
+        assert torch.equal(got, ws), f"member {m} differs from its single-basin run"
+        g, phys = oracle_setup(c)
+        w_or = w0s[m]
+        for _ in range(5):
+            w_or = om.step(w_or, Fs[m], g, c.level, phys, c.dt)
+        err = rel_l2(to_np(got), w_or)
+        say(f"  member {m} {c.nx}x{c.ny} level {c.level}: rel L2 vs oracle {err:.3e}")
+        assert err < TOL64
+
+
 # ----------------------------------------------------------------- adjoint
 def test_adjoint_segment_matches_oracle():
     case = ci.make_case(32, 64, level=1, dt=2.5e-4)
