@@ -52,6 +52,14 @@ def test_workspace_size_is_positive_and_grows():
     assert a % 256 == 0
 
 
+def test_workspace_shrinks_with_the_coarsening_level():
+    """512 x 1024 at levels 0-3 (c = 1 .. 8, all fused-kernel sizes): the fine
+    stage buffers stay, the coarse spectra and transform tables shrink."""
+    from paper_1308_3290_amd.api import cgp_workspace_size
+    sizes = [cgp_workspace_size(_cfg(nx=512, ny=1024, level=lv)) for lv in range(4)]
+    assert all(a > b > 0 for a, b in zip(sizes, sizes[1:]))
+
+
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=65), 1),                  # not divisible by 2^level
     (dict(nlayers=3), 1),
