@@ -146,11 +146,13 @@ def test_c0_physics_100_steps_fp32(level):
 # not a multiple of the 4 a fused block owns at c = 1 (unfused); (24, 12, 0)
 # and (16, 12, 1): the smallest fused grids (3 blocks).  c = 8: (256, 512, 3)
 # the fused pass with a runtime transform length (64 points), (512, 256, 3)
-# with the compile-time 128-point one, (1024, 64, 3) the unfused passes.
+# with the compile-time 128-point one, (1024, 64, 3) the unfused passes;
+# (256, 512, 4): c = 16 (16 x 32 coarse grid), the unfused passes.
 @pytest.mark.parametrize("nx,ny,level", [(96, 192, 1), (48, 96, 0), (192, 96, 2),
                                          (512, 32, 0), (1024, 64, 1), (1024, 48, 0),
                                          (8, 6, 0), (24, 12, 0), (16, 12, 1), (256, 512, 3),
-                                         (512, 256, 3), (1024, 64, 3), (64, 768, 0)])
+                                         (512, 256, 3), (1024, 64, 3), (256, 512, 4),
+                                         (64, 768, 0)])
 def test_ragged_and_radix3_trajectories(nx, ny, level):
     case = ci.make_case(nx, ny, level=level, dt=1e-4)
     say(f"{nx}x{ny} level {level}, 30 steps FP64")
