@@ -114,7 +114,7 @@ def test_c0_full_grid_100_steps_fp64():
     assert np.all(w[[0, -1], :] == 0) and np.all(w[:, [0, -1]] == 0)
 
 
-@pytest.mark.parametrize("level", [1, 2])
+@pytest.mark.parametrize("level", [1, 2, 3])
 def test_c0_physics_cgp_100_steps_fp64(level):
     case = ci.case_c0()
     case.level = level
@@ -127,7 +127,7 @@ def test_c0_physics_cgp_100_steps_fp64(level):
     assert errs.max() < TOL64
 
 
-@pytest.mark.parametrize("level", [0, 1, 2])
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
 def test_c0_physics_100_steps_fp32(level):
     case = ci.case_c0()
     case.level = level
@@ -136,6 +136,18 @@ def test_c0_physics_100_steps_fp32(level):
     w0 = ci.initial_field(case, rng)
     F = ci.forcing_field(case)
     errs, _, _ = _trajectory_errors(case, w0, F, case.nsteps, dtype="f32")
+    say(f"  max per-step rel L2 = {errs.max():.3e}")
+    assert errs.max() < TOL32
+
+
+def test_fused_c8_fp32():
+    """The FP32 fused stage kernel at c = 8 with its compile-time 128-point
+    transform (512 x 256, a 64 x 32 solve), 30 steps against the FP64 oracle."""
+    case = ci.make_case(512, 256, level=3, dt=1e-4, dtype="f32")
+    say("512x256 level 3, 30 steps FP32")
+    w0 = random_state(case, 7, 1e-3)
+    F = ci.forcing_field(case)
+    errs, _, _ = _trajectory_errors(case, w0, F, 30, dtype="f32")
     say(f"  max per-step rel L2 = {errs.max():.3e}")
     assert errs.max() < TOL32
 
