@@ -142,6 +142,8 @@ def source_hash():
     for f in ("stencil_kernels.hip", "solve_kernels.hip", "fused_kernels.hip", "fft_lds.hpp",
               "stencil.hpp", "cgp_internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1308_3290_amd", "csrc", f), "rb").read())
+    # the compile flags are part of the kernels too
+    h.update(open(os.path.join(ROOT, "paper_1308_3290_amd", "build.py"), "rb").read())
     return h.hexdigest()[:16]
 
 
