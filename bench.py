@@ -1,16 +1,20 @@
 """Throughput of the CGP QG time step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extras]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--repeats R] [--no-cpu] [--extras]
 
 Workload (the value): single-layer barotropic QG, 512 x 1024 fine grid, FP64,
 CGP factor 2 (256 x 512 coarse solve), Re 450, Ro 0.0036, dt 2.5e-5, seeded
 omega0 = 1e-3 N(0,1), forcing (1/Ro) sin(pi y).  Metric: fine-grid
-Mpoint-steps/s = 512 * 1024 * K / seconds over K timed steps (hipGraph replay
-of one step, inputs resident in HBM).  Beside it: the same basin with the
-full-grid solve (factor 1) and factor 4, the CGP/full-grid speed-up, the
-adjoint/forward time ratio of the 256 x 512, 200-step checkpointed adjoint,
-per-pass launch times (HIP events on the library's stream), the roofline of
-the dominant kernel and the FP64 oracle timed on the host CPU.
+Mpoint-steps/s = 512 * 1024 * K / seconds over K timed steps (inputs resident
+in HBM), the median of R timed runs of each launch mode (captured-graph
+replays and direct launches), the faster mode's median reported.  Beside it:
+the same basin with the full-grid solve (factor 1) and factor 4, the
+CGP/full-grid speed-up, the two-layer workload at factors 1, 2, 4, the
+64-member ensemble (FP64 and FP32, 200 steps) and a batch of 16 identical
+512 x 1024 basins, the adjoint/forward time ratio of the 256 x 512, 200-step
+checkpointed adjoint, per-kernel times inside time steps (HIP events around
+each launch on the library's stream), the roofline of the dominant kernel and
+of the whole step, and the FP64 oracle timed on the host CPU.
 
 Prints ONE JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
 """
@@ -41,10 +45,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs per launch mode and workload (the median is reported)")
     ap.add_argument("--extras", action="store_true",
-                    help="also time two layers, FP32 and the 64-member ensemble")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--only", default="", help="comma list: l0,l1,l2,timed (profiling runs)")
+                    help="also time FP32 single basins, level 3, multigrid and adaptive steps")
+    ap.add_argument("--only", default="",
+                    help="comma list of sections (profiling runs): l0,l1,l2,timed,adj,c2,ens,"
+                         "batch,cpu; with --extras also fp32,l3,mg,adaptive")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration runs)")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
@@ -53,9 +60,13 @@ def parse():
     ap.add_argument("--trace-tail", type=int, default=0, metavar="N",
                     help="with --summarize-trace: statistics over each kernel's last N launches "
                          "(the cgp_time_passes launches that end a --only timed run)")
+    ap.add_argument("--trace-json", metavar="PATH",
+                    help="with --summarize-trace: also write the per-kernel means (with the "
+                         "kernel source hash) as JSON to PATH")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) into "
-                         "profiles/traffic_c1_l1.json and exit (no GPU needed)")
+                         "per-kernel HBM bytes (default profiles/traffic_c1_l1.json) and exit")
+    ap.add_argument("--pmc-out", metavar="PATH", help="with --summarize-pmc: output path")
     return ap.parse_args()
 
 
@@ -104,9 +115,10 @@ def summarize_pmc(fetch_csv, write_csv, out_path=None):
     print(json.dumps(out, indent=1))
 
 
-def summarize_trace(trace_csv, tail=0):
+def summarize_trace(trace_csv, tail=0, json_out=None):
     """Launch count and duration statistics (us) per kernel of a kernel trace
-    (tail > 0: over each kernel's last `tail` launches in start order)."""
+    (tail > 0: over each kernel's last `tail` launches in start order);
+    json_out: also the means, keyed by kernel, with the kernel source hash."""
     import csv
     import statistics
     per = {}
@@ -122,6 +134,11 @@ def summarize_trace(trace_csv, tail=0):
     for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
         print(f"| {name} | {len(d)} | {statistics.mean(d):.2f} | {statistics.median(d):.2f} | "
               f"{min(d):.2f} | {max(d):.2f} |")
+    if json_out:
+        doc = {"source_hash": source_hash(), "trace": os.path.basename(trace_csv), "tail": tail,
+               "kernels": {k: {"launches": len(d), "mean_us": statistics.mean(d),
+                               "median_us": statistics.median(d)} for k, d in per.items()}}
+        json.dump(doc, open(json_out, "w"), indent=1)
 
 
 def pass_bytes(case, es):
@@ -138,22 +155,66 @@ def pass_bytes(case, es):
 
 
 def source_hash():
+    """Hash of every kernel and runtime source and the build flags: profile
+    figures taken with other sources are not used."""
     h = hashlib.sha256()
-    for f in ("stencil_kernels.hip", "solve_kernels.hip", "fused_kernels.hip", "fft_lds.hpp",
-              "stencil.hpp", "cgp_internal.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_1308_3290_amd", "csrc", f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_1308_3290_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
     # the compile flags are part of the kernels too
     h.update(open(os.path.join(ROOT, "paper_1308_3290_amd", "build.py"), "rb").read())
     return h.hexdigest()[:16]
 
 
+def step_bytes(case, es):
+    """Algorithmic bytes of one fused time step (three stages): per stage the
+    fused pass reads the psi spectra S, the stage input, the forcing and (in
+    stages 2 and 3) omega_n, writes the stage output and the next spectra S;
+    pass B reads and writes S.  Over a step: 11 F + 12 S (F a fine field)."""
+    fine = (case.nx + 1) * (case.ny + 1) * case.nlayers * es
+    c = 2 ** case.level
+    coarse = (case.nx // c - 1) * (case.ny // c - 1) * case.nlayers * es
+    return {"fine": fine, "coarse": coarse, "step": 11 * fine + 12 * coarse,
+            "fused_avg": (11 * fine + 6 * coarse) / 3.0, "B": 2 * coarse}
+
+
+def model_bytes(c, es):
+    """Bytes per fine point-step of the four-pass model, e (20 + 12/c^2)."""
+    return es * (20 + 12 / (c * c))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_share():
+    """Cores this process may use, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def median(xs):
+    import statistics
+    return statistics.median(xs)
+
+
 def main():
     args = parse()
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.trace_tail)
+        summarize_trace(args.summarize_trace, args.trace_tail, args.trace_json)
         return
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc)
+        summarize_pmc(*args.summarize_pmc, out_path=args.pmc_out)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
@@ -168,37 +229,62 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     only = set(filter(None, args.only.split(",")))
-    K, W = args.steps, args.warmup
+    want = (lambda k: not only or k in only)
+    K, W, R = args.steps, args.warmup, max(1, args.repeats)
 
-    def timed_run(case, use_graph=True, steps=K, warm=W, dtype="f64"):
-        tdt = torch.float64 if dtype == "f64" else torch.float32
-        rng = np.random.default_rng(case.seed)
-        w0 = ci.initial_field(case, rng)
-        F = torch.as_tensor(ci.forcing_field(case), dtype=tdt, device=dev)
-        ens = api.Ensemble([api.config_from_case(case, dtype)], device=dev)
-        w = torch.as_tensor(w0, dtype=tdt, device=dev).reshape(-1).contiguous()
-        Fp = F.reshape(-1).contiguous()
-        if case.nlayers == 2:
-            Fp = torch.cat([Fp, torch.zeros_like(Fp)])  # layer-2 forcing slot unused
-            Fp = Fp[: w.numel()].contiguous()
-        # a non-default stream (graphs cannot be captured on the default one);
-        # the events are recorded on it
+    def timed_runs(cfgs, w0s, Fs, steps, warm, use_graph, reps):
+        """reps timed runs of `steps` steps of an ensemble (one member: a single
+        basin) on a non-default stream (graphs cannot be captured on the
+        default one), HIP events recorded on that stream; ms per run."""
+        ens = api.Ensemble(cfgs, device=dev)
+        w = ens.pack(w0s)
+        Fp = ens.pack(Fs)
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             ens.step(w, Fp, nsteps=warm, use_graph=use_graph)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(s):
-            e0.record(s)
-            ens.step(w, Fp, nsteps=steps, use_graph=use_graph)
-            e1.record(s)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
+        out = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(s):
+                e0.record(s)
+                ens.step(w, Fp, nsteps=steps, use_graph=use_graph)
+                e1.record(s)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
         finite = bool(torch.isfinite(w).all().item())
-        return ms, finite, ens, w, Fp
+        del ens, w, Fp
+        return out, finite
 
-    result = {}
+    def basin_inputs(case):
+        rng = np.random.default_rng(case.seed)
+        w0 = ci.initial_field(case, rng)
+        F = ci.forcing_field(case)
+        if case.nlayers == 2:  # packed fields hold both layers (layer-2 forcing unused)
+            F = np.stack([F, np.zeros_like(F)])
+        return w0, F
+
+    def rate_both_modes(case, steps, warm, label, dtype="f64"):
+        """Median rate of each launch mode; the faster mode's median wins."""
+        w0, F = basin_inputs(case)
+        cfg = api.config_from_case(case, dtype)
+        by_mode = {}
+        for mode in ("graph", "direct"):
+            ms, finite = timed_runs([cfg], [w0], [F], steps, warm, mode == "graph", R)
+            rates = [case.points * steps / (m * 1e-3) / 1e6 for m in ms]
+            by_mode[mode] = dict(ms=median(ms), rate=median(rates), finite=finite, launch=mode,
+                                 runs=[round(r, 1) for r in rates])
+            log(f"{label} ({mode}): {median(ms) / steps * 1e3:.1f} us/step, median "
+                f"{median(rates):.0f} Mpoint-steps/s over {R} runs {by_mode[mode]['runs']} "
+                f"(finite={finite})")
+        best = dict(max(by_mode.values(), key=lambda r: r["rate"]))
+        best["modes"] = {m: round(r["rate"], 1) for m, r in by_mode.items()}
+        best["runs_by_mode"] = {m: r["runs"] for m, r in by_mode.items()}
+        return best
+
+    out = {}
     if args.copy_calibration:
         a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -209,60 +295,49 @@ def main():
     # ---------------------------------------------------------------- main line
     rates = {}
     for lv in (1, 0, 2):
-        if only and f"l{lv}" not in only:
-            continue
-        case = ci.case_c1(lv)
-        # the same K steps as captured-graph replays and as direct launches;
-        # the faster of the two is the level's rate (both are library modes)
-        by_mode = {}
-        for mode in ("graph", "direct"):
-            ms, finite, ens, w, Fp = timed_run(case, use_graph=mode == "graph")
-            by_mode[mode] = dict(ms=ms, rate=case.points * K / (ms * 1e-3) / 1e6, finite=finite,
-                                 launch=mode)
-            log(f"512x1024 FP64 level {lv} ({mode}): {ms / K * 1e3:.1f} us/step, "
-                f"{by_mode[mode]['rate']:.0f} Mpoint-steps/s (finite={finite})")
-            del ens, w, Fp
-        rates[lv] = max(by_mode.values(), key=lambda r: r["rate"])
-        rates[lv]["modes"] = {m: round(r["rate"], 1) for m, r in by_mode.items()}
-    # ---------------------------------------------------------------- per-pass roofline
+        if want(f"l{lv}"):
+            rates[lv] = rate_both_modes(ci.case_c1(lv), K, W, f"512x1024 FP64 level {lv}")
+    # ---------------------------------------------------------------- kernels in the step
     roof = None
-    if not only or "timed" in only:
+    passes = None
+    if want("timed"):
         case = ci.case_c1(1)
-        rng = np.random.default_rng(case.seed)
+        w0, F0 = basin_inputs(case)
         b = api.Basin(api.config_from_case(case), device=dev)
-        w = torch.as_tensor(ci.initial_field(case, rng), device=dev)
-        F = torch.as_tensor(ci.forcing_field(case), device=dev)
+        w = torch.as_tensor(w0, device=dev)
+        F = torch.as_tensor(F0, device=dev)
         b.step(w, F, nsteps=2)  # fills psi, the stage buffers and the spectra
+        # back-to-back launches of each pass alone (hot inputs)
         api.cgp_time_passes(b.handle, w, F, 10)
         ms = api.cgp_time_passes(b.handle, w, F, 200)
         by = pass_bytes(case, 8)
         names = ["A", "B", "C", "D", "CD", "CDA"]
-        if ms[4] <= 0:
-            names = names[:4]
-        # passes a time step launches: B and the fused pass (C, D and the next
-        # stage's A) per stage, A once per call; else A, B, C, D per stage
-        in_step = ["B", "CDA"] if "CDA" in names else ["A", "B", "C", "D"]
-        dom = max(in_step, key=lambda n: ms[names.index(n)])
-        i = names.index(dom)
-        achieved = by[dom] / (ms[i] * 1e-3) / 1e9
         kernel_names = {"A": "k_restrict_rowdst", "B": "k_col_solve", "C": "k_rowdst_prolong",
                         "D": "k_stencil_rk3", "CD": "k_prolong_stencil<NEXT=false>",
                         "CDA": "k_prolong_stencil<NEXT=true>"}
-        passes = {kernel_names[n]: {"us_per_launch": ms[j] * 1e3,
-                                    "alg_bytes_per_launch": by[n],
-                                    "achieved_GBs": by[n] / (ms[j] * 1e-3) / 1e9,
-                                    "in_time_step": n in in_step}
-                  for j, n in enumerate(names)}
-        log("per-pass: " + json.dumps(passes))
-        traffic = None
-        tfile = os.path.join(ROOT, "profiles", "traffic_c1_l1.json")
-        if os.path.exists(tfile):
-            t = json.load(open(tfile))
-            # counters are taken on a time-stepping run: the fused kernel there
-            # is always the NEXT=true form
-            base = kernel_names[dom].split("<")[0]
-            if t.get("source_hash") == source_hash() and base in t.get("kernels", {}):
-                traffic = t["kernels"][base]["hbm_bytes_per_launch"]
+        passes = {kernel_names[n]: {"us_back_to_back": round(ms[j] * 1e3, 3),
+                                    "alg_bytes_per_launch": by[n]}
+                  for j, n in enumerate(names) if ms[j] > 0}
+        # diagnostics (E and Z, eq. 26): outside the time step, timed on
+        # their own over the same fields; they read psi and omega once
+        psi = b.solve(w)
+        ez = torch.empty(2, dtype=torch.float64, device=dev)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(5):
+                api.cgp_diagnostics(b.handle, w, psi, ez, s)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(200):
+                api.cgp_diagnostics(b.handle, w, psi, ez, s)
+            e1.record(s)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 200
+        dbytes = 2 * w.numel() * 8
+        out["diagnostics"] = {"us_per_call": round(us, 2), "alg_bytes_per_call": dbytes,
+                              "achieved_GBs": round(dbytes / (us * 1e-6) / 1e9, 1)}
+        log(f"diagnostics: {us:.1f} us per call ({dbytes / (us * 1e-6) / 1e9:.0f} GB/s)")
         # achievable HBM bandwidth: 1 GiB read + 1 GiB written by a device
         # copy and by an elementwise kernel, the better of the two
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -280,36 +355,104 @@ def main():
             best = max(best, 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
         del src, dst
         log(f"achievable HBM bandwidth (1 GiB copy): {best:.0f} GB/s")
-        roof = {"bound": "hbm", "kernel": kernel_names[dom], "achieved": round(achieved, 1),
+        # the kernels inside time steps: HIP events on the library's stream
+        # around every pass B and fused launch of IN_STEP steps (the last
+        # launches of this section, so that a kernel trace's last 3 * IN_STEP
+        # launches of each kernel are these)
+        IN_STEP = 100
+        api.cgp_time_step_passes(b.handle, w, F, 10)
+        mb, mf, mstep = api.cgp_time_step_passes(b.handle, w, F, IN_STEP)
+        sb = step_bytes(case, 8)
+        passes["k_col_solve"].update(us_in_step=round(mb * 1e3, 3), alg_bytes_in_step=sb["B"])
+        passes["k_prolong_stencil<NEXT=true>"].update(us_in_step=round(mf * 1e3, 3),
+                                                      alg_bytes_in_step=sb["fused_avg"])
+        for k, v in passes.items():
+            t = v.get("us_in_step", v["us_back_to_back"])
+            nb = v.get("alg_bytes_in_step", v["alg_bytes_per_launch"])
+            v["achieved_GBs"] = round(nb / (t * 1e-6) / 1e9, 1)
+            v["in_time_step"] = "us_in_step" in v
+        log("per-pass: " + json.dumps(passes))
+        dom, t_dom, b_dom = max((("k_prolong_stencil<NEXT=true>", mf, sb["fused_avg"]),
+                                 ("k_col_solve", mb, sb["B"])), key=lambda x: x[1])
+        achieved = b_dom / (t_dom * 1e-3) / 1e9
+        traffic = None
+        tfile = os.path.join(ROOT, "profiles", "traffic_c1_l1.json")
+        if os.path.exists(tfile):
+            t = json.load(open(tfile))
+            base = dom.split("<")[0]
+            if t.get("source_hash") == source_hash() and base in t.get("kernels", {}):
+                traffic = t["kernels"][base]["hbm_bytes_per_launch"]
+        prof_us = None
+        pfile = os.path.join(ROOT, "profiles", "trace_c1_l1.json")
+        if os.path.exists(pfile):
+            t = json.load(open(pfile))
+            if t.get("source_hash") == source_hash():
+                for k, v in t.get("kernels", {}).items():
+                    if k.startswith(dom.split("<")[0]) and k.endswith("true>"
+                                                                      if "NEXT" in dom else ">"):
+                        prof_us = round(v["mean_us"], 3)
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": traffic, "alg_bytes_per_launch": by[dom],
-                "us_per_launch": round(ms[i] * 1e3, 2),
+                "traffic": traffic, "alg_bytes_per_launch": round(b_dom),
+                "us_per_launch": round(t_dom * 1e3, 3),
+                "timing": f"HIP events around each launch inside {IN_STEP} time steps "
+                          "(mean over the three stages' launches)",
+                "profile_us_per_launch": prof_us,
+                "frac_from_profile": round(b_dom / (prof_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
+                if prof_us else None,
                 "achievable_copy": round(best, 1), "frac_of_achievable": round(achieved / best, 4)}
-        result["passes"] = passes
-        # diagnostics (E and Z per layer, eq. 26): outside the time step, timed
-        # on their own over the same fields; they read psi and omega once
-        psi = b.solve(w)
-        ez = torch.empty(2, dtype=torch.float64, device=dev)
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            for _ in range(5):
-                api.cgp_diagnostics(b.handle, w, psi, ez, s)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(s)
-            for _ in range(200):
-                api.cgp_diagnostics(b.handle, w, psi, ez, s)
-            e1.record(s)
-        torch.cuda.synchronize()
-        us = e0.elapsed_time(e1) * 1e3 / 200
-        dbytes = 2 * w.numel() * 8
-        result["diagnostics"] = {"us_per_call": round(us, 2), "alg_bytes_per_call": dbytes,
-                                 "achieved_GBs": round(dbytes / (us * 1e-6) / 1e9, 1)}
-        log(f"diagnostics: {us:.1f} us per call ({dbytes / (us * 1e-6) / 1e9:.0f} GB/s)")
+        out["in_step_ms_per_step_with_events"] = round(mstep, 6)
         del b, w, F, psi
+    # ---------------------------------------------------------------- two layers
+    two = {}
+    if want("c2"):
+        for lv in (1, 0, 2):
+            case = ci.case_c2(lv)
+            n = min(K, case.nsteps) if K >= 100 else 100
+            r = rate_both_modes(case, n, W, f"two-layer 512x1024 FP64 level {lv}")
+            two[f"l{lv}"] = {"value": round(r["rate"], 1), "launch": r["launch"],
+                             "modes": r["modes"], "us_per_step": round(r["ms"] / n * 1e3, 2),
+                             "steps": n,
+                             "frac_step_alg": round(step_bytes(case, 8)["step"] / (r["ms"] / n * 1e-3)
+                                                    / 1e9 / PEAK_HBM_GBS, 4)}
+    # ---------------------------------------------------------------- ensembles
+    ens_out = {}
+    if want("ens"):
+        n_ens = 200
+        for dt_ in ("f64", "f32"):
+            members = ci.ensemble_c3(dtype=dt_)
+            cfgs = [api.config_from_case(m.case) for m in members]
+            ms, finite = timed_runs(cfgs, [m.omega0 for m in members],
+                                    [m.forcing for m in members], n_ens, 5, True, max(3, R // 2))
+            pts = sum(m.case.points for m in members)
+            es = 8 if dt_ == "f64" else 4
+            alg = sum(step_bytes(m.case, es)["step"] for m in members)
+            t = median(ms) * 1e-3 / n_ens
+            ens_out[dt_] = {"value": round(pts / t / 1e6, 1), "unit": "Mpoint-steps/s",
+                            "members": len(members), "points": pts, "steps": n_ens,
+                            "runs": [round(pts * n_ens / (m * 1e-3) / 1e6, 1) for m in ms],
+                            "alg_bytes_per_step": alg, "GBs_alg": round(alg / t / 1e9, 1),
+                            "frac_alg": round(alg / t / 1e9 / PEAK_HBM_GBS, 4),
+                            "GBs_model": round(pts * model_bytes(2, es) / t / 1e9, 1),
+                            "finite": finite, "launch": "hipGraph replays, member chains forked"}
+            log(f"ensemble 64 {dt_}: {ens_out[dt_]}")
+    batch = None
+    if want("batch"):
+        # the 512 x 1024 level-1 kernel set as a batch of 16 identical basins
+        case = ci.case_c1(1)
+        w0, F = basin_inputs(case)
+        cfgs = [api.config_from_case(case)] * 16
+        n_b = 100
+        ms, finite = timed_runs(cfgs, [w0] * 16, [F] * 16, n_b, 5, True, 3)
+        t = median(ms) * 1e-3 / n_b
+        sb = step_bytes(case, 8)["step"] * 16
+        batch = {"value": round(16 * case.points / t / 1e6, 1), "unit": "Mpoint-steps/s",
+                 "basins": 16, "steps": n_b, "GBs_alg": round(sb / t / 1e9, 1),
+                 "frac_alg": round(sb / t / 1e9 / PEAK_HBM_GBS, 4), "finite": finite}
+        log(f"batch of 16 x 512x1024 level 1: {batch}")
     # ---------------------------------------------------------------- adjoint ratio
     adj = None
-    if not args.no_adjoint and (not only or "adj" in only):
+    if not args.no_adjoint and want("adj"):
         p = ci.adjoint_c4()
         c = p.case
         b = api.Basin(api.config_from_case(c), device=dev)
@@ -317,7 +460,8 @@ def main():
         F = torch.as_tensor(p.forcing, device=dev).requires_grad_(True)
         idx = torch.as_tensor(p.obs_index, device=dev)
         obs = torch.as_tensor(p.obs_value, device=dev)
-        for rep in range(2):  # first pass warms up
+        fw, bw = [], []
+        for rep in range(1 + max(3, R // 2)):  # the first pass warms up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             wT = api.Trajectory.apply(w0, F, b, c.nsteps, p.ckpt_every)
@@ -331,103 +475,104 @@ def main():
             L.backward()
             torch.cuda.synchronize()
             t3 = time.perf_counter()
-        adj = {"forward_ms": (t1 - t0) * 1e3, "backward_ms": (t3 - t2) * 1e3,
-               "ratio": (t3 - t2) / (t1 - t0), "workload": "256x512 FP64 CGP factor 2, "
-               "200 steps, checkpoint every 20, final-time misfit at 1% of nodes"}
+            if rep:
+                fw.append((t1 - t0) * 1e3)
+                bw.append((t3 - t2) * 1e3)
+        adj = {"forward_ms": round(median(fw), 3), "backward_ms": round(median(bw), 3),
+               "ratio": round(median(bw) / median(fw), 3),
+               "ratios": [round(y / x, 3) for x, y in zip(fw, bw)],
+               "workload": "256x512 FP64 CGP factor 2, 200 steps, checkpoint every 20, "
+                           "final-time misfit at 1% of nodes"}
         log(f"adjoint: forward {adj['forward_ms']:.1f} ms, backward {adj['backward_ms']:.1f} ms, "
             f"ratio {adj['ratio']:.2f}")
         del b, w0, F
     # ---------------------------------------------------------------- extras
     extras = {}
     if args.extras:
-        # --only may pick extras too: two_layer, l3, mg, adaptive, fp32, ens
-        want = (lambda k: not only or k in only)
-        for lv in (1, 0, 2):
-            if not want("two_layer"):
-                break
-            case = ci.case_c2(lv)
-            ms, finite, *_ = timed_run(case, steps=min(K, 500))
-            extras[f"two_layer_l{lv}"] = case.points * min(K, 500) / (ms * 1e-3) / 1e6
+        def rate(case, steps, warm=W, dtype="f64"):
+            w0, F = basin_inputs(case)
+            ms, _ = timed_runs([api.config_from_case(case, dtype)], [w0], [F], steps, warm, True,
+                               3)
+            return case.points * steps / (median(ms) * 1e-3) / 1e6
         if want("l3"):  # three levels of coarsening (64x128 solve)
-            case = ci.case_c1(3)
-            ms, finite, *_ = timed_run(case, steps=min(K, 500))
-            extras["cgp8_l3"] = case.points * min(K, 500) / (ms * 1e-3) / 1e6
+            extras["cgp8_l3"] = rate(ci.case_c1(3), min(K, 500))
         if want("mg"):  # the multigrid coarse solver (12 V-cycles) at levels 0, 1, 2
             for lv in (0, 1, 2):
                 case = ci.case_c1(lv)
                 case.solver = 1
-                ms, finite, *_ = timed_run(case, steps=20, warm=2)
-                extras[f"multigrid_l{lv}"] = case.points * 20 / (ms * 1e-3) / 1e6
+                extras[f"multigrid_l{lv}"] = rate(case, 20, 2)
         if want("adaptive"):  # the step size of Sec. 4.2 (CFL 0.5, capped at dt)
             case = ci.case_c1(1)
             case.cfl = 0.5
-            ms, finite, *_ = timed_run(case)
-            extras["adaptive_l1"] = case.points * K / (ms * 1e-3) / 1e6
+            extras["adaptive_l1"] = rate(case, K)
         for lv in (1, 0):
-            if not want("fp32"):
-                break
-            case = ci.case_c1(lv)
-            ms, finite, *_ = timed_run(case, dtype="f32")
-            extras[f"fp32_l{lv}"] = case.points * K / (ms * 1e-3) / 1e6
-        for dt_ in ("f64", "f32"):
-            if not want("ens"):
-                break
-            members = ci.ensemble_c3(dtype=dt_)
-            tdt = torch.float64 if dt_ == "f64" else torch.float32
-            ens = api.Ensemble([api.config_from_case(m.case) for m in members], device=dev)
-            Wp = ens.pack([m.omega0 for m in members])
-            Fp = ens.pack([m.forcing for m in members])
-            s = torch.cuda.Stream()  # graphs are captured on a non-default stream
-            s.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(s):
-                ens.step(Wp, Fp, nsteps=5)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            n_ens = 200
-            with torch.cuda.stream(s):
-                e0.record(s)
-                ens.step(Wp, Fp, nsteps=n_ens)
-                e1.record(s)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            pts = sum(m.case.points for m in members)
-            es = 8 if dt_ == "f64" else 4
-            extras[f"ensemble64_{dt_}"] = pts * n_ens / (ms * 1e-3) / 1e6
-            # bytes per point-step: the unfused model e (20 + 12/c^2) and the
-            # fused path's algorithmic 12 e (1 + 1/c^2), c = 2
-            extras[f"ensemble64_{dt_}_GBs_model"] = (pts * n_ens * (20 + 12 / 4) * es
-                                                     / (ms * 1e-3) / 1e9)
-            extras[f"ensemble64_{dt_}_GBs_alg"] = (pts * n_ens * 12 * (1 + 1 / 4) * es
-                                                   / (ms * 1e-3) / 1e9)
-            assert tdt == Wp.dtype
-            del ens, Wp, Fp
+            if want("fp32"):
+                extras[f"fp32_l{lv}"] = rate(ci.case_c1(lv), K, dtype="f32")
         log("extras: " + json.dumps(extras))
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
-    if not args.no_cpu and not only:
+    if not args.no_cpu and want("cpu"):
+        import scipy.fft
+
         from oracle import model as om
         from oracle.grid import Grid
         from oracle.model import Physics
-        case = ci.case_c1(1)
-        rng = np.random.default_rng(case.seed)
-        w = ci.initial_field(case, rng)
-        F = ci.forcing_field(case)
-        g = Grid(case.nx, case.ny)
-        phys = Physics(inv_re=case.inv_re, inv_ro=case.inv_ro)
-        n = 0
-        t0 = time.perf_counter()
-        while n < 3 or time.perf_counter() - t0 < args.cpu_seconds:
-            w = om.step(w, F, g, case.level, phys, case.dt)
-            n += 1
-        dt_cpu = time.perf_counter() - t0
-        cpu = {"value": round(case.points * n / dt_cpu / 1e6, 4), "unit": "Mpoint-steps/s",
-               "cores": 1, "kind": "oracle",
-               "sample": f"{n} steps of the 512x1024 FP64 CGP-factor-2 workload "
-                         f"({dt_cpu:.1f} s; NumPy/SciPy single-threaded)"}
-        log(f"cpu oracle: {cpu['value']} Mpoint-steps/s over {n} steps")
+        share = cpu_share()
+        table = {}
+
+        def per_step(case, steps=4, reps=3):
+            w, F = basin_inputs(case)
+            if case.nlayers == 2:
+                F = F[0]
+            g = Grid(case.nx, case.ny)
+            phys = Physics(inv_re=case.inv_re, inv_ro=case.inv_ro, f1=case.f1, f2=case.f2,
+                           drag=case.drag)
+            fn = om.step if case.nlayers == 1 else om.step_two_layer
+            w = fn(w, F, g, case.level, phys, case.dt)  # warm-up
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    w = fn(w, F, g, case.level, phys, case.dt)
+                ts.append((time.perf_counter() - t0) / steps)
+            return median(ts), steps * reps + 1
+        t_all = time.perf_counter()
+        total_steps = 0
+        for workers in (1, share):
+            with scipy.fft.set_workers(workers):
+                for name, case in (("c1_l0", ci.case_c1(0)), ("c1_l1", ci.case_c1(1)),
+                                   ("c1_l2", ci.case_c1(2)), ("c2_l0", ci.case_c2(0)),
+                                   ("c2_l1", ci.case_c2(1)), ("c2_l2", ci.case_c2(2))):
+                    t, n = per_step(case)
+                    total_steps += n
+                    table[f"{name}_workers{workers}"] = round(case.points / t / 1e6, 3)
+            if share == 1:
+                break
+        wall = time.perf_counter() - t_all
+        k1 = f"c1_l1_workers{share}"
+        head_key = max(("c1_l1_workers1", k1), key=lambda k: table[k])
+        cpu = {"value": table[head_key], "unit": "Mpoint-steps/s",
+               "cores": 1 if head_key.endswith("workers1") else share, "kind": "oracle",
+               "sample": f"FP64 oracle steps of the 512x1024 one-layer workload at level 1 "
+                         f"(median of 3 runs of 4 steps after one warm-up step; the table also "
+                         f"holds levels 0 and 2 and the two-layer workload, with scipy.fft "
+                         f"workers = 1 and = {share}; {total_steps} steps, {wall:.1f} s in all)",
+               "table": table, "nproc": os.cpu_count(), "cpu_share": share,
+               "cpu_model": cpu_model()}
+        log(f"cpu oracle: {json.dumps(cpu)}")
 
     main_rate = rates.get(1, {}).get("rate")
-    out = {
+    c1 = ci.case_c1(1)
+    step_roof = None
+    if 1 in rates:
+        t = rates[1]["ms"] * 1e-3 / K
+        sb = step_bytes(c1, 8)["step"]
+        step_roof = {"alg_bytes_per_step": sb, "GBs_alg": round(sb / t / 1e9, 1),
+                     "frac_alg": round(sb / t / 1e9 / PEAK_HBM_GBS, 4),
+                     "model_bytes_per_point_step": model_bytes(2, 8),
+                     "frac_model": round(c1.points * model_bytes(2, 8) / t / 1e9 / PEAK_HBM_GBS,
+                                         4)}
+    res = {
         "metric": METRIC,
         "value": round(main_rate, 1) if main_rate else None,
         "unit": "Mpoint-steps/s",
@@ -440,7 +585,8 @@ def main():
                                "dt 2.5e-5, seeded omega0", "global_batch": 1, "seq_len": None,
                    "parallelism": "single GPU",
                    "launch": ("hipGraph replays of a 3-step rotation" if rates[1]["launch"] == "graph"
-                              else "direct launches") if 1 in rates else None},
+                              else "direct launches") if 1 in rates else None,
+                   "repeats": R, "statistic": "median of the repeats, faster launch mode"},
         "full_grid_value": round(rates[0]["rate"], 1) if 0 in rates else None,
         "cgp4_value": round(rates[2]["rate"], 1) if 2 in rates else None,
         "speedup_cgp2_vs_full": round(rates[1]["rate"] / rates[0]["rate"], 3)
@@ -448,19 +594,23 @@ def main():
         "speedup_cgp4_vs_full": round(rates[2]["rate"] / rates[0]["rate"], 3)
         if 0 in rates and 2 in rates else None,
         "launch_modes": rates[1]["modes"] if 1 in rates else None,
+        "runs": rates[1]["runs_by_mode"] if 1 in rates else None,
         "all_finite": all(v["finite"] for v in rates.values()),
-        "adjoint_forward_ratio": round(adj["ratio"], 3) if adj else None,
+        "step_roofline": step_roof,
+        "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": adj,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "two_layer": two or None,
+        "ensemble64": ens_out or None,
+        "batch16_c1_l1": batch,
     }
     if extras:
-        out["extras"] = {k: round(v, 1) for k, v in extras.items()}
-    if "passes" in result:
-        out["passes"] = result["passes"]
-    if "diagnostics" in result:
-        out["diagnostics"] = result["diagnostics"]
-    print(json.dumps(out), flush=True)
+        res["extras"] = {k: round(v, 1) for k, v in extras.items()}
+    if passes:
+        res["passes"] = passes
+    res.update(out)
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -229,6 +229,18 @@ cgp_status cgp_ensemble_step(cgp_handle* h, void* omega_packed_dev,
 cgp_status cgp_time_passes(cgp_handle* h, const void* omega_dev, const void* forcing_dev,
                            int32_t reps, double* ms_host, void* stream);
 
+/* Measurement in the context of a time step.  Advances omega_dev by nsteps
+ * (1..4096) steps with direct launches, exactly as cgp_step does (pass A of
+ * the initial state, then per stage pass B and the fused stage pass with the
+ * next stage's restriction and x transform), with a HIP event recorded on
+ * `stream` before and after each of those launches.  ms_host (3 doubles,
+ * host memory) receives the mean milliseconds per launch of pass B, the mean
+ * per launch of the fused pass, and the mean milliseconds per step of the
+ * whole run (events included).  Synchronises the stream.  Handles whose
+ * steps do not use the fused pass give CGP_ERR_UNSUPPORTED. */
+cgp_status cgp_time_step_passes(cgp_handle* h, void* omega_dev, const void* forcing_dev,
+                                int32_t nsteps, double* ms_host, void* stream);
+
 /* Message for the calling thread's last failure ("" if none). */
 const char* cgp_last_error(void);
 

@@ -58,6 +58,7 @@ SIGNATURES = {
     "cgp_ensemble_create": (_I32, [_CFG, _I32, _P, _SZ, _P, ctypes.POINTER(_P)]),
     "cgp_ensemble_step": (_I32, [_P, _P, _P, _I32, _I32, _P]),
     "cgp_time_passes": (_I32, [_P, _P, _P, _I32, ctypes.POINTER(ctypes.c_double), _P]),
+    "cgp_time_step_passes": (_I32, [_P, _P, _P, _I32, ctypes.POINTER(ctypes.c_double), _P]),
     "cgp_last_error": (ctypes.c_char_p, []),
     "cgp_version": (ctypes.c_char_p, []),
 }

@@ -166,6 +166,15 @@ def cgp_time_passes(h, omega, forcing, reps, stream=None):
     return list(ms)
 
 
+def cgp_time_step_passes(h, omega, forcing, nsteps, stream=None):
+    """nsteps time steps (direct launches) with HIP events around every pass B
+    and fused-pass launch: mean ms per launch of each and mean ms per step."""
+    ms = (ctypes.c_double * 3)()
+    call("cgp_time_step_passes", h, _ptr(omega), _ptr(forcing), int(nsteps), ms,
+         ctypes.c_void_p(stream_ptr(stream)))
+    return list(ms)
+
+
 def cgp_last_error() -> str:
     return _lib.load().cgp_last_error().decode(errors="replace")
 

@@ -221,6 +221,18 @@ __device__ __forceinline__ int group_member(const MemberDesc* md, const int* grp
   return grp[lo];
 }
 
+// Allow kernel f up to `total` bytes of LDS per workgroup: its dynamic-LDS
+// cap is set to total minus the kernel's own static LDS (the runtime rejects
+// caps whose sum with the static part exceeds the workgroup's LDS).
+inline hipError_t allow_dynamic_lds(const void* f, int total) {
+  hipFuncAttributes a{};
+  hipError_t e = hipFuncGetAttributes(&a, f);
+  if (e != hipSuccess) return e;
+  const int st = (int)a.sharedSizeBytes;
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             total > st ? total - st : 0);
+}
+
 // One launch of a transform pass over a group of members.
 struct Group {
   int L;               // transform length with a compile-time transform, or 0

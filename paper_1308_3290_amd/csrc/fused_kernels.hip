@@ -474,7 +474,7 @@ hipError_t Launch<T>::prepare_fused(size_t bytes) {
 #undef K
   };
   for (const void* f : fns) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    const hipError_t e = allow_dynamic_lds(f, b);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

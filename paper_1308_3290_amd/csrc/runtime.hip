@@ -645,6 +645,23 @@ hipError_t enqueue_pass_reps(cgp_handle* h, int p, const T* omega, const T* forc
   return hipSuccess;
 }
 
+// The dynamic-LDS cap is an attribute of the kernel function, shared by every
+// handle of the process: it is raised once to the whole 160 KiB a workgroup
+// may use (it only bounds what a launch may request), never lowered, so that
+// a handle created later with smaller blocks cannot cap the launches of one
+// created earlier.  Done once per scalar type, under the lock of a static.
+template <typename T>
+hipError_t allow_full_lds() {
+  static const hipError_t once = [] {
+    hipError_t e = Launch<T>::prepare(kMaxLds);
+    if (e == hipSuccess) e = Launch<T>::prepare_fused(kMaxLds);
+    if (e == hipSuccess) e = Launch<T>::prepare_fused2(kMaxLds);
+    if (e == hipSuccess && sizeof(T) == 8) e = AdjLaunch::prepare_fused(kMaxLds);
+    return e;
+  }();
+  return once;
+}
+
 template <typename T>
 cgp_status create_tables(cgp_handle* h, hipStream_t s) {
   const Plan& p = h->plan;
@@ -736,21 +753,7 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
     }
     std::memcpy(h->host_tables.data() + L.mgm, X.data(), X.size() * sizeof(double));
   }
-  size_t lds_max = 0;
-  for (int pass = 0; pass < 3; ++pass)
-    for (const HostGroup& g : p.groups[pass]) lds_max = std::max(lds_max, g.lds);
-  HIP_TRY(Launch<T>::prepare(lds_max), "LDS attribute");
-  if (p.fused) {
-    size_t lds_f = 0;
-    for (const HostGroup& g : p.groups[3]) lds_f = std::max(lds_f, g.lds);
-    if (p.nlayers == 1) {
-      HIP_TRY(Launch<T>::prepare_fused(lds_f), "LDS attribute (fused pass)");
-      if (p.dtype == CGP_F64)
-        HIP_TRY(AdjLaunch::prepare_fused(lds_f), "LDS attribute (adjoint)");
-    } else {
-      HIP_TRY(Launch<T>::prepare_fused2(lds_f), "LDS attribute (fused pass)");
-    }
-  }
+  HIP_TRY(allow_full_lds<T>(), "LDS attribute");
   HIP_TRY(hipMemcpyAsync(h->ws, h->host_tables.data(), L.wt, hipMemcpyHostToDevice, s),
           "table upload");
   // ring of the internal psi / stage buffers: produced fields always write
@@ -1112,6 +1115,89 @@ cgp_status cgp_time_passes(cgp_handle* h, const void* omega, const void* forcing
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  return st;
+}
+
+cgp_status cgp_time_step_passes(cgp_handle* h, void* omega, const void* forcing, int32_t nsteps,
+                                double* ms, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!omega || !forcing || !ms || nsteps < 1 || nsteps > 4096)
+    return fail(CGP_ERR_INVALID, "bad argument (nsteps in 1..4096)");
+  if (!h->plan.fused)
+    return fail(CGP_ERR_UNSUPPORTED, "in-step pass timing needs the fused stage pass");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // events: one before and one after each of the 6 launches per step, plus
+  // one at each end of the whole run
+  const int nev = 12 * nsteps + 2;
+  std::vector<hipEvent_t> ev(nev, nullptr);
+  cgp_status st = CGP_OK;
+  // timing-only events: no system-scope fence (cache writeback and
+  // invalidation) when they are recorded, which would slow the launches
+  // between them
+  for (int i = 0; i < nev && st == CGP_OK; ++i)
+    if (hipEventCreateWithFlags(&ev[i], hipEventDisableSystemFence) != hipSuccess)
+      st = fail(CGP_ERR_DEVICE, "event create");
+  hipError_t e = hipSuccess;
+  if (st == CGP_OK) {
+    auto run = [&](auto tag) -> hipError_t {
+      using T = decltype(tag);
+      T* w = static_cast<T*>(omega);
+      const T* F = static_cast<const T*>(forcing);
+      const Plan& p = h->plan;
+      T* bufs[3] = {w, h->at<T>(p.lay.st1), h->at<T>(p.lay.st2)};
+      double* ctl = h->at<double>(p.lay.ctl);
+      hipError_t r = enqueue_pass<T>(h, 0, w, nullptr, 0, s);
+      if (r == hipSuccess) r = hipEventRecord(ev[0], s);
+      int k = 1;
+      for (int n = 0; n < nsteps && r == hipSuccess; ++n) {
+        // the launches of enqueue_step_fused at rotation phase n mod 3
+        const int pos = n % 3;
+        T* S = bufs[pos];
+        T* X = bufs[(pos + 1) % 3];
+        T* Y = bufs[(pos + 2) % 3];
+        const T* src[3] = {S, X, Y};
+        T* dst[3] = {X, Y, X};
+        for (int stg = 0; stg < 3 && r == hipSuccess; ++stg) {
+          r = hipEventRecord(ev[k++], s);
+          if (r == hipSuccess)
+            r = enqueue_pass<T>(h, 1, nullptr, nullptr, 0, s, stg == 0 ? ctl : nullptr);
+          if (r == hipSuccess) r = hipEventRecord(ev[k++], s);
+          if (r == hipSuccess) r = hipEventRecord(ev[k++], s);
+          if (r == hipSuccess)
+            r = enqueue_fused<T>(h, src[stg], F, S, dst[stg], kRkA[stg], kRkB[stg], true, s,
+                                 nullptr, StepCtl{ctl, stg == 2});
+          if (r == hipSuccess) r = hipEventRecord(ev[k++], s);
+        }
+      }
+      if (r == hipSuccess) r = hipEventRecord(ev[k], s);
+      if (r == hipSuccess && nsteps % 3 != 0)
+        r = hipMemcpyAsync(w, bufs[nsteps % 3], (size_t)p.lay.field_elems * sizeof(T),
+                           hipMemcpyDeviceToDevice, s);
+      return r;
+    };
+    e = h->plan.dtype == CGP_F64 ? run(double{}) : run(float{});
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    double sum[2] = {0.0, 0.0};
+    for (int n = 0; n < nsteps && e == hipSuccess; ++n)
+      for (int stg = 0; stg < 3 && e == hipSuccess; ++stg)
+        for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+          const int a = 1 + 12 * n + 4 * stg + 2 * q;
+          float t = 0.f;
+          e = hipEventElapsedTime(&t, ev[a], ev[a + 1]);
+          sum[q] += t;
+        }
+    float tot = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&tot, ev[0], ev[nev - 1]);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "in-step pass timing");
+    } else {
+      ms[0] = sum[0] / (3.0 * nsteps);
+      ms[1] = sum[1] / (3.0 * nsteps);
+      ms[2] = (double)tot / nsteps;
+    }
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
   return st;
 }
 

@@ -68,3 +68,18 @@ def test_pmc_summary_scales_by_the_copy(tmp_path):
     assert k["fetch_bytes"] == pytest.approx(2000.0 * 1024)
     assert k["hbm_bytes_per_launch"] == pytest.approx(2500.0 * 1024)
     assert t["source_hash"] == bench.source_hash()
+
+
+def test_algorithmic_bytes_per_step_and_in_step_launch():
+    """A fused step moves 11 fine fields and 12 coarse spectra: per stage the
+    fused pass reads the psi spectra, omega_s, the forcing and (stages 2, 3)
+    omega_n, writes the stage output and the next spectra; pass B reads and
+    writes the spectra.  That is the fused lower bound e (11 + 12/c^2) per
+    point-step of the byte model, up to the ring nodes."""
+    fine, coarse = 513 * 1025 * 8, 255 * 511 * 8
+    sb = bench.step_bytes(ci.case_c1(1), 8)
+    assert sb["step"] == 11 * fine + 12 * coarse
+    assert sb["fused_avg"] * 3 + 3 * sb["B"] == sb["step"]
+    per_point = sb["step"] / (512 * 1024)
+    assert abs(per_point - 8 * (11 + 12 / 4)) / per_point < 0.01
+    assert bench.model_bytes(2, 8) == 184.0
