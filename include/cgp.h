@@ -125,6 +125,26 @@ cgp_status cgp_destroy(cgp_handle* h);
 cgp_status cgp_step(cgp_handle* h, void* omega_dev, const void* forcing_dev,
                     void* psi_out_dev, int32_t nsteps, void* stream);
 
+/* cgp_step for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc or any device allocation): the
+ * same kernels on the same arrays as cgp_create + cgp_step + cgp_destroy of a
+ * fresh single-basin handle, with the workspace in a static device array of
+ * the library (48 MiB on each GPU it runs on, held until the process ends)
+ * instead of a caller workspace.  The caller passes cfg (host), omega_dev
+ * (in/out), forcing_dev and psi_out_dev (nullable) exactly as for cgp_step.
+ * No call allocates device memory: the library takes the array's address
+ * with hipGetSymbolAddress at its first call on a device.  Every call
+ * uploads the handle tables and a fresh step state into the array (the model
+ * time of cgp_time_state restarts at 0; with cfl > 0 the first step is dt)
+ * and synchronises `stream` once after that upload, so it cannot itself be
+ * captured into a graph.  Configurations whose workspace (cgp_workspace_size)
+ * exceeds 48 MiB give CGP_ERR_INVALID before any device work; every
+ * 512 x 1024 one- and two-layer FP64 configuration fits.  All calls on one
+ * GPU share the array: calls that overlap in time on one GPU (two streams,
+ * two host threads) race and must be serialised by the caller. */
+cgp_status cgp_step_noalloc(const cgp_config* cfg, void* omega_dev, const void* forcing_dev,
+                            void* psi_out_dev, int32_t nsteps, void* stream);
+
 /* Step state: out_dev[2m] = the dt of member m's latest step (the configured
  * dt before the first step), out_dev[2m+1] = the model time its steps have
  * advanced since cgp_create (m = 0 for a single basin).  out_dev holds

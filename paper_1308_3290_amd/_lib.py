@@ -45,6 +45,7 @@ SIGNATURES = {
     "cgp_create": (_I32, [_CFG, _P, _SZ, _P, ctypes.POINTER(_P)]),
     "cgp_destroy": (_I32, [_P]),
     "cgp_step": (_I32, [_P, _P, _P, _P, _I32, _P]),
+    "cgp_step_noalloc": (_I32, [_CFG, _P, _P, _P, _I32, _P]),
     "cgp_solve": (_I32, [_P, _P, _P, _P]),
     "cgp_time_state": (_I32, [_P, _P, _P]),
     "cgp_accumulate": (_I32, [_P, _P, _P, ctypes.c_double, _I32, _P]),

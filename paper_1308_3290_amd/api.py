@@ -79,6 +79,13 @@ def cgp_step(h, omega, forcing, psi_out=None, nsteps=1, stream=None):
          ctypes.c_void_p(stream_ptr(stream)))
 
 
+def cgp_step_noalloc(cfg: cgp_config, omega, forcing, psi_out=None, nsteps=1, stream=None):
+    """cgp_step of a fresh handle whose workspace is the library's static device
+    scratch (no device allocation by the library or by this binding)."""
+    call("cgp_step_noalloc", ctypes.byref(cfg), _ptr(omega), _ptr(forcing), _ptr(psi_out),
+         int(nsteps), ctypes.c_void_p(stream_ptr(stream)))
+
+
 def cgp_time_state(h, out, stream=None):
     """out (FP64 device tensor, 2 per member) <- (dt of the latest step, model time)."""
     call("cgp_time_state", h, _ptr(out), ctypes.c_void_p(stream_ptr(stream)))

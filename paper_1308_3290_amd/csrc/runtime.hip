@@ -15,6 +15,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <utility>
@@ -928,6 +929,66 @@ cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_
   return CGP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Static device scratch of cgp_step_noalloc: the workspace of one call, for
+// callers that cannot allocate device memory.  Each GPU the library runs on
+// holds its own copy of the array until the process ends.  In host code the
+// array's name is only a host-side stand-in: its device address on the
+// current device comes from hipGetSymbolAddress, taken once per device at the
+// first call on that device and kept in g_scratch_ptr; only that pointer is
+// handed to kernels and copies.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)48 << 20;  // the 512 x 1024 workloads, FP64, 1-2 layers
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // device address of `scratch`, per device id
+
+cgp_status scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "current device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "address of the static scratch");
+    if (!p || reinterpret_cast<uintptr_t>(p) % kAlign)
+      return fail(CGP_ERR_DEVICE, "static scratch has no 256-byte aligned device address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CGP_OK;
+}
+
+template <typename T>
+cgp_status step_noalloc_impl(const cgp_config* cfg, void* omega, const void* forcing,
+                             void* psi_out, int nsteps, hipStream_t s) {
+  cgp_handle h;
+  cgp_status st = make_plan(cfg, 1, &h.plan);
+  if (st != CGP_OK) return st;
+  if (h.plan.lay.total > kScratchBytes)
+    return fail(CGP_ERR_INVALID,
+                "cgp_step_noalloc: this configuration needs %zu bytes of workspace, above the "
+                "%zu bytes of the static scratch (use cgp_create with a caller workspace)",
+                h.plan.lay.total, kScratchBytes);
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != CGP_OK) return st;
+  h.ws = static_cast<char*>(ws);
+  // the tables and the step state of a fresh handle, every call (the array
+  // keeps whatever the last call on this GPU left)
+  st = create_tables<T>(&h, s);
+  if (st != CGP_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s), "table upload sync");  // the host image dies with h
+  // direct launches only: no graph, stream or event is created
+  return step_impl<T>(&h, omega, forcing, psi_out, nsteps, 0, s);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1003,6 +1064,17 @@ cgp_status cgp_step(cgp_handle* h, void* omega, const void* forcing, void* psi_o
   return h->plan.dtype == CGP_F64
              ? step_impl<double>(h, omega, forcing, psi_out, nsteps, 0, s)
              : step_impl<float>(h, omega, forcing, psi_out, nsteps, 0, s);
+}
+
+cgp_status cgp_step_noalloc(const cgp_config* cfg, void* omega, const void* forcing,
+                            void* psi_out, int32_t nsteps, void* stream) {
+  if (!cfg) return fail(CGP_ERR_INVALID, "config is NULL");
+  if (!omega || !forcing) return fail(CGP_ERR_INVALID, "omega or forcing is NULL");
+  if (nsteps < 0) return fail(CGP_ERR_INVALID, "nsteps < 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return cfg->dtype == CGP_F64
+             ? step_noalloc_impl<double>(cfg, omega, forcing, psi_out, nsteps, s)
+             : step_noalloc_impl<float>(cfg, omega, forcing, psi_out, nsteps, s);
 }
 
 cgp_status cgp_step_mean(cgp_handle* h, void* omega, const void* forcing, int32_t nsteps,

@@ -154,3 +154,20 @@ def test_multigrid_workspace_and_limits():
     assert e.value.status == 2
     with pytest.raises(CGPError):       # members share the solver
         cgp_ensemble_workspace_size([_cfg(solver=1), _cfg()])
+
+
+def test_noalloc_step_rejects_an_oversized_workspace_on_the_host():
+    """cgp_step_noalloc checks the workspace size against its static scratch
+    before any device work (no GPU needed for the refusal)."""
+    import torch
+    from paper_1308_3290_amd._lib import CGP_ERR_INVALID, CGPError
+    from paper_1308_3290_amd.api import cgp_step_noalloc, make_config
+    cfg = make_config(1024, 1024, level=0, nlayers=2, f1=10.0, f2=5.0, inv_re=1e-3, dt=1e-5)
+    host = torch.zeros(4)  # never dereferenced: the call fails before touching memory
+    with pytest.raises(CGPError) as ei:
+        cgp_step_noalloc(cfg, host, host, None, 1, stream=_NoStream())
+    assert ei.value.status == CGP_ERR_INVALID and "static scratch" in str(ei.value)
+
+
+class _NoStream:
+    cuda_stream = 0
