@@ -402,6 +402,12 @@ def main():
                 if prof_us else None,
                 "achievable_copy": round(best, 1), "frac_of_achievable": round(achieved / best, 4)}
         out["in_step_ms_per_step_with_events"] = round(mstep, 6)
+        if 1 in rates:
+            # the fused pass's share of the step wall time without events:
+            # a step is three (pass B, fused pass) pairs; pass B back to back
+            t_b = ms[names.index("B")]
+            share = rates[1]["ms"] / K / 3.0 - t_b
+            roof["us_step_share"] = round(share * 1e3, 3)
         del b, w, F, psi
     # ---------------------------------------------------------------- two layers
     two = {}
