@@ -31,7 +31,7 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = [
-    "Case", "make_case", "case_c0", "case_c1", "case_c2", "ensemble_c3",
+    "Case", "make_case", "case_c0", "case_c1", "case_c2", "ensemble_c3", "experiment_case",
     "adjoint_c4", "node_y", "forcing_field", "initial_field", "AdjointProblem",
     "EnsembleMember",
 ]
@@ -181,6 +181,23 @@ def ensemble_c3(count: int = 64, dtype: str = "f64", nsteps: int = 200,
         out.append(EnsembleMember(case=c, amplitude=float(amps[m]), omega0=w0,
                                   forcing=forcing_field(c, float(amps[m]))))
     return out
+
+
+# The one-layer experiments of Sec. 5.1 (Table 1): Exp. I Re = 200,
+# Ro = 0.0016; Exp. II Re = 312.5, Ro = 0.0025; forcing sin(pi y)/Ro on the
+# [0, 1] x [-1, 1] basin, started from 1e-3 N(0,1) noise, adaptive steps.
+EXPERIMENTS_1L = {"I": dict(ro=0.0016, re=200.0), "II": dict(ro=0.0025, re=312.5)}
+
+
+def experiment_case(exp: str, nx: int, ny: int, level: int, seed: int = 1, cfl: float = 0.5,
+                    dt_max: float = 5e-4, dtype: str = "f64"):
+    """(Case, omega0, forcing) of one long run of experiment `exp` on an
+    nx x ny grid with CGP level `level`."""
+    p = EXPERIMENTS_1L[exp]
+    c = Case(nx=nx, ny=ny, level=level, inv_re=1.0 / p["re"], inv_ro=1.0 / p["ro"], dt=dt_max,
+             cfl=cfl, seed=seed, dtype=dtype, name=f"exp{exp}_{nx}x{ny}_l{level}")
+    w0 = initial_field(c, np.random.default_rng(seed))
+    return c, w0, forcing_field(c)
 
 
 @dataclasses.dataclass

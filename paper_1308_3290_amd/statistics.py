@@ -4,17 +4,23 @@ A run spins up from the initial state to t_spin, then averages omega over
 [t_spin, t_end] in time (every step adds dt * omega to an FP64 running sum in
 the library, `cgp_step_mean`), and records the basin energy and enstrophy
 (eq. 26, `cgp_diagnostics`) every chunk of steps.  The mean of psi is the
-elliptic map of the mean of omega (the map is linear); the mean potential
-vorticity is q = Ro <omega> + y (vorticity form).
+elliptic map of the mean of omega (the map is linear, `cgp_solve`); the mean
+potential vorticity is q = Ro <omega> + y (vorticity form).  The division of
+the running sum by the window length and q = Ro <omega> + y are applied once
+per run to the final fields, in NumPy: post-processing of the statistics,
+outside the time step, whose per-step work all runs in the library.
 
-    python -m paper_1308_3290_amd.statistics --exp I --levels 0 1 2
+    python -m paper_1308_3290_amd.statistics --exp I --runs 256x512:0 256x512:1 256x512:2
 
 runs the one-layer four-gyre experiments of Sec. 5.1 (Table 1: Exp. I
 Re = 200, Ro = 0.0016; Exp. II Re = 312.5, Ro = 0.0025; forcing
-sin(pi y) / Ro on [0, 1] x [-1, 1]) at 256 x 512 with CGP levels 0 (the
-full-grid run the paper calls DNS), 1 and 2, adaptive steps (Sec. 4.2), and
-prints one JSON line per run with the differences of its mean fields from
-the level-0 run.
+sin(pi y) / Ro on [0, 1] x [-1, 1], inputs from cgp_inputs.experiment_case)
+with adaptive steps (Sec. 4.2) and prints one JSON line per run with the
+differences of its mean fields from the first run (the reference, the
+full-grid run the paper calls DNS).  Runs on coarser fine grids than the
+reference (the fixed 16 x 32 elliptic grid of the paper's last comparison:
+16x32:0, 32x64:1, 64x128:2) are compared at their own nodes, where the
+grids nest (the reference sampled every nx_ref / nx nodes).
 """
 from __future__ import annotations
 
@@ -27,10 +33,9 @@ from typing import Optional
 import numpy as np
 import torch
 
-from .api import Basin, make_config
+import cgp_inputs as ci
 
-# Table 1 (one layer): Ro = (delta_I / L)^2, Re = Ro / (delta_M / L)^3
-EXPERIMENTS = {"I": dict(ro=0.0016, re=200.0), "II": dict(ro=0.0025, re=312.5)}
+from .api import Basin, config_from_case
 
 
 def _now(basin: Basin, stream=None) -> float:
@@ -108,12 +113,28 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def on_grid(field: np.ndarray, nx: int, ny: int) -> np.ndarray:
+    """field (a node array of a finer nested grid) at the nodes of an nx x ny
+    grid over the same basin."""
+    fy, fx = field.shape[-2] - 1, field.shape[-1] - 1
+    if fx % nx or fy % ny or fx // nx != fy // ny:
+        raise ValueError(f"{fx}x{fy} does not nest {nx}x{ny}")
+    k = fx // nx
+    return field[..., ::k, ::k]
+
+
+def parse_run(spec: str):
+    """'NXxNY:LEVEL' -> (nx, ny, level)."""
+    g, lv = spec.split(":")
+    nx, ny = g.lower().split("x")
+    return int(nx), int(ny), int(lv)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--exp", default="I", choices=sorted(EXPERIMENTS))
-    ap.add_argument("--nx", type=int, default=256)
-    ap.add_argument("--ny", type=int, default=512)
-    ap.add_argument("--levels", type=int, nargs="+", default=[0, 1, 2])
+    ap.add_argument("--exp", default="I", choices=sorted(ci.EXPERIMENTS_1L))
+    ap.add_argument("--runs", nargs="+", default=["256x512:0", "256x512:1", "256x512:2"],
+                    help="NXxNY:LEVEL per run; the first is the reference")
     ap.add_argument("--t-spin", type=float, default=10.0)
     ap.add_argument("--t-end", type=float, default=50.0)
     ap.add_argument("--cfl", type=float, default=0.5)
@@ -122,41 +143,40 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--control-seed", type=int, default=None,
-                    help="also run level 0 from another initial state (this seed) and report "
-                         "its differences from the first level-0 run: the sampling spread of "
-                         "the time means")
+                    help="also run the reference configuration from another initial state "
+                         "(this seed) and report its differences from the reference: the "
+                         "sampling spread of the time means")
+    ap.add_argument("--save", default=None, help="write every run's mean fields to this .npz")
     args = ap.parse_args(argv)
-    p = EXPERIMENTS[args.exp]
-    nx, ny = args.nx, args.ny
-    y = -1.0 + np.arange(ny + 1) * (2.0 / ny)
-    F = np.broadcast_to((np.sin(np.pi * y) / p["ro"])[:, None], (ny + 1, nx + 1)).copy()
     tdt = torch.float64 if args.dtype == "f64" else torch.float32
     dev = torch.device("cuda:0")
     side = torch.cuda.Stream()  # graphs are captured on a non-default stream
     ref = None
-    runs = [(lv, args.seed) for lv in args.levels]
+    runs = [(parse_run(r), args.seed) for r in args.runs]
     if args.control_seed is not None:
-        runs.append((0, args.control_seed))
-    for lv, seed in runs:
-        w0 = np.zeros((ny + 1, nx + 1))
-        w0[1:-1, 1:-1] = 1e-3 * np.random.default_rng(seed).standard_normal((ny - 1, nx - 1))
-        cfg = make_config(nx, ny, level=lv, dtype=args.dtype, inv_re=1.0 / p["re"],
-                          inv_ro=1.0 / p["ro"], dt=args.dt_max, cfl=args.cfl)
-        b = Basin(cfg, device=dev)
+        runs.append((runs[0][0], args.control_seed))
+    saved = {}
+    for (nx, ny, lv), seed in runs:
+        case, w0, F = ci.experiment_case(args.exp, nx, ny, lv, seed=seed, cfl=args.cfl,
+                                         dt_max=args.dt_max, dtype=args.dtype)
+        ro = 1.0 / case.inv_ro
+        y = ci.node_y(case)
+        b = Basin(config_from_case(case), device=dev)
         w = torch.as_tensor(w0, dtype=tdt, device=dev).contiguous()
         Fd = torch.as_tensor(F, dtype=tdt, device=dev).contiguous()
         mark = [0.0]
 
-        def progress(t, n, lv=lv):
+        def progress(t, n, lv=lv, nx=nx, ny=ny):
             if t >= mark[0]:
-                print(f"level {lv}: t = {t:.3f} after {n} steps", file=sys.stderr, flush=True)
+                print(f"{nx}x{ny} level {lv}: t = {t:.3f} after {n} steps", file=sys.stderr,
+                      flush=True)
                 mark[0] += 5.0
 
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
             r = long_run(b, w, Fd, args.t_spin, args.t_end, chunk=args.chunk, stream=side,
                          progress=progress)
-        q = p["ro"] * r["mean_omega"] + y[:, None]
+        q = ro * r["mean_omega"] + y[:, None]
         sel = r["times"] >= r["t0"]
         out = dict(experiment=args.exp, grid=f"{nx}x{ny}", level=lv, seed=seed,
                    elliptic_grid=f"{nx >> lv}x{ny >> lv}", cfl=args.cfl, dt_max=args.dt_max,
@@ -168,12 +188,20 @@ def main(argv=None):
                    gyres=gyre_count(r["mean_psi"]),
                    finite=bool(np.isfinite(r["mean_omega"]).all()))
         if ref is None:
-            ref = dict(psi=r["mean_psi"], q=q)
+            ref = dict(psi=r["mean_psi"], q=q, grid=f"{nx}x{ny}:{lv}")
         else:
-            out["mean_psi_rel_diff_vs_level0"] = _rel(r["mean_psi"], ref["psi"])
-            out["mean_q_rel_diff_vs_level0"] = _rel(q, ref["q"])
+            out["reference"] = ref["grid"]
+            out["mean_psi_rel_diff_vs_ref"] = _rel(r["mean_psi"], on_grid(ref["psi"], nx, ny))
+            out["mean_q_rel_diff_vs_ref"] = _rel(q, on_grid(ref["q"], nx, ny))
+        tag = f"{nx}x{ny}_l{lv}_s{seed}"
+        saved[f"psi_{tag}"] = r["mean_psi"]
+        saved[f"q_{tag}"] = q
+        saved[f"t_{tag}"] = r["times"]
+        saved[f"E_{tag}"] = r["energy"][:, 0]
         print(json.dumps(out), flush=True)
         b.close()
+    if args.save:
+        np.savez_compressed(args.save, **saved)
 
 
 if __name__ == "__main__":

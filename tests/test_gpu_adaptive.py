@@ -228,3 +228,28 @@ def test_long_run_driver_matches_oracle():
     assert rel_l2(to_np(w), w_ref) < TOL64
     n = (r["steps_spin"] + r["steps_avg"]) // 5 + 1
     assert r["energy"].shape == (n, 1) and np.all(np.diff(r["times"]) > 0)
+
+
+@pytest.mark.parametrize("nx,ny,level", [(16, 32, 0), (32, 64, 1), (64, 128, 2)])
+def test_long_run_driver_at_the_fixed_16x32_elliptic_grid(nx, ny, level):
+    """The driver on the shapes of the paper's fixed 16 x 32 elliptic grid
+    comparison (Sec. 5.1: fine grids 16x32, 32x64 and 64x128 over one 16x32
+    solve), Exp. I physics and inputs, a short window against the oracle."""
+    from oracle import statistics as ost
+    from paper_1308_3290_amd.api import Basin, config_from_case
+    from paper_1308_3290_amd.statistics import long_run
+    case, w0, F = ci.experiment_case("I", nx, ny, level, seed=1, cfl=0.5, dt_max=5e-4)
+    g, phys = oracle_setup(case)
+    b = Basin(config_from_case(case))
+    w = to_dev(w0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        r = long_run(b, w, to_dev(F), t_spin=0.02, t_end=0.06, chunk=10, stream=side)
+    say(f"{nx}x{ny}:{level} long run: {r['steps_spin']} + {r['steps_avg']} steps")
+    mw_ref, mp_ref, tsum_ref, w_ref = ost.time_mean(w0, F, g, level, phys, case.cfl, case.dt,
+                                                    r["steps_spin"], r["steps_avg"])
+    assert (r["t1"] - r["t0"]) == pytest.approx(tsum_ref, rel=1e-12)
+    e = (rel_l2(r["mean_omega"], mw_ref), rel_l2(r["mean_psi"], mp_ref), rel_l2(to_np(w), w_ref))
+    say(f"  rel L2 mean omega {e[0]:.2e}, mean psi {e[1]:.2e}, final state {e[2]:.2e}")
+    assert max(e) < TOL64
