@@ -232,11 +232,13 @@ def main():
     want = (lambda k: not only or k in only)
     K, W, R = args.steps, args.warmup, max(1, args.repeats)
 
-    def timed_runs(cfgs, w0s, Fs, steps, warm, use_graph, reps):
+    def timed_runs(cfgs, w0s, Fs, steps, warm, use_graph, reps, launch=None):
         """reps timed runs of `steps` steps of an ensemble (one member: a single
         basin) on a non-default stream (graphs cannot be captured on the
         default one), HIP events recorded on that stream; ms per run."""
         ens = api.Ensemble(cfgs, device=dev)
+        if launch is not None:
+            ens.set_launch(**launch)
         w = ens.pack(w0s)
         Fp = ens.pack(Fs)
         s = torch.cuda.Stream()
@@ -423,13 +425,39 @@ def main():
                                                     / 1e9 / PEAK_HBM_GBS, 4)}
     # ---------------------------------------------------------------- ensembles
     ens_out = {}
+
+    def tuned_rate(cfgs, w0s, Fs, n_steps, label):
+        """The autotuner's choice of launch for this workload (every candidate
+        checked bit for bit against the reference launch), then R timed runs
+        of it; also the best time of each launch mode among the candidates."""
+        from paper_1308_3290_amd import autotune
+        probe = api.Ensemble(cfgs, device=dev)
+        Wp, Fpk = probe.pack(w0s), probe.pack(Fs)
+        probe.close()
+        report = []
+        setting = autotune.tune(cfgs, Wp, Fpk, steps=30, warmup=6, repeats=3, report=report,
+                                retune=True)
+        ms, finite = timed_runs(cfgs, w0s, Fs, n_steps, 5, setting["use_graph"], max(3, R // 2),
+                                launch=setting["launch"])
+        best_by_mode = {}
+        for r in report:
+            k = ("persistent" if r["launch"]["mode"] == 1 else
+                 ("per-pass graphs" if r["use_graph"] else "per-pass direct"))
+            if r["accepted"] and (k not in best_by_mode or r["ms_per_step"] < best_by_mode[k][0]):
+                best_by_mode[k] = (r["ms_per_step"], r["launch"])
+        log(f"{label}: tuned {setting} over {len(report)} candidates "
+            f"({sum(r['accepted'] for r in report)} accepted); best per mode "
+            + json.dumps({k: round(v[0], 4) for k, v in best_by_mode.items()}))
+        return ms, finite, setting, best_by_mode
+
     if want("ens"):
         n_ens = 200
         for dt_ in ("f64", "f32"):
             members = ci.ensemble_c3(dtype=dt_)
             cfgs = [api.config_from_case(m.case) for m in members]
-            ms, finite = timed_runs(cfgs, [m.omega0 for m in members],
-                                    [m.forcing for m in members], n_ens, 5, True, max(3, R // 2))
+            ms, finite, setting, by_mode = tuned_rate(
+                cfgs, [m.omega0 for m in members], [m.forcing for m in members], n_ens,
+                f"ensemble 64 {dt_}")
             pts = sum(m.case.points for m in members)
             es = 8 if dt_ == "f64" else 4
             alg = sum(step_bytes(m.case, es)["step"] for m in members)
@@ -440,7 +468,10 @@ def main():
                             "alg_bytes_per_step": alg, "GBs_alg": round(alg / t / 1e9, 1),
                             "frac_alg": round(alg / t / 1e9 / PEAK_HBM_GBS, 4),
                             "GBs_model": round(pts * model_bytes(2, es) / t / 1e9, 1),
-                            "finite": finite, "launch": "hipGraph replays, member chains forked"}
+                            "finite": finite, "launch": setting,
+                            "tuning_best_Mpts_by_mode": {
+                                k: round(pts / (v[0] * 1e-3) / 1e6, 1)
+                                for k, v in by_mode.items()}}
             log(f"ensemble 64 {dt_}: {ens_out[dt_]}")
     batch = None
     if want("batch"):
@@ -449,12 +480,16 @@ def main():
         w0, F = basin_inputs(case)
         cfgs = [api.config_from_case(case)] * 16
         n_b = 100
-        ms, finite = timed_runs(cfgs, [w0] * 16, [F] * 16, n_b, 5, True, 3)
+        ms, finite, setting, by_mode = tuned_rate(cfgs, [w0] * 16, [F] * 16, n_b,
+                                                  "batch of 16 x 512x1024")
         t = median(ms) * 1e-3 / n_b
         sb = step_bytes(case, 8)["step"] * 16
         batch = {"value": round(16 * case.points / t / 1e6, 1), "unit": "Mpoint-steps/s",
                  "basins": 16, "steps": n_b, "GBs_alg": round(sb / t / 1e9, 1),
-                 "frac_alg": round(sb / t / 1e9 / PEAK_HBM_GBS, 4), "finite": finite}
+                 "frac_alg": round(sb / t / 1e9 / PEAK_HBM_GBS, 4), "finite": finite,
+                 "launch": setting,
+                 "tuning_best_Mpts_by_mode": {k: round(16 * case.points / (v[0] * 1e-3) / 1e6, 1)
+                                              for k, v in by_mode.items()}}
         log(f"batch of 16 x 512x1024 level 1: {batch}")
     # ---------------------------------------------------------------- adjoint ratio
     adj = None

@@ -102,6 +102,26 @@ typedef struct cgp_config {
 
 typedef struct cgp_handle cgp_handle;
 
+/* How a handle's time steps are launched (cgp_set_launch).  mode 0: every
+ * pass of a stage is its own launch (one per group of members of one
+ * transform length; captured steps run the groups' chains on forked
+ * streams).  mode 1: ONE persistent launch per RK3 stage over every member:
+ * workgroups take tiles of work from a queue in the workspace (first every
+ * member's pass-B column pairs, b_tile per tile, then its fused-pass row
+ * blocks, f_tile per tile), and per-member counters make a member's fused
+ * tiles wait until its pass B is done.  Mode 1 needs one layer and every
+ * member at coarsening factor 2 with row transforms of 128, 256, 384 or 512
+ * points and column transforms of 256, 512, 768 or 1024 points (rows of at
+ * most 256 intervals, 128 x 256 up to 512 x 1024 grids).  wg_per_cu: the
+ * launch grid's workgroups per compute unit (0: as many as can be
+ * resident).  Both modes give the same bits. */
+typedef struct cgp_launch {
+  int32_t mode;
+  int32_t b_tile;
+  int32_t f_tile;
+  int32_t wg_per_cu;
+} cgp_launch;
+
 /* Bytes of device workspace a single-basin handle needs.  Host only. */
 cgp_status cgp_workspace_size(const cgp_config* cfg, size_t* bytes);
 
@@ -233,6 +253,22 @@ cgp_status cgp_ensemble_create(const cgp_config* members, int32_t count, void* w
 cgp_status cgp_ensemble_step(cgp_handle* h, void* omega_packed_dev,
                              const void* forcing_packed_dev, int32_t nsteps, int32_t use_graph,
                              void* stream);
+
+/* Select how h's time steps are launched (cgp_launch; the default is mode 0
+ * with tiles of 1).  Mode 1 on a handle without it gives
+ * CGP_ERR_UNSUPPORTED; tiles below 1 or wg_per_cu outside 0..16,
+ * CGP_ERR_INVALID.  Uploads the work queue of mode 1 into the workspace on
+ * `stream` and synchronises it; graphs captured before are dropped. */
+cgp_status cgp_set_launch(cgp_handle* h, const cgp_launch* launch, void* stream);
+
+/* The handle's launch setting; *persistent_available (nullable) = 1 when
+ * the handle can take mode 1.  Host only. */
+cgp_status cgp_get_launch(cgp_handle* h, cgp_launch* launch, int32_t* persistent_available);
+
+/* The sticky fault flag of mode 1 (host memory): 1 if a fused tile ever
+ * stopped waiting for its member's pass B after its bounded number of polls
+ * (its results are then wrong), else 0.  Synchronises `stream`. */
+cgp_status cgp_persistent_fault(cgp_handle* h, int32_t* flag_host, void* stream);
 
 /* Measurement.  Times each pass of one RK3 stage on the handle's current
  * workspace contents: pass 0 (restriction + x transform of omega_dev),

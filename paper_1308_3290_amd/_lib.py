@@ -27,6 +27,11 @@ class cgp_config(ctypes.Structure):
                 ("solver", ctypes.c_int32), ("mg_cycles", ctypes.c_int32)]
 
 
+class cgp_launch(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("b_tile", ctypes.c_int32), ("f_tile", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32)]
+
+
 class CGPError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -60,6 +65,9 @@ SIGNATURES = {
     "cgp_ensemble_step": (_I32, [_P, _P, _P, _I32, _I32, _P]),
     "cgp_time_passes": (_I32, [_P, _P, _P, _I32, ctypes.POINTER(ctypes.c_double), _P]),
     "cgp_time_step_passes": (_I32, [_P, _P, _P, _I32, ctypes.POINTER(ctypes.c_double), _P]),
+    "cgp_set_launch": (_I32, [_P, ctypes.POINTER(cgp_launch), _P]),
+    "cgp_get_launch": (_I32, [_P, ctypes.POINTER(cgp_launch), ctypes.POINTER(_I32)]),
+    "cgp_persistent_fault": (_I32, [_P, ctypes.POINTER(_I32), _P]),
     "cgp_last_error": (ctypes.c_char_p, []),
     "cgp_version": (ctypes.c_char_p, []),
 }

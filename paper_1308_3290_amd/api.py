@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import CGP_F32, CGP_F64, CGPError, call, cgp_config  # noqa: F401
+from ._lib import CGP_F32, CGP_F64, CGPError, call, cgp_config, cgp_launch  # noqa: F401
 
 _TORCH_DTYPE = {CGP_F32: torch.float32, CGP_F64: torch.float64}
 
@@ -173,6 +173,28 @@ def cgp_time_passes(h, omega, forcing, reps, stream=None):
     return list(ms)
 
 
+def cgp_set_launch(h, mode=0, b_tile=1, f_tile=1, wg_per_cu=0, stream=None):
+    """Launch mode of the handle's steps: 0 per-pass launches, 1 one persistent
+    launch per RK3 stage (tiles of b_tile pass-B and f_tile fused blocks)."""
+    lc = cgp_launch(mode=mode, b_tile=b_tile, f_tile=f_tile, wg_per_cu=wg_per_cu)
+    call("cgp_set_launch", h, ctypes.byref(lc), ctypes.c_void_p(stream_ptr(stream)))
+
+
+def cgp_get_launch(h):
+    """(dict of the launch setting, whether the persistent mode is available)."""
+    lc = cgp_launch()
+    avail = ctypes.c_int32()
+    call("cgp_get_launch", h, ctypes.byref(lc), ctypes.byref(avail))
+    return dict(mode=lc.mode, b_tile=lc.b_tile, f_tile=lc.f_tile,
+                wg_per_cu=lc.wg_per_cu), bool(avail.value)
+
+
+def cgp_persistent_fault(h, stream=None) -> int:
+    flag = ctypes.c_int32()
+    call("cgp_persistent_fault", h, ctypes.byref(flag), ctypes.c_void_p(stream_ptr(stream)))
+    return flag.value
+
+
 def cgp_time_step_passes(h, omega, forcing, nsteps, stream=None):
     """nsteps time steps (direct launches) with HIP events around every pass B
     and fused-pass launch: mean ms per launch of each and mean ms per step."""
@@ -314,6 +336,15 @@ class Ensemble:
         _check_tensor(forcing_packed, self.dtype, self.total, "forcing_packed")
         cgp_ensemble_step(self.handle, omega_packed, forcing_packed, nsteps, use_graph, stream)
         return omega_packed
+
+    def set_launch(self, mode=0, b_tile=1, f_tile=1, wg_per_cu=0, stream=None):
+        cgp_set_launch(self.handle, mode, b_tile, f_tile, wg_per_cu, stream)
+
+    def launch(self):
+        return cgp_get_launch(self.handle)
+
+    def persistent_fault(self, stream=None) -> int:
+        return cgp_persistent_fault(self.handle, stream)
 
     def time_state(self, stream=None):
         """FP64 device tensor (members, 2): dt of each member's latest step and

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcgp.so")
 SOURCES = ["solve_kernels.hip", "stencil_kernels.hip", "fused_kernels.hip", "fused2_kernels.hip",
-           "adjoint_kernels.hip", "mg_kernels.hip", "runtime.hip"]
+           "adjoint_kernels.hip", "mg_kernels.hip", "persistent_kernels.hip", "runtime.hip"]
 ARCH = "gfx950"
 
 

@@ -5,6 +5,24 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Thread index within the block, as the block-level device code reads it.
+// A translation unit whose kernels run that code inside a loop over work
+// tiles (the persistent stage kernel) defines CGP_OPAQUE_TID before the
+// first include: every use then re-reads the index through an opaque
+// zero, so that the many per-thread index values derived from it are
+// recomputed in each tile instead of being hoisted out of the tile loop and
+// held live across it (which exceeds the register budget and spills).
+#ifdef CGP_OPAQUE_TID
+#define CGP_TID                                 \
+  ({                                            \
+    int z_;                                     \
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z_)); \
+    (int)threadIdx.x + z_;                      \
+  })
+#else
+#define CGP_TID ((int)threadIdx.x)
+#endif
+
 namespace cgp {
 
 constexpr int kMaxStages = 12;   // radix stages of one complex FFT (L <= 4096)
@@ -94,15 +112,15 @@ __device__ __forceinline__ void update_step_dt(const MemberDesc& d, double* ctl,
   double m = 0.0;
   if (d.cfl > 0) {
     const int n = d.npart * kVmaxSlots;
-    for (int i = threadIdx.x; i < n; i += NT) m = fmax(m, st[2 + i]);
+    for (int i = CGP_TID; i < n; i += NT) m = fmax(m, st[2 + i]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    if ((CGP_TID & 63) == 0) red[CGP_TID >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0)
+    if (CGP_TID == 0)
       for (int i = 1; i < NT / 64; ++i) m = fmax(m, red[i]);
   }
-  if (threadIdx.x == 0) {
+  if (CGP_TID == 0) {
     const double dt = m > 0 ? fmin(d.dt, d.cfl * d.hmin / m) : d.dt;
     st[0] = dt;
     st[1] += dt;
@@ -131,8 +149,8 @@ __device__ __forceinline__ void put_vmax(const MemberDesc& d, const StepCtl& c, 
     mx = fmax(mx, __shfl_xor(mx, o));
     my = fmax(my, __shfl_xor(my, o));
   }
-  if ((threadIdx.x & 63) == 0)
-    c.w[d.cfl_off + 2 + (long long)lb * kVmaxSlots + (threadIdx.x >> 6)] = fmax(mx / hx, my / hy);
+  if ((CGP_TID & 63) == 0)
+    c.w[d.cfl_off + 2 + (long long)lb * kVmaxSlots + (CGP_TID >> 6)] = fmax(mx / hx, my / hy);
 }
 
 // The velocity maxima of a fused stage block, from its coarse psi rows in
@@ -155,7 +173,7 @@ __device__ __forceinline__ void put_vmax_coarse(const MemberDesc& d, const StepC
   double mx = 0.0, my = 0.0;
   for (int l = 0; l < (psc2 ? 2 : 1); ++l) {
     const T* P = l ? psc2 : psc;
-    for (int I = threadIdx.x; I < Mx; I += NT) {
+    for (int I = CGP_TID; I < Mx; I += NT) {
 #pragma unroll
       for (int r = 1; r <= TJ; ++r) {
         const int J = j0 - 1 + r;
@@ -290,6 +308,34 @@ struct Launch {
   // the nm members, w_m = the dt of member m's latest step (ctl != NULL) or 1
   static hipError_t accumulate(const MemberDesc* md, int nm, const T* f, long long n,
                                double* sum, double weight, const double* ctl, hipStream_t s);
+};
+
+// Persistent stage kernel of ensembles (persistent_kernels.hip): a queue of
+// work tiles, pass-B tiles first.  kind 0: pass-B blocks lb0 .. lb0+count-1
+// of the member; kind 1: fused-pass blocks.
+struct PTile {
+  int member, kind, lb0, count;
+};
+// Coarsening factor, row and column transform lengths the persistent kernel
+// takes (compile-time transforms only, so that it stays within the
+// two-blocks-per-CU register budget of the fused pass).
+__host__ __device__ constexpr bool persistent_lengths(int c, int lr, int lc) {
+  return c == 2 && (lr == 128 || lr == 256 || lr == 384 || lr == 512) &&
+         (lc == 256 || lc == 512 || lc == 768 || lc == 1024);
+}
+constexpr int kPersistCounters = 3;  // head, exited, fault; then one per member
+
+template <typename T>
+struct PersistLaunch {
+  // one RK3 stage of every member: pass B of the stage input's spectra wt
+  // into wt2, then the fused pass from wt2 and ws into out and the next
+  // spectra (wt)
+  static hipError_t stage(const MemberDesc* md, const PTile* tiles, int ntiles, int* ctr, int nm,
+                          int grid, size_t lds, T* wt, T* wt2, const cplx<T>* tw,
+                          const double* lam, double* ctl_b, const T* ws, const T* forcing,
+                          const T* wn, T* out, double a, double b, StepCtl ctl, hipStream_t s);
+  static hipError_t prepare(size_t bytes);
+  static hipError_t blocks_per_cu(size_t lds, int* n);
 };
 
 // Multigrid V-cycle operations on one level (an nx x ny interval node array

@@ -107,7 +107,7 @@ __device__ __forceinline__ void fft_stage(const cplx<T>* in, cplx<T>* out, int n
   const int LP = lpad(L);
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
-    const int b = threadIdx.x + NT * q;
+    const int b = CGP_TID + NT * q;
     if (b < nb) {
       const int p = b / LR;
       const int j = b - p * LR;
@@ -253,7 +253,7 @@ __device__ __forceinline__ void reg_tw_load(cplx<T>* v, const cplx<T>* __restric
     const int nb = nseq * LR;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int b = threadIdx.x + NT * q;
+      const int b = CGP_TID + NT * q;
       const int bb = b < nb ? b : 0;
       const int j = bb - (bb / LR) * LR;
       const int k = j & (NS - 1);
@@ -276,7 +276,7 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
   const int nb = nseq * LR;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int b = threadIdx.x + NT * q;
+    const int b = CGP_TID + NT * q;
     if (b < nb) {
       const int p = b / LR;
       const int j = b - p * LR;
@@ -347,7 +347,7 @@ __device__ __forceinline__ void ct_stage_last(const cplx<T>* in, int nseq, const
   const int nb = nseq * LR;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int b = threadIdx.x + NT * q;
+    const int b = CGP_TID + NT * q;
     if (b < nb) {
       const int p = b / LR;
       const int j = b - p * LR;  // = j mod Ns
@@ -445,7 +445,7 @@ __host__ __device__ constexpr int fft_special(int L) {
 template <typename T>
 __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __restrict__ src,
                                               int n) {
-  for (int m = threadIdx.x; m < n; m += kThreads) dst[m] = src[m];
+  for (int m = CGP_TID; m < n; m += kThreads) dst[m] = src[m];
 }
 
 }  // namespace cgp

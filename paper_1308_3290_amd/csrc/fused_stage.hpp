@@ -1,0 +1,383 @@
+// The fused stage pass (passes C + D and the next stage's pass A, one
+// layer) as a block-level device function, shared by the fused-pass kernel
+// and the persistent stage kernel of ensembles.  See fused_kernels.hip for
+// the block's phases.
+#pragma once
+
+#include "cgp_internal.hpp"
+#include "fft_lds.hpp"
+#include "stencil.hpp"
+
+namespace cgp {
+
+// Vorticity tile rows of a block (KW elements per thread; element e of the
+// tile is tile row e / pitch, column e % pitch, tracked incrementally); the
+// ring and the rows outside 1 .. ny-1 are stored as 0, so that the stencil
+// reads the tile without masks.
+template <typename T, int NT, int KW>
+__device__ __forceinline__ void load_tile(const T* __restrict__ W, long long g0, int nW, int RB0,
+                                          int pitch, int nx, int ny, T (&wv)[KW]) {
+  const int t = CGP_TID;
+  int er = t / pitch, ec = t - er * pitch;
+  const int dr = NT / pitch, dc = NT - dr * pitch;
+#pragma unroll
+  for (int q = 0; q < KW; ++q) {
+    const int e = t + NT * q;
+    const int fr = RB0 + er;
+    const bool in = e < nW && fr >= 1 && fr <= ny - 1 && ec >= 1 && ec <= nx - 1;
+    const T v = W[in ? g0 + e : 0];
+    wv[q] = in ? v : T(0);
+    er += dr;
+    ec += dc;
+    if (ec >= pitch) {
+      ec -= pitch;
+      ++er;
+    }
+  }
+}
+
+// Waves per SIMD the register allocation must allow: four (two blocks per
+// CU, which ensembles of many blocks need) where that fits without spills.
+__host__ __device__ constexpr int fused_waves_per_simd(int c, int lc) {
+  return (c <= 2 && lc != 0) ? 4 : 2;
+}
+
+// C: coarsening factor; TJ: coarse rows owned per block; LC: transform
+// length with a compile-time transform, or 0.  NEXT: also restrict the new
+// vorticity of the block's coarse rows and transform it along x (pass A of
+// the next stage), which needs it on the C-1 fine rows below the block too;
+// those rows are computed here as well but not stored.
+// One block of the fused pass: member d's coarse rows lb*TJ .. lb*TJ+TJ-1,
+// kFusedThreads threads; smem is the block's dynamic LDS.  EARLY: issue the
+// vorticity tile loads with the spectra (the faster order at c = 2) rather
+// than once the spectra are in LDS (fewer registers live across the
+// transform).
+template <typename T, int C, int TJ, int LC, bool NEXT, bool EARLY = (C == 2)>
+__device__ __forceinline__ void fused_stage_block(
+    const MemberDesc& d, int lb, const T* __restrict__ wt, T* __restrict__ wnext,
+    const cplx<T>* __restrict__ twg, const T* __restrict__ ws, const T* __restrict__ forcing,
+    const T* __restrict__ wn, T* __restrict__ out, T* __restrict__ psi_out, double a_,
+    double b_, StepCtl ctl, unsigned char* smem) {
+  constexpr int NT = kFusedThreads;
+  constexpr int NR = C * TJ + 1;      // the most own fine rows (+1: top wall row)
+  constexpr int E = NEXT ? C - 1 : 0;  // computed rows below the block
+  constexpr int NO = NR + E;          // the most computed rows
+  constexpr int NP = NO + 2;          // tile rows: computed rows and one on each side
+  constexpr int OFF = C - 1 - E;      // tile row u is fine row C*(j0-1) + OFF + u
+  constexpr int NSQ = fused_nseq(TJ);  // complex sequences of the inverse transform
+  constexpr int NQ = (TJ + 1) / 2;     // complex sequences of the next stage's transform
+  // twiddles per thread: (R-1) Ns summed over the stages, < L <= 1024
+  constexpr int kTwPer = ((LC ? stage_plan(LC).ntw : 1023) + NT - 1) / NT;
+  static_assert(kFusedMaxNx - 1 <= NT, "one spectral column and one fine column per thread");
+  constexpr int kWPer = (NP * (kFusedMaxNx + 1) + NT - 1) / NT;
+  const int t = CGP_TID;
+  // with a compile-time transform length the row sizes are constants too
+  // (Lr = 2 Mx, nx = C Mx), which turns tile and row addresses into
+  // immediate offsets
+  const int Mx = LC ? LC / 2 : d.Mx, My = d.My, L = LC ? LC : d.Lr;
+  const int nx = LC ? C * (LC / 2) : d.nx, ny = d.ny, pitch = nx + 1;
+  const int LP = lpad(L);
+  const int ntw = d.ntw_r;
+
+  // coarse rows j0-1 .. j0+TJ are synthesised in the global pairs (2m-1, 2m),
+  // so that every block that synthesises a row gets the same bits for it
+  const int j0 = lb * TJ;
+  const int rlo = max(1, j0 - 1);
+  const int ilo = rlo - ((rlo & 1) ? 0 : 1);      // odd: first row of its pair
+  const int rhi = min(My - 1, j0 + TJ);
+  const int ihi = min(My - 1, rhi + (rhi & 1));   // even: last row of its pair
+                                                  // (My-1 odd: its partner is the wall)
+  const int nint = ihi >= ilo ? ihi - ilo + 1 : 0;
+  const int nseq = (nint + 1) / 2;
+  const int last = (lb == d.nblk[PASS_CD] - 1);
+  const int R0 = C * j0;
+  const int R1 = last ? ny + 1 : C * (j0 + TJ);  // exclusive end of the own rows
+  const int nfr = R1 - R0;                       // own rows (<= NR)
+  const int nrow = nfr + E;                      // computed rows: tile rows 1 .. nrow
+  const int RB0 = R0 - 1 - E;                    // fine row of tile row 0
+  const int nW = (nrow + 2) * pitch;
+
+  // LDS: [ FFT buffers | later the vorticity tile | later the restriction
+  // rows and the next transform's buffers ] [ twiddles ] [ coarse psi rows ].
+  // Sharing the first region keeps the block small enough for two blocks per
+  // CU when there are many (ensembles).
+  const int region =
+      (max(2 * NSQ * LP * (int)sizeof(cplx<T>), NP * pitch * (int)sizeof(T)) + 15) & ~15;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  T* wtile = reinterpret_cast<T*>(smem);
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + region);
+  T* psc = reinterpret_cast<T*>(tw + ntw);
+  const int prow = Mx + 1;
+
+  // ---- global loads are unconditional (a lane without an element reads
+  // element 0 of the same array and discards it), so that they sit in one
+  // basic block.  The transform's twiddles and spectra come first.
+  T twx[kTwPer], twy[kTwPer];
+#pragma unroll
+  for (int q = 0; q < kTwPer; ++q) {
+    const int m = t + NT * q;
+    const cplx<T> z = twg[d.twr_off + (m < ntw ? m : 0)];
+    twx[q] = z.x;
+    twy[q] = z.y;
+  }
+  // Spectra: row pair p of column k (rows ilo+2p, ilo+2p+1, consecutive in
+  // the column) is one load; item c = (k-1) NSQ + p, so that neighbouring
+  // lanes read neighbouring pairs.  A pair whose second row is the wall row
+  // My is read one element lower, which keeps the load inside the column.
+  const T* w = wt + d.wt_off;
+  constexpr int kPairs = ((kFusedMaxNx / C - 1) * NSQ + NT - 1) / NT;
+  upair<T> sp[kPairs];
+#pragma unroll
+  for (int q = 0; q < kPairs; ++q) {
+    const int c = t + NT * q;
+    const int k = 1 + c / NSQ, p = c - (k - 1) * NSQ;
+    const int r0 = ilo + 2 * p;
+    const bool in = k < Mx && p < nseq;
+    const bool top = r0 + 1 > My - 1;
+    const size_t e = (size_t)(k - 1) * (My - 1) + (r0 - 1) - (top ? 1 : 0);
+    const upair<T> v = *reinterpret_cast<const upair<T>*>(w + (in ? e : 0));
+    upair<T> z;
+    z.x = in ? (top ? v.y : v.x) : T(0);
+    z.y = in && !top ? v.y : T(0);
+    sp[q] = z;
+  }
+  constexpr bool kEarlyTile = EARLY;
+  T wv[kWPer];
+  if constexpr (kEarlyTile)
+    load_tile<T, NT, kWPer>(ws + d.field_off, (long long)RB0 * pitch, nW, RB0, pitch, nx, ny, wv);
+  // ---- twiddles and the two packed sequences (odd extension) into LDS
+#pragma unroll
+  for (int q = 0; q < kTwPer; ++q) {
+    const int m = t + NT * q;
+    if (m < ntw) tw[m] = {twx[q], twy[q]};
+  }
+  if (t < nseq) {
+    buf[t * LP + pad(0)] = {T(0), T(0)};
+    buf[t * LP + pad(Mx)] = {T(0), T(0)};
+  }
+#pragma unroll
+  for (int q = 0; q < kPairs; ++q) {
+    const int c = t + NT * q;
+    const int k = 1 + c / NSQ, p = c - (k - 1) * NSQ;
+    if (k < Mx && p < nseq) {
+      const cplx<T> z = {sp[q].x, sp[q].y};
+      buf[p * LP + pad(k)] = z;
+      buf[p * LP + pad(2 * Mx - k)] = {-z.x, -z.y};
+    }
+  }
+  const T* W = ws + d.field_off;
+  const T* FF = forcing + d.field_off;
+  const T* WN = wn + d.field_off;
+  T* O = out + d.field_off;
+  const long long g0 = (long long)RB0 * pitch;
+  // ---- the stencil's inputs, issued once the transform's inputs are in
+  // LDS: they arrive while the transform runs
+  if constexpr (!kEarlyTile) load_tile<T, NT, kWPer>(W, g0, nW, RB0, pitch, nx, ny, wv);
+  // forcing and omega_n at the thread's column x = 1 + t, computed rows
+  const int x = 1 + t;
+  T fv[NO], nv[NO];
+#pragma unroll
+  for (int u = 1; u <= NO; ++u) {
+    const int rr = RB0 + u;
+    const bool in = x < nx && u <= nrow && rr >= 1 && rr < ny;
+    const size_t o = in ? (size_t)rr * pitch + x : 0;
+    const T f = FF[o], n = WN[o];
+    fv[u - 1] = in ? f : T(0);
+    nv[u - 1] = in ? n : T(0);
+  }
+
+  const cplx<T>* Z =
+      fft_runn<T, LC, NT, NSQ>(buf, buf + NSQ * LP, nseq, L, d.nst_r, d.stw_r, tw);
+
+  // ---- coarse psi rows J = j0-1 .. j0+TJ (zero walls) into psc
+  for (int i = t; i <= Mx; i += NT) {
+#pragma unroll
+    for (int r = 0; r < TJ + 2; ++r) {
+      const int J = j0 - 1 + r;
+      T v = T(0);
+      if (J >= 1 && J <= My - 1 && i >= 1 && i <= Mx - 1) {
+        const int idx = J - ilo;
+        const cplx<T> zi = Z[(idx >> 1) * LP + pad(i)];
+        v = (idx & 1) ? T(0.5) * zi.x : T(-0.5) * zi.y;
+      }
+      psc[r * prow + i] = v;
+    }
+  }
+  __syncthreads();  // the transform's output is consumed: the tile may overwrite it
+#pragma unroll
+  for (int q = 0; q < kWPer; ++q) {
+    const int e = t + NT * q;
+    if (e < nW) wtile[e] = wv[q];
+  }
+  __syncthreads();
+
+  // ---- walls: columns 0 and nx of the own rows (of psi_out too)
+  T* PO = psi_out ? psi_out + d.field_off : nullptr;
+  if (t < nfr) {
+    O[(size_t)(R0 + t) * pitch] = T(0);
+    if (PO) PO[(size_t)(R0 + t) * pitch] = T(0);
+  } else if (t >= 64 && t < 64 + nfr) {
+    O[(size_t)(R0 + t - 64) * pitch + nx] = T(0);
+    if (PO) PO[(size_t)(R0 + t - 64) * pitch + nx] = T(0);
+  }
+
+  // ---- stencil + RK3 on the computed rows (tile row u = fine row RB0 + u)
+  const T dt = stage_dt<T>(d, ctl), a = T(a_), b = T(b_);
+  const T cj = T(d.cj), cb = T(d.cb);
+  const T idx2 = T(d.idx2), idy2 = T(d.idy2);
+  const T nu = T(d.inv_re);
+  constexpr T kInvC2 = T(1) / T(C * C);
+  T res[NO];
+#pragma unroll
+  for (int u = 0; u < NO; ++u) res[u] = T(0);
+  if (x < nx) {
+    // P[dx][u]: psi at fine column x-1+dx, tile row u (bilinear, Sec. 3.1):
+    // x weights (C - fx, fx)/C^2 on the coarse columns I, I+1 (I+1 clamped
+    // to the wall column Mx), then the compile-time y weights (C - fy, fy).
+    // The coarse rows are prow apart; prow is a constant when L is.
+    const int prow_c = LC ? LC / 2 + 1 : prow;
+    T P[3][NP];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int xx = x - 1 + dx;  // 0 .. nx
+      T cv[TJ + 2];
+      if constexpr (C == 1) {
+#pragma unroll
+        for (int r = 0; r < TJ + 2; ++r) cv[r] = psc[r * prow_c + xx];
+      } else {
+        const int I = xx / C, fx = xx - I * C;
+        const T a0 = T(C - fx) * kInvC2, a1 = T(fx) * kInvC2;
+        const T* p0 = psc + I;
+        const T* p1 = psc + min(I + 1, Mx);
+#pragma unroll
+        for (int r = 0; r < TJ + 2; ++r) cv[r] = a0 * p0[r * prow_c] + a1 * p1[r * prow_c];
+      }
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        // fine row C*(j0-1) + m: coarse row j0-1+jr, weight fy toward jr+1
+        // (rows past the last coarse row are never used; they are clamped)
+        const int m = OFF + u;
+        const int jr = m / C, fy = m - jr * C;
+        const T top = jr + 1 < TJ + 2 ? cv[jr + 1 < TJ + 2 ? jr + 1 : TJ + 1] : T(0);
+        const T on = T(C - fy) * cv[jr < TJ + 2 ? jr : TJ + 1];
+        P[dx][u] = fy == 0 ? on : on + T(fy) * top;  // fy is a constant here
+      }
+    }
+    // rows 1 .. NO-1 exist in every block (the last block's row NO is the top
+    // wall); rows below 1 (first block) are computed from zeros and dropped
+    const T* wt0 = wtile + x;
+    T ws0 = wt0[-1], ws1 = wt0[0], ws2 = wt0[1];
+    T wc0 = wt0[pitch - 1], wc1 = wt0[pitch], wc2 = wt0[pitch + 1];
+#pragma unroll
+    for (int u = 1; u < NO; ++u) {
+      const T* wr = wt0 + (u + 1) * pitch;
+      const T wn0 = wr[-1], wn1 = wr[0], wn2 = wr[1];
+      const int rr = RB0 + u;
+      Nbr<T> p, w;
+      p.C = P[1][u]; p.E = P[2][u]; p.W = P[0][u];
+      p.N = P[1][u + 1]; p.S = P[1][u - 1];
+      p.NE = P[2][u + 1]; p.NW = P[0][u + 1];
+      p.SE = P[2][u - 1]; p.SW = P[0][u - 1];
+      w.C = wc1; w.E = wc2; w.W = wc0;
+      w.N = wn1; w.S = ws1;
+      w.NE = wn2; w.NW = wn0;
+      w.SE = ws2; w.SW = ws0;
+      const T G = -cj * arakawa12(p, w) - cb * beta3(p) + nu * lap5(w, idx2, idy2) + fv[u - 1];
+      T v = a * nv[u - 1] + b * (w.C + dt * G);  // a = 0 in stage 1
+      v = rr >= 1 ? v : T(0);
+      if (u > E) {
+        O[(size_t)rr * pitch + x] = v;
+        if (PO) PO[(size_t)rr * pitch + x] = P[1][u];  // the prolonged psi (0 on wall rows)
+      }
+      res[u - 1] = v;
+      ws0 = wc0; ws1 = wc1; ws2 = wc2;
+      wc0 = wn0; wc1 = wn1; wc2 = wn2;
+    }
+    if (last) {  // the top wall row
+      O[(size_t)ny * pitch + x] = T(0);
+      if (PO) PO[(size_t)ny * pitch + x] = T(0);
+    }
+  }
+  // last stage of an adaptive step: the velocity maxima for the next dt
+  if (wants_vmax(d, ctl)) put_vmax_coarse<T, C, TJ, NT>(d, ctl, lb, psc, nullptr, prow, j0);
+  if constexpr (NEXT) {
+    // ---- pass A of the next stage on the block's coarse rows j0 .. j0+TJ-1:
+    // their full-weighting stencils cover the computed rows R0-E .. R1-1
+    // (row k of rt = fine row R0-E+k = tile row k+1), Sec. 3.1 and 4.3
+    constexpr int NRT = C * (TJ + 1) - 1;
+    T* rt = wtile;
+    __syncthreads();  // every thread is done with wtile and psc
+    if (x < nx) {
+#pragma unroll
+      for (int k = 0; k < NRT; ++k) rt[k * pitch + x] = res[k];
+    }
+    __syncthreads();
+    const int i = 1 + t;
+    cplx<T> z[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) z[q] = {T(0), T(0)};
+    if (i < Mx) {
+      // x-weighted sums of each fine row, then the y weights (as pass A)
+      T racc[NRT];
+#pragma unroll
+      for (int q = 0; q < NRT; ++q) {
+        const T* row = rt + q * pitch + C * i;
+        T acc = T(0);
+#pragma unroll
+        for (int dx = -(C - 1); dx <= C - 1; ++dx) acc += T(C - (dx < 0 ? -dx : dx)) * row[dx];
+        racc[q] = acc;
+      }
+      T v[2 * NQ];
+#pragma unroll
+      for (int r = 0; r < 2 * NQ; ++r) v[r] = T(0);
+#pragma unroll
+      for (int r = 0; r < TJ; ++r) {
+        T acc = T(0);
+#pragma unroll
+        for (int dy = -(C - 1); dy <= C - 1; ++dy)
+          acc += T(C - (dy < 0 ? -dy : dy)) * racc[C * r + dy + (C - 1)];
+        v[r] = acc * (T(1) / T(C * C * C * C));
+      }
+      // packed as pass A packs them (rows in pairs (2m, 2m+1), the wall row 0
+      // as 0), so that both give the same spectra bit for bit
+      if (j0 == 0) v[0] = T(0);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) z[q] = {v[2 * q], v[2 * q + 1]};
+    }
+    __syncthreads();  // rt is read: the transform buffers may overwrite it
+    if (i < Mx) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        buf[q * LP + pad(i)] = z[q];
+        buf[q * LP + pad(2 * Mx - i)] = {-z[q].x, -z[q].y};
+      }
+    }
+    if (t < NQ) {
+      buf[t * LP + pad(0)] = {T(0), T(0)};
+      buf[t * LP + pad(Mx)] = {T(0), T(0)};
+    }
+    const cplx<T>* Z2 = fft_runn<T, LC, NT, (NQ > 2 ? 4 : 2)>(buf, buf + NQ * LP, NQ, L, d.nst_r,
+                                                              d.stw_r, tw);
+    if (i < Mx) {
+      // rows j0+2q, j0+2q+1 are consecutive in column i: one store per pair
+      T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int j = j0 + 2 * q;
+        const cplx<T> zk = Z2[q * LP + pad(i)];
+        const T v0 = T(-0.5) * zk.y, v1 = T(0.5) * zk.x;
+        if (2 * q + 1 < TJ && j >= 1 && j + 1 <= My - 1) {
+          upair<T> pr;
+          pr.x = v0;
+          pr.y = v1;
+          *reinterpret_cast<upair<T>*>(wo + j - 1) = pr;
+        } else {
+          if (j >= 1 && j <= My - 1) wo[j - 1] = v0;
+          if (2 * q + 1 < TJ && j + 1 <= My - 1) wo[j] = v1;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace cgp

@@ -111,8 +111,8 @@ cgp_status validate(const cgp_config* c) {
 struct Layout {
   // wt: spectra of omega (pass A out, pass B in); wt2: spectra of psi (pass B
   // out, pass C / fused pass in)
-  size_t desc = 0, order = 0, tw = 0, lam = 0, ctl = 0, mgm = 0, wt = 0, wt2 = 0, psi = 0,
-         st1 = 0, st2 = 0, diag = 0, fin = 0, mg = 0, total = 0;
+  size_t desc = 0, order = 0, tw = 0, lam = 0, ctl = 0, mgm = 0, ptile = 0, pctr = 0, wt = 0,
+         wt2 = 0, psi = 0, st1 = 0, st2 = 0, diag = 0, fin = 0, mg = 0, total = 0;
   long long field_elems = 0;
 };
 
@@ -151,9 +151,14 @@ struct Plan {
   // the same members; the chains of a step are independent, so a captured
   // step runs them on separate streams (ensembles of several sizes)
   std::vector<std::pair<int, int>> chains;
+  // persistent stage kernel (one launch per RK3 stage over every member):
+  // available when every member takes it (persistent_lengths), its launch
+  // setting, the LDS a workgroup needs and the most tiles the queue can hold
+  bool persist_ok = false;
+  cgp_launch launch{0, 1, 1, 0};
+  size_t persist_lds = 0;
+  int persist_max_tiles = 0;
 };
-
-constexpr int kGenericThreads = 256;
 
 // Group the members of one transform pass by length and size each launch.
 // `len` gives a member's transform length, `fill` sets its per-block share
@@ -375,6 +380,28 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   }
   L.ctl = off; off = align_up(off + (size_t)ctl * sizeof(double));
   L.mgm = off; off = align_up(off + (size_t)plan->mg_nb * plan->mg_nb * sizeof(double));
+  // persistent stage kernel: the tile queue (at most one tile per block of
+  // passes B and CD) and its counters, zero at create
+  plan->persist_ok = plan->fused && nl == 1;
+  plan->persist_max_tiles = 0;
+  for (const MemberDesc& d : plan->md) {
+    plan->persist_ok = plan->persist_ok && persistent_lengths(d.c, d.Lr, d.Lc);
+    plan->persist_max_tiles += d.nblk[PASS_B] + d.nblk[PASS_CD];
+  }
+  if (plan->persist_ok) {
+    for (const MemberDesc& d : plan->md) {
+      const size_t b_lds = (size_t)2 * lpad(d.Lc) * cs;  // compile-time column transform
+      size_t f_lds = 0;
+      for (const HostGroup& g : plan->groups[3])
+        for (int m : g.members)
+          if (&plan->md[m] == &d) f_lds = g.lds;
+      plan->persist_lds = std::max(plan->persist_lds, std::max(b_lds, f_lds));
+    }
+  }
+  L.ptile = off;
+  off = align_up(off + (plan->persist_ok ? sizeof(PTile) * plan->persist_max_tiles : 0));
+  L.pctr = off;
+  off = align_up(off + (plan->persist_ok ? sizeof(int) * (kPersistCounters + count) : 0));
   L.wt = off; off = align_up(off + (size_t)wt * es);
   L.wt2 = off; off = align_up(off + (size_t)wt * es);
   L.field_elems = fld;
@@ -410,6 +437,8 @@ struct cgp_handle {
   // side streams and events of chained graph captures (made on first use)
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> events;
+  // persistent stage kernel: tiles in the queue and the launch grid
+  int persist_ntiles = 0, persist_grid = 0;
   int nm() const { return (int)plan.md.size(); }
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   const MemberDesc* d_md() const { return at<MemberDesc>(plan.lay.desc); }
@@ -608,6 +637,38 @@ hipError_t enqueue_step_fused(cgp_handle* h, T* omega, const T* forcing, int pos
   return hipSuccess;
 }
 
+// One CGPRK3 step as three launches of the persistent stage kernel, with the
+// state rotation of enqueue_step_fused (the spectra of the state must be in
+// place on entry).
+template <typename T>
+hipError_t enqueue_step_persistent(cgp_handle* h, T* omega, const T* forcing, int pos,
+                                   hipStream_t s) {
+  const Plan& p = h->plan;
+  T* bufs[3] = {omega, h->at<T>(p.lay.st1), h->at<T>(p.lay.st2)};
+  T* S = bufs[pos];
+  T* X = bufs[(pos + 1) % 3];
+  T* Y = bufs[(pos + 2) % 3];
+  const T* src[3] = {S, X, Y};
+  T* dst[3] = {X, Y, X};
+  double* ctl = h->at<double>(p.lay.ctl);
+  for (int st = 0; st < 3; ++st) {
+    hipError_t e = PersistLaunch<T>::stage(
+        h->d_md(), h->at<PTile>(p.lay.ptile), h->persist_ntiles, h->at<int>(p.lay.pctr), h->nm(),
+        h->persist_grid, p.persist_lds, h->at<T>(p.lay.wt), h->at<T>(p.lay.wt2),
+        h->at<cplx<T>>(p.lay.tw), h->at<double>(p.lay.lam), st == 0 ? ctl : nullptr, src[st],
+        forcing, S, dst[st], kRkA[st], kRkB[st], StepCtl{ctl, st == 2}, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// A fused step in the handle's launch mode.
+template <typename T>
+hipError_t enqueue_step_mode(cgp_handle* h, T* omega, const T* forcing, int pos, hipStream_t s) {
+  return h->plan.launch.mode == 1 ? enqueue_step_persistent<T>(h, omega, forcing, pos, s)
+                                  : enqueue_step_fused<T>(h, omega, forcing, pos, s);
+}
+
 // One fused step into explicit buffers (the adjoint's tape): stage inputs
 // w[0..2] (w[0] holds omega_n, and the spectra of w[0] must be in place),
 // stream functions psi[0..2], result wnext (distinct from all of them).
@@ -646,6 +707,32 @@ hipError_t enqueue_pass_reps(cgp_handle* h, int p, const T* omega, const T* forc
   return hipSuccess;
 }
 
+// The work queue of the persistent stage kernel for launch setting l: every
+// member's pass-B tiles (l.b_tile column pairs each), then every member's
+// fused tiles (l.f_tile row blocks each), members in order.
+std::vector<PTile> persist_tiles(const Plan& p, const cgp_launch& l) {
+  std::vector<PTile> t;
+  for (int kind = 0; kind < 2; ++kind)
+    for (int m = 0; m < (int)p.md.size(); ++m) {
+      const int n = p.md[m].nblk[kind == 0 ? PASS_B : PASS_CD];
+      const int per = kind == 0 ? l.b_tile : l.f_tile;
+      for (int lb = 0; lb < n; lb += per) t.push_back(PTile{m, kind, lb, std::min(per, n - lb)});
+    }
+  return t;
+}
+
+// Launch grid of the persistent kernel: wg_per_cu (or as many workgroups as
+// can be resident) per compute unit, at most one per tile.
+template <typename T>
+cgp_status persist_grid(cgp_handle* h, int ntiles, int* grid) {
+  int dev = 0, ncu = 0, per = h->plan.launch.wg_per_cu;
+  HIP_TRY(hipGetDevice(&dev), "device");
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+  if (per <= 0) HIP_TRY(PersistLaunch<T>::blocks_per_cu(h->plan.persist_lds, &per), "occupancy");
+  *grid = std::max(1, std::min(ntiles, std::max(1, per) * ncu));
+  return CGP_OK;
+}
+
 // The dynamic-LDS cap is an attribute of the kernel function, shared by every
 // handle of the process: it is raised once to the whole 160 KiB a workgroup
 // may use (it only bounds what a launch may request), never lowered, so that
@@ -658,6 +745,7 @@ hipError_t allow_full_lds() {
     if (e == hipSuccess) e = Launch<T>::prepare_fused(kMaxLds);
     if (e == hipSuccess) e = Launch<T>::prepare_fused2(kMaxLds);
     if (e == hipSuccess && sizeof(T) == 8) e = AdjLaunch::prepare_fused(kMaxLds);
+    if (e == hipSuccess) e = PersistLaunch<T>::prepare(kMaxLds);
     return e;
   }();
   return once;
@@ -708,6 +796,14 @@ cgp_status create_tables(cgp_handle* h, hipStream_t s) {
       const double sn = std::sin(pi * l / (2.0 * d.My));
       ly[l - 1] = -4.0 * sn * sn / (hy * hy);
     }
+  }
+  // the persistent kernel's work queue (its counters stay 0)
+  if (p.persist_ok) {
+    const std::vector<PTile> t = persist_tiles(p, p.launch);
+    std::memcpy(h->host_tables.data() + L.ptile, t.data(), t.size() * sizeof(PTile));
+    h->persist_ntiles = (int)t.size();
+    cgp_status st = persist_grid<T>(h, h->persist_ntiles, &h->persist_grid);
+    if (st != CGP_OK) return st;
   }
   // step state: dt of the latest step = the configured dt, time 0, maxima 0
   double* ctl = reinterpret_cast<double*>(h->host_tables.data() + L.ctl);
@@ -826,7 +922,7 @@ cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, double* sum, hip
     return CGP_OK;
   }
   const size_t nch = h->plan.chains.size();
-  if (h->plan.fused && nch > 1 && !sum && h->side.size() + 1 < nch) {
+  if (h->plan.fused && nch > 1 && !sum && h->plan.launch.mode == 0 && h->side.size() + 1 < nch) {
     // side streams (default priority) and fork / join events, made once
     while (h->side.size() + 1 < nch) {
       hipStream_t st = nullptr;
@@ -846,7 +942,7 @@ cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, double* sum, hip
   if (!h->plan.fused) {
     e = enqueue_step<T>(h, w, F, s);
     if (e == hipSuccess && sum) e = enqueue_mean<T>(h, w, sum, s);
-  } else if (nch > 1 && !sum) {
+  } else if (nch > 1 && !sum && h->plan.launch.mode == 0) {
     // independent member chains forked onto side streams and joined back
     const int nc = (int)nch;
     hipEvent_t* ev = h->events.data();
@@ -860,7 +956,7 @@ cgp_status step_graph(cgp_handle* h, T* w, const T* F, int pos, double* sum, hip
     for (int k = 1; k < nc && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, ev[k], 0);
   } else {
     for (int q = q0; q < q1 && e == hipSuccess; ++q) {
-      e = enqueue_step_fused<T>(h, w, F, q, s);
+      e = enqueue_step_mode<T>(h, w, F, q, s);
       if (e == hipSuccess && sum) e = enqueue_mean<T>(h, fused_state_after<T>(h, w, q), sum, s);
     }
   }
@@ -911,7 +1007,7 @@ cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_
         n += done;
         pos = (pos + done) % 3;
       } else {
-        HIP_TRY(enqueue_step_fused<T>(h, w, F, pos, s), "step launch");
+        HIP_TRY(enqueue_step_mode<T>(h, w, F, pos, s), "step launch");
         if (sum) HIP_TRY(enqueue_mean<T>(h, fused_state_after<T>(h, w, pos), sum, s),
                          "accumulate launch");
         ++n;
@@ -1188,6 +1284,60 @@ cgp_status cgp_time_passes(cgp_handle* h, const void* omega, const void* forcing
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;
+}
+
+cgp_status cgp_set_launch(cgp_handle* h, const cgp_launch* l, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!l) return fail(CGP_ERR_INVALID, "launch is NULL");
+  if (l->mode != 0 && l->mode != 1) return fail(CGP_ERR_INVALID, "mode must be 0 or 1");
+  if (l->b_tile < 1 || l->f_tile < 1) return fail(CGP_ERR_INVALID, "tiles must be >= 1");
+  if (l->wg_per_cu < 0 || l->wg_per_cu > 16) return fail(CGP_ERR_INVALID, "wg_per_cu in 0..16");
+  Plan& p = h->plan;
+  if (l->mode == 1 && !p.persist_ok)
+    return fail(CGP_ERR_UNSUPPORTED,
+                "the persistent stage kernel takes one layer at coarsening factor 2 with row "
+                "transforms of 128-512 and column transforms of 256-1024 points");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  p.launch = *l;
+  if (p.persist_ok) {
+    // the queue of the new tiles (same counters: they are zero between launches)
+    const std::vector<PTile> t = persist_tiles(p, p.launch);
+    char* img = h->host_tables.data() + p.lay.ptile;
+    std::memcpy(img, t.data(), t.size() * sizeof(PTile));
+    h->persist_ntiles = (int)t.size();
+    HIP_TRY(hipMemcpyAsync(h->ws + p.lay.ptile, img, t.size() * sizeof(PTile),
+                           hipMemcpyHostToDevice, s),
+            "tile upload");
+    HIP_TRY(hipStreamSynchronize(s), "tile upload sync");
+    const cgp_status st = p.dtype == CGP_F64
+                              ? persist_grid<double>(h, h->persist_ntiles, &h->persist_grid)
+                              : persist_grid<float>(h, h->persist_ntiles, &h->persist_grid);
+    if (st != CGP_OK) return st;
+  }
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+  return CGP_OK;
+}
+
+cgp_status cgp_get_launch(cgp_handle* h, cgp_launch* l, int32_t* available) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!l) return fail(CGP_ERR_INVALID, "launch is NULL");
+  *l = h->plan.launch;
+  if (available) *available = h->plan.persist_ok ? 1 : 0;
+  return CGP_OK;
+}
+
+cgp_status cgp_persistent_fault(cgp_handle* h, int32_t* flag, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!flag) return fail(CGP_ERR_INVALID, "flag is NULL");
+  *flag = 0;
+  if (!h->plan.persist_ok) return CGP_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(flag, h->ws + h->plan.lay.pctr + 2 * sizeof(int), sizeof(int),
+                         hipMemcpyDeviceToHost, s),
+          "fault flag read");
+  HIP_TRY(hipStreamSynchronize(s), "fault flag sync");
+  return CGP_OK;
 }
 
 cgp_status cgp_time_step_passes(cgp_handle* h, void* omega, const void* forcing, int32_t nsteps,

@@ -16,6 +16,7 @@
 // coarse column (or spectral index) and handle all of the block's rows in
 // registers, so that each thread issues its global loads together.
 #include "cgp_internal.hpp"
+#include "col_solve.hpp"
 #include "fft_lds.hpp"
 
 namespace cgp {
@@ -187,26 +188,10 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
   }
 }
 
-// ---------------------------------------------------------------------------
-// Pass B.  A block transforms one pair of coarse spectral columns (one layer:
-// columns k, k+1; two layers: the barotropic and baroclinic column k) along
-// y, multiplies by (2/Mx)(2/My)/lambda_kl (baroclinic: 1/(lambda_kl - F1 -
-// F2)), and transforms back, from the spectra of omega (win) to those of psi
-// (wout, same layout).  Loads are batched as in pass A.  The transforms use
-// the column plan (stage_plan(L, kWideCols)): one sequence per 256-thread
-// block has enough butterflies for radix 8 only from L = 2048 on.
-// ---------------------------------------------------------------------------
-// 1/x for the eigenvalues (negative, far from the overflow and subnormal
-// ranges): the hardware estimate refined by two Newton steps
-// r <- r + r (1 - x r), within an ulp or two of the quotient, at a third of
-// the instructions of a full IEEE division.
-__device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
 
+// ---------------------------------------------------------------------------
+// Pass B: one block per pair of spectral columns (col_solve.hpp).
+// ---------------------------------------------------------------------------
 template <typename T, int LC>
 __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __restrict__ md,
                                                         const int* __restrict__ grp, int ng,
@@ -217,148 +202,9 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
                                                         double* __restrict__ ctl) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kThreads / 64];  // step-size reduction
-  // twiddles: with a compile-time length each thread keeps the ones of its
-  // own butterflies in registers (no LDS table), else the block stages the
-  // table in LDS
-  constexpr int kTw = LC ? 1 : tw_per_thread<LC, kThreads, kWideCols>();
-  constexpr int kRegTw = LC ? reg_tw_count<LC, kThreads, 1, kWideCols>() : 1;
-  constexpr int kRowIter = 4;  // My - 1 <= 1023
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_B, blockIdx.x)];
-  const int lb = blockIdx.x - d.blk0[PASS_B];
-  // a compile-time transform length fixes the column length (Lc = 2 My)
-  const int Mx = d.Mx, My = LC ? LC / 2 : d.My, L = LC ? LC : d.Lc, nl = d.nlayers;
-  const int ntw = d.ntw_c;
-  const int ny1 = My - 1;
-  const int LP = lpad(L);
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* buf2 = buf + LP;
-  cplx<T>* tw = buf2 + LP;
-  const size_t mplane = (size_t)(Mx - 1) * (My - 1);
-  const double* lamx = lam + d.lam_off;
-  const double* lamy = lamx + (Mx - 1);
-  const double scale = 4.0 / ((double)Mx * (double)My);
-  const double shift = nl == 2 ? d.f1 + d.f2 : 0.0;
-
-  // the pair's columns (1-based); kb may be absent (one layer, Mx - 1 odd)
-  const int ka = nl == 1 ? 1 + 2 * lb : 1 + lb;
-  const int kb = nl == 1 ? ka + 1 : ka;
-  const bool has_b = kb <= Mx - 1;
-  const size_t offa = d.wt_off + (size_t)(ka - 1) * ny1;
-  const size_t offb = d.wt_off + (nl == 2 ? mplane : 0) + (size_t)((has_b ? kb : ka) - 1) * ny1;
-  const T* cola = win + offa;
-  const T* colb = win + offb;
-  const double lxa = lamx[ka - 1];
-  const double lxb = lamx[(has_b ? kb : ka) - 1] - shift;
-
-  T twx[kTw], twy[kTw];
-  cplx<T> rtw[kRegTw];
-  if constexpr (LC != 0) {
-    reg_tw_load<T, LC, 1, kThreads, 1, kWideCols>(rtw, twg + d.twc_off, 1);
-  } else {
-#pragma unroll
-    for (int q = 0; q < kTw; ++q) {
-      const int m = threadIdx.x + kThreads * q;
-      const cplx<T> z = twg[d.twc_off + (m < ntw ? m : 0)];
-      twx[q] = z.x;
-      twy[q] = z.y;
-    }
-  }
-  T va[kRowIter], vb[kRowIter];
-  double ly[kRowIter];
-#pragma unroll
-  for (int q = 0; q < kRowIter; ++q) {
-    const int l = min(1 + (int)threadIdx.x + kThreads * q, My - 1);
-    va[q] = cola[l - 1];
-    const T b = colb[l - 1];
-    vb[q] = has_b ? b : T(0);
-    ly[q] = lamy[l - 1];
-  }
-  if constexpr (LC == 0) {
-#pragma unroll
-    for (int q = 0; q < kTw; ++q) {
-      const int m = threadIdx.x + kThreads * q;
-      if (m < ntw) tw[m] = {twx[q], twy[q]};
-    }
-  }
-  if (threadIdx.x == 0) {
-    buf[pad(0)] = {T(0), T(0)};
-    buf[pad(My)] = {T(0), T(0)};
-  }
-#pragma unroll
-  for (int q = 0; q < kRowIter; ++q) {
-    const int l = 1 + threadIdx.x + kThreads * q;
-    if (l < My) {
-      buf[pad(l)] = {va[q], vb[q]};
-      buf[pad(2 * My - l)] = {-va[q], -vb[q]};
-    }
-  }
-  if constexpr (LC != 0) {
-    // Compile-time transform: the last stage of the forward transform divides
-    // by the eigenvalues and writes the synthesis input, and the last stage of
-    // the inverse stores the result (no separate LDS passes for either).
-    constexpr StagePlan P = stage_plan(LC, kWideCols);
-    constexpr int RL = P.R[P.n - 1], NSL = LC / RL;
-    constexpr int QL = (NSL + kThreads - 1) / kThreads;
-    // lambda_y at the outputs m = j + r L/R of the thread's last-stage butterflies
-    double lyl[QL][RL];
-#pragma unroll
-    for (int q = 0; q < QL; ++q)
-#pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int m = (int)threadIdx.x + kThreads * q + r * NSL;
-        lyl[q][r] = lamy[min(max(m, 1), My - 1) - 1];
-      }
-    constexpr bool kLastA = ct_last_reads_a<LC, kWideCols>();
-    cplx<T>* Y = kLastA ? buf2 : buf;
-    auto divide = [&](int, int m, cplx<T> z, int q, int r) {
-      if (m >= 1 && m < My) {
-        const T a = T(-0.5) * z.y * T(scale * recip(lxa + lyl[q][r]));
-        const T b = T(0.5) * z.x * T(scale * recip(lxb + lyl[q][r]));
-        Y[pad(m)] = {a, b};
-        Y[pad(2 * My - m)] = {-a, -b};
-      } else if (m == 0 || m == My) {
-        Y[pad(m)] = {T(0), T(0)};
-      }
-    };
-    ct_run_to<T, LC, kThreads, 1, kWideCols, true>(divide, buf, buf2, 1, rtw);
-    auto store = [&](int, int m, cplx<T> z, int, int) {
-      if (m >= 1 && m < My) {
-        wout[offa + m - 1] = T(-0.5) * z.y;
-        if (has_b) wout[offb + m - 1] = T(0.5) * z.x;
-      }
-    };
-    ct_run_to<T, LC, kThreads, 1, kWideCols, true>(store, Y, kLastA ? buf : buf2, 1, rtw);
-  } else {
-    cplx<T>* Z = fft_run<T, LC, kThreads, kWideCols>(buf, buf2, 1, L, d.nst_c, d.stw_c, tw);
-    cplx<T>* Y = (Z == buf) ? buf2 : buf;
-#pragma unroll
-    for (int q = 0; q < kRowIter; ++q) {
-      const int l = 1 + threadIdx.x + kThreads * q;
-      if (l < My) {
-        const cplx<T> z = Z[pad(l)];
-        const T a = T(-0.5) * z.y * T(scale * recip(lxa + ly[q]));
-        const T b = T(0.5) * z.x * T(scale * recip(lxb + ly[q]));
-        Y[pad(l)] = {a, b};
-        Y[pad(2 * My - l)] = {-a, -b};
-      }
-    }
-    if (threadIdx.x == 0) {
-      Y[pad(0)] = {T(0), T(0)};
-      Y[pad(My)] = {T(0), T(0)};
-    }
-    const cplx<T>* R = fft_run<T, LC, kThreads, kWideCols>(Y, Z, 1, L, d.nst_c, d.stw_c, tw);
-#pragma unroll
-    for (int q = 0; q < kRowIter; ++q) {
-      const int l = 1 + threadIdx.x + kThreads * q;
-      if (l < My) {
-        const cplx<T> z = R[pad(l)];
-        wout[offa + l - 1] = T(-0.5) * z.y;
-        if (has_b) wout[offb + l - 1] = T(0.5) * z.x;
-      }
-    }
-  }
-  // first stage of a step: the member's dt
-  if (ctl != nullptr && lb == 0) update_step_dt<kThreads>(d, ctl, red);
+  col_solve_block<T, LC, kThreads>(d, blockIdx.x - d.blk0[PASS_B], win, wout, twg, lam, ctl,
+                                   smem, red);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,143 @@
+"""The persistent stage kernel of ensembles (one launch per RK3 stage, a queue
+of work tiles and per-member counters) against the per-pass launches and the
+FP64 oracle: the same block-level code, so every member must get the same
+bits in both modes, for every tile setting, with graph replays and direct
+launches, fixed and adaptive steps."""
+import numpy as np
+import pytest
+import torch
+
+import cgp_inputs as ci
+from oracle import model as om
+
+from gpu_common import oracle_setup, rel_l2, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1308_3290_amd import _lib
+    _lib.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def _cases(dtype, cfl=0.0):
+    sizes = [(128, 256), (256, 512), (384, 768), (128, 256), (512, 1024), (256, 512)]
+    return [ci.make_case(nx, ny, level=1, inv_re=1.0 / (250 + 60 * k), dt=2.5e-5, cfl=cfl,
+                         dtype=dtype) for k, (nx, ny) in enumerate(sizes)]
+
+
+def _run(cases, w0s, Fs, nsteps, launch, use_graph):
+    from paper_1308_3290_amd.api import Ensemble, config_from_case
+    ens = Ensemble([config_from_case(c) for c in cases])
+    if launch is not None:
+        ens.set_launch(**launch)
+    W = ens.pack(w0s)
+    Fp = ens.pack(Fs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ens.step(W, Fp, nsteps=nsteps // 2, use_graph=use_graph, stream=side)
+        ens.step(W, Fp, nsteps=nsteps - nsteps // 2, use_graph=use_graph, stream=side)
+    torch.cuda.synchronize()
+    fault = ens.persistent_fault()
+    return ens, W, fault
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("launch", [dict(mode=1, b_tile=1, f_tile=1, wg_per_cu=0),
+                                    dict(mode=1, b_tile=4, f_tile=2, wg_per_cu=1),
+                                    dict(mode=1, b_tile=2, f_tile=3, wg_per_cu=2)])
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_persistent_stage_kernel_matches_per_pass_launches(dtype, launch, use_graph):
+    say(f"persistent {launch} dtype={dtype} graph={use_graph}: 6 members, 7 steps")
+    cases = _cases(dtype)
+    rng = np.random.default_rng(71)
+    w0s = [ci.initial_field(c, rng, 1.0) for c in cases]
+    Fs = [ci.forcing_field(c, 277.0 * (1 + 0.05 * k)) for k, c in enumerate(cases)]
+    ens0, W0, _ = _run(cases, w0s, Fs, 7, None, True)
+    ens1, W1, fault = _run(cases, w0s, Fs, 7, launch, use_graph)
+    assert ens1.launch()[0]["mode"] == 1 and ens1.launch()[1]
+    assert fault == 0
+    for m in range(len(cases)):
+        assert torch.equal(ens1.member_view(W1, m), ens0.member_view(W0, m)), f"member {m}"
+
+
+def test_persistent_adaptive_steps_match():
+    """cfl > 0: the first pass-B block of each member sets the step's dt inside
+    the persistent launch; every member's dt sequence and state must match."""
+    cases = _cases("f64", cfl=0.3)
+    rng = np.random.default_rng(72)
+    w0s = [ci.initial_field(c, rng, 1.0) for c in cases]
+    Fs = [ci.forcing_field(c) for c in cases]
+    ens0, W0, _ = _run(cases, w0s, Fs, 6, None, True)
+    ens1, W1, fault = _run(cases, w0s, Fs, 6, dict(mode=1, b_tile=2, f_tile=1, wg_per_cu=0), True)
+    assert fault == 0
+    assert torch.equal(ens0.time_state(), ens1.time_state())
+    assert torch.equal(W0, W1)
+
+
+def test_persistent_64_member_workload_follows_the_oracle():
+    """The 64-member FP64 workload in the persistent mode: every member equal
+    to the per-pass run, and a sample of members against the oracle."""
+    from paper_1308_3290_amd.api import Ensemble, config_from_case
+    members = ci.ensemble_c3(64, dtype="f64")
+    cases = [m.case for m in members]
+    w0s = [m.omega0 for m in members]
+    Fs = [m.forcing for m in members]
+    ens0, W0, _ = _run(cases, w0s, Fs, 4, None, True)
+    ens1, W1, fault = _run(cases, w0s, Fs, 4, dict(mode=1, b_tile=2, f_tile=1, wg_per_cu=0),
+                           True)
+    assert fault == 0
+    assert torch.equal(W0, W1)
+    for m in (0, 17, 40, 63):
+        c = cases[m]
+        g, phys = oracle_setup(c)
+        w = w0s[m]
+        for _ in range(4):
+            w = om.step(w, Fs[m], g, c.level, phys, c.dt)
+        err = rel_l2(to_np(ens1.member_view(W1, m)), w)
+        say(f"  member {m} {c.nx}x{c.ny}: rel L2 vs oracle {err:.3e}")
+        assert err < 1e-11
+
+
+def test_persistent_mode_refused_where_unavailable():
+    from paper_1308_3290_amd.api import CGPError, Ensemble, config_from_case
+    ens = Ensemble([config_from_case(ci.make_case(128, 256, level=0))])
+    assert ens.launch()[1] is False
+    with pytest.raises(CGPError, match="persistent"):
+        ens.set_launch(mode=1)
+    with pytest.raises(CGPError):
+        Ensemble([config_from_case(ci.make_case(128, 256, level=1))]).set_launch(mode=1, b_tile=0)
+
+
+def test_autotuner_caches_an_accepted_setting(tmp_path):
+    """The autotuner times every candidate on fresh handles, accepts only
+    those that reproduce the reference launch's bits, caches the fastest under
+    the workload key and returns it from the cache afterwards."""
+    from paper_1308_3290_amd import autotune
+    from paper_1308_3290_amd.api import Ensemble, config_from_case
+    cases = _cases("f32")[:3]
+    cfgs = [config_from_case(c) for c in cases]
+    rng = np.random.default_rng(73)
+    ens = Ensemble(cfgs)
+    W = ens.pack([ci.initial_field(c, rng, 1.0) for c in cases])
+    Fp = ens.pack([ci.forcing_field(c) for c in cases])
+    path = str(tmp_path / "tune.json")
+    report = []
+    setting = autotune.tune(cfgs, W, Fp, steps=6, warmup=2, repeats=2, cache=path, report=report)
+    say(f"autotune: {setting}; {len(report)} candidates, "
+        f"{sum(r['accepted'] for r in report)} accepted")
+    assert len(report) == len(autotune.candidates(True))
+    assert all(r["accepted"] for r in report)  # every launch form gives the reference bits
+    best = min(report, key=lambda r: r["ms_per_step"])
+    assert setting["launch"] == best["launch"] and setting["use_graph"] == best["use_graph"]
+    again = []
+    assert autotune.tune(cfgs, W, Fp, cache=path, report=again) == setting and again == []
+    import json
+    doc = json.load(open(path))
+    assert list(doc) == [autotune.workload_key(cfgs)]
