@@ -208,6 +208,13 @@ cgp_status cgp_diagnostics(cgp_handle* h, const void* omega_dev, const void* psi
 cgp_status cgp_check_finite(cgp_handle* h, const void* field_dev, int64_t count,
                             int32_t* flag_dev, void* stream);
 
+/* The same check, synchronous: CGP_OK if the count elements of field_dev
+ * (the handle's dtype) are all finite, CGP_ERR_NONFINITE if any is NaN or
+ * infinite.  Synchronises `stream`; the flag lives in the handle's
+ * workspace, so this call is not graph-capturable and must not overlap other
+ * work on the handle.  The time step itself never reads back. */
+cgp_status cgp_assert_finite(cgp_handle* h, const void* field_dev, int64_t count, void* stream);
+
 /* ------------------------------------------------------------------------
  * Adjoint (one-layer, FP64).  For w_{s+1} = a_s w_n + b_s (w_s + dt G(w_s)),
  * (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3), the adjoint reverses the stages:

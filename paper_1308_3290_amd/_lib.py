@@ -57,6 +57,7 @@ SIGNATURES = {
     "cgp_step_mean": (_I32, [_P, _P, _P, _I32, _P, _I32, _P]),
     "cgp_diagnostics": (_I32, [_P, _P, _P, _P, _P]),
     "cgp_check_finite": (_I32, [_P, _P, _I64, _P, _P]),
+    "cgp_assert_finite": (_I32, [_P, _P, _I64, _P]),
     "cgp_tape_size": (_I32, [_CFG, _I32, ctypes.POINTER(_SZ)]),
     "cgp_adjoint_step": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
     "cgp_ensemble_offsets": (_I32, [_CFG, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),

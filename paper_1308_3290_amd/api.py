@@ -116,6 +116,11 @@ def cgp_check_finite(h, field, flag, stream=None):
          ctypes.c_void_p(stream_ptr(stream)))
 
 
+def cgp_assert_finite(h, field, stream=None):
+    """Raises CGPError (CGP_ERR_NONFINITE) if field holds a NaN or an infinity."""
+    call("cgp_assert_finite", h, _ptr(field), field.numel(), ctypes.c_void_p(stream_ptr(stream)))
+
+
 def cgp_tape_size(cfg: cgp_config, nsteps: int) -> int:
     n = ctypes.c_size_t()
     call("cgp_tape_size", ctypes.byref(cfg), int(nsteps), ctypes.byref(n))
@@ -259,6 +264,10 @@ class Basin:
         flag = torch.empty(1, dtype=torch.int32, device=self.device)
         cgp_check_finite(self.handle, field, flag, stream)
         return flag
+
+    def assert_finite(self, field, stream=None):
+        _check_tensor(field, self.dtype, None, "field")
+        cgp_assert_finite(self.handle, field, stream)
 
     def time_state(self, stream=None):
         """FP64 device tensor [dt of the latest step, model time advanced]."""

@@ -70,6 +70,12 @@ struct MemberDesc {
   int nblk[NUM_PASSES]; // blocks of this member in each pass
   long long field_off;  // packed fine fields ([L][ny+1][nx+1] per member)
   long long wt_off;     // coarse spectra: L modes x (Mx-1) x (My-1), k-major
+  // One layer at c >= 4 (fused steps): the restriction of a coarse row is
+  // split into the sums over two blocks' own fine rows (split_restrict), A_j
+  // from rows c j .. c j + c-1 in the spectra at wt_off, B_j from rows
+  // c j - c+1 .. c j - 1 at wt_off + split_off; pass B adds the two.  0: the
+  // spectra hold whole restrictions.
+  long long split_off;
   long long twr_off;    // row twiddle tables, in complex elements of T (ntw_r values)
   long long twc_off;    // column twiddle tables (ntw_c values)
   long long lam_off;    // doubles: lambda_x (Mx-1) then lambda_y (My-1)
@@ -260,6 +266,7 @@ struct Group {
   int nblk, threads;  // threads = kThreads
   size_t lds;
   int nlayers;         // layers of every member of the handle
+  int split;           // some member has a split restriction (pass B adds its b spectra)
 };
 
 // Launch wrappers implemented in the kernel translation units.
@@ -272,8 +279,10 @@ struct Launch {
   // spectra of omega (win) to those of psi (wout)
   // With ctl != NULL (the first stage of a step) the member's first block
   // also sets the step's dt in the step state.
+  // split != 0: add the B partial spectra of split members (time steps and
+  // pass A); 0 where win holds whole restrictions (the adjoint's sources)
   static hipError_t col_solve(const MemberDesc* md, const Group& g, const T* win, T* wout,
-                              const cplx<T>* tw, const double* lam, double* ctl,
+                              const cplx<T>* tw, const double* lam, double* ctl, int split,
                               hipStream_t s);
   // pass C: inverse x sine transform + prolongation; accumulate != 0 adds to dst
   static hipError_t rowdst_prolong(const MemberDesc* md, const Group& g, const T* wt, T* dst,

@@ -32,13 +32,15 @@ __device__ __forceinline__ double recip(double x) {
 // of the block calls it; a block of more threads than the transform has
 // butterflies leaves the rest idle between the barriers).  smem is the
 // block's dynamic LDS, red NT/64 doubles of LDS for the step-size reduction.
-template <typename T, int LC, int NT>
+// SPLIT: a member with a split restriction (split_off) gets the sum of its a
+// and b spectra as the input (groups without such members skip the check).
+template <typename T, int LC, int NT, bool SPLIT = false>
 __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
                                                 const T* __restrict__ win, T* __restrict__ wout,
                                                 const cplx<T>* __restrict__ twg,
                                                 const double* __restrict__ lam,
-                                                double* __restrict__ ctl, unsigned char* smem,
-                                                double* red) {
+                                                double* __restrict__ ctl,
+                                                unsigned char* smem, double* red) {
   // twiddles: with a compile-time length each thread keeps the ones of its
   // own butterflies in registers (no LDS table), else the block stages the
   // table in LDS
@@ -92,6 +94,17 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
     const T b = colb[l - 1];
     vb[q] = has_b ? b : T(0);
     ly[q] = lamy[l - 1];
+  }
+  if (SPLIT && d.split_off != 0) {
+    // split restriction: the spectra of the b parts are added to those of
+    // the a parts (the x transform is linear)
+#pragma unroll
+    for (int q = 0; q < kRowIter; ++q) {
+      const int l = min(1 + CGP_TID + NT * q, My - 1);
+      va[q] += cola[d.split_off + l - 1];
+      const T b = colb[d.split_off + l - 1];
+      vb[q] += has_b ? b : T(0);
+    }
   }
   if constexpr (LC == 0) {
 #pragma unroll

@@ -60,7 +60,12 @@ __device__ __forceinline__ void fused_stage_block(
     double b_, StepCtl ctl, unsigned char* smem) {
   constexpr int NT = kFusedThreads;
   constexpr int NR = C * TJ + 1;      // the most own fine rows (+1: top wall row)
-  constexpr int E = NEXT ? C - 1 : 0;  // computed rows below the block
+  // c >= 4 (one coarse row per block): the next stage's restriction is split
+  // (split_restrict), so the block restricts its own fine rows only; c <= 2
+  // computes the C-1 rows below the block as well, for whole restrictions
+  constexpr bool SPLIT = NEXT && C >= 4;
+  static_assert(!SPLIT || TJ == 1, "split restriction: one coarse row per block");
+  constexpr int E = (NEXT && !SPLIT) ? C - 1 : 0;  // computed rows below the block
   constexpr int NO = NR + E;          // the most computed rows
   constexpr int NP = NO + 2;          // tile rows: computed rows and one on each side
   constexpr int OFF = C - 1 - E;      // tile row u is fine row C*(j0-1) + OFF + u
@@ -304,7 +309,7 @@ __device__ __forceinline__ void fused_stage_block(
     // ---- pass A of the next stage on the block's coarse rows j0 .. j0+TJ-1:
     // their full-weighting stencils cover the computed rows R0-E .. R1-1
     // (row k of rt = fine row R0-E+k = tile row k+1), Sec. 3.1 and 4.3
-    constexpr int NRT = C * (TJ + 1) - 1;
+    constexpr int NRT = SPLIT ? C : C * (TJ + 1) - 1;
     T* rt = wtile;
     __syncthreads();  // every thread is done with wtile and psc
     if (x < nx) {
@@ -316,7 +321,19 @@ __device__ __forceinline__ void fused_stage_block(
     cplx<T> z[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) z[q] = {T(0), T(0)};
-    if (i < Mx) {
+    if (SPLIT && i < Mx) {
+      // the parts of coarse rows j0 (a) and j0+1 (b) that the block's own fine
+      // rows carry, packed as pass A packs them (a of the wall row 0 and b of
+      // the wall row My as 0)
+      T racc[C];
+#pragma unroll
+      for (int e = 0; e < C; ++e) racc[e] = xweight<T, C>(rt + e * pitch + C * i);
+      T a, b;
+      split_restrict<T, C>(racc, a, b);
+      if (j0 == 0) a = T(0);
+      if (j0 + 1 > My - 1) b = T(0);
+      z[0] = {a, b};
+    } else if (i < Mx) {
       // x-weighted sums of each fine row, then the y weights (as pass A)
       T racc[NRT];
 #pragma unroll
@@ -358,7 +375,13 @@ __device__ __forceinline__ void fused_stage_block(
     }
     const cplx<T>* Z2 = fft_runn<T, LC, NT, (NQ > 2 ? 4 : 2)>(buf, buf + NQ * LP, NQ, L, d.nst_r,
                                                               d.stw_r, tw);
-    if (i < Mx) {
+    if (SPLIT && i < Mx) {
+      // a of row j0 with the spectra, b of row j0+1 at the split offset
+      T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
+      const cplx<T> zk = Z2[pad(i)];
+      if (j0 >= 1) wo[j0 - 1] = T(-0.5) * zk.y;
+      if (j0 + 1 <= My - 1) wo[d.split_off + j0] = T(0.5) * zk.x;
+    } else if (i < Mx) {
       // rows j0+2q, j0+2q+1 are consecutive in column i: one store per pair
       T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
 #pragma unroll

@@ -291,14 +291,22 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
               d.My % fused_tj(d.c, nl) == 0;
     if (nl == 2) fusable = fusable && fft_special(d.Lr) != 0;
   }
+  // one layer at c >= 4 with the fused pass: split restrictions (the b
+  // spectra after every member's a spectra, in the same region)
+  bool any_split = false;
+  for (MemberDesc& d : plan->md) {
+    d.split_off = (fusable && nl == 1 && d.c >= 4) ? wt : 0;
+    any_split = any_split || d.split_off != 0;
+  }
   // pass A: one complex sequence per block: coarse rows packed as the fused
   // pass packs them when it computes the next stage's spectra (so that both
-  // give the same bits), else a pair of rows; two layers: one row's modes
+  // give the same bits), else a pair of rows; two layers: one row's modes;
+  // split members: one block per coarse row j0 = 0 .. My-1
   build_groups(plan->md, PASS_A, [](const MemberDesc& d) { return fft_special(d.Lr); },
                [&](MemberDesc& d, HostGroup&) {
                  d.pa = 1;
                  d.a_rows = nl == 1 ? (fusable && fused_tj(d.c) == 1 ? 1 : 2) : 1;
-                 d.a_first = (nl == 1 && fusable && d.a_rows == 2) ? 0 : 1;
+                 d.a_first = (nl == 1 && fusable && (d.a_rows == 2 || d.split_off)) ? 0 : 1;
                  const int nrows = d.My - d.a_first;
                  const size_t lds = ((size_t)2 * lpad(d.Lr) + d.ntw_r) * cs;
                  return std::make_pair((nrows + d.a_rows - 1) / d.a_rows, lds);
@@ -402,14 +410,14 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   off = align_up(off + (plan->persist_ok ? sizeof(PTile) * plan->persist_max_tiles : 0));
   L.pctr = off;
   off = align_up(off + (plan->persist_ok ? sizeof(int) * (kPersistCounters + count) : 0));
-  L.wt = off; off = align_up(off + (size_t)wt * es);
+  L.wt = off; off = align_up(off + (size_t)wt * (any_split ? 2 : 1) * es);
   L.wt2 = off; off = align_up(off + (size_t)wt * es);
   L.field_elems = fld;
   L.psi = off; off = align_up(off + (size_t)fld * es);
   L.st1 = off; off = align_up(off + (size_t)fld * es);
   L.st2 = off; off = align_up(off + (size_t)fld * es);
   L.diag = off; off = align_up(off + (size_t)kDiagBlocks * 2 * 3 * sizeof(double));
-  L.fin = off; off = align_up(off + (size_t)kFiniteBlocks * sizeof(int));
+  L.fin = off; off = align_up(off + (size_t)(kFiniteBlocks + 1) * sizeof(int));
   long long mg_elems = 0;
   for (const MgLevel& lv : plan->mg) mg_elems += 2LL * (lv.nx + 1) * (lv.ny + 1);
   L.mg = off; off = align_up(off + (size_t)mg_elems * es);
@@ -445,8 +453,10 @@ struct cgp_handle {
   Group group(int pass, int i) const {
     const HostGroup& g = plan.groups[pass][i];
     const int count = g.members.size() == 1 ? -(g.members[0] + 1) : (int)g.members.size();
+    int split = 0;
+    for (int m : g.members) split |= plan.md[m].split_off != 0 ? 1 : 0;
     return Group{g.L,   count, at<int>(plan.lay.order) + g.order_off, g.nblk,
-                 kThreads, g.lds, plan.nlayers};
+                 kThreads, g.lds, plan.nlayers, split};
   }
   int ngroups(int pass) const { return (int)plan.groups[pass].size(); }
 };
@@ -459,9 +469,11 @@ const double kRkB[3] = {1.0, 0.25, 2.0 / 3.0};
 // One pass of the coarse solve (0: A, 1: B, 2: C) over every member.
 // ctl (pass B of a step's first stage): the step state, whose dt is set.
 // only >= 0: that group of the pass alone.
+// split (pass B): add the b spectra of split members (0 after the adjoint's
+// fused stage, whose sources are whole restrictions).
 template <typename T>
 hipError_t enqueue_pass(cgp_handle* h, int pass, const T* src, T* dst, int accumulate,
-                        hipStream_t s, double* ctl = nullptr, int only = -1) {
+                        hipStream_t s, double* ctl = nullptr, int only = -1, int split = 1) {
   const Plan& p = h->plan;
   const cplx<T>* tw = h->at<cplx<T>>(p.lay.tw);
   T* wt = h->at<T>(p.lay.wt);
@@ -473,7 +485,8 @@ hipError_t enqueue_pass(cgp_handle* h, int pass, const T* src, T* dst, int accum
     if (pass == 0)
       e = Launch<T>::restrict_rowdst(h->d_md(), g, src, wt, tw, s);
     else if (pass == 1)
-      e = Launch<T>::col_solve(h->d_md(), g, wt, wt2, tw, h->at<double>(p.lay.lam), ctl, s);
+      e = Launch<T>::col_solve(h->d_md(), g, wt, wt2, tw, h->at<double>(p.lay.lam), ctl, split,
+                               s);
     else
       e = Launch<T>::rowdst_prolong(h->d_md(), g, wt2, dst, accumulate, tw, s);
     if (e != hipSuccess) return e;
@@ -1232,6 +1245,25 @@ cgp_status cgp_check_finite(cgp_handle* h, const void* field, int64_t count, int
   return CGP_OK;
 }
 
+cgp_status cgp_assert_finite(cgp_handle* h, const void* field, int64_t count, void* stream) {
+  if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
+  if (!field || count < 0) return fail(CGP_ERR_INVALID, "bad argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int* part = h->at<int>(h->plan.lay.fin);
+  int* flag = part + kFiniteBlocks;  // the workspace's own flag word
+  hipError_t e = h->plan.dtype == CGP_F64
+                     ? Launch<double>::check_finite(static_cast<const double*>(field), count,
+                                                    part, kFiniteBlocks, flag, s)
+                     : Launch<float>::check_finite(static_cast<const float*>(field), count, part,
+                                                   kFiniteBlocks, flag, s);
+  if (e != hipSuccess) return hip_fail(e, "finite-check launch");
+  int host = 0;
+  HIP_TRY(hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, s), "flag read");
+  HIP_TRY(hipStreamSynchronize(s), "flag sync");
+  if (host) return fail(CGP_ERR_NONFINITE, "the field holds a NaN or an infinity");
+  return CGP_OK;
+}
+
 cgp_status cgp_accumulate(cgp_handle* h, const void* field, double* sum, double weight,
                           int32_t times_dt, void* stream) {
   if (check_handle(h) != CGP_OK) return CGP_ERR_INVALID;
@@ -1522,7 +1554,8 @@ cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forc
                                    slot(n, st), slot(n, 3 + st), lout[st], ACC, gF, kRkA[st],
                                    kRkB[st], mode, s),
                   "adjoint stage");
-        HIP_TRY(enqueue_pass<double>(h, 1, nullptr, nullptr, 0, s), "adjoint solve");
+        HIP_TRY(enqueue_pass<double>(h, 1, nullptr, nullptr, 0, s, nullptr, -1, 0),
+                "adjoint solve");
         prev = true;
       }
     }

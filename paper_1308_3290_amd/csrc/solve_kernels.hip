@@ -18,6 +18,7 @@
 #include "cgp_internal.hpp"
 #include "col_solve.hpp"
 #include "fft_lds.hpp"
+#include "stencil.hpp"
 
 namespace cgp {
 
@@ -128,6 +129,36 @@ __device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __r
   }
 }
 
+// Split restriction (one layer, c >= 4): block j0 packs the parts a of
+// coarse row j0 and b of row j0+1 that fine rows C j0 .. C j0 + C-1 carry
+// (split_restrict), the fused pass's packing; a of the wall row 0 and b of
+// the wall row My are 0.
+template <typename T, int C>
+__device__ __forceinline__ void split_block(const MemberDesc& d, const T* __restrict__ f,
+                                            cplx<T>* buf, int j0) {
+  const int Mx = d.Mx, My = d.My, pitch = d.nx + 1;
+  T a[kColIter], b[kColIter];
+#pragma unroll
+  for (int q = 0; q < kColIter; ++q) {
+    const int i = min(1 + (int)threadIdx.x + kThreads * q, Mx - 1);
+    if (q * kThreads < Mx - 1) {
+      T r[C];
+#pragma unroll
+      for (int e = 0; e < C; ++e) r[e] = xweight<T, C>(f + (size_t)(C * j0 + e) * pitch + C * i);
+      split_restrict<T, C>(r, a[q], b[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kColIter; ++q) {
+    const int i = 1 + threadIdx.x + kThreads * q;
+    if (i < Mx) {
+      const cplx<T> z = {j0 >= 1 ? a[q] : T(0), j0 + 1 <= My - 1 ? b[q] : T(0)};
+      buf[pad(i)] = z;
+      buf[pad(2 * Mx - i)] = {-z.x, -z.y};
+    }
+  }
+}
+
 template <typename T, int LC, int NL>
 __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng,
@@ -158,12 +189,18 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     buf[pad(Mx)] = {T(0), T(0)};
   }
   const T* f = src + d.field_off;
-  switch (d.c) {
-    case 1: restrict_block<T, 1, NL>(d, f, buf, j0, keep); break;
-    case 2: restrict_block<T, 2, NL>(d, f, buf, j0, keep); break;
-    case 4: restrict_block<T, 4, NL>(d, f, buf, j0, keep); break;
-    case 8: restrict_block<T, 8, NL>(d, f, buf, j0, keep); break;
-    default: restrict_block<T, 0, NL>(d, f, buf, j0, keep);
+  const bool split = NL == 1 && d.split_off != 0;
+  if (split) {
+    if (d.c == 4) split_block<T, 4>(d, f, buf, j0);
+    else split_block<T, 8>(d, f, buf, j0);
+  } else {
+    switch (d.c) {
+      case 1: restrict_block<T, 1, NL>(d, f, buf, j0, keep); break;
+      case 2: restrict_block<T, 2, NL>(d, f, buf, j0, keep); break;
+      case 4: restrict_block<T, 4, NL>(d, f, buf, j0, keep); break;
+      case 8: restrict_block<T, 8, NL>(d, f, buf, j0, keep); break;
+      default: restrict_block<T, 0, NL>(d, f, buf, j0, keep);
+    }
   }
 #pragma unroll
   for (int q = 0; q < kTw; ++q) {
@@ -179,8 +216,13 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     const cplx<T> zk = Z[pad(k)];
     const long long o = (long long)(k - 1) * (My - 1) + (j0 - 1);  // row j0 (-1 if j0 = 0)
     if constexpr (NL == 1) {
-      if (keep & 1) w[o] = T(-0.5) * zk.y;
-      if (keep & 2) w[o + 1] = T(0.5) * zk.x;
+      if (split) {  // a of row j0; b of row j0+1 at the split offset
+        if (j0 >= 1) w[o] = T(-0.5) * zk.y;
+        if (j0 + 1 <= My - 1) w[d.split_off + o + 1] = T(0.5) * zk.x;
+      } else {
+        if (keep & 1) w[o] = T(-0.5) * zk.y;
+        if (keep & 2) w[o + 1] = T(0.5) * zk.x;
+      }
     } else {
       w[o] = T(-0.5) * zk.y;
       w[mplane + o] = T(0.5) * zk.x;
@@ -192,7 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
 // ---------------------------------------------------------------------------
 // Pass B: one block per pair of spectral columns (col_solve.hpp).
 // ---------------------------------------------------------------------------
-template <typename T, int LC>
+template <typename T, int LC, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __restrict__ md,
                                                         const int* __restrict__ grp, int ng,
                                                         const T* __restrict__ win,
@@ -203,8 +245,8 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kThreads / 64];  // step-size reduction
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_B, blockIdx.x)];
-  col_solve_block<T, LC, kThreads>(d, blockIdx.x - d.blk0[PASS_B], win, wout, twg, lam, ctl,
-                                   smem, red);
+  col_solve_block<T, LC, kThreads, SPLIT>(d, blockIdx.x - d.blk0[PASS_B], win, wout, twg, lam,
+                                          ctl, smem, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -374,13 +416,21 @@ hipError_t Launch<T>::restrict_rowdst(const MemberDesc* md, const Group& g, cons
 
 template <typename T>
 hipError_t Launch<T>::col_solve(const MemberDesc* md, const Group& g, const T* win, T* wout,
-                                const cplx<T>* tw, const double* lam, double* ctl,
+                                const cplx<T>* tw, const double* lam, double* ctl, int split,
                                 hipStream_t s) {
-#define CALL(LC)                                                                                \
-  hipLaunchKernelGGL((k_col_solve<T, LC>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, g.members, \
-                     g.count, win, wout, tw, lam, ctl)
-  CGP_BY_LENGTH(g.L, CALL)
+#define CALL(LC)                                                                       \
+  hipLaunchKernelGGL((k_col_solve<T, LC, false>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
+                     g.members, g.count, win, wout, tw, lam, ctl)
+#define CALLS(LC)                                                                     \
+  hipLaunchKernelGGL((k_col_solve<T, LC, true>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
+                     g.members, g.count, win, wout, tw, lam, ctl)
+  if (split && g.split) {
+    CGP_BY_LENGTH(g.L, CALLS)
+  } else {
+    CGP_BY_LENGTH(g.L, CALL)
+  }
 #undef CALL
+#undef CALLS
   return hipGetLastError();
 }
 
@@ -402,7 +452,8 @@ hipError_t Launch<T>::prepare(size_t bytes) {
 #define FNS(LC)                                                      \
   reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC, 1>),       \
       reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC, 2>),   \
-      reinterpret_cast<const void*>(&k_col_solve<T, LC>),            \
+      reinterpret_cast<const void*>(&k_col_solve<T, LC, false>),     \
+      reinterpret_cast<const void*>(&k_col_solve<T, LC, true>),      \
       reinterpret_cast<const void*>(&k_rowdst_prolong<T, LC>)
       FNS(0), FNS(128), FNS(256), FNS(384), FNS(512), FNS(768), FNS(1024), FNS(1536), FNS(2048)
 #undef FNS

@@ -65,6 +65,33 @@ __device__ __forceinline__ T lap5(const Nbr<T>& q, T idx2, T idy2) {
   return (q.E - T(2) * q.C + q.W) * idx2 + (q.N - T(2) * q.C + q.S) * idy2;
 }
 
+// Full weighting applied log2(C) times (Sec. 3.1) has 1-D weights
+// (C - |d|)/C^2, |d| < C.  Split restriction: for the C fine rows
+// C j .. C j + C-1 of a block (r[e], e = 0..C-1, each already weighted and
+// summed along x), a = the part of coarse row j's restriction they carry
+// (weights C - e) and b = the part of coarse row j+1's (weights e); coarse
+// row j's restriction is then a_j + b_j, with b_j from the block below.  The
+// same code serves pass A and the fused pass, so both give the same bits.
+template <typename T, int C>
+__device__ __forceinline__ void split_restrict(const T* r, T& a, T& b) {
+  T sa = T(0), sb = T(0);
+#pragma unroll
+  for (int e = 0; e < C; ++e) sa += T(C - e) * r[e];
+#pragma unroll
+  for (int e = 1; e < C; ++e) sb += T(e) * r[e];
+  a = sa * (T(1) / T(C * C * C * C));
+  b = sb * (T(1) / T(C * C * C * C));
+}
+
+// x-weighted sum of one fine row at coarse column i (weights C - |dx|).
+template <typename T, int C>
+__device__ __forceinline__ T xweight(const T* row) {
+  T acc = T(0);
+#pragma unroll
+  for (int dx = -(C - 1); dx <= C - 1; ++dx) acc += T(C - (dx < 0 ? -dx : dx)) * row[dx];
+  return acc;
+}
+
 // Remap block b of nb so that the blocks dispatched to one XCD (round robin,
 // b mod 8) own a contiguous range of work items: neighbouring bands share
 // their halo rows in one L2.

@@ -297,6 +297,18 @@ def test_check_finite_flags_nan_and_inf():
     assert int(b.check_finite(w).item()) == 1
 
 
+def test_assert_finite_returns_the_nonfinite_status():
+    from paper_1308_3290_amd._lib import CGP_ERR_NONFINITE, CGPError
+    case = ci.make_case(32, 64)
+    b = _basin(case)
+    w = to_dev(random_state(case, 2))
+    b.assert_finite(w)
+    w[3, 4] = float("-inf")
+    with pytest.raises(CGPError) as ei:
+        b.assert_finite(w)
+    assert ei.value.status == CGP_ERR_NONFINITE
+
+
 def test_blow_up_is_detected():
     """A far too large dt drives the state non-finite; the finite check reports it."""
     case = ci.make_case(64, 128, level=0, dt=0.1)
