@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--repeats", type=int, default=5,
                     help="timed runs per launch mode and workload (the median is reported)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="ensembles: time the reference launch (per-pass graphs) without tuning")
+    ap.add_argument("--ens-steps", type=int, default=200,
+                    help="timed steps of the 64-member ensemble (the workload's 200)")
     ap.add_argument("--extras", action="store_true",
                     help="also time FP32 single basins, level 3, multigrid and adaptive steps")
     ap.add_argument("--only", default="",
@@ -105,11 +109,12 @@ def summarize_pmc(fetch_csv, write_csv, out_path=None):
     for name in fetch:
         if "cgp::" not in name:
             continue
-        short = name.split("cgp::")[1].split("<")[0].split("(")[0]
+        # the instantiation, e.g. k_prolong_stencil<double, 2, 2, 512, true>
+        inst = name.split("cgp::")[1].split("(")[0]
         fb = fetch[name] * 1024.0 * sf
         wb = write.get(name, 0.0) * 1024.0 * sw
-        out["kernels"][short] = {"fetch_bytes": fb, "write_bytes": wb,
-                                 "hbm_bytes_per_launch": fb + wb}
+        out["kernels"][inst] = {"fetch_bytes": fb, "write_bytes": wb,
+                                "hbm_bytes_per_launch": fb + wb}
     path = out_path or os.path.join(ROOT, "profiles", "traffic_c1_l1.json")
     json.dump(out, open(path, "w"), indent=1)
     print(json.dumps(out, indent=1))
@@ -377,22 +382,25 @@ def main():
         dom, t_dom, b_dom = max((("k_prolong_stencil<NEXT=true>", mf, sb["fused_avg"]),
                                  ("k_col_solve", mb, sb["B"])), key=lambda x: x[1])
         achieved = b_dom / (t_dom * 1e-3) / 1e9
+        def instance(doc):
+            """The dominant kernel's entry of a profile summary (the 512-point
+            compile-time instantiations that the 512x1024 level-1 step runs)."""
+            if doc.get("source_hash") != source_hash():
+                return None
+            want = ("k_prolong_stencil<double, 2, 2, 512, true>"
+                    if dom.startswith("k_prolong_stencil") else "k_col_solve<double, 1024, false>")
+            return doc.get("kernels", {}).get(want)
+
         traffic = None
         tfile = os.path.join(ROOT, "profiles", "traffic_c1_l1.json")
         if os.path.exists(tfile):
-            t = json.load(open(tfile))
-            base = dom.split("<")[0]
-            if t.get("source_hash") == source_hash() and base in t.get("kernels", {}):
-                traffic = t["kernels"][base]["hbm_bytes_per_launch"]
+            e = instance(json.load(open(tfile)))
+            traffic = e["hbm_bytes_per_launch"] if e else None
         prof_us = None
         pfile = os.path.join(ROOT, "profiles", "trace_c1_l1.json")
         if os.path.exists(pfile):
-            t = json.load(open(pfile))
-            if t.get("source_hash") == source_hash():
-                for k, v in t.get("kernels", {}).items():
-                    if k.startswith(dom.split("<")[0]) and k.endswith("true>"
-                                                                      if "NEXT" in dom else ">"):
-                        prof_us = round(v["mean_us"], 3)
+            e = instance(json.load(open(pfile)))
+            prof_us = round(e["mean_us"], 3) if e else None
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic, "alg_bytes_per_launch": round(b_dom),
@@ -435,8 +443,11 @@ def main():
         Wp, Fpk = probe.pack(w0s), probe.pack(Fs)
         probe.close()
         report = []
-        setting = autotune.tune(cfgs, Wp, Fpk, steps=30, warmup=6, repeats=3, report=report,
-                                retune=True)
+        if args.no_tune:
+            setting = dict(autotune.REFERENCE)
+        else:
+            setting = autotune.tune(cfgs, Wp, Fpk, steps=30, warmup=6, repeats=3, report=report,
+                                    retune=True)
         ms, finite = timed_runs(cfgs, w0s, Fs, n_steps, 5, setting["use_graph"], max(3, R // 2),
                                 launch=setting["launch"])
         best_by_mode = {}
@@ -451,7 +462,7 @@ def main():
         return ms, finite, setting, best_by_mode
 
     if want("ens"):
-        n_ens = 200
+        n_ens = args.ens_steps
         for dt_ in ("f64", "f32"):
             members = ci.ensemble_c3(dtype=dt_)
             cfgs = [api.config_from_case(m.case) for m in members]

@@ -64,7 +64,7 @@ def test_pmc_summary_scales_by_the_copy(tmp_path):
     bench.summarize_pmc(str(pf), str(pw), out_path=str(out))
     t = json.load(open(out))
     assert t["scale_fetch"] == pytest.approx(2.0) and t["scale_write"] == pytest.approx(1.0)
-    k = t["kernels"]["k_col_solve"]
+    k = t["kernels"]["k_col_solve<double, 1024>"]
     assert k["fetch_bytes"] == pytest.approx(2000.0 * 1024)
     assert k["hbm_bytes_per_launch"] == pytest.approx(2500.0 * 1024)
     assert t["source_hash"] == bench.source_hash()
