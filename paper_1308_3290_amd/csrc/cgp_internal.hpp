@@ -205,6 +205,23 @@ struct cplx {
   T x, y;
 };
 
+// Store of a fine-grid field element (the new vorticity); with NT the
+// non-temporal hint, which lets the lines leave the L2 as they fill instead
+// of at the end of the launch.  The host asks for it when a launch has at
+// most one block per CU, whose stores are then the tail of the launch: 2 %
+// per step for single basins.  With more blocks than CUs later blocks hide
+// that tail, and the hint measured slower (4 % for the FP32 ensemble).  The
+// coarse spectra, stored with a stride of one column, are slower with it in
+// every case and use ordinary stores.  (A compile-time choice: a runtime
+// branch between the two stores is merged into one ordinary store.)
+template <bool NT, typename T>
+__device__ __forceinline__ void store_field(T* p, T v) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 // Two consecutive elements at an address aligned to one element, moved by one
 // memory instruction (the target allows unaligned vector accesses).
 template <typename T>
@@ -296,13 +313,13 @@ struct Launch {
   static hipError_t prolong_stencil(const MemberDesc* md, const Group& g, const T* wt, T* wnext,
                                     const cplx<T>* tw, const T* ws, const T* forcing, const T* wn,
                                     T* out, T* psi_out, double a, double b, StepCtl ctl,
-                                    hipStream_t s);
+                                    bool nt_store, hipStream_t s);
   static hipError_t prepare_fused(size_t bytes);
   // the same for two layers (mode recombination and split inside; c = 1, 2, 4)
   static hipError_t prolong_stencil2(const MemberDesc* md, const Group& g, const T* wt, T* wnext,
                                      const cplx<T>* tw, const T* ws, const T* forcing,
                                      const T* wn, T* out, double a, double b, StepCtl ctl,
-                                     hipStream_t s);
+                                     bool nt_store, hipStream_t s);
   static hipError_t prepare_fused2(size_t bytes);
   // pass D: Arakawa right-hand side + TVD-RK3 stage combine
   static hipError_t stencil_rk3(const MemberDesc* md, int nm, int nblk, const T* ws,

@@ -19,7 +19,7 @@
 
 namespace cgp {
 
-template <typename T, int C, int TJ, int LC, bool NEXT>
+template <typename T, int C, int TJ, int LC, bool NEXT, bool NTS>
 __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
     const T* __restrict__ wt, T* __restrict__ wnext, const cplx<T>* __restrict__ twg,
@@ -270,15 +270,15 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
       v1 = rr >= 1 ? v1 : T(0);
       v2 = rr >= 1 ? v2 : T(0);
       if (u > E) {
-        O[(size_t)rr * pitch + x] = v1;
-        O[plane + (size_t)rr * pitch + x] = v2;
+        store_field<NTS>(&O[(size_t)rr * pitch + x], v1);
+        store_field<NTS>(&O[plane + (size_t)rr * pitch + x], v2);
       }
       res1[u - 1] = v1;
       res2[u - 1] = v2;
     }
     if (last) {  // the top wall row
-      O[(size_t)ny * pitch + x] = T(0);
-      O[plane + (size_t)ny * pitch + x] = T(0);
+      store_field<NTS>(&O[(size_t)ny * pitch + x], T(0));
+      store_field<NTS>(&O[plane + (size_t)ny * pitch + x], T(0));
     }
   }
   // last stage of an adaptive step: the velocity maxima for the next dt
@@ -359,31 +359,34 @@ template <typename T>
 hipError_t Launch<T>::prolong_stencil2(const MemberDesc* md, const Group& g, const T* wt,
                                        T* wnext, const cplx<T>* tw, const T* ws,
                                        const T* forcing, const T* wn, T* out, double a, double b,
-                                       StepCtl ctl, hipStream_t s) {
-#define LAUNCH(C, TJ, LC, NX)                                                                  \
-  hipLaunchKernelGGL((k_prolong_stencil2<T, C, TJ, LC, NX>), dim3(g.nblk), dim3(kFusedThreads), \
-                     g.lds, s, md, g.members, g.count, g.nblk, wt, wnext, tw, ws, forcing, wn,  \
-                     out, a, b, ctl)
-#define BY_C(NX)                                                  \
-  switch (g.L) {                                                  \
-    case (1 << 16) | 128: LAUNCH(1, 1, 128, NX); break;           \
-    case (1 << 16) | 256: LAUNCH(1, 1, 256, NX); break;           \
-    case (1 << 16) | 384: LAUNCH(1, 1, 384, NX); break;           \
-    case (1 << 16) | 512: LAUNCH(1, 1, 512, NX); break;           \
-    case (1 << 16) | 768: LAUNCH(1, 1, 768, NX); break;           \
-    case (1 << 16) | 1024: LAUNCH(1, 1, 1024, NX); break;         \
-    case (2 << 16) | 128: LAUNCH(2, 2, 128, NX); break;           \
-    case (2 << 16) | 256: LAUNCH(2, 2, 256, NX); break;           \
-    case (2 << 16) | 384: LAUNCH(2, 2, 384, NX); break;           \
-    case (2 << 16) | 512: LAUNCH(2, 2, 512, NX); break;           \
-    case (4 << 16) | 128: LAUNCH(4, 1, 128, NX); break;           \
-    case (4 << 16) | 256: LAUNCH(4, 1, 256, NX); break;           \
-    default: return hipErrorInvalidValue;                         \
+                                       StepCtl ctl, bool nt_store, hipStream_t s) {
+#define LAUNCH(C, TJ, LC, NX, NTS)                                                      \
+  hipLaunchKernelGGL((k_prolong_stencil2<T, C, TJ, LC, NX, NTS>), dim3(g.nblk),         \
+                     dim3(kFusedThreads), g.lds, s, md, g.members, g.count, g.nblk, wt, \
+                     wnext, tw, ws, forcing, wn, out, a, b, ctl)
+#define BY_C(NX, NTS)                                          \
+  switch (g.L) {                                               \
+    case (1 << 16) | 128: LAUNCH(1, 1, 128, NX, NTS); break;   \
+    case (1 << 16) | 256: LAUNCH(1, 1, 256, NX, NTS); break;   \
+    case (1 << 16) | 384: LAUNCH(1, 1, 384, NX, NTS); break;   \
+    case (1 << 16) | 512: LAUNCH(1, 1, 512, NX, NTS); break;   \
+    case (1 << 16) | 768: LAUNCH(1, 1, 768, NX, NTS); break;   \
+    case (1 << 16) | 1024: LAUNCH(1, 1, 1024, NX, NTS); break; \
+    case (2 << 16) | 128: LAUNCH(2, 2, 128, NX, NTS); break;   \
+    case (2 << 16) | 256: LAUNCH(2, 2, 256, NX, NTS); break;   \
+    case (2 << 16) | 384: LAUNCH(2, 2, 384, NX, NTS); break;   \
+    case (2 << 16) | 512: LAUNCH(2, 2, 512, NX, NTS); break;   \
+    case (4 << 16) | 128: LAUNCH(4, 1, 128, NX, NTS); break;   \
+    case (4 << 16) | 256: LAUNCH(4, 1, 256, NX, NTS); break;   \
+    default: return hipErrorInvalidValue;                      \
   }
-  if (wnext) {
-    BY_C(true)
+  // the new vorticity with the non-temporal hint only where asked for
+  if (!wnext) {
+    BY_C(false, false)
+  } else if (nt_store) {
+    BY_C(true, true)
   } else {
-    BY_C(false)
+    BY_C(true, false)
   }
 #undef BY_C
 #undef LAUNCH
@@ -394,8 +397,10 @@ template <typename T>
 hipError_t Launch<T>::prepare_fused2(size_t bytes) {
   const int b = (int)bytes;
   const void* fns[] = {
-#define K(C, TJ, LC) reinterpret_cast<const void*>(&k_prolong_stencil2<T, C, TJ, LC, false>), \
-                     reinterpret_cast<const void*>(&k_prolong_stencil2<T, C, TJ, LC, true>)
+#define K(C, TJ, LC)                                                                 \
+  reinterpret_cast<const void*>(&k_prolong_stencil2<T, C, TJ, LC, false, false>),    \
+      reinterpret_cast<const void*>(&k_prolong_stencil2<T, C, TJ, LC, true, false>), \
+      reinterpret_cast<const void*>(&k_prolong_stencil2<T, C, TJ, LC, true, true>)
       K(1, 1, 128), K(1, 1, 256), K(1, 1, 384), K(1, 1, 512), K(1, 1, 768), K(1, 1, 1024),
       K(2, 2, 128), K(2, 2, 256), K(2, 2, 384), K(2, 2, 512), K(4, 1, 128), K(4, 1, 256)
 #undef K

@@ -31,7 +31,7 @@
 
 namespace cgp {
 
-template <typename T, int C, int TJ, int LC, bool NEXT>
+template <typename T, int C, int TJ, int LC, bool NEXT, bool NTS>
 __global__ __launch_bounds__(kFusedThreads, fused_waves_per_simd(C, LC)) void k_prolong_stencil(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
     const T* __restrict__ wt, T* __restrict__ wnext, const cplx<T>* __restrict__ twg,
@@ -40,8 +40,9 @@ __global__ __launch_bounds__(kFusedThreads, fused_waves_per_simd(C, LC)) void k_
   extern __shared__ __align__(16) unsigned char smem[];
   const int bid = xcd_contiguous(blockIdx.x, nblk);
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_CD, bid)];
-  fused_stage_block<T, C, TJ, LC, NEXT>(d, bid - d.blk0[PASS_CD], wt, wnext, twg, ws, forcing,
-                                        wn, out, psi_out, a_, b_, ctl, smem);
+  fused_stage_block<T, C, TJ, LC, NEXT, (C == 2), NTS>(d, bid - d.blk0[PASS_CD], wt, wnext, twg,
+                                                      ws, forcing, wn, out, psi_out, a_, b_, ctl,
+                                                      smem);
 }
 
 // g.L = (c << 16) | transform length with a compile-time transform (or 0).
@@ -49,54 +50,58 @@ template <typename T>
 hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, const T* wt,
                                       T* wnext, const cplx<T>* tw, const T* ws,
                                       const T* forcing, const T* wn, T* out, T* psi_out,
-                                      double a, double b, StepCtl ctl, hipStream_t s) {
-#define LAUNCH(C, TJ, LC, NX)                                                                \
-  hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC, NX>), dim3(g.nblk), dim3(kFusedThreads), \
-                     g.lds, s, md, g.members, g.count, g.nblk, wt, wnext, tw, ws, forcing, wn, \
-                     out, psi_out, a, b, ctl)
+                                      double a, double b, StepCtl ctl, bool nt_store,
+                                      hipStream_t s) {
+#define LAUNCH(C, TJ, LC, NX, NTS)                                                      \
+  hipLaunchKernelGGL((k_prolong_stencil<T, C, TJ, LC, NX, NTS>), dim3(g.nblk),          \
+                     dim3(kFusedThreads), g.lds, s, md, g.members, g.count, g.nblk, wt, \
+                     wnext, tw, ws, forcing, wn, out, psi_out, a, b, ctl)
 // rows hold at most kFusedMaxNx intervals, so c = 1, 2, 4, 8 have transform
 // lengths of at most 1024, 512, 256, 128
-#define BY_LEN1(NX)                            \
-  switch (g.L & 0xffff) {                      \
-    case 128: LAUNCH(1, 4, 128, NX); break;    \
-    case 256: LAUNCH(1, 4, 256, NX); break;    \
-    case 384: LAUNCH(1, 4, 384, NX); break;    \
-    case 512: LAUNCH(1, 4, 512, NX); break;    \
-    case 768: LAUNCH(1, 4, 768, NX); break;    \
-    case 1024: LAUNCH(1, 4, 1024, NX); break;  \
-    default: LAUNCH(1, 4, 0, NX);              \
+#define BY_LEN1(NX, NTS)                           \
+  switch (g.L & 0xffff) {                          \
+    case 128: LAUNCH(1, 4, 128, NX, NTS); break;   \
+    case 256: LAUNCH(1, 4, 256, NX, NTS); break;   \
+    case 384: LAUNCH(1, 4, 384, NX, NTS); break;   \
+    case 512: LAUNCH(1, 4, 512, NX, NTS); break;   \
+    case 768: LAUNCH(1, 4, 768, NX, NTS); break;   \
+    case 1024: LAUNCH(1, 4, 1024, NX, NTS); break; \
+    default: LAUNCH(1, 4, 0, NX, NTS);             \
   }
-#define BY_LEN2(NX)                            \
-  switch (g.L & 0xffff) {                      \
-    case 128: LAUNCH(2, 2, 128, NX); break;    \
-    case 256: LAUNCH(2, 2, 256, NX); break;    \
-    case 384: LAUNCH(2, 2, 384, NX); break;    \
-    case 512: LAUNCH(2, 2, 512, NX); break;    \
-    default: LAUNCH(2, 2, 0, NX);              \
+#define BY_LEN2(NX, NTS)                         \
+  switch (g.L & 0xffff) {                        \
+    case 128: LAUNCH(2, 2, 128, NX, NTS); break; \
+    case 256: LAUNCH(2, 2, 256, NX, NTS); break; \
+    case 384: LAUNCH(2, 2, 384, NX, NTS); break; \
+    case 512: LAUNCH(2, 2, 512, NX, NTS); break; \
+    default: LAUNCH(2, 2, 0, NX, NTS);           \
   }
-#define BY_LEN4(NX)                            \
-  switch (g.L & 0xffff) {                      \
-    case 128: LAUNCH(4, 1, 128, NX); break;    \
-    case 256: LAUNCH(4, 1, 256, NX); break;    \
-    default: LAUNCH(4, 1, 0, NX);              \
+#define BY_LEN4(NX, NTS)                         \
+  switch (g.L & 0xffff) {                        \
+    case 128: LAUNCH(4, 1, 128, NX, NTS); break; \
+    case 256: LAUNCH(4, 1, 256, NX, NTS); break; \
+    default: LAUNCH(4, 1, 0, NX, NTS);           \
   }
-#define BY_LEN8(NX)                            \
-  switch (g.L & 0xffff) {                      \
-    case 128: LAUNCH(8, 1, 128, NX); break;    \
-    default: LAUNCH(8, 1, 0, NX);              \
+#define BY_LEN8(NX, NTS)                         \
+  switch (g.L & 0xffff) {                        \
+    case 128: LAUNCH(8, 1, 128, NX, NTS); break; \
+    default: LAUNCH(8, 1, 0, NX, NTS);           \
   }
-#define BY_C(NX)                          \
+#define BY_C(NX, NTS)                     \
   switch (g.L >> 16) {                    \
-    case 1: BY_LEN1(NX); break;           \
-    case 2: BY_LEN2(NX); break;           \
-    case 4: BY_LEN4(NX); break;           \
-    case 8: BY_LEN8(NX); break;           \
+    case 1: BY_LEN1(NX, NTS); break;      \
+    case 2: BY_LEN2(NX, NTS); break;      \
+    case 4: BY_LEN4(NX, NTS); break;      \
+    case 8: BY_LEN8(NX, NTS); break;      \
     default: return hipErrorInvalidValue; \
   }
-  if (wnext) {
-    BY_C(true)
+  // the new vorticity with the non-temporal hint only where asked for
+  if (!wnext) {
+    BY_C(false, false)
+  } else if (nt_store) {
+    BY_C(true, true)
   } else {
-    BY_C(false)
+    BY_C(true, false)
   }
 #undef BY_C
 #undef BY_LEN1
@@ -111,8 +116,10 @@ template <typename T>
 hipError_t Launch<T>::prepare_fused(size_t bytes) {
   const int b = (int)bytes;
   const void* fns[] = {
-#define K(C, TJ, LC) reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, false>), \
-                     reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, true>)
+#define K(C, TJ, LC)                                                                \
+  reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, false, false>),    \
+      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, true, false>), \
+      reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, true, true>)
       K(1, 4, 0), K(1, 4, 128), K(1, 4, 256), K(1, 4, 384), K(1, 4, 512), K(1, 4, 768),
       K(1, 4, 1024), K(2, 2, 0), K(2, 2, 128), K(2, 2, 256), K(2, 2, 384), K(2, 2, 512),
       K(4, 1, 0), K(4, 1, 128), K(4, 1, 256), K(8, 1, 0), K(8, 1, 128)

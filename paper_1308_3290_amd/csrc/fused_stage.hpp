@@ -52,7 +52,7 @@ __host__ __device__ constexpr int fused_waves_per_simd(int c, int lc) {
 // vorticity tile loads with the spectra (the faster order at c = 2) rather
 // than once the spectra are in LDS (fewer registers live across the
 // transform).
-template <typename T, int C, int TJ, int LC, bool NEXT, bool EARLY = (C == 2)>
+template <typename T, int C, int TJ, int LC, bool NEXT, bool EARLY = (C == 2), bool NTS = false>
 __device__ __forceinline__ void fused_stage_block(
     const MemberDesc& d, int lb, const T* __restrict__ wt, T* __restrict__ wnext,
     const cplx<T>* __restrict__ twg, const T* __restrict__ ws, const T* __restrict__ forcing,
@@ -291,7 +291,7 @@ __device__ __forceinline__ void fused_stage_block(
       T v = a * nv[u - 1] + b * (w.C + dt * G);  // a = 0 in stage 1
       v = rr >= 1 ? v : T(0);
       if (u > E) {
-        O[(size_t)rr * pitch + x] = v;
+        store_field<NTS>(&O[(size_t)rr * pitch + x], v);
         if (PO) PO[(size_t)rr * pitch + x] = P[1][u];  // the prolonged psi (0 on wall rows)
       }
       res[u - 1] = v;
@@ -299,7 +299,7 @@ __device__ __forceinline__ void fused_stage_block(
       wc0 = wn0; wc1 = wn1; wc2 = wn2;
     }
     if (last) {  // the top wall row
-      O[(size_t)ny * pitch + x] = T(0);
+      store_field<NTS>(&O[(size_t)ny * pitch + x], T(0));
       if (PO) PO[(size_t)ny * pitch + x] = T(0);
     }
   }

@@ -447,6 +447,7 @@ struct cgp_handle {
   std::vector<hipEvent_t> events;
   // persistent stage kernel: tiles in the queue and the launch grid
   int persist_ntiles = 0, persist_grid = 0;
+  int ncu = 0;  // compute units of the handle's device
   int nm() const { return (int)plan.md.size(); }
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   const MemberDesc* d_md() const { return at<MemberDesc>(plan.lay.desc); }
@@ -581,14 +582,17 @@ hipError_t enqueue_fused(cgp_handle* h, const T* ws, const T* forcing, const T* 
   for (int i = 0; i < h->ngroups(3); ++i) {
     if (only >= 0 && i != only) continue;
     T* wnext = next ? h->at<T>(p.lay.wt) : nullptr;
+    const Group g = h->group(3, i);
+    // at most one block per CU: the new vorticity with the non-temporal hint
+    const bool nt = g.nblk <= h->ncu;
     hipError_t e =
         p.nlayers == 1
-            ? Launch<T>::prolong_stencil(h->d_md(), h->group(3, i), h->at<T>(p.lay.wt2), wnext,
+            ? Launch<T>::prolong_stencil(h->d_md(), g, h->at<T>(p.lay.wt2), wnext,
                                          h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, psi_out,
-                                         a, b, ctl, s)
-            : Launch<T>::prolong_stencil2(h->d_md(), h->group(3, i), h->at<T>(p.lay.wt2), wnext,
+                                         a, b, ctl, nt, s)
+            : Launch<T>::prolong_stencil2(h->d_md(), g, h->at<T>(p.lay.wt2), wnext,
                                           h->at<cplx<T>>(p.lay.tw), ws, forcing, wn, out, a, b,
-                                          ctl, s);
+                                          ctl, nt, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -888,9 +892,15 @@ cgp_status create_common(const cgp_config* cfgs, int count, void* ws, size_t byt
     return fail(CGP_ERR_INVALID, "workspace must be 256-byte aligned");
   if (bytes < plan.lay.total)
     return fail(CGP_ERR_INVALID, "workspace too small: %zu < %zu", bytes, plan.lay.total);
+  int dev = 0, ncu = 0;
+  hipError_t de = hipGetDevice(&dev);
+  if (de == hipSuccess)
+    de = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (de != hipSuccess) return hip_fail(de, "CU count");
   cgp_handle* h = new cgp_handle;
   h->plan = std::move(plan);
   h->ws = static_cast<char*>(ws);
+  h->ncu = ncu;
   hipStream_t s = static_cast<hipStream_t>(stream);
   st = h->plan.dtype == CGP_F64 ? create_tables<double>(h, s) : create_tables<float>(h, s);
   if (st != CGP_OK) {

@@ -68,15 +68,16 @@ def test_no_kernel_uses_scratch(kernels):
 
 
 def test_fused_c2_kernels_fit_two_blocks_per_cu(kernels):
-    # k_prolong_stencil<T, C = 2, TJ = 2, LC, NEXT = true>, LC = 128 .. 512
-    pat = re.compile(r"_ZN3cgp17k_prolong_stencilI([df])Li2ELi2ELi(\d+)ELb1E")
+    # k_prolong_stencil<T, C = 2, TJ = 2, LC, NEXT = true, NTS>, LC = 128 .. 512,
+    # with and without the non-temporal stores of the new vorticity
+    pat = re.compile(r"_ZN3cgp17k_prolong_stencilI([df])Li2ELi2ELi(\d+)ELb1ELb[01]E")
     seen = 0
     for name, v in kernels.items():
         m = pat.match(name)
         if m and m.group(2) != "0":
             seen += 1
             assert v["vgpr_count"] <= 128, (name, v)
-    assert seen == 8  # two element types x four compile-time lengths
+    assert seen == 16  # two element types x four compile-time lengths x two store forms
 
 
 def test_metadata_covers_every_translation_unit(kernels):
