@@ -285,48 +285,53 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
   if (wants_vmax(d, ctl)) put_vmax_coarse<T, C, TJ, NT>(d, ctl, lb, psc1, psc2, PROW, j0);
   if constexpr (NEXT) {
     // ---- pass A of the next stage on the block's coarse rows j0 .. j0+TJ-1
-    // (row k of rt = fine row R0-E+k = tile row k+1), as pass A computes it
-    constexpr int NRT = C * (TJ + 1) - 1;
-    T* rt1 = tile1;
-    T* rt2 = tile1 + NRT * pitch;
-    __syncthreads();  // every thread is done with the tiles and psc
-    if (x < nx) {
-#pragma unroll
-      for (int k = 0; k < NRT; ++k) {
-        rt1[k * pitch + x] = res1[k];
-        rt2[k * pitch + x] = res2[k];
-      }
-    }
-    __syncthreads();
+    // (res[k] = fine row R0-E+k): the y weights of each thread's column in
+    // registers, then the x weights over the neighbouring columns' sums
+    // (through LDS rows of their own), as pass A computes them
+    // (restrict_rows); both layers
     const int i = 1 + t;
     cplx<T> z[TJ];
 #pragma unroll
     for (int r = 0; r < TJ; ++r) z[r] = {T(0), T(0)};
-    if (i < MX) {
-      auto restrict_row = [&](const T* rtl, int r) -> T {
-        T racc[2 * C - 1];
+    T y1[TJ], y2[TJ];
 #pragma unroll
-        for (int q = 0; q < 2 * C - 1; ++q) {
-          const T* row = rtl + (C * r + q) * pitch + C * i;
-          T s = T(0);
-#pragma unroll
-          for (int dx = -(C - 1); dx <= C - 1; ++dx) s += T(C - (dx < 0 ? -dx : dx)) * row[dx];
-          racc[q] = s;
-        }
-        T s = T(0);
-#pragma unroll
-        for (int dy = -(C - 1); dy <= C - 1; ++dy)
-          s += T(C - (dy < 0 ? -dy : dy)) * racc[dy + (C - 1)];
-        return s * (T(1) / T(C * C * C * C));
-      };
-      const T wbt1 = T(d.delta), wbt2 = T(1.0 - d.delta);
+    for (int r = 0; r < TJ; ++r) {
+      y1[r] = yweight<T, C>(res1 + C * r);
+      y2[r] = yweight<T, C>(res2 + C * r);
+    }
+    T v1[TJ], v2[TJ];
+    if constexpr (C == 1) {
+      // coarse column i is the thread's own column: nothing to exchange
 #pragma unroll
       for (int r = 0; r < TJ; ++r) {
-        const T v = restrict_row(rt1, r), u = restrict_row(rt2, r);
-        z[r] = {wbt1 * v + wbt2 * u, v - u};  // (barotropic, baroclinic)
+        v1[r] = y1[r];
+        v2[r] = y2[r];
+      }
+      __syncthreads();  // every thread is done with the tiles and psc
+    } else {
+      T* yc1 = psc2 + NS * PROW;
+      T* yc2 = yc1 + TJ * pitch;
+      if (x < nx) {
+#pragma unroll
+        for (int r = 0; r < TJ; ++r) {
+          yc1[r * pitch + x] = y1[r];
+          yc2[r * pitch + x] = y2[r];
+        }
+      }
+      __syncthreads();  // also: every thread is done with the tiles and psc
+      const int ii = i < MX ? i : 1;
+#pragma unroll
+      for (int r = 0; r < TJ; ++r) {
+        v1[r] = xweight<T, C>(yc1 + r * pitch + C * ii) * (T(1) / T(C * C * C * C));
+        v2[r] = xweight<T, C>(yc2 + r * pitch + C * ii) * (T(1) / T(C * C * C * C));
       }
     }
-    __syncthreads();  // rt is read: the transform buffers may overwrite it
+    if (i < MX) {
+      const T wbt1 = T(d.delta), wbt2 = T(1.0 - d.delta);
+#pragma unroll
+      for (int r = 0; r < TJ; ++r)
+        z[r] = {wbt1 * v1[r] + wbt2 * v2[r], v1[r] - v2[r]};  // (barotropic, baroclinic)
+    }
     if (i < MX) {
 #pragma unroll
       for (int r = 0; r < TJ; ++r) {

@@ -308,52 +308,62 @@ __device__ __forceinline__ void fused_stage_block(
   if constexpr (NEXT) {
     // ---- pass A of the next stage on the block's coarse rows j0 .. j0+TJ-1:
     // their full-weighting stencils cover the computed rows R0-E .. R1-1
-    // (row k of rt = fine row R0-E+k = tile row k+1), Sec. 3.1 and 4.3
-    constexpr int NRT = SPLIT ? C : C * (TJ + 1) - 1;
-    T* rt = wtile;
-    __syncthreads();  // every thread is done with wtile and psc
-    if (x < nx) {
-#pragma unroll
-      for (int k = 0; k < NRT; ++k) rt[k * pitch + x] = res[k];
-    }
-    __syncthreads();
+    // (res[k] = fine row R0-E+k = tile row k+1), Sec. 3.1 and 4.3
     const int i = 1 + t;
     cplx<T> z[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) z[q] = {T(0), T(0)};
-    if (SPLIT && i < Mx) {
+    if constexpr (SPLIT) {
       // the parts of coarse rows j0 (a) and j0+1 (b) that the block's own fine
       // rows carry, packed as pass A packs them (a of the wall row 0 and b of
-      // the wall row My as 0)
-      T racc[C];
+      // the wall row My as 0); the rows go through LDS for the x weights
+      T* rt = wtile;
+      __syncthreads();  // every thread is done with wtile and psc
+      if (x < nx) {
 #pragma unroll
-      for (int e = 0; e < C; ++e) racc[e] = xweight<T, C>(rt + e * pitch + C * i);
-      T a, b;
-      split_restrict<T, C>(racc, a, b);
-      if (j0 == 0) a = T(0);
-      if (j0 + 1 > My - 1) b = T(0);
-      z[0] = {a, b};
-    } else if (i < Mx) {
-      // x-weighted sums of each fine row, then the y weights (as pass A)
-      T racc[NRT];
-#pragma unroll
-      for (int q = 0; q < NRT; ++q) {
-        const T* row = rt + q * pitch + C * i;
-        T acc = T(0);
-#pragma unroll
-        for (int dx = -(C - 1); dx <= C - 1; ++dx) acc += T(C - (dx < 0 ? -dx : dx)) * row[dx];
-        racc[q] = acc;
+        for (int k = 0; k < C; ++k) rt[k * pitch + x] = res[k];
       }
+      __syncthreads();
+      if (i < Mx) {
+        T racc[C];
+#pragma unroll
+        for (int e = 0; e < C; ++e) racc[e] = xweight<T, C>(rt + e * pitch + C * i);
+        T a, b;
+        split_restrict<T, C>(racc, a, b);
+        if (j0 == 0) a = T(0);
+        if (j0 + 1 > My - 1) b = T(0);
+        z[0] = {a, b};
+      }
+      __syncthreads();  // rt is read: the transform buffers may overwrite it
+    } else {
+      // whole restrictions: each thread holds its fine column's rows, so the
+      // y weights come first, in registers, and one value per coarse row and
+      // column crosses threads (through its own LDS rows, which no other
+      // phase uses) for the x weights; pass A computes the same sums in the
+      // same order (restrict_rows), so both give the same spectra bit for bit
+      T yv[TJ];
+#pragma unroll
+      for (int r = 0; r < TJ; ++r) yv[r] = yweight<T, C>(res + C * r);
       T v[2 * NQ];
 #pragma unroll
       for (int r = 0; r < 2 * NQ; ++r) v[r] = T(0);
+      if constexpr (C == 1) {
+        // coarse column i is the thread's own column: nothing to exchange
 #pragma unroll
-      for (int r = 0; r < TJ; ++r) {
-        T acc = T(0);
+        for (int r = 0; r < TJ; ++r) v[r] = yv[r];
+        __syncthreads();  // every thread is done with wtile and psc
+      } else {
+        T* yc = psc + (TJ + 2) * prow;
+        if (x < nx) {
 #pragma unroll
-        for (int dy = -(C - 1); dy <= C - 1; ++dy)
-          acc += T(C - (dy < 0 ? -dy : dy)) * racc[C * r + dy + (C - 1)];
-        v[r] = acc * (T(1) / T(C * C * C * C));
+          for (int r = 0; r < TJ; ++r) yc[r * pitch + x] = yv[r];
+        }
+        __syncthreads();  // also: every thread is done with wtile and psc
+        if (i < Mx) {
+#pragma unroll
+          for (int r = 0; r < TJ; ++r)
+            v[r] = xweight<T, C>(yc + r * pitch + C * i) * (T(1) / T(C * C * C * C));
+        }
       }
       // packed as pass A packs them (rows in pairs (2m, 2m+1), the wall row 0
       // as 0), so that both give the same spectra bit for bit
@@ -361,7 +371,6 @@ __device__ __forceinline__ void fused_stage_block(
 #pragma unroll
       for (int q = 0; q < NQ; ++q) z[q] = {v[2 * q], v[2 * q + 1]};
     }
-    __syncthreads();  // rt is read: the transform buffers may overwrite it
     if (i < Mx) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {

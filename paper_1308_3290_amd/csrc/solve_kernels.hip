@@ -50,32 +50,33 @@ __device__ __forceinline__ T restrict_generic(const T* __restrict__ f, int pitch
 // without a column reads a valid neighbour), so that they are in flight
 // together.
 // ---------------------------------------------------------------------------
-// Restriction of coarse rows j0 .. j0+RB-1 at coarse column i, separably: the
-// x-weighted sums of the fine rows C j0-(C-1) .. C (j0+RB-1)+(C-1) first, then
-// the y weights.  Rows of absent coarse rows (the wall row 0, rows past
-// My-1) are clamped to the array; their values are discarded.
+// Restriction of coarse rows j0 .. j0+RB-1 at coarse column i, separably:
+// the y-weighted sums of the fine columns C i-(C-1) .. C i+(C-1) over each
+// coarse row's stencil rows first, then the x weights (yweight, xweight, the
+// fused kernels' order).  Rows of absent coarse rows (the wall row 0, rows
+// past My-1) are clamped to the array; their values are discarded.
 template <typename T, int C, int RB>
 __device__ __forceinline__ void restrict_rows(const T* __restrict__ f, int pitch, int ny, int i,
                                               int j0, T* v) {
-  constexpr int NF = C * (RB + 1) - 1;
+  constexpr int NF = C * (RB + 1) - 1;  // fine rows C j0-(C-1) .. C (j0+RB-1)+(C-1)
   const int fr0 = C * j0 - (C - 1);
-  T racc[NF];
+  // the x weights accumulate column by column in xweight's order (one
+  // column's rows live at a time)
+  T acc[RB];
 #pragma unroll
-  for (int q = 0; q < NF; ++q) {
-    const T* row = f + (size_t)max(0, min(fr0 + q, ny)) * pitch + C * i;
-    T acc = T(0);
+  for (int r = 0; r < RB; ++r) acc[r] = T(0);
+#pragma unroll 1
+  for (int e = 0; e < 2 * C - 1; ++e) {
+    const T* colp = f + C * i - (C - 1) + e;
+    T col[NF];
 #pragma unroll
-    for (int dx = -(C - 1); dx <= C - 1; ++dx) acc += T(C - (dx < 0 ? -dx : dx)) * row[dx];
-    racc[q] = acc;
+    for (int q = 0; q < NF; ++q) col[q] = colp[(size_t)max(0, min(fr0 + q, ny)) * pitch];
+    const T wx = T(C - (e < C - 1 ? C - 1 - e : e - (C - 1)));
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] += wx * yweight<T, C>(col + C * r);
   }
 #pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    T acc = T(0);
-#pragma unroll
-    for (int dy = -(C - 1); dy <= C - 1; ++dy)
-      acc += T(C - (dy < 0 ? -dy : dy)) * racc[C * r + dy + (C - 1)];
-    v[r] = acc * (T(1) / T(C * C * C * C));
-  }
+  for (int r = 0; r < RB; ++r) v[r] = acc[r] * (T(1) / T(C * C * C * C));
 }
 
 // keep: which of the one-layer pair's rows are present (bit 0: j0, bit 1: j0+1)

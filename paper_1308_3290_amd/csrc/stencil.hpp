@@ -92,6 +92,19 @@ __device__ __forceinline__ T xweight(const T* row) {
   return acc;
 }
 
+// y-weighted sum of one fine column over the 2C-1 rows of a coarse row's
+// stencil (weights C - |dy|); col[0] is the lowest of them.  A whole
+// restriction (not split) takes these first and then xweight over the
+// columns' sums, times 1/C^4: pass A and the fused kernels hold a column's
+// rows in one thread, so only one value per coarse row crosses threads.
+template <typename T, int C>
+__device__ __forceinline__ T yweight(const T* col) {
+  T acc = T(0);
+#pragma unroll
+  for (int dy = -(C - 1); dy <= C - 1; ++dy) acc += T(C - (dy < 0 ? -dy : dy)) * col[dy + C - 1];
+  return acc;
+}
+
 // Remap block b of nb so that the blocks dispatched to one XCD (round robin,
 // b mod 8) own a contiguous range of work items: neighbouring bands share
 // their halo rows in one L2.
