@@ -71,7 +71,7 @@ struct MemberDesc {
   long long field_off;  // packed fine fields ([L][ny+1][nx+1] per member)
   long long wt_off;     // coarse spectra: L modes x (Mx-1) x (My-1), k-major
   // One layer at c >= 4 (fused steps): the restriction of a coarse row is
-  // split into the sums over two blocks' own fine rows (split_restrict), A_j
+  // split into the sums over two blocks' own fine rows (split_yweights), A_j
   // from rows c j .. c j + c-1 in the spectra at wt_off, B_j from rows
   // c j - c+1 .. c j - 1 at wt_off + split_off; pass B adds the two.  0: the
   // spectra hold whole restrictions.

@@ -61,7 +61,7 @@ __device__ __forceinline__ void fused_stage_block(
   constexpr int NT = kFusedThreads;
   constexpr int NR = C * TJ + 1;      // the most own fine rows (+1: top wall row)
   // c >= 4 (one coarse row per block): the next stage's restriction is split
-  // (split_restrict), so the block restricts its own fine rows only; c <= 2
+  // (split_yweights), so the block restricts its own fine rows only; c <= 2
   // computes the C-1 rows below the block as well, for whole restrictions
   constexpr bool SPLIT = NEXT && C >= 4;
   static_assert(!SPLIT || TJ == 1, "split restriction: one coarse row per block");
@@ -315,26 +315,25 @@ __device__ __forceinline__ void fused_stage_block(
     for (int q = 0; q < NQ; ++q) z[q] = {T(0), T(0)};
     if constexpr (SPLIT) {
       // the parts of coarse rows j0 (a) and j0+1 (b) that the block's own fine
-      // rows carry, packed as pass A packs them (a of the wall row 0 and b of
-      // the wall row My as 0); the rows go through LDS for the x weights
-      T* rt = wtile;
-      __syncthreads();  // every thread is done with wtile and psc
+      // rows (res[e] = fine row C j0 + e) carry, packed as pass A packs them
+      // (a of the wall row 0 and b of the wall row My as 0): the y weights of
+      // the thread's column in registers, then the x weights over the
+      // neighbouring columns' sums (two LDS rows of their own)
+      T ya, yb;
+      split_yweights<T, C>(res, ya, yb);
+      T* yc = psc + (TJ + 2) * prow;
       if (x < nx) {
-#pragma unroll
-        for (int k = 0; k < C; ++k) rt[k * pitch + x] = res[k];
+        yc[x] = ya;
+        yc[pitch + x] = yb;
       }
-      __syncthreads();
+      __syncthreads();  // also: every thread is done with wtile and psc
       if (i < Mx) {
-        T racc[C];
-#pragma unroll
-        for (int e = 0; e < C; ++e) racc[e] = xweight<T, C>(rt + e * pitch + C * i);
-        T a, b;
-        split_restrict<T, C>(racc, a, b);
+        T a = xweight<T, C>(yc + C * i) * (T(1) / T(C * C * C * C));
+        T b = xweight<T, C>(yc + pitch + C * i) * (T(1) / T(C * C * C * C));
         if (j0 == 0) a = T(0);
         if (j0 + 1 > My - 1) b = T(0);
         z[0] = {a, b};
       }
-      __syncthreads();  // rt is read: the transform buffers may overwrite it
     } else {
       // whole restrictions: each thread holds its fine column's rows, so the
       // y weights come first, in registers, and one value per coarse row and

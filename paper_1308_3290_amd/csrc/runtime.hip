@@ -357,12 +357,13 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                    const size_t fft =
                        (size_t)2 * (nl == 1 ? fused_nseq(tj) : tj + 2) * lpad(d.Lr) * cs;
                    const size_t region = (std::max(fft, tile) + 15) & ~(size_t)15;
-                   // rows of the column sums of whole restrictions at c > 1
-                   // (one layer at c >= 4 restricts split, in the tile region)
-                   const bool ysums = d.c == 2 || (nl == 2 && d.c > 2);
+                   // rows of the restriction's column sums at c > 1: tj per
+                   // layer (whole restrictions), or two (the a and b parts of
+                   // a split one, one layer at c >= 4)
+                   const int ysums = d.c == 1 ? 0 : nl == 2 ? 2 * tj : d.c >= 4 ? 2 : tj;
                    const size_t lds = region + (size_t)d.ntw_r * cs +
                                       (size_t)nl * (tj + 2) * (d.Mx + 1) * es +
-                                      (ysums ? (size_t)nl * tj * (d.nx + 1) * es : 0);
+                                      (size_t)ysums * (d.nx + 1) * es;
                    return std::make_pair((d.My + tj - 1) / tj, lds);
                  },
                  plan->groups[3]);

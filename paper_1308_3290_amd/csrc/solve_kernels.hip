@@ -132,8 +132,9 @@ __device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __r
 
 // Split restriction (one layer, c >= 4): block j0 packs the parts a of
 // coarse row j0 and b of row j0+1 that fine rows C j0 .. C j0 + C-1 carry
-// (split_restrict), the fused pass's packing; a of the wall row 0 and b of
-// the wall row My are 0.
+// (split_yweights of each fine column, then xweight over the columns' sums,
+// in the fused pass's order); a of the wall row 0 and b of the wall row My
+// are 0.
 template <typename T, int C>
 __device__ __forceinline__ void split_block(const MemberDesc& d, const T* __restrict__ f,
                                             cplx<T>* buf, int j0) {
@@ -143,10 +144,21 @@ __device__ __forceinline__ void split_block(const MemberDesc& d, const T* __rest
   for (int q = 0; q < kColIter; ++q) {
     const int i = min(1 + (int)threadIdx.x + kThreads * q, Mx - 1);
     if (q * kThreads < Mx - 1) {
-      T r[C];
+      T sa = T(0), sb = T(0);
+#pragma unroll 1
+      for (int e = 0; e < 2 * C - 1; ++e) {
+        const T* colp = f + (size_t)C * j0 * pitch + C * i - (C - 1) + e;
+        T r[C];
 #pragma unroll
-      for (int e = 0; e < C; ++e) r[e] = xweight<T, C>(f + (size_t)(C * j0 + e) * pitch + C * i);
-      split_restrict<T, C>(r, a[q], b[q]);
+        for (int k = 0; k < C; ++k) r[k] = colp[(size_t)k * pitch];
+        T ya, yb;
+        split_yweights<T, C>(r, ya, yb);
+        const T wx = T(C - (e < C - 1 ? C - 1 - e : e - (C - 1)));
+        sa += wx * ya;
+        sb += wx * yb;
+      }
+      a[q] = sa * (T(1) / T(C * C * C * C));
+      b[q] = sb * (T(1) / T(C * C * C * C));
     }
   }
 #pragma unroll

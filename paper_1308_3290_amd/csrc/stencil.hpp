@@ -67,20 +67,22 @@ __device__ __forceinline__ T lap5(const Nbr<T>& q, T idx2, T idy2) {
 
 // Full weighting applied log2(C) times (Sec. 3.1) has 1-D weights
 // (C - |d|)/C^2, |d| < C.  Split restriction: for the C fine rows
-// C j .. C j + C-1 of a block (r[e], e = 0..C-1, each already weighted and
-// summed along x), a = the part of coarse row j's restriction they carry
-// (weights C - e) and b = the part of coarse row j+1's (weights e); coarse
-// row j's restriction is then a_j + b_j, with b_j from the block below.  The
-// same code serves pass A and the fused pass, so both give the same bits.
+// C j .. C j + C-1 of a block, a = the part of coarse row j's restriction
+// they carry (y weights C - e for fine row C j + e) and b = the part of coarse
+// row j+1's (y weights e); coarse row j's restriction is then a_j + b_j, with
+// b_j from the block below.  This gives the y-weighted sums of one fine
+// column (r[e] = its value on fine row C j + e); the x weights (xweight over
+// the columns' sums) and 1/C^4 follow.  The same code serves pass A and the
+// fused pass, so both give the same bits.
 template <typename T, int C>
-__device__ __forceinline__ void split_restrict(const T* r, T& a, T& b) {
+__device__ __forceinline__ void split_yweights(const T* r, T& a, T& b) {
   T sa = T(0), sb = T(0);
 #pragma unroll
   for (int e = 0; e < C; ++e) sa += T(C - e) * r[e];
 #pragma unroll
   for (int e = 1; e < C; ++e) sb += T(e) * r[e];
-  a = sa * (T(1) / T(C * C * C * C));
-  b = sb * (T(1) / T(C * C * C * C));
+  a = sa;
+  b = sb;
 }
 
 // x-weighted sum of one fine row at coarse column i (weights C - |dx|).
