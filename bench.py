@@ -387,9 +387,11 @@ def main():
             compile-time instantiations that the 512x1024 level-1 step runs)."""
             if doc.get("source_hash") != source_hash():
                 return None
-            want = ("k_prolong_stencil<double, 2, 2, 512, true>"
-                    if dom.startswith("k_prolong_stencil") else "k_col_solve<double, 1024, false>")
-            return doc.get("kernels", {}).get(want)
+            # (the fused kernel's last template argument is the store form)
+            want = ("k_prolong_stencil<double, 2, 2, 512, true, "
+                    if dom.startswith("k_prolong_stencil") else "k_col_solve<double, 1024, 0>")
+            hits = [v for k, v in doc.get("kernels", {}).items() if k.startswith(want)]
+            return hits[0] if len(hits) == 1 else None
 
         traffic = None
         tfile = os.path.join(ROOT, "profiles", "traffic_c1_l1.json")

@@ -44,7 +44,15 @@ constexpr int kDiagBlocks = 2048;   // most blocks (partial sums) of the diagnos
 __host__ __device__ constexpr int fused_tj(int c, int nl = 1) {
   return c >= 4 ? 1 : (c == 2 ? 2 : (nl == 2 ? 1 : 4));
 }
-__host__ __device__ constexpr int fused_nr(int c, int nl = 1) { return c * fused_tj(c, nl) + 1; }
+// One layer at c >= 4 (a coarse row per block, split restrictions): a
+// block owns at most kSplitRows of the coarse row's c fine rows, so that
+// c = 8 runs two blocks per coarse row (one CU each for a single basin)
+// instead of one block doing eight rows' stencils.
+constexpr int kSplitRows = 4;
+__host__ __device__ constexpr int split_blocks(int c) { return c > kSplitRows ? c / kSplitRows : 1; }
+__host__ __device__ constexpr int fused_nr(int c, int nl = 1) {
+  return (nl == 1 && c >= 4 ? c / split_blocks(c) : c * fused_tj(c, nl)) + 1;
+}
 // complex sequences the fused one-layer pass transforms at most: the coarse
 // rows j0-1 .. j0+TJ in whole pairs (2m-1, 2m)
 __host__ __device__ constexpr int fused_nseq(int tj) { return (tj + 3) / 2; }
@@ -70,12 +78,15 @@ struct MemberDesc {
   int nblk[NUM_PASSES]; // blocks of this member in each pass
   long long field_off;  // packed fine fields ([L][ny+1][nx+1] per member)
   long long wt_off;     // coarse spectra: L modes x (Mx-1) x (My-1), k-major
-  // One layer at c >= 4 (fused steps): the restriction of a coarse row is
-  // split into the sums over two blocks' own fine rows (split_yweights), A_j
-  // from rows c j .. c j + c-1 in the spectra at wt_off, B_j from rows
-  // c j - c+1 .. c j - 1 at wt_off + split_off; pass B adds the two.  0: the
-  // spectra hold whole restrictions.
+  // One layer at c >= 4 (fused steps): the restriction of a coarse row j is
+  // split into the sums over the own fine rows of the blocks that cover
+  // fine rows c (j-1) + 1 .. c j + c-1 (split_yweights): a block of coarse
+  // row j's h-th share of its fine rows stores its part of row j at
+  // wt_off + 2h split_off and its part of row j+1 at wt_off + (2h+1)
+  // split_off; pass B adds the nparts parts (2 split_blocks(c)).
+  // split_off = 0, nparts = 0: the spectra hold whole restrictions.
   long long split_off;
+  int nparts;
   long long twr_off;    // row twiddle tables, in complex elements of T (ntw_r values)
   long long twc_off;    // column twiddle tables (ntw_c values)
   long long lam_off;    // doubles: lambda_x (Mx-1) then lambda_y (My-1)
@@ -283,7 +294,8 @@ struct Group {
   int nblk, threads;  // threads = kThreads
   size_t lds;
   int nlayers;         // layers of every member of the handle
-  int split;           // some member has a split restriction (pass B adds its b spectra)
+  int split;           // the most parts of a split restriction among the members (0: none;
+                       // pass B adds a member's parts)
 };
 
 // Launch wrappers implemented in the kernel translation units.

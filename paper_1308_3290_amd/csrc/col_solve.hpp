@@ -32,9 +32,10 @@ __device__ __forceinline__ double recip(double x) {
 // of the block calls it; a block of more threads than the transform has
 // butterflies leaves the rest idle between the barriers).  smem is the
 // block's dynamic LDS, red NT/64 doubles of LDS for the step-size reduction.
-// SPLIT: a member with a split restriction (split_off) gets the sum of its a
-// and b spectra as the input (groups without such members skip the check).
-template <typename T, int LC, int NT, bool SPLIT = false>
+// SP: the most parts of a split restriction among the group's members (0:
+// none); a member with a split restriction (split_off) gets the sum of its
+// nparts part spectra as the input.
+template <typename T, int LC, int NT, int SP = 0>
 __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
                                                 const T* __restrict__ win, T* __restrict__ wout,
                                                 const cplx<T>* __restrict__ twg,
@@ -95,15 +96,23 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
     vb[q] = has_b ? b : T(0);
     ly[q] = lamy[l - 1];
   }
-  if (SPLIT && d.split_off != 0) {
-    // split restriction: the spectra of the b parts are added to those of
-    // the a parts (the x transform is linear)
+  if (SP > 0 && d.split_off != 0) {
+    // split restriction: the spectra of the other parts are added to those
+    // of the first, in part order (the x transform is linear); every part's
+    // loads are issued together (a member with fewer parts than SP reads
+    // part 0 in their place and discards it)
+    const int np = d.nparts;
 #pragma unroll
-    for (int q = 0; q < kRowIter; ++q) {
-      const int l = min(1 + CGP_TID + NT * q, My - 1);
-      va[q] += cola[d.split_off + l - 1];
-      const T b = colb[d.split_off + l - 1];
-      vb[q] += has_b ? b : T(0);
+    for (int p = 1; p < SP; ++p) {
+      const size_t po = (size_t)(p < np ? p : 0) * d.split_off;
+#pragma unroll
+      for (int q = 0; q < kRowIter; ++q) {
+        const int l = min(1 + CGP_TID + NT * q, My - 1);
+        const T a = cola[po + l - 1];
+        const T b = colb[po + l - 1];
+        va[q] = p < np ? va[q] + a : va[q];
+        vb[q] = p < np ? vb[q] + (has_b ? b : T(0)) : vb[q];
+      }
     }
   }
   if constexpr (LC == 0) {

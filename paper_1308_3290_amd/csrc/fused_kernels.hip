@@ -40,9 +40,20 @@ __global__ __launch_bounds__(kFusedThreads, fused_waves_per_simd(C, LC)) void k_
   extern __shared__ __align__(16) unsigned char smem[];
   const int bid = xcd_contiguous(blockIdx.x, nblk);
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_CD, bid)];
-  fused_stage_block<T, C, TJ, LC, NEXT, (C == 2), NTS>(d, bid - d.blk0[PASS_CD], wt, wnext, twg,
-                                                      ws, forcing, wn, out, psi_out, a_, b_, ctl,
-                                                      smem);
+  const int lb = bid - d.blk0[PASS_CD];
+  if constexpr (C >= 4 && split_blocks(C) == 2) {
+    // two blocks per coarse row: the share index selects the row weights
+    if (lb & 1)
+      fused_stage_block<T, C, TJ, LC, NEXT, false, NTS, 1>(d, lb, wt, wnext, twg, ws, forcing, wn,
+                                                           out, psi_out, a_, b_, ctl, smem);
+    else
+      fused_stage_block<T, C, TJ, LC, NEXT, false, NTS, 0>(d, lb, wt, wnext, twg, ws, forcing, wn,
+                                                           out, psi_out, a_, b_, ctl, smem);
+  } else {
+    static_assert(C < 4 || split_blocks(C) == 1, "one or two blocks per coarse row");
+    fused_stage_block<T, C, TJ, LC, NEXT, (C == 2), NTS>(d, lb, wt, wnext, twg, ws, forcing, wn,
+                                                        out, psi_out, a_, b_, ctl, smem);
+  }
 }
 
 // g.L = (c << 16) | transform length with a compile-time transform (or 0).

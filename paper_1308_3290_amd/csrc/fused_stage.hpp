@@ -51,15 +51,23 @@ __host__ __device__ constexpr int fused_waves_per_simd(int c, int lc) {
 // kFusedThreads threads; smem is the block's dynamic LDS.  EARLY: issue the
 // vorticity tile loads with the spectra (the faster order at c = 2) rather
 // than once the spectra are in LDS (fewer registers live across the
-// transform).
-template <typename T, int C, int TJ, int LC, bool NEXT, bool EARLY = (C == 2), bool NTS = false>
+// transform).  At c >= 4 (TJ = 1) split_blocks(C) consecutive blocks share
+// a coarse row, block lb owning share HB = lb mod split_blocks(C) of its
+// fine rows (the caller passes HB: the prolongation weights are then
+// constants).
+template <typename T, int C, int TJ, int LC, bool NEXT, bool EARLY = (C == 2), bool NTS = false,
+          int HB = 0>
 __device__ __forceinline__ void fused_stage_block(
     const MemberDesc& d, int lb, const T* __restrict__ wt, T* __restrict__ wnext,
     const cplx<T>* __restrict__ twg, const T* __restrict__ ws, const T* __restrict__ forcing,
     const T* __restrict__ wn, T* __restrict__ out, T* __restrict__ psi_out, double a_,
     double b_, StepCtl ctl, unsigned char* smem) {
   constexpr int NT = kFusedThreads;
-  constexpr int NR = C * TJ + 1;      // the most own fine rows (+1: top wall row)
+  constexpr int H = C >= 4 ? split_blocks(C) : 1;  // blocks per coarse row
+  constexpr int CR = C / H;           // fine rows of a coarse row a block owns
+  static_assert(H == 1 || TJ == 1, "shared coarse rows: one coarse row per block");
+  static_assert(HB < H, "share index");
+  constexpr int NR = CR * TJ + 1;     // the most own fine rows (+1: top wall row)
   // c >= 4 (one coarse row per block): the next stage's restriction is split
   // (split_yweights), so the block restricts its own fine rows only; c <= 2
   // computes the C-1 rows below the block as well, for whole restrictions
@@ -68,7 +76,7 @@ __device__ __forceinline__ void fused_stage_block(
   constexpr int E = (NEXT && !SPLIT) ? C - 1 : 0;  // computed rows below the block
   constexpr int NO = NR + E;          // the most computed rows
   constexpr int NP = NO + 2;          // tile rows: computed rows and one on each side
-  constexpr int OFF = C - 1 - E;      // tile row u is fine row C*(j0-1) + OFF + u
+  constexpr int OFF = C - 1 - E + HB * CR;  // tile row u is fine row C*(j0-1) + OFF + u
   constexpr int NSQ = fused_nseq(TJ);  // complex sequences of the inverse transform
   constexpr int NQ = (TJ + 1) / 2;     // complex sequences of the next stage's transform
   // twiddles per thread: (R-1) Ns summed over the stages, < L <= 1024
@@ -86,7 +94,7 @@ __device__ __forceinline__ void fused_stage_block(
 
   // coarse rows j0-1 .. j0+TJ are synthesised in the global pairs (2m-1, 2m),
   // so that every block that synthesises a row gets the same bits for it
-  const int j0 = lb * TJ;
+  const int j0 = (lb / H) * TJ;
   const int rlo = max(1, j0 - 1);
   const int ilo = rlo - ((rlo & 1) ? 0 : 1);      // odd: first row of its pair
   const int rhi = min(My - 1, j0 + TJ);
@@ -95,8 +103,8 @@ __device__ __forceinline__ void fused_stage_block(
   const int nint = ihi >= ilo ? ihi - ilo + 1 : 0;
   const int nseq = (nint + 1) / 2;
   const int last = (lb == d.nblk[PASS_CD] - 1);
-  const int R0 = C * j0;
-  const int R1 = last ? ny + 1 : C * (j0 + TJ);  // exclusive end of the own rows
+  const int R0 = C * j0 + HB * CR;
+  const int R1 = last ? ny + 1 : R0 + CR * TJ;   // exclusive end of the own rows
   const int nfr = R1 - R0;                       // own rows (<= NR)
   const int nrow = nfr + E;                      // computed rows: tile rows 1 .. nrow
   const int RB0 = R0 - 1 - E;                    // fine row of tile row 0
@@ -315,12 +323,13 @@ __device__ __forceinline__ void fused_stage_block(
     for (int q = 0; q < NQ; ++q) z[q] = {T(0), T(0)};
     if constexpr (SPLIT) {
       // the parts of coarse rows j0 (a) and j0+1 (b) that the block's own fine
-      // rows (res[e] = fine row C j0 + e) carry, packed as pass A packs them
+      // rows (res[k] = fine row C j0 + HB CR + k, k < CR) carry, packed as
+      // pass A packs them
       // (a of the wall row 0 and b of the wall row My as 0): the y weights of
       // the thread's column in registers, then the x weights over the
       // neighbouring columns' sums (two LDS rows of their own)
       T ya, yb;
-      split_yweights<T, C>(res, ya, yb);
+      split_yweights<T, C, CR>(res, HB * CR, ya, yb);
       T* yc = psc + (TJ + 2) * prow;
       if (x < nx) {
         yc[x] = ya;
@@ -384,11 +393,11 @@ __device__ __forceinline__ void fused_stage_block(
     const cplx<T>* Z2 = fft_runn<T, LC, NT, (NQ > 2 ? 4 : 2)>(buf, buf + NQ * LP, NQ, L, d.nst_r,
                                                               d.stw_r, tw);
     if (SPLIT && i < Mx) {
-      // a of row j0 with the spectra, b of row j0+1 at the split offset
+      // the part of row j0 in part array 2 HB, that of row j0+1 in 2 HB + 1
       T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
       const cplx<T> zk = Z2[pad(i)];
-      if (j0 >= 1) wo[j0 - 1] = T(-0.5) * zk.y;
-      if (j0 + 1 <= My - 1) wo[d.split_off + j0] = T(0.5) * zk.x;
+      if (j0 >= 1) wo[2 * HB * d.split_off + j0 - 1] = T(-0.5) * zk.y;
+      if (j0 + 1 <= My - 1) wo[(2 * HB + 1) * d.split_off + j0] = T(0.5) * zk.x;
     } else if (i < Mx) {
       // rows j0+2q, j0+2q+1 are consecutive in column i: one store per pair
       T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);

@@ -291,17 +291,19 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
               d.My % fused_tj(d.c, nl) == 0;
     if (nl == 2) fusable = fusable && fft_special(d.Lr) != 0;
   }
-  // one layer at c >= 4 with the fused pass: split restrictions (the b
-  // spectra after every member's a spectra, in the same region)
-  bool any_split = false;
+  // one layer at c >= 4 with the fused pass: split restrictions (part p of
+  // every member's spectra at p times the size of all members' spectra, in
+  // the same region)
+  int max_parts = 1;
   for (MemberDesc& d : plan->md) {
     d.split_off = (fusable && nl == 1 && d.c >= 4) ? wt : 0;
-    any_split = any_split || d.split_off != 0;
+    d.nparts = d.split_off ? 2 * split_blocks(d.c) : 0;
+    max_parts = std::max(max_parts, d.nparts);
   }
   // pass A: one complex sequence per block: coarse rows packed as the fused
   // pass packs them when it computes the next stage's spectra (so that both
   // give the same bits), else a pair of rows; two layers: one row's modes;
-  // split members: one block per coarse row j0 = 0 .. My-1
+  // split members: split_blocks(c) blocks per coarse row j0 = 0 .. My-1
   build_groups(plan->md, PASS_A, [](const MemberDesc& d) { return fft_special(d.Lr); },
                [&](MemberDesc& d, HostGroup&) {
                  d.pa = 1;
@@ -309,7 +311,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                  d.a_first = (nl == 1 && fusable && (d.a_rows == 2 || d.split_off)) ? 0 : 1;
                  const int nrows = d.My - d.a_first;
                  const size_t lds = ((size_t)2 * lpad(d.Lr) + d.ntw_r) * cs;
-                 return std::make_pair((nrows + d.a_rows - 1) / d.a_rows, lds);
+                 const int shares = d.split_off ? d.nparts / 2 : 1;
+                 return std::make_pair((nrows + d.a_rows - 1) / d.a_rows * shares, lds);
                },
                plan->groups[0]);
   // pass B: one complex sequence per block: a pair of spectral columns (one
@@ -341,9 +344,10 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
     for (const HostGroup& g : plan->groups[p])
       if (g.lds > kMaxLds)
         return fail(CGP_ERR_UNSUPPORTED, "a transform pass needs more than 160 KiB LDS per block");
-  // fused C + D: a block owns fused_tj(c) coarse rows and synthesises the
-  // two neighbouring ones (at most two packed sequences); one launch per
-  // coarsening factor and transform length.
+  // fused C + D: a block owns fused_tj(c) coarse rows (one layer at c >= 4:
+  // a share of one coarse row's fine rows, split_blocks(c) blocks per row)
+  // and synthesises the two neighbouring ones (at most two packed
+  // sequences); one launch per coarsening factor and transform length.
   if (fusable) {
     build_groups(plan->md, PASS_CD,
                  [](const MemberDesc& d) { return (d.c << 16) | fft_special(d.Lr); },
@@ -364,7 +368,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                    const size_t lds = region + (size_t)d.ntw_r * cs +
                                       (size_t)nl * (tj + 2) * (d.Mx + 1) * es +
                                       (size_t)ysums * (d.nx + 1) * es;
-                   return std::make_pair((d.My + tj - 1) / tj, lds);
+                   const int shares = nl == 1 && d.c >= 4 ? split_blocks(d.c) : 1;
+                   return std::make_pair((d.My + tj - 1) / tj * shares, lds);
                  },
                  plan->groups[3]);
     plan->fused = true;
@@ -415,7 +420,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   off = align_up(off + (plan->persist_ok ? sizeof(PTile) * plan->persist_max_tiles : 0));
   L.pctr = off;
   off = align_up(off + (plan->persist_ok ? sizeof(int) * (kPersistCounters + count) : 0));
-  L.wt = off; off = align_up(off + (size_t)wt * (any_split ? 2 : 1) * es);
+  L.wt = off; off = align_up(off + (size_t)wt * max_parts * es);
   L.wt2 = off; off = align_up(off + (size_t)wt * es);
   L.field_elems = fld;
   L.psi = off; off = align_up(off + (size_t)fld * es);
@@ -460,7 +465,7 @@ struct cgp_handle {
     const HostGroup& g = plan.groups[pass][i];
     const int count = g.members.size() == 1 ? -(g.members[0] + 1) : (int)g.members.size();
     int split = 0;
-    for (int m : g.members) split |= plan.md[m].split_off != 0 ? 1 : 0;
+    for (int m : g.members) split = std::max(split, plan.md[m].nparts);
     return Group{g.L,   count, at<int>(plan.lay.order) + g.order_off, g.nblk,
                  kThreads, g.lds, plan.nlayers, split};
   }

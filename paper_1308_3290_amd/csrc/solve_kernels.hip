@@ -130,15 +130,18 @@ __device__ __forceinline__ void restrict_block(const MemberDesc& d, const T* __r
   }
 }
 
-// Split restriction (one layer, c >= 4): block j0 packs the parts a of
-// coarse row j0 and b of row j0+1 that fine rows C j0 .. C j0 + C-1 carry
-// (split_yweights of each fine column, then xweight over the columns' sums,
+// Split restriction (one layer, c >= 4): the block of share h of coarse row
+// j0 packs the parts a of row j0 and b of row j0+1 that fine rows
+// C j0 + h CR .. C j0 + h CR + CR-1 carry (CR = C / split_blocks(C);
+// split_yweights of each fine column, then xweight over the columns' sums,
 // in the fused pass's order); a of the wall row 0 and b of the wall row My
 // are 0.
 template <typename T, int C>
 __device__ __forceinline__ void split_block(const MemberDesc& d, const T* __restrict__ f,
-                                            cplx<T>* buf, int j0) {
+                                            cplx<T>* buf, int j0, int h) {
+  constexpr int CR = C / split_blocks(C);
   const int Mx = d.Mx, My = d.My, pitch = d.nx + 1;
+  const int e0 = h * CR;
   T a[kColIter], b[kColIter];
 #pragma unroll
   for (int q = 0; q < kColIter; ++q) {
@@ -147,12 +150,12 @@ __device__ __forceinline__ void split_block(const MemberDesc& d, const T* __rest
       T sa = T(0), sb = T(0);
 #pragma unroll 1
       for (int e = 0; e < 2 * C - 1; ++e) {
-        const T* colp = f + (size_t)C * j0 * pitch + C * i - (C - 1) + e;
-        T r[C];
+        const T* colp = f + (size_t)(C * j0 + e0) * pitch + C * i - (C - 1) + e;
+        T r[CR];
 #pragma unroll
-        for (int k = 0; k < C; ++k) r[k] = colp[(size_t)k * pitch];
+        for (int k = 0; k < CR; ++k) r[k] = colp[(size_t)k * pitch];
         T ya, yb;
-        split_yweights<T, C>(r, ya, yb);
+        split_yweights<T, C, CR>(r, e0, ya, yb);
         const T wx = T(C - (e < C - 1 ? C - 1 - e : e - (C - 1)));
         sa += wx * ya;
         sb += wx * yb;
@@ -185,7 +188,11 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
   const int LP = lpad(L);
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + 2 * LP;
-  const int j0 = NL == 1 ? d.a_first + lb * d.a_rows : 1 + lb;
+  // split members: split_blocks(c) blocks per coarse row (share h)
+  const bool split = NL == 1 && d.split_off != 0;
+  const int hs = split ? d.nparts / 2 : 1;
+  const int h = lb % hs;
+  const int j0 = NL == 1 ? d.a_first + (lb / hs) * d.a_rows : 1 + lb;
   // rows of the pair that exist and are interior (1 .. My-1)
   const int keep = NL == 1 ? ((j0 >= 1 ? 1 : 0) | (d.a_rows == 2 && j0 + 1 <= My - 1 ? 2 : 0)) : 1;
 
@@ -202,10 +209,9 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     buf[pad(Mx)] = {T(0), T(0)};
   }
   const T* f = src + d.field_off;
-  const bool split = NL == 1 && d.split_off != 0;
   if (split) {
-    if (d.c == 4) split_block<T, 4>(d, f, buf, j0);
-    else split_block<T, 8>(d, f, buf, j0);
+    if (d.c == 4) split_block<T, 4>(d, f, buf, j0, h);
+    else split_block<T, 8>(d, f, buf, j0, h);
   } else {
     switch (d.c) {
       case 1: restrict_block<T, 1, NL>(d, f, buf, j0, keep); break;
@@ -229,9 +235,9 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     const cplx<T> zk = Z[pad(k)];
     const long long o = (long long)(k - 1) * (My - 1) + (j0 - 1);  // row j0 (-1 if j0 = 0)
     if constexpr (NL == 1) {
-      if (split) {  // a of row j0; b of row j0+1 at the split offset
-        if (j0 >= 1) w[o] = T(-0.5) * zk.y;
-        if (j0 + 1 <= My - 1) w[d.split_off + o + 1] = T(0.5) * zk.x;
+      if (split) {  // a of row j0 in part 2h; b of row j0+1 in part 2h+1
+        if (j0 >= 1) w[2 * h * d.split_off + o] = T(-0.5) * zk.y;
+        if (j0 + 1 <= My - 1) w[(2 * h + 1) * d.split_off + o + 1] = T(0.5) * zk.x;
       } else {
         if (keep & 1) w[o] = T(-0.5) * zk.y;
         if (keep & 2) w[o + 1] = T(0.5) * zk.x;
@@ -247,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
 // ---------------------------------------------------------------------------
 // Pass B: one block per pair of spectral columns (col_solve.hpp).
 // ---------------------------------------------------------------------------
-template <typename T, int LC, bool SPLIT>
+template <typename T, int LC, int SP>
 __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __restrict__ md,
                                                         const int* __restrict__ grp, int ng,
                                                         const T* __restrict__ win,
@@ -258,8 +264,8 @@ __global__ __launch_bounds__(kThreads) void k_col_solve(const MemberDesc* __rest
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kThreads / 64];  // step-size reduction
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_B, blockIdx.x)];
-  col_solve_block<T, LC, kThreads, SPLIT>(d, blockIdx.x - d.blk0[PASS_B], win, wout, twg, lam,
-                                          ctl, smem, red);
+  col_solve_block<T, LC, kThreads, SP>(d, blockIdx.x - d.blk0[PASS_B], win, wout, twg, lam, ctl,
+                                       smem, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -431,26 +437,31 @@ template <typename T>
 hipError_t Launch<T>::col_solve(const MemberDesc* md, const Group& g, const T* win, T* wout,
                                 const cplx<T>* tw, const double* lam, double* ctl, int split,
                                 hipStream_t s) {
-#define CALL(LC)                                                                       \
-  hipLaunchKernelGGL((k_col_solve<T, LC, false>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
+#define CALL(LC, SP)                                                                       \
+  hipLaunchKernelGGL((k_col_solve<T, LC, SP>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
                      g.members, g.count, win, wout, tw, lam, ctl)
-#define CALLS(LC)                                                                     \
-  hipLaunchKernelGGL((k_col_solve<T, LC, true>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
-                     g.members, g.count, win, wout, tw, lam, ctl)
-  if (split && g.split) {
-    CGP_BY_LENGTH(g.L, CALLS)
+#define CALL0(LC) CALL(LC, 0)
+#define CALL2(LC) CALL(LC, 2)
+#define CALL4(LC) CALL(LC, 4)
+  // g.split: the most parts of a split restriction among the members
+  if (!split || g.split == 0) {
+    CGP_BY_LENGTH(g.L, CALL0)
+  } else if (g.split <= 2) {
+    CGP_BY_LENGTH(g.L, CALL2)
   } else {
-    CGP_BY_LENGTH(g.L, CALL)
+    CGP_BY_LENGTH(g.L, CALL4)
   }
+#undef CALL0
+#undef CALL2
+#undef CALL4
 #undef CALL
-#undef CALLS
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t Launch<T>::rowdst_prolong(const MemberDesc* md, const Group& g, const T* wt, T* dst,
                                      int accumulate, const cplx<T>* tw, hipStream_t s) {
-#define CALL(LC)                                                                             \
+#define CALL(LC)                                                                            \
   hipLaunchKernelGGL((k_rowdst_prolong<T, LC>), dim3(g.nblk), dim3(kThreads), g.lds, s, md, \
                      g.members, g.count, wt, dst, accumulate, tw)
   CGP_BY_LENGTH(g.L, CALL)
@@ -462,11 +473,12 @@ template <typename T>
 hipError_t Launch<T>::prepare(size_t bytes) {
   const int b = (int)bytes;
   const void* fns[] = {
-#define FNS(LC)                                                      \
-  reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC, 1>),       \
-      reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC, 2>),   \
-      reinterpret_cast<const void*>(&k_col_solve<T, LC, false>),     \
-      reinterpret_cast<const void*>(&k_col_solve<T, LC, true>),      \
+#define FNS(LC)                                                    \
+  reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC, 1>),     \
+      reinterpret_cast<const void*>(&k_restrict_rowdst<T, LC, 2>), \
+      reinterpret_cast<const void*>(&k_col_solve<T, LC, 0>),       \
+      reinterpret_cast<const void*>(&k_col_solve<T, LC, 2>),       \
+      reinterpret_cast<const void*>(&k_col_solve<T, LC, 4>),       \
       reinterpret_cast<const void*>(&k_rowdst_prolong<T, LC>)
       FNS(0), FNS(128), FNS(256), FNS(384), FNS(512), FNS(768), FNS(1024), FNS(1536), FNS(2048)
 #undef FNS

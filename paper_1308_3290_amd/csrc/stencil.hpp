@@ -66,21 +66,23 @@ __device__ __forceinline__ T lap5(const Nbr<T>& q, T idx2, T idy2) {
 }
 
 // Full weighting applied log2(C) times (Sec. 3.1) has 1-D weights
-// (C - |d|)/C^2, |d| < C.  Split restriction: for the C fine rows
-// C j .. C j + C-1 of a block, a = the part of coarse row j's restriction
-// they carry (y weights C - e for fine row C j + e) and b = the part of coarse
-// row j+1's (y weights e); coarse row j's restriction is then a_j + b_j, with
-// b_j from the block below.  This gives the y-weighted sums of one fine
-// column (r[e] = its value on fine row C j + e); the x weights (xweight over
-// the columns' sums) and 1/C^4 follow.  The same code serves pass A and the
-// fused pass, so both give the same bits.
-template <typename T, int C>
-__device__ __forceinline__ void split_yweights(const T* r, T& a, T& b) {
+// (C - |d|)/C^2, |d| < C.  Split restriction: fine row C j + e (0 <= e < C)
+// carries a share of coarse row j's restriction (y weight C - e) and of
+// coarse row j+1's (y weight e), so coarse row j's restriction is the sum of
+// the parts from the blocks owning fine rows C j .. C j + C-1 (the a parts)
+// and C j - C+1 .. C j - 1 (the b parts of the coarse row below).  This gives
+// the y-weighted sums of one fine column over the CR rows e0 .. e0+CR-1 a
+// block owns (r[k] = the column's value on fine row C j + e0 + k); the x
+// weights (xweight over the columns' sums) and 1/C^4 follow.  The same code
+// serves pass A and the fused pass, so both give the same bits.
+template <typename T, int C, int CR>
+__device__ __forceinline__ void split_yweights(const T* r, int e0, T& a, T& b) {
   T sa = T(0), sb = T(0);
 #pragma unroll
-  for (int e = 0; e < C; ++e) sa += T(C - e) * r[e];
+  for (int k = 0; k < CR; ++k) sa += T(C - (e0 + k)) * r[k];
 #pragma unroll
-  for (int e = 1; e < C; ++e) sb += T(e) * r[e];
+  for (int k = 0; k < CR; ++k)
+    if (e0 + k > 0) sb += T(e0 + k) * r[k];
   a = sa;
   b = sb;
 }
