@@ -306,6 +306,71 @@ __device__ __forceinline__ void ct_stage(const cplx<T>* in, cplx<T>* out, int ns
   __syncthreads();
 }
 
+// The same stage in place (one buffer, half the LDS of a ping-pong pair): a
+// thread reads the inputs of all its butterflies, a barrier, then it writes
+// their outputs (the arithmetic, and so the bits, of ct_stage).
+template <typename T, int L, int S, int NT, int MAXSEQ, int WF>
+__device__ __forceinline__ void ct_stage_inplace(cplx<T>* buf, int nseq, const cplx<T>* tw) {
+  constexpr StagePlan P = stage_plan(L, WF);
+  constexpr int R = P.R[S], LNS = P.lns[S], NS = 1 << LNS, OFF = P.off[S];
+  constexpr int LR = L / R, LP = lpad(L), RS = lpad(LR);
+  static_assert(LR % 8 == 0, "read offsets need L/R to be a multiple of 8");
+  static_assert((NS & (NS - 1)) == 0, "write offsets need a power-of-two span");
+  constexpr int Q = (MAXSEQ * LR + NT - 1) / NT;
+  const int nb = nseq * LR;
+  cplx<T> v[Q][R];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int b = CGP_TID + NT * q;
+    if (b < nb) {
+      const int p = b / LR;
+      const int j = b - p * LR;
+      const cplx<T>* src = buf + p * LP + pad(j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * RS];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int b = CGP_TID + NT * q;
+    if (b < nb) {
+      const int p = b / LR;
+      const int j = b - p * LR;
+      const int k = j & (NS - 1);
+      if constexpr (NS > 1) {
+        const cplx<T>* t = tw + OFF + k;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], t[(r - 1) * NS]);
+      }
+      small_dft<T, R>(v[q]);
+      const int o = ((j >> LNS) << LNS) * R + k;
+      cplx<T>* dst = buf + p * LP + pad(o);
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * NS + ((r * NS) >> 3)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int L, int S, int NT, int MAXSEQ, int WF>
+__device__ __forceinline__ void ct_stages_inplace(cplx<T>* buf, int nseq, const cplx<T>* tw) {
+  if constexpr (S < stage_plan(L, WF).n) {
+    ct_stage_inplace<T, L, S, NT, MAXSEQ, WF>(buf, nseq, tw);
+    ct_stages_inplace<T, L, S + 1, NT, MAXSEQ, WF>(buf, nseq, tw);
+  }
+}
+
+// Compile-time transform of up to four sequences in place in buf (L = LC);
+// begins and ends with a barrier.
+template <typename T, int LC, int NT>
+__device__ __forceinline__ cplx<T>* fft_run4_inplace(cplx<T>* buf, int nseq, const cplx<T>* tw) {
+  static_assert(LC != 0, "in place: a compile-time length");
+  __syncthreads();
+  ct_stages_inplace<T, LC, 0, NT, 4, kWideRows>(buf, nseq, tw);
+  return buf;
+}
+
 // Stages S .. SEND-1, ping-ponging between a and b; returns the buffer that
 // holds the output of stage SEND-1 (a when S == SEND).
 template <typename T, int L, int S, int SEND, int NT, int MAXSEQ, int WF, bool RT = false>

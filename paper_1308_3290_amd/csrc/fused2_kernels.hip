@@ -62,14 +62,24 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
 
   // LDS: [ transform buffers | the two vorticity tiles | restriction rows and
   // the next transform's buffers ] [ twiddles ] [ coarse psi rows, 2 layers ]
+  // [ restriction column sums ].  C = 1: the row transform runs in place
+  // and the coarse psi rows and the tiles follow it in the first region,
+  // [ transform buffer | psi rows, tiles | the next transform's buffers ]
+  // [ twiddles ], which keeps a block within half a CU's LDS (two blocks per
+  // CU; the 1024-point full grid otherwise runs one).
+  constexpr bool INPLACE = C == 1;
+  constexpr int kPsc = 2 * NS * PROW * (int)sizeof(T);
   const int region =
-      (max(2 * NS * LP * (int)sizeof(cplx<T>), 2 * NP * pitch * (int)sizeof(T)) + 15) & ~15;
+      INPLACE ? (max(NS * LP * (int)sizeof(cplx<T>), kPsc + 2 * NP * pitch * (int)sizeof(T)) +
+                 15) & ~15
+              : (max(2 * NS * LP * (int)sizeof(cplx<T>), 2 * NP * pitch * (int)sizeof(T)) + 15) &
+                    ~15;
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  T* tile1 = reinterpret_cast<T*>(smem);
-  T* tile2 = tile1 + NP * pitch;
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + region);
-  T* psc1 = reinterpret_cast<T*>(tw + ntw);
+  T* psc1 = INPLACE ? reinterpret_cast<T*>(smem) : reinterpret_cast<T*>(tw + ntw);
   T* psc2 = psc1 + NS * PROW;
+  T* tile1 = INPLACE ? reinterpret_cast<T*>(smem + kPsc) : reinterpret_cast<T*>(smem);
+  T* tile2 = tile1 + NP * pitch;
 
   // ---- global loads (unconditional; see the one-layer pass): twiddles,
   // spectra and the vorticity tiles first, then (once the transform's inputs
@@ -153,11 +163,16 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
     nv2[u - 1] = in ? n2 : T(0);
   }
 
-  const cplx<T>* Z = fft_run4<T, LC, NT>(buf, buf + NS * LP, NS, tw);
+  const cplx<T>* Z = INPLACE ? fft_run4_inplace<T, LC, NT>(buf, NS, tw)
+                             : fft_run4<T, LC, NT>(buf, buf + NS * LP, NS, tw);
 
   // ---- coarse psi of both layers, rows j0-1 .. j0+TJ (zero walls)
   const T wbc1 = T(1.0 - d.delta), wbc2 = T(d.delta);
-  for (int i = t; i <= MX; i += NT) {
+  constexpr int kPscIter = (MX + 1 + NT - 1) / NT;
+  T pv1[kPscIter][NS], pv2[kPscIter][NS];
+#pragma unroll
+  for (int q = 0; q < kPscIter; ++q) {
+    const int i = t + NT * q;
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
       const int J = j0 - 1 + r;
@@ -168,11 +183,27 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
         v1 = bt + wbc1 * bc;  // psi_1 = psi_bt + (1 - delta) psi_bc
         v2 = bt - wbc2 * bc;  // psi_2 = psi_bt - delta psi_bc
       }
-      psc1[r * PROW + i] = v1;
-      psc2[r * PROW + i] = v2;
+      pv1[q][r] = v1;
+      pv2[q][r] = v2;
     }
   }
-  __syncthreads();  // the transform's output is consumed: the tiles may overwrite it
+  // in place, the psi rows overwrite the transform's output: every thread
+  // reads its values first
+  if constexpr (INPLACE) __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPscIter; ++q) {
+    const int i = t + NT * q;
+    if (i <= MX) {
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        psc1[r * PROW + i] = pv1[q][r];
+        psc2[r * PROW + i] = pv2[q][r];
+      }
+    }
+  }
+  // the transform's output is consumed: the tiles may overwrite it (in place,
+  // the tiles follow the psi rows and were never part of it)
+  if constexpr (!INPLACE) __syncthreads();
 #pragma unroll
   for (int q = 0; q < kWPer; ++q) {
     const int e = t + NT * q;

@@ -358,16 +358,23 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                    // per block for one layer, tj + 2 for two)
                    const int tj = fused_tj(d.c, nl), nr = fused_nr(d.c, nl);
                    const size_t tile = (size_t)nl * (nr + 2 + d.c - 1) * (d.nx + 1) * es;
-                   const size_t fft =
-                       (size_t)2 * (nl == 1 ? fused_nseq(tj) : tj + 2) * lpad(d.Lr) * cs;
-                   const size_t region = (std::max(fft, tile) + 15) & ~(size_t)15;
+                   const size_t psc = (size_t)nl * (tj + 2) * (d.Mx + 1) * es;
                    // rows of the restriction's column sums at c > 1: tj per
                    // layer (whole restrictions), or two (the a and b parts of
                    // a split one, one layer at c >= 4)
                    const int ysums = d.c == 1 ? 0 : nl == 2 ? 2 * tj : d.c >= 4 ? 2 : tj;
-                   const size_t lds = region + (size_t)d.ntw_r * cs +
-                                      (size_t)nl * (tj + 2) * (d.Mx + 1) * es +
-                                      (size_t)ysums * (d.nx + 1) * es;
+                   size_t lds;
+                   if (nl == 2 && d.c == 1) {
+                     // in-place row transform; psi rows and tiles in its region
+                     const size_t fft = (size_t)(tj + 2) * lpad(d.Lr) * cs;
+                     lds = ((std::max(fft, psc + tile) + 15) & ~(size_t)15) +
+                           (size_t)d.ntw_r * cs;
+                   } else {
+                     const size_t fft =
+                         (size_t)2 * (nl == 1 ? fused_nseq(tj) : tj + 2) * lpad(d.Lr) * cs;
+                     const size_t region = (std::max(fft, tile) + 15) & ~(size_t)15;
+                     lds = region + (size_t)d.ntw_r * cs + psc + (size_t)ysums * (d.nx + 1) * es;
+                   }
                    const int shares = nl == 1 && d.c >= 4 ? split_blocks(d.c) : 1;
                    return std::make_pair((d.My + tj - 1) / tj * shares, lds);
                  },
