@@ -450,12 +450,14 @@ def main():
         else:
             setting = autotune.tune(cfgs, Wp, Fpk, steps=30, warmup=6, repeats=3, report=report,
                                     retune=True)
-        ms, finite = timed_runs(cfgs, w0s, Fs, n_steps, 5, setting["use_graph"], max(3, R // 2),
-                                launch=setting["launch"])
+        ms, finite = timed_runs(autotune.configs(cfgs, setting), w0s, Fs, n_steps, 5,
+                                setting["use_graph"], max(3, R // 2), launch=setting["launch"])
         best_by_mode = {}
         for r in report:
             k = ("persistent" if r["launch"]["mode"] == 1 else
                  ("per-pass graphs" if r["use_graph"] else "per-pass direct"))
+            if r.get("fused_rows", 2) == 4:
+                k += ", 4 rows per block"
             if r["accepted"] and (k not in best_by_mode or r["ms_per_step"] < best_by_mode[k][0]):
                 best_by_mode[k] = (r["ms_per_step"], r["launch"])
         log(f"{label}: tuned {setting} over {len(report)} candidates "

@@ -98,6 +98,17 @@ typedef struct cgp_config {
                         * single basin, no adjoint */
   int32_t mg_cycles;   /* V-cycles per solve with solver 1 (0: 12; each cycle cuts
                         * the residual about tenfold) */
+  int32_t fused_rows;  /* one layer at coarsening factor 2: coarse rows per block of the
+                        * fused stage pass, 0 (the default, 2) or 4.  A block
+                        * synthesises its rows and one on each side, and recomputes
+                        * one fine row below its own: 4 rows per block transform 6
+                        * coarse rows for 4 owned instead of 4 for 2 and recompute 1
+                        * fine row in 9 instead of 1 in 5, in half the blocks.
+                        * Faster for large FP32 ensembles (two blocks still fit a
+                        * CU), slower for single basins (half the CUs) and FP64
+                        * ensembles (one block per CU); both give the same bits.
+                        * Shared by every member of a handle; ignored elsewhere.  The
+                        * persistent launch (cgp_set_launch mode 1) needs 2. */
 } cgp_config;
 
 typedef struct cgp_handle cgp_handle;

@@ -24,7 +24,8 @@ class cgp_config(ctypes.Structure):
                 ("y0", ctypes.c_double), ("inv_re", ctypes.c_double),
                 ("inv_ro", ctypes.c_double), ("f1", ctypes.c_double), ("f2", ctypes.c_double),
                 ("drag", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("solver", ctypes.c_int32), ("mg_cycles", ctypes.c_int32)]
+                ("solver", ctypes.c_int32), ("mg_cycles", ctypes.c_int32),
+                ("fused_rows", ctypes.c_int32)]
 
 
 class cgp_launch(ctypes.Structure):

@@ -22,11 +22,23 @@ _TORCH_DTYPE = {CGP_F32: torch.float32, CGP_F64: torch.float64}
 
 def make_config(nx, ny, level=0, nlayers=1, dtype="f64", lx=1.0, ly=2.0, y0=-1.0,
                 inv_re=1.0, inv_ro=0.0, f1=0.0, f2=0.0, drag=0.0, dt=1e-4,
-                cfl=0.0, solver=0, mg_cycles=0) -> cgp_config:
+                cfl=0.0, solver=0, mg_cycles=0, fused_rows=0) -> cgp_config:
     dt_code = {"f64": CGP_F64, "f32": CGP_F32}.get(dtype, dtype)  # ints pass through
     return cgp_config(nx=nx, ny=ny, level=level, nlayers=nlayers, dtype=dt_code, reserved=0,
                       lx=lx, ly=ly, y0=y0, inv_re=inv_re, inv_ro=inv_ro, f1=f1, f2=f2,
-                      drag=drag, dt=dt, cfl=cfl, solver=solver, mg_cycles=mg_cycles)
+                      drag=drag, dt=dt, cfl=cfl, solver=solver, mg_cycles=mg_cycles,
+                      fused_rows=fused_rows)
+
+
+def with_fused_rows(cfgs, rows: int) -> list:
+    """Copies of cfgs with cgp_config.fused_rows = rows (the autotuner's
+    choice for a workload)."""
+    out = []
+    for c in cfgs:
+        d = cgp_config.from_buffer_copy(c)
+        d.fused_rows = rows
+        out.append(d)
+    return out
 
 
 def config_from_case(case, dtype: Optional[str] = None) -> cgp_config:

@@ -3,9 +3,11 @@
     setting = tune(cfgs, omega_packed, forcing_packed)   # cached per device and workload
     ens.set_launch(**setting["launch"]); ens.step(..., use_graph=setting["use_graph"])
 
-Candidates (``cgp_launch`` in include/cgp.h):
+Candidates (``cgp_launch`` and ``cgp_config.fused_rows`` in include/cgp.h):
   - launch mode 0 (one launch per pass and group of members), as replays of
-    captured graphs (member chains forked onto streams) or as direct launches;
+    captured graphs (member chains forked onto streams) or as direct
+    launches, each with 2 and (where a member has one layer at coarsening
+    factor 2) 4 coarse rows per fused-pass block;
   - launch mode 1 (one persistent launch per RK3 stage over every member),
     where the handle has it, over the work-tile shapes b_tile (pass-B column
     pairs per tile), f_tile (fused-pass row blocks per tile) and the grid's
@@ -21,6 +23,8 @@ fastest accepted candidate is stored in a JSON cache keyed by the device's
 architecture name, the dtype, the layer count and the members' grid sizes
 and levels, and later calls with the same key return it without timing.
 The cache file is $CGP_TUNE_CACHE if set, else ~/.cache/cgp/autotune.json.
+A setting is applied as ``configs(cfgs, setting)`` (the handle's configs),
+``ens.set_launch(**setting["launch"])`` and ``use_graph``.
 """
 from __future__ import annotations
 
@@ -33,7 +37,18 @@ import torch
 
 from . import api
 
-REFERENCE = {"launch": dict(mode=0, b_tile=1, f_tile=1, wg_per_cu=0), "use_graph": True}
+REFERENCE = {"launch": dict(mode=0, b_tile=1, f_tile=1, wg_per_cu=0), "use_graph": True,
+             "fused_rows": 2}
+
+
+def configs(cfgs: Sequence[api.cgp_config], setting: dict) -> List[api.cgp_config]:
+    """The members' configs with the setting's fused-pass rows per block."""
+    return api.with_fused_rows(cfgs, setting.get("fused_rows", 2))
+
+
+def has_rows_choice(cfgs: Sequence[api.cgp_config]) -> bool:
+    """Whether fused_rows changes anything: a one-layer member at factor 2."""
+    return any(c.nlayers == 1 and c.level == 1 for c in cfgs)
 
 
 def cache_path() -> str:
@@ -56,14 +71,17 @@ def workload_key(cfgs: Sequence[api.cgp_config], device=None) -> str:
     return f"{arch}|{dt}|L{cfgs[0].nlayers}|{body}"
 
 
-def candidates(persistent: bool) -> List[dict]:
-    out = [dict(REFERENCE), {"launch": dict(REFERENCE["launch"]), "use_graph": False}]
+def candidates(persistent: bool, rows: bool = False) -> List[dict]:
+    base = dict(REFERENCE["launch"])
+    out = [dict(REFERENCE), {"launch": dict(base), "use_graph": False, "fused_rows": 2}]
+    if rows:
+        out += [{"launch": dict(base), "use_graph": g, "fused_rows": 4} for g in (True, False)]
     if persistent:
         for b_tile in (1, 2, 4, 8):
             for f_tile in (1, 2, 4):
                 for wg in (0, 1):
                     out.append({"launch": dict(mode=1, b_tile=b_tile, f_tile=f_tile, wg_per_cu=wg),
-                                "use_graph": True})
+                                "use_graph": True, "fused_rows": 2})
     return out
 
 
@@ -84,7 +102,7 @@ def _store(path: str, doc: dict) -> None:
 
 
 def _run(cfgs, omega, forcing, cand, steps, warmup, repeats, device):
-    ens = api.Ensemble(cfgs, device=device)
+    ens = api.Ensemble(configs(cfgs, cand), device=device)
     ens.set_launch(**cand["launch"])
     w = omega.clone()
     side = torch.cuda.Stream(device=device)
@@ -123,9 +141,10 @@ def tune(cfgs: Sequence[api.cgp_config], omega_packed: torch.Tensor,
     probe = api.Ensemble(cfgs, device=device)
     persistent = probe.launch()[1]
     probe.close()
+    rows = has_rows_choice(cfgs)
     best = None
     ref_state = None
-    for cand in candidates(persistent):
+    for cand in candidates(persistent, rows):
         ms, state, fault = _run(cfgs, omega_packed, forcing_packed, cand, steps, warmup, repeats,
                                 device)
         if ref_state is None:
@@ -139,6 +158,7 @@ def tune(cfgs: Sequence[api.cgp_config], omega_packed: torch.Tensor,
     setting = best[1]
     doc = _load(path)  # another process may have written meanwhile
     doc[key] = {"setting": setting, "ms_per_step": best[0],
-                "steps": steps, "repeats": repeats, "candidates": len(candidates(persistent))}
+                "steps": steps, "repeats": repeats,
+                "candidates": len(candidates(persistent, rows))}
     _store(path, doc)
     return setting

@@ -296,6 +296,7 @@ struct Group {
   int nlayers;         // layers of every member of the handle
   int split;           // the most parts of a split restriction among the members (0: none;
                        // pass B adds a member's parts)
+  int rows2;           // fused pass, one layer at c = 2: coarse rows per block (2 or 4)
 };
 
 // Launch wrappers implemented in the kernel translation units.

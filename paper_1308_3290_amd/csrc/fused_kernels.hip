@@ -32,7 +32,8 @@
 namespace cgp {
 
 template <typename T, int C, int TJ, int LC, bool NEXT, bool NTS>
-__global__ __launch_bounds__(kFusedThreads, fused_waves_per_simd(C, LC)) void k_prolong_stencil(
+__global__ __launch_bounds__(kFusedThreads, fused_waves_per_simd(C, LC, TJ, sizeof(T))) void
+k_prolong_stencil(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng, int nblk,
     const T* __restrict__ wt, T* __restrict__ wnext, const cplx<T>* __restrict__ twg,
     const T* __restrict__ ws, const T* __restrict__ forcing, const T* __restrict__ wn,
@@ -79,13 +80,20 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
     case 1024: LAUNCH(1, 4, 1024, NX, NTS); break; \
     default: LAUNCH(1, 4, 0, NX, NTS);             \
   }
-#define BY_LEN2(NX, NTS)                         \
-  switch (g.L & 0xffff) {                        \
-    case 128: LAUNCH(2, 2, 128, NX, NTS); break; \
-    case 256: LAUNCH(2, 2, 256, NX, NTS); break; \
-    case 384: LAUNCH(2, 2, 384, NX, NTS); break; \
-    case 512: LAUNCH(2, 2, 512, NX, NTS); break; \
-    default: LAUNCH(2, 2, 0, NX, NTS);           \
+#define BY_LEN2T(TJ, NX, NTS)                     \
+  switch (g.L & 0xffff) {                         \
+    case 128: LAUNCH(2, TJ, 128, NX, NTS); break; \
+    case 256: LAUNCH(2, TJ, 256, NX, NTS); break; \
+    case 384: LAUNCH(2, TJ, 384, NX, NTS); break; \
+    case 512: LAUNCH(2, TJ, 512, NX, NTS); break; \
+    default: LAUNCH(2, TJ, 0, NX, NTS);           \
+  }
+// c = 2: g.rows2 coarse rows per block (cgp_config.fused_rows)
+#define BY_LEN2(NX, NTS) \
+  if (g.rows2 == 4) {    \
+    BY_LEN2T(4, NX, NTS) \
+  } else {               \
+    BY_LEN2T(2, NX, NTS) \
   }
 #define BY_LEN4(NX, NTS)                         \
   switch (g.L & 0xffff) {                        \
@@ -117,6 +125,7 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
 #undef BY_C
 #undef BY_LEN1
 #undef BY_LEN2
+#undef BY_LEN2T
 #undef BY_LEN4
 #undef BY_LEN8
 #undef LAUNCH
@@ -133,6 +142,7 @@ hipError_t Launch<T>::prepare_fused(size_t bytes) {
       reinterpret_cast<const void*>(&k_prolong_stencil<T, C, TJ, LC, true, true>)
       K(1, 4, 0), K(1, 4, 128), K(1, 4, 256), K(1, 4, 384), K(1, 4, 512), K(1, 4, 768),
       K(1, 4, 1024), K(2, 2, 0), K(2, 2, 128), K(2, 2, 256), K(2, 2, 384), K(2, 2, 512),
+      K(2, 4, 0), K(2, 4, 128), K(2, 4, 256), K(2, 4, 384), K(2, 4, 512),
       K(4, 1, 0), K(4, 1, 128), K(4, 1, 256), K(8, 1, 0), K(8, 1, 128)
 #undef K
   };

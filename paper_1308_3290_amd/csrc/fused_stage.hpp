@@ -37,9 +37,11 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ W, long long g0,
 }
 
 // Waves per SIMD the register allocation must allow: four (two blocks per
-// CU, which ensembles of many blocks need) where that fits without spills.
-__host__ __device__ constexpr int fused_waves_per_simd(int c, int lc) {
-  return (c <= 2 && lc != 0) ? 4 : 2;
+// CU, which ensembles of many blocks need) where that fits without spills
+// (FP64 blocks of four coarse rows at c = 2 need about 170 VGPRs, and their
+// LDS allows one block per CU anyway).
+__host__ __device__ constexpr int fused_waves_per_simd(int c, int lc, int tj = 2, int es = 8) {
+  return (c <= 2 && lc != 0 && (c == 1 || tj <= 2 || es == 4)) ? 4 : 2;
 }
 
 // C: coarsening factor; TJ: coarse rows owned per block; LC: transform

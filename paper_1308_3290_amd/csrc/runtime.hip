@@ -105,6 +105,8 @@ cgp_status validate(const cgp_config* c) {
     return fail(CGP_ERR_INVALID, "solver must be 0 (sine transform) or 1 (multigrid)");
   if (c->mg_cycles < 0 || c->mg_cycles > 1000)
     return fail(CGP_ERR_INVALID, "mg_cycles must be in 0..1000");
+  if (c->fused_rows != 0 && c->fused_rows != 2 && c->fused_rows != 4)
+    return fail(CGP_ERR_INVALID, "fused_rows must be 0, 2 or 4 (got %d)", c->fused_rows);
   return CGP_OK;
 }
 
@@ -156,6 +158,7 @@ struct Plan {
   // setting, the LDS a workgroup needs and the most tiles the queue can hold
   bool persist_ok = false;
   cgp_launch launch{0, 1, 1, 0};
+  int rows2 = 2;                     // coarse rows per fused block at c = 2 (one layer)
   size_t persist_lds = 0;
   int persist_max_tiles = 0;
 };
@@ -206,6 +209,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
       return fail(CGP_ERR_INVALID, "all members must share dtype and nlayers");
     if (c.solver != cfgs[0].solver)
       return fail(CGP_ERR_INVALID, "all members must share the coarse solver");
+    if (c.fused_rows != cfgs[0].fused_rows)
+      return fail(CGP_ERR_INVALID, "all members must share fused_rows");
     MemberDesc& d = plan->md[m];
     d.nx = c.nx;
     d.ny = c.ny;
@@ -250,8 +255,14 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   auto pairs = [](int L) { return L <= 512 ? 2 : 1; };
   // fused C + D pass (rows of at most kFusedMaxNx intervals, c <= 8; two
   // layers: c <= 4 and a compile-time transform length).  Its last block
-  // owns exactly fused_tj(c, layers) coarse rows, so the coarse row count
-  // must be a multiple of that (only My = 6 at c = 1, one layer, is not).
+  // owns exactly tj(c) coarse rows (fused_tj, or cgp_config.fused_rows at
+  // c = 2, one layer), so the coarse row count must be a multiple of that
+  // (only My = 6 at c = 1, one layer, and My = 6 at c = 2 with 4 rows, are
+  // not).
+  plan->rows2 = nl == 1 && cfgs[0].fused_rows == 4 ? 4 : 2;
+  auto tj_of = [&](const MemberDesc& d) {
+    return nl == 1 && d.c == 2 ? plan->rows2 : fused_tj(d.c, nl);
+  };
   // multigrid (one layer, single basin): levels from the coarse CGP grid
   // down to the coarsest (an odd interval count or one below 8)
   plan->solver = cfgs[0].solver;
@@ -288,7 +299,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   bool fusable = plan->solver == 0;
   for (const MemberDesc& d : plan->md) {
     fusable = fusable && d.nx <= kFusedMaxNx && d.c <= (nl == 1 ? 8 : 4) &&
-              d.My % fused_tj(d.c, nl) == 0;
+              d.My % tj_of(d) == 0;
     if (nl == 2) fusable = fusable && fft_special(d.Lr) != 0;
   }
   // one layer at c >= 4 with the fused pass: split restrictions (part p of
@@ -356,7 +367,8 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
                    // the next stage's restriction, one more on each side
                    // (shares LDS with the transform buffers: two sequences
                    // per block for one layer, tj + 2 for two)
-                   const int tj = fused_tj(d.c, nl), nr = fused_nr(d.c, nl);
+                   const int tj = tj_of(d);
+                   const int nr = d.c <= 2 ? d.c * tj + 1 : fused_nr(d.c, nl);
                    const size_t tile = (size_t)nl * (nr + 2 + d.c - 1) * (d.nx + 1) * es;
                    const size_t psc = (size_t)nl * (tj + 2) * (d.Mx + 1) * es;
                    // rows of the restriction's column sums at c > 1: tj per
@@ -407,7 +419,7 @@ cgp_status make_plan(const cgp_config* cfgs, int count, Plan* plan) {
   L.mgm = off; off = align_up(off + (size_t)plan->mg_nb * plan->mg_nb * sizeof(double));
   // persistent stage kernel: the tile queue (at most one tile per block of
   // passes B and CD) and its counters, zero at create
-  plan->persist_ok = plan->fused && nl == 1;
+  plan->persist_ok = plan->fused && nl == 1 && plan->rows2 == 2;
   plan->persist_max_tiles = 0;
   for (const MemberDesc& d : plan->md) {
     plan->persist_ok = plan->persist_ok && persistent_lengths(d.c, d.Lr, d.Lc);
@@ -473,8 +485,9 @@ struct cgp_handle {
     const int count = g.members.size() == 1 ? -(g.members[0] + 1) : (int)g.members.size();
     int split = 0;
     for (int m : g.members) split = std::max(split, plan.md[m].nparts);
-    return Group{g.L,   count, at<int>(plan.lay.order) + g.order_off, g.nblk,
-                 kThreads, g.lds, plan.nlayers, split};
+    return Group{g.L,     count,        at<int>(plan.lay.order) + g.order_off,
+                 g.nblk,  kThreads,     g.lds,
+                 plan.nlayers, split,   plan.rows2};
   }
   int ngroups(int pass) const { return (int)plan.groups[pass].size(); }
 };

@@ -1,0 +1,113 @@
+"""Four coarse rows per fused-pass block at coarsening factor 2
+(cgp_config.fused_rows = 4) against the default two: the blocks synthesise
+their coarse psi rows in the same global pairs, restrict with the same sums
+and pack the next stage's spectra in the same row pairs, so every field must
+come out bit for bit equal, for single basins and ensembles, fixed and
+adaptive steps, one call or many; the default path itself is checked against
+the FP64 oracle by the other parity tests, and one horizon here checks the
+four-row path against the oracle directly."""
+import numpy as np
+import pytest
+import torch
+
+import cgp_inputs as ci
+from oracle import model as om
+
+from gpu_common import oracle_setup, rel_l2, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1308_3290_amd import _lib
+    _lib.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def _run(cases, w0s, Fs, rows, splits, use_graph=True):
+    from paper_1308_3290_amd.api import Ensemble, config_from_case, with_fused_rows
+    cfgs = with_fused_rows([config_from_case(c) for c in cases], rows)
+    ens = Ensemble(cfgs)
+    W = ens.pack(w0s)
+    Fp = ens.pack(Fs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for n in splits:
+            ens.step(W, Fp, nsteps=n, use_graph=use_graph, stream=side)
+    torch.cuda.synchronize()
+    return ens, W
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_single_basin_four_rows_give_the_same_bits(dtype, use_graph):
+    case = ci.make_case(512, 1024, level=1, inv_re=1 / 450, dt=2.5e-5, dtype=dtype)
+    rng = np.random.default_rng(81)
+    w0 = ci.initial_field(case, rng, 1.0)
+    F = ci.forcing_field(case)
+    say(f"fused_rows 4 vs 2: 512x1024 level 1 {dtype} graph={use_graph}, 8 steps in 3 calls")
+    e2, W2 = _run([case], [w0], [F], 2, (3, 1, 4), use_graph)
+    e4, W4 = _run([case], [w0], [F], 4, (3, 1, 4), use_graph)
+    assert e4.launch()[1] is False  # the persistent launch needs two rows per block
+    assert torch.equal(W4, W2)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ensemble_four_rows_give_the_same_bits(dtype):
+    members = ci.ensemble_c3(64, dtype=dtype)
+    cases = [m.case for m in members]
+    w0s = [m.omega0 for m in members]
+    Fs = [m.forcing for m in members]
+    say(f"fused_rows 4 vs 2: 64-member ensemble {dtype}, 5 steps")
+    e2, W2 = _run(cases, w0s, Fs, 2, (2, 3))
+    e4, W4 = _run(cases, w0s, Fs, 4, (2, 3))
+    for m in range(len(cases)):
+        assert torch.equal(e4.member_view(W4, m), e2.member_view(W2, m)), f"member {m}"
+
+
+def test_adaptive_steps_four_rows_give_the_same_steps():
+    """cfl > 0: the last stage leaves velocity maxima per block (half as many
+    blocks with four rows); the next step's dt must not change."""
+    cases = [ci.make_case(nx, ny, level=1, inv_re=1 / 300, dt=2.5e-5, cfl=0.3)
+             for nx, ny in ((256, 512), (128, 256), (384, 768))]
+    rng = np.random.default_rng(82)
+    w0s = [ci.initial_field(c, rng, 1.0) for c in cases]
+    Fs = [ci.forcing_field(c) for c in cases]
+    e2, W2 = _run(cases, w0s, Fs, 2, (4, 3))
+    e4, W4 = _run(cases, w0s, Fs, 4, (4, 3))
+    assert torch.equal(e4.time_state(), e2.time_state())
+    assert torch.equal(W4, W2)
+
+
+def test_four_rows_follow_the_oracle():
+    """30 steps of the 256x512 level-1 basin with four rows per block against
+    the FP64 oracle (the bound of the default path's parity tests)."""
+    case = ci.make_case(256, 512, level=1, inv_re=1 / 450, dt=2.5e-5)
+    rng = np.random.default_rng(83)
+    w0 = ci.initial_field(case, rng, 1.0)
+    F = ci.forcing_field(case)
+    e4, W4 = _run([case], [w0], [F], 4, (30,))
+    g, phys = oracle_setup(case)
+    w = w0
+    for _ in range(30):
+        w = om.step(w, F, g, case.level, phys, case.dt)
+    err = rel_l2(to_np(e4.member_view(W4, 0)), w)
+    say(f"  four rows, 30 steps vs oracle: rel L2 {err:.3e}")
+    assert err < 1e-11
+
+
+def test_two_layers_ignore_fused_rows():
+    f = ci.two_layer_coefficients()
+    case = ci.make_case(256, 512, level=1, nlayers=2, f1=f["f1"], f2=f["f2"], inv_re=1 / 450,
+                        dt=2.5e-5)
+    rng = np.random.default_rng(84)
+    w0 = ci.initial_field(case, rng, 1.0)
+    F = ci.forcing_field(case)
+    e2, W2 = _run([case], [w0], [F], 2, (3,))
+    e4, W4 = _run([case], [w0], [F], 4, (3,))
+    assert torch.equal(W4, W2)

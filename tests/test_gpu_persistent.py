@@ -132,10 +132,14 @@ def test_autotuner_caches_an_accepted_setting(tmp_path):
     setting = autotune.tune(cfgs, W, Fp, steps=6, warmup=2, repeats=2, cache=path, report=report)
     say(f"autotune: {setting}; {len(report)} candidates, "
         f"{sum(r['accepted'] for r in report)} accepted")
-    assert len(report) == len(autotune.candidates(True))
+    # level-1 members: the rows-per-block choice is among the candidates
+    assert autotune.has_rows_choice(cfgs)
+    assert len(report) == len(autotune.candidates(True, True))
+    assert any(r["fused_rows"] == 4 for r in report)
     assert all(r["accepted"] for r in report)  # every launch form gives the reference bits
     best = min(report, key=lambda r: r["ms_per_step"])
     assert setting["launch"] == best["launch"] and setting["use_graph"] == best["use_graph"]
+    assert setting["fused_rows"] == best["fused_rows"]
     again = []
     assert autotune.tune(cfgs, W, Fp, cache=path, report=again) == setting and again == []
     import json

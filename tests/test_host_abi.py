@@ -156,6 +156,23 @@ def test_multigrid_workspace_and_limits():
         cgp_ensemble_workspace_size([_cfg(solver=1), _cfg()])
 
 
+def test_fused_rows_validation_and_workspace():
+    """cgp_config.fused_rows: 0, 2 or 4, shared by every member; 4 rows per
+    fused block at c = 2 changes the fused blocks (fewer step-state slots),
+    not the spectra, so the workspace is no larger."""
+    from paper_1308_3290_amd.api import (CGPError, cgp_ensemble_workspace_size,
+                                         cgp_workspace_size)
+    for bad in (1, 3, 8, -2):
+        with pytest.raises(CGPError) as e:
+            cgp_workspace_size(_cfg(level=1, fused_rows=bad))
+        assert e.value.status == 1
+    with pytest.raises(CGPError):
+        cgp_ensemble_workspace_size([_cfg(level=1, fused_rows=4), _cfg(level=1)])
+    two = cgp_workspace_size(_cfg(level=1))
+    assert cgp_workspace_size(_cfg(level=1, fused_rows=2)) == two
+    assert cgp_workspace_size(_cfg(level=1, fused_rows=4)) <= two
+
+
 def test_noalloc_step_rejects_an_oversized_workspace_on_the_host():
     """cgp_step_noalloc checks the workspace size against its static scratch
     before any device work (no GPU needed for the refusal)."""
