@@ -134,7 +134,42 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
       buf[pad(2 * My - l)] = {-va[q], -vb[q]};
     }
   }
-  if constexpr (LC != 0) {
+  if constexpr (LC != 0 && ct_can_merge_ends<LC, kWideCols>()) {
+    // Compile-time transform whose first and last radix agree (1024 and 256
+    // points): the forward transform's last stage, the eigenvalue divide and
+    // the inverse transform's first stage run in registers, one pass through
+    // LDS fewer (ct_last_map_first).  The divide takes every output m of the
+    // forward transform: for m > My the packed odd sequences give
+    // Z_m = -Z_(2My-m), so the same divide at wavenumber 2My - m yields the
+    // odd extension of the quotients the inverse transform needs.
+    constexpr StagePlan P = stage_plan(LC, kWideCols);
+    constexpr int RL = P.R[P.n - 1], NSL = LC / RL;
+    constexpr int QL = (NSL + NT - 1) / NT;
+    double lyl[QL][RL];
+#pragma unroll
+    for (int q = 0; q < QL; ++q)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int m = CGP_TID + NT * q + r * NSL;
+        const int k = m < My ? m : 2 * My - m;
+        lyl[q][r] = lamy[min(max(k, 1), My - 1) - 1];
+      }
+    __syncthreads();
+    cplx<T>* X = ct_stage_range<T, LC, 0, P.n - 1, NT, 1, kWideCols, true>(buf, buf2, 1, rtw);
+    cplx<T>* Y = X == buf ? buf2 : buf;
+    ct_last_map_first<T, LC, NT, kWideCols>(X, Y, rtw, [&](int m, cplx<T> z, int q, int r) {
+      if (m == 0 || m == My) return cplx<T>{T(0), T(0)};
+      return cplx<T>{T(-0.5) * z.y * T(scale * recip(lxa + lyl[q][r])),
+                     T(0.5) * z.x * T(scale * recip(lxb + lyl[q][r]))};
+    });
+    const cplx<T>* X2 = ct_stage_range<T, LC, 1, P.n - 1, NT, 1, kWideCols, true>(Y, X, 1, rtw);
+    ct_stage_last<T, LC, NT, 1, kWideCols, true>(X2, 1, rtw, [&](int, int m, cplx<T> z, int, int) {
+      if (m >= 1 && m < My) {
+        wout[offa + m - 1] = T(-0.5) * z.y;
+        if (has_b) wout[offb + m - 1] = T(0.5) * z.x;
+      }
+    });
+  } else if constexpr (LC != 0) {
     // Compile-time transform: the last stage of the forward transform divides
     // by the eigenvalues and writes the synthesis input, and the last stage of
     // the inverse stores the result (no separate LDS passes for either).

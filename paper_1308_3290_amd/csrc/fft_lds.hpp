@@ -436,6 +436,56 @@ __device__ __forceinline__ void ct_stage_last(const cplx<T>* in, int nseq, const
   }
 }
 
+// A forward transform's last stage followed, in registers, by a pointwise
+// map and the first stage of a second transform with the same plan, for
+// plans whose first and last radix agree (the last stage's butterfly j
+// gives outputs j + r L/R, exactly the inputs of the first stage's
+// butterfly j): no pass through LDS between the two transforms.  in: the
+// input of the forward's last stage; out: receives the second transform's
+// first-stage output (padded layout, as ct_stage writes it); map(m, z, q, r)
+// gives the second transform's input at index m from the forward output z
+// at m, output r of the thread's q-th butterfly.  Register twiddles (RT) of
+// the forward's last stage; the first stage has none.  Ends with a barrier.
+template <int L, int WF>
+__host__ __device__ constexpr bool ct_can_merge_ends() {
+  if constexpr (L == 0) {
+    return false;  // the runtime engine
+  } else {
+    constexpr StagePlan P = stage_plan(L, WF);
+    return P.n >= 3 && P.R[0] == P.R[P.n - 1];
+  }
+}
+
+template <typename T, int L, int NT, int WF, class Map>
+__device__ __forceinline__ void ct_last_map_first(const cplx<T>* in, cplx<T>* out,
+                                                  const cplx<T>* rtw, Map&& map) {
+  constexpr StagePlan P = stage_plan(L, WF);
+  static_assert(ct_can_merge_ends<L, WF>(), "the first and the last radix must agree");
+  constexpr int S = P.n - 1;
+  constexpr int R = P.R[S], LR = L / R, RS = lpad(LR);
+  constexpr int Q = (LR + NT - 1) / NT;
+  constexpr int BASE = reg_tw_base<L, NT, 1, WF>(S);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int j = CGP_TID + NT * q;
+    if (j < LR) {
+      cplx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = in[pad(j) + r * RS];
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], rtw[BASE + q * (R - 1) + r - 1]);
+      small_dft<T, R>(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = map(j + r * LR, v[r], q, r);
+      small_dft<T, R>(v);  // the first stage (span 1: no twiddles)
+      cplx<T>* dst = out + pad(j * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r + (r >> 3)] = v[r];
+    }
+  }
+  __syncthreads();
+}
+
 // Whether the last stage of ct_run_to reads buffer a (else b): the n - 1
 // stages before it ping-pong from a.
 template <int L, int WF>
