@@ -56,9 +56,12 @@ __host__ __device__ constexpr int fused_waves_per_simd(int c, int lc, int tj = 2
 // transform).  At c >= 4 (TJ = 1) split_blocks(C) consecutive blocks share
 // a coarse row, block lb owning share HB = lb mod split_blocks(C) of its
 // fine rows (the caller passes HB: the prolongation weights are then
-// constants).
+// constants).  DS: with a compile-time transform, the inverse transform's
+// last stage writes the coarse psi rows and the forward transform's last
+// stage the spectra directly, without a copy through LDS (off in the
+// persistent kernel, whose register budget it exceeds).
 template <typename T, int C, int TJ, int LC, bool NEXT, bool EARLY = (C == 2), bool NTS = false,
-          int HB = 0>
+          int HB = 0, bool DS = true>
 __device__ __forceinline__ void fused_stage_block(
     const MemberDesc& d, int lb, const T* __restrict__ wt, T* __restrict__ wnext,
     const cplx<T>* __restrict__ twg, const T* __restrict__ ws, const T* __restrict__ forcing,
@@ -201,21 +204,46 @@ __device__ __forceinline__ void fused_stage_block(
     nv[u - 1] = in ? n : T(0);
   }
 
-  const cplx<T>* Z =
-      fft_runn<T, LC, NT, NSQ>(buf, buf + NSQ * LP, nseq, L, d.nst_r, d.stw_r, tw);
-
-  // ---- coarse psi rows J = j0-1 .. j0+TJ (zero walls) into psc
-  for (int i = t; i <= Mx; i += NT) {
+  // ---- coarse psi rows J = j0-1 .. j0+TJ (zero walls) into psc: sequence
+  // p holds rows ilo+2p (imaginary part) and ilo+2p+1 (real part)
+  if constexpr (DS && LC != 0) {
+    // the transform's last stage writes its outputs straight into psc (no
+    // LDS pass and barrier of a separate copy)
+    __syncthreads();
+    constexpr int NLAST = stage_plan(LC).n - 1;
+    const cplx<T>* X =
+        ct_stage_range<T, LC, 0, NLAST, NT, NSQ, kWideRows>(buf, buf + NSQ * LP, nseq, tw);
+    ct_stage_last<T, LC, NT, NSQ, kWideRows, false>(
+        X, nseq, tw, [&](int p, int m, cplx<T> z, int, int) {
+          if (m >= 1 && m < Mx) {
+            const int J = ilo + 2 * p, r = J - (j0 - 1);
+            if (r >= 0 && r < TJ + 2) psc[r * prow + m] = T(-0.5) * z.y;
+            if (r + 1 >= 0 && r + 1 < TJ + 2 && J + 1 <= My - 1)
+              psc[(r + 1) * prow + m] = T(0.5) * z.x;
+          }
+        });
+    for (int i = t; i <= Mx; i += NT) {
 #pragma unroll
-    for (int r = 0; r < TJ + 2; ++r) {
-      const int J = j0 - 1 + r;
-      T v = T(0);
-      if (J >= 1 && J <= My - 1 && i >= 1 && i <= Mx - 1) {
-        const int idx = J - ilo;
-        const cplx<T> zi = Z[(idx >> 1) * LP + pad(i)];
-        v = (idx & 1) ? T(0.5) * zi.x : T(-0.5) * zi.y;
+      for (int r = 0; r < TJ + 2; ++r) {
+        const int J = j0 - 1 + r;
+        if (J < 1 || J > My - 1 || i == 0 || i == Mx) psc[r * prow + i] = T(0);
       }
-      psc[r * prow + i] = v;
+    }
+  } else {
+    const cplx<T>* Z =
+        fft_runn<T, LC, NT, NSQ>(buf, buf + NSQ * LP, nseq, L, d.nst_r, d.stw_r, tw);
+    for (int i = t; i <= Mx; i += NT) {
+#pragma unroll
+      for (int r = 0; r < TJ + 2; ++r) {
+        const int J = j0 - 1 + r;
+        T v = T(0);
+        if (J >= 1 && J <= My - 1 && i >= 1 && i <= Mx - 1) {
+          const int idx = J - ilo;
+          const cplx<T> zi = Z[(idx >> 1) * LP + pad(i)];
+          v = (idx & 1) ? T(0.5) * zi.x : T(-0.5) * zi.y;
+        }
+        psc[r * prow + i] = v;
+      }
     }
   }
   __syncthreads();  // the transform's output is consumed: the tile may overwrite it
@@ -392,22 +420,19 @@ __device__ __forceinline__ void fused_stage_block(
       buf[t * LP + pad(0)] = {T(0), T(0)};
       buf[t * LP + pad(Mx)] = {T(0), T(0)};
     }
-    const cplx<T>* Z2 = fft_runn<T, LC, NT, (NQ > 2 ? 4 : 2)>(buf, buf + NQ * LP, NQ, L, d.nst_r,
-                                                              d.stw_r, tw);
-    if (SPLIT && i < Mx) {
-      // the part of row j0 in part array 2 HB, that of row j0+1 in 2 HB + 1
-      T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
-      const cplx<T> zk = Z2[pad(i)];
-      if (j0 >= 1) wo[2 * HB * d.split_off + j0 - 1] = T(-0.5) * zk.y;
-      if (j0 + 1 <= My - 1) wo[(2 * HB + 1) * d.split_off + j0] = T(0.5) * zk.x;
-    } else if (i < Mx) {
-      // rows j0+2q, j0+2q+1 are consecutive in column i: one store per pair
-      T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
+    // output k of sequence q (rows j0+2q, j0+2q+1) into column k of the
+    // next stage's spectra
+    auto put = [&](int q, int k, cplx<T> zk) {
+      if (k < 1 || k >= Mx) return;
+      T* wo = wnext + d.wt_off + (size_t)(k - 1) * (My - 1);
+      const T v0 = T(-0.5) * zk.y, v1 = T(0.5) * zk.x;
+      if constexpr (SPLIT) {
+        // the part of row j0 in part array 2 HB, that of row j0+1 in 2 HB + 1
+        if (j0 >= 1) wo[2 * HB * d.split_off + j0 - 1] = v0;
+        if (j0 + 1 <= My - 1) wo[(2 * HB + 1) * d.split_off + j0] = v1;
+      } else {
+        // rows j0+2q, j0+2q+1 are consecutive in the column: one store per pair
         const int j = j0 + 2 * q;
-        const cplx<T> zk = Z2[q * LP + pad(i)];
-        const T v0 = T(-0.5) * zk.y, v1 = T(0.5) * zk.x;
         if (2 * q + 1 < TJ && j >= 1 && j + 1 <= My - 1) {
           upair<T> pr;
           pr.x = v0;
@@ -416,6 +441,43 @@ __device__ __forceinline__ void fused_stage_block(
         } else {
           if (j >= 1 && j <= My - 1) wo[j - 1] = v0;
           if (2 * q + 1 < TJ && j + 1 <= My - 1) wo[j] = v1;
+        }
+      }
+    };
+    constexpr int MQ = NQ > 2 ? 4 : 2;
+    // (not at 256 points in FP64, where the register allocation then spills)
+    if constexpr (DS && LC != 0 && !(LC == 256 && sizeof(T) == 8)) {
+      // the last stage stores its outputs straight to global memory
+      __syncthreads();
+      constexpr int NLAST = stage_plan(LC).n - 1;
+      const cplx<T>* X =
+          ct_stage_range<T, LC, 0, NLAST, NT, MQ, kWideRows>(buf, buf + NQ * LP, NQ, tw);
+      ct_stage_last<T, LC, NT, MQ, kWideRows, false>(
+          X, NQ, tw, [&](int q, int k, cplx<T> z, int, int) { put(q, k, z); });
+    } else {
+      const cplx<T>* Z2 =
+          fft_runn<T, LC, NT, MQ>(buf, buf + NQ * LP, NQ, L, d.nst_r, d.stw_r, tw);
+      if (SPLIT && i < Mx) {
+        T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
+        const cplx<T> zk = Z2[pad(i)];
+        if (j0 >= 1) wo[2 * HB * d.split_off + j0 - 1] = T(-0.5) * zk.y;
+        if (j0 + 1 <= My - 1) wo[(2 * HB + 1) * d.split_off + j0] = T(0.5) * zk.x;
+      } else if (i < Mx) {
+        T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int j = j0 + 2 * q;
+          const cplx<T> zk = Z2[q * LP + pad(i)];
+          const T v0 = T(-0.5) * zk.y, v1 = T(0.5) * zk.x;
+          if (2 * q + 1 < TJ && j >= 1 && j + 1 <= My - 1) {
+            upair<T> pr;
+            pr.x = v0;
+            pr.y = v1;
+            *reinterpret_cast<upair<T>*>(wo + j - 1) = pr;
+          } else {
+            if (j >= 1 && j <= My - 1) wo[j - 1] = v0;
+            if (2 * q + 1 < TJ && j + 1 <= My - 1) wo[j] = v1;
+          }
         }
       }
     }
