@@ -163,47 +163,71 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
     nv2[u - 1] = in ? n2 : T(0);
   }
 
-  const cplx<T>* Z = INPLACE ? fft_run4_inplace<T, LC, NT>(buf, NS, tw)
-                             : fft_run4<T, LC, NT>(buf, buf + NS * LP, NS, tw);
-
   // ---- coarse psi of both layers, rows j0-1 .. j0+TJ (zero walls)
   const T wbc1 = T(1.0 - d.delta), wbc2 = T(d.delta);
-  constexpr int kPscIter = (MX + 1 + NT - 1) / NT;
-  T pv1[kPscIter][NS], pv2[kPscIter][NS];
+  if constexpr (INPLACE) {
+    const cplx<T>* Z = fft_run4_inplace<T, LC, NT>(buf, NS, tw);
+    constexpr int kPscIter = (MX + 1 + NT - 1) / NT;
+    T pv1[kPscIter][NS], pv2[kPscIter][NS];
 #pragma unroll
-  for (int q = 0; q < kPscIter; ++q) {
-    const int i = t + NT * q;
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      const int J = j0 - 1 + r;
-      T v1 = T(0), v2 = T(0);
-      if (J >= 1 && J <= My - 1 && i >= 1 && i <= MX - 1) {
-        const cplx<T> zi = Z[r * LP + pad(i)];
-        const T bt = T(-0.5) * zi.y, bc = T(0.5) * zi.x;
-        v1 = bt + wbc1 * bc;  // psi_1 = psi_bt + (1 - delta) psi_bc
-        v2 = bt - wbc2 * bc;  // psi_2 = psi_bt - delta psi_bc
-      }
-      pv1[q][r] = v1;
-      pv2[q][r] = v2;
-    }
-  }
-  // in place, the psi rows overwrite the transform's output: every thread
-  // reads its values first
-  if constexpr (INPLACE) __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kPscIter; ++q) {
-    const int i = t + NT * q;
-    if (i <= MX) {
+    for (int q = 0; q < kPscIter; ++q) {
+      const int i = t + NT * q;
 #pragma unroll
       for (int r = 0; r < NS; ++r) {
-        psc1[r * PROW + i] = pv1[q][r];
-        psc2[r * PROW + i] = pv2[q][r];
+        const int J = j0 - 1 + r;
+        T v1 = T(0), v2 = T(0);
+        if (J >= 1 && J <= My - 1 && i >= 1 && i <= MX - 1) {
+          const cplx<T> zi = Z[r * LP + pad(i)];
+          const T bt = T(-0.5) * zi.y, bc = T(0.5) * zi.x;
+          v1 = bt + wbc1 * bc;  // psi_1 = psi_bt + (1 - delta) psi_bc
+          v2 = bt - wbc2 * bc;  // psi_2 = psi_bt - delta psi_bc
+        }
+        pv1[q][r] = v1;
+        pv2[q][r] = v2;
       }
     }
+    // the psi rows overwrite the transform's output: every thread reads its
+    // values first (the tiles follow the psi rows and were never part of it)
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPscIter; ++q) {
+      const int i = t + NT * q;
+      if (i <= MX) {
+#pragma unroll
+        for (int r = 0; r < NS; ++r) {
+          psc1[r * PROW + i] = pv1[q][r];
+          psc2[r * PROW + i] = pv2[q][r];
+        }
+      }
+    }
+  } else {
+    // the transform's last stage writes both layers' psi rows directly (no
+    // LDS pass and barrier of a separate copy)
+    __syncthreads();
+    constexpr int NLAST = stage_plan(LC).n - 1;
+    const cplx<T>* X =
+        ct_stage_range<T, LC, 0, NLAST, NT, 4, kWideRows>(buf, buf + NS * LP, NS, tw);
+    ct_stage_last<T, LC, NT, 4, kWideRows, false>(
+        X, NS, tw, [&](int r, int i, cplx<T> zi, int, int) {
+          const int J = j0 - 1 + r;
+          if (J >= 1 && J <= My - 1 && i >= 1 && i <= MX - 1) {
+            const T bt = T(-0.5) * zi.y, bc = T(0.5) * zi.x;
+            psc1[r * PROW + i] = bt + wbc1 * bc;  // psi_1 = psi_bt + (1 - delta) psi_bc
+            psc2[r * PROW + i] = bt - wbc2 * bc;  // psi_2 = psi_bt - delta psi_bc
+          }
+        });
+    for (int i = t; i <= MX; i += NT) {
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        const int J = j0 - 1 + r;
+        if (J < 1 || J > My - 1 || i == 0 || i == MX) {
+          psc1[r * PROW + i] = T(0);
+          psc2[r * PROW + i] = T(0);
+        }
+      }
+    }
+    __syncthreads();  // the transform's output is consumed: the tiles may overwrite it
   }
-  // the transform's output is consumed: the tiles may overwrite it (in place,
-  // the tiles follow the psi rows and were never part of it)
-  if constexpr (!INPLACE) __syncthreads();
 #pragma unroll
   for (int q = 0; q < kWPer; ++q) {
     const int e = t + NT * q;
@@ -374,19 +398,20 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
       buf[t * LP + pad(0)] = {T(0), T(0)};
       buf[t * LP + pad(MX)] = {T(0), T(0)};
     }
-    const cplx<T>* Z2 = fft_run4<T, LC, NT>(buf, buf + TJ * LP, TJ, tw);
-    if (i < MX) {
-      T* wo = wnext + d.wt_off + (size_t)(i - 1) * (My - 1);
-#pragma unroll
-      for (int r = 0; r < TJ; ++r) {
-        const int j = j0 + r;
-        if (j >= 1 && j <= My - 1) {
-          const cplx<T> zk = Z2[r * LP + pad(i)];
-          wo[j - 1] = T(-0.5) * zk.y;
-          wo[mplane + j - 1] = T(0.5) * zk.x;
-        }
-      }
-    }
+    // the last stage stores the spectra (row j0+r: sequence r) directly
+    __syncthreads();
+    constexpr int NLAST = stage_plan(LC).n - 1;
+    const cplx<T>* X =
+        ct_stage_range<T, LC, 0, NLAST, NT, 4, kWideRows>(buf, buf + TJ * LP, TJ, tw);
+    ct_stage_last<T, LC, NT, 4, kWideRows, false>(
+        X, TJ, tw, [&](int r, int k, cplx<T> zk, int, int) {
+          const int j = j0 + r;
+          if (k >= 1 && k < MX && j >= 1 && j <= My - 1) {
+            T* wo = wnext + d.wt_off + (size_t)(k - 1) * (My - 1);
+            wo[j - 1] = T(-0.5) * zk.y;
+            wo[mplane + j - 1] = T(0.5) * zk.x;
+          }
+        });
   }
 }
 
