@@ -445,8 +445,8 @@ __device__ __forceinline__ void fused_stage_block(
       }
     };
     constexpr int MQ = NQ > 2 ? 4 : 2;
-    // (not at 256 points in FP64, where the register allocation then spills)
-    if constexpr (DS && LC != 0 && !(LC == 256 && sizeof(T) == 8)) {
+    // (not at c = 2 and 256 points in FP64, where the register allocation then spills)
+    if constexpr (DS && LC != 0 && !(C == 2 && LC == 256 && sizeof(T) == 8)) {
       // the last stage stores its outputs straight to global memory
       __syncthreads();
       constexpr int NLAST = stage_plan(LC).n - 1;
