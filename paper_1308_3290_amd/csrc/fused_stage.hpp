@@ -280,11 +280,44 @@ __device__ __forceinline__ void fused_stage_block(
     // The coarse rows are prow apart; prow is a constant when L is.
     const int prow_c = LC ? LC / 2 + 1 : prow;
     T P[3][NP];
+    // c = 2: fine columns x-1, x, x+1 lie on the coarse columns I, I+1, I+2
+    // (I = (x-1)/2), the first two of them on I and I+1 and the last on I+1
+    // and I+2, so three coarse values per row serve all three; the weights
+    // are powers of two, which makes every sum exact whatever the order
+    T c3[C == 2 ? 3 : 1][TJ + 2];
+    T w3[C == 2 ? 6 : 1];
+    if constexpr (C == 2) {
+      const int I = (x - 1) >> 1, odd = (x - 1) & 1;
+      const T* p0 = psc + I;
+      const T* p1 = psc + min(I + 1, Mx);
+      const T* p2 = psc + min(I + 2, Mx);
+#pragma unroll
+      for (int r = 0; r < TJ + 2; ++r) {
+        c3[0][r] = p0[r * prow_c];
+        c3[1][r] = p1[r * prow_c];
+        c3[2][r] = p2[r * prow_c];
+      }
+      // x-1 = 2I + odd: column x-1 has x weights (2 - odd, odd)/4 on (I, I+1),
+      // column x (x = 2I + 1 + odd) (1 - odd, 1 + odd)/4 on (I, I+1), column
+      // x+1 (2 - odd, odd)/4 on (I+1, I+2)
+      const T q = T(0.25);
+      w3[0] = T(2 - odd) * q;
+      w3[1] = T(odd) * q;
+      w3[2] = T(1 - odd) * q;
+      w3[3] = T(1 + odd) * q;
+      w3[4] = w3[0];
+      w3[5] = w3[1];
+    }
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
       const int xx = x - 1 + dx;  // 0 .. nx
       T cv[TJ + 2];
-      if constexpr (C == 1) {
+      if constexpr (C == 2) {
+        const int k = dx == 2 ? 1 : 0;
+#pragma unroll
+        for (int r = 0; r < TJ + 2; ++r)
+          cv[r] = w3[2 * dx] * c3[k][r] + w3[2 * dx + 1] * c3[k + 1][r];
+      } else if constexpr (C == 1) {
 #pragma unroll
         for (int r = 0; r < TJ + 2; ++r) cv[r] = psc[r * prow_c + xx];
       } else {
