@@ -263,16 +263,39 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
     // coarse psi of both layers at the coarse columns of x-1, x, x+1, with the
     // x weights (C - fx, fx)/C^2 applied
     T cv1[3][NS], cv2[3][NS];
-#pragma unroll
-    for (int dx = 0; dx < 3; ++dx) {
-      const int xx = x - 1 + dx;
-      const int I = xx / C, fx = xx - I * C;
-      const T a0 = T(C - fx) * kInvC2, a1 = T(fx) * kInvC2;
-      const int i1 = min(I + 1, MX);
+    if constexpr (C == 2) {
+      // x-1, x, x+1 lie on the coarse columns I, I+1, I+2 (I = (x-1)/2): the
+      // first two on I and I+1, the last on I+1 and I+2, so three values per
+      // row and layer serve all three; x-1 = 2I + odd has x weights
+      // (2 - odd, odd)/4, x (1 - odd, 1 + odd)/4 on (I, I+1), x+1 the weights
+      // of x-1 on (I+1, I+2); powers of two, so every sum is exact
+      const int I = (x - 1) >> 1, odd = (x - 1) & 1;
+      const int k1 = min(I + 1, MX), k2 = min(I + 2, MX);
+      const T q = T(0.25);
+      const T w0 = T(2 - odd) * q, w1 = T(odd) * q, v0 = T(1 - odd) * q, v1 = T(1 + odd) * q;
 #pragma unroll
       for (int r = 0; r < NS; ++r) {
-        cv1[dx][r] = a0 * psc1[r * PROW + I] + a1 * psc1[r * PROW + i1];
-        cv2[dx][r] = a0 * psc2[r * PROW + I] + a1 * psc2[r * PROW + i1];
+        const T a1 = psc1[r * PROW + I], b1 = psc1[r * PROW + k1], c1 = psc1[r * PROW + k2];
+        const T a2 = psc2[r * PROW + I], b2 = psc2[r * PROW + k1], c2 = psc2[r * PROW + k2];
+        cv1[0][r] = w0 * a1 + w1 * b1;
+        cv1[1][r] = v0 * a1 + v1 * b1;
+        cv1[2][r] = w0 * b1 + w1 * c1;
+        cv2[0][r] = w0 * a2 + w1 * b2;
+        cv2[1][r] = v0 * a2 + v1 * b2;
+        cv2[2][r] = w0 * b2 + w1 * c2;
+      }
+    } else {
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int xx = x - 1 + dx;
+        const int I = xx / C, fx = xx - I * C;
+        const T a0 = T(C - fx) * kInvC2, a1 = T(fx) * kInvC2;
+        const int i1 = min(I + 1, MX);
+#pragma unroll
+        for (int r = 0; r < NS; ++r) {
+          cv1[dx][r] = a0 * psc1[r * PROW + I] + a1 * psc1[r * PROW + i1];
+          cv2[dx][r] = a0 * psc2[r * PROW + I] + a1 * psc2[r * PROW + i1];
+        }
       }
     }
     // psi at column x-1+dx, tile row u (compile-time y weights)
