@@ -47,7 +47,8 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
   // table in LDS
   constexpr int kTw = LC ? 1 : tw_per_thread<LC, NT, kWideCols>();
   constexpr int kRegTw = LC ? reg_tw_count<LC, NT, 1, kWideCols>() : 1;
-  constexpr int kRowIter = (1023 + NT - 1) / NT;  // My - 1 <= 1023
+  // rows per thread: My - 1 <= 1023, or My - 1 = LC/2 - 1 with a compile-time length
+  constexpr int kRowIter = ((LC ? LC / 2 - 1 : 1023) + NT - 1) / NT;
   // a compile-time transform length fixes the column length (Lc = 2 My)
   const int Mx = d.Mx, My = LC ? LC / 2 : d.My, L = LC ? LC : d.Lc, nl = d.nlayers;
   const int ntw = d.ntw_c;
