@@ -175,6 +175,23 @@ def test_ragged_and_radix3_trajectories(nx, ny, level):
     assert errs.max() < TOL64
 
 
+# Every compile-time row length of the one-layer fused pass at c = 1 (rows of
+# 256, 384, 512 and 768 points: nx = 128, 192, 256, 384 at l = 0) and at c = 4
+# with 128 points (256x512 at l = 2), whose transforms' last stages write the
+# coarse psi rows and the next spectra directly; FP64 and FP32.
+@pytest.mark.parametrize("nx,ny,level", [(128, 256, 0), (192, 384, 0), (256, 512, 0),
+                                         (384, 768, 0), (256, 512, 2)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fused_row_lengths_follow_the_oracle(nx, ny, level, dtype):
+    case = ci.make_case(nx, ny, level=level, dt=1e-4)
+    say(f"{nx}x{ny} level {level} {dtype}, 10 steps")
+    w0 = random_state(case, 6, 1e-3)
+    F = ci.forcing_field(case)
+    errs, _, _ = _trajectory_errors(case, w0, F, 10, dtype=dtype)
+    say(f"  max per-step rel L2 = {errs.max():.3e}")
+    assert errs.max() < (TOL64 if dtype == "f64" else TOL32)
+
+
 # 64x128 at l = 1, 2 (transforms of 64 and 32 points): the unfused two-layer
 # passes; 128x256 / 256x128 / 384x192 at l >= 1 (transforms of 128 and 384)
 # and 64x128 / 192x96 / 384x192 at l = 0 (c = 1: transforms of 128, 384 and
