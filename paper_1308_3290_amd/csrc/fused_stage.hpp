@@ -56,12 +56,11 @@ __host__ __device__ constexpr int fused_waves_per_simd(int c, int lc, int tj = 2
 // transform).  At c >= 4 (TJ = 1) split_blocks(C) consecutive blocks share
 // a coarse row, block lb owning share HB = lb mod split_blocks(C) of its
 // fine rows (the caller passes HB: the prolongation weights are then
-// constants).  DS: with a compile-time transform, the inverse transform's
-// last stage writes the coarse psi rows and the forward transform's last
-// stage the spectra directly, without a copy through LDS (off in the
-// persistent kernel, whose register budget it exceeds).
+// constants).  With a compile-time transform, the inverse transform's last
+// stage writes the coarse psi rows and the forward transform's last stage
+// the spectra directly, without a copy through LDS.
 template <typename T, int C, int TJ, int LC, bool NEXT, bool EARLY = (C == 2), bool NTS = false,
-          int HB = 0, bool DS = true>
+          int HB = 0>
 __device__ __forceinline__ void fused_stage_block(
     const MemberDesc& d, int lb, const T* __restrict__ wt, T* __restrict__ wnext,
     const cplx<T>* __restrict__ twg, const T* __restrict__ ws, const T* __restrict__ forcing,
@@ -206,7 +205,7 @@ __device__ __forceinline__ void fused_stage_block(
 
   // ---- coarse psi rows J = j0-1 .. j0+TJ (zero walls) into psc: sequence
   // p holds rows ilo+2p (imaginary part) and ilo+2p+1 (real part)
-  if constexpr (DS && LC != 0) {
+  if constexpr (LC != 0) {
     // the transform's last stage writes its outputs straight into psc (no
     // LDS pass and barrier of a separate copy)
     __syncthreads();
@@ -478,8 +477,7 @@ __device__ __forceinline__ void fused_stage_block(
       }
     };
     constexpr int MQ = NQ > 2 ? 4 : 2;
-    // (not at c = 2 and 256 points in FP64, where the register allocation then spills)
-    if constexpr (DS && LC != 0 && !(C == 2 && LC == 256 && sizeof(T) == 8)) {
+    if constexpr (LC != 0) {
       // the last stage stores its outputs straight to global memory
       __syncthreads();
       constexpr int NLAST = stage_plan(LC).n - 1;

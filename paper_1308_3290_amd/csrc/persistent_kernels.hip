@@ -54,19 +54,19 @@ __device__ __forceinline__ void persistent_f(const MemberDesc& d, int lb, const 
                                              StepCtl ctl, unsigned char* smem) {
   switch (d.Lr) {
     case 128:
-      fused_stage_block<T, 2, 2, 128, true, true, false, 0, false>(d, lb, wt2, wnext, tw, ws, forcing, wn, out, nullptr,
+      fused_stage_block<T, 2, 2, 128, true>(d, lb, wt2, wnext, tw, ws, forcing, wn, out, nullptr,
                                             a, b, ctl, smem);
       break;
     case 256:
-      fused_stage_block<T, 2, 2, 256, true, true, false, 0, false>(d, lb, wt2, wnext, tw, ws, forcing, wn, out, nullptr,
+      fused_stage_block<T, 2, 2, 256, true>(d, lb, wt2, wnext, tw, ws, forcing, wn, out, nullptr,
                                             a, b, ctl, smem);
       break;
     case 384:
-      fused_stage_block<T, 2, 2, 384, true, true, false, 0, false>(d, lb, wt2, wnext, tw, ws, forcing, wn, out, nullptr,
+      fused_stage_block<T, 2, 2, 384, true>(d, lb, wt2, wnext, tw, ws, forcing, wn, out, nullptr,
                                             a, b, ctl, smem);
       break;
     default:
-      fused_stage_block<T, 2, 2, 512, true, true, false, 0, false>(d, lb, wt2, wnext, tw, ws, forcing, wn, out, nullptr,
+      fused_stage_block<T, 2, 2, 512, true>(d, lb, wt2, wnext, tw, ws, forcing, wn, out, nullptr,
                                             a, b, ctl, smem);
   }
 }
