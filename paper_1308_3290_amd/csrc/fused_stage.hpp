@@ -114,10 +114,10 @@ __device__ __forceinline__ void fused_stage_block(
   const int RB0 = R0 - 1 - E;                    // fine row of tile row 0
   const int nW = (nrow + 2) * pitch;
 
-  // LDS: [ FFT buffers | later the vorticity tile | later the restriction
-  // rows and the next transform's buffers ] [ twiddles ] [ coarse psi rows ].
-  // Sharing the first region keeps the block small enough for two blocks per
-  // CU when there are many (ensembles).
+  // LDS: [ FFT buffers | later the vorticity tile | later the next
+  // transform's buffers ] [ twiddles ] [ coarse psi rows ] [ the
+  // restriction's column sums ].  Sharing the first region keeps the block
+  // small enough for two blocks per CU when there are many (ensembles).
   const int region =
       (max(2 * NSQ * LP * (int)sizeof(cplx<T>), NP * pitch * (int)sizeof(T)) + 15) & ~15;
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
