@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--only", default="",
                     help="comma list of sections (profiling runs): l0,l1,l2,timed,adj,c2,ens,"
                          "batch,cpu; with --extras also fp32,l3,mg,adaptive")
+    ap.add_argument("--tune-child", nargs=3, metavar=("KIND", "DTYPE", "OUT_JSON"),
+                    help=argparse.SUPPRESS)  # the autotuner's process (see tune_in_child)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration runs)")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
@@ -213,6 +215,66 @@ def median(xs):
     return statistics.median(xs)
 
 
+# the launch a handle starts with (cgp_set_launch is not needed for it)
+DEFAULT_LAUNCH = {"mode": 0, "b_tile": 1, "f_tile": 1, "wg_per_cu": 0}
+
+
+def tune_workload(kind, dtype_):
+    """Configs and inputs of a tuned bench workload: "ens" the 64-member
+    ensemble, "batch" 16 copies of the 512x1024 level-1 basin."""
+    import numpy as np
+
+    import cgp_inputs as ci
+    from paper_1308_3290_amd import api
+    if kind == "ens":
+        members = ci.ensemble_c3(dtype=dtype_)
+        return ([api.config_from_case(m.case) for m in members], [m.omega0 for m in members],
+                [m.forcing for m in members])
+    case = ci.case_c1(1)
+    rng = np.random.default_rng(case.seed)
+    w0, F = ci.initial_field(case, rng), ci.forcing_field(case)
+    return [api.config_from_case(case)] * 16, [w0] * 16, [F] * 16
+
+
+def tune_child(kind, dtype_, out_json):
+    """The autotuner run for one workload (retuned, every candidate timed and
+    checked against the reference launch); writes the chosen setting and the
+    report to out_json."""
+    import torch
+
+    from paper_1308_3290_amd import api, autotune
+    cfgs, w0s, Fs = tune_workload(kind, dtype_)
+    probe = api.Ensemble(cfgs, device=torch.device("cuda:0"))
+    Wp, Fpk = probe.pack(w0s), probe.pack(Fs)
+    probe.close()
+    report = []
+    setting = autotune.tune(cfgs, Wp, Fpk, steps=30, warmup=6, repeats=3, report=report,
+                            retune=True)
+    with open(out_json, "w") as f:
+        json.dump({"setting": setting, "report": report}, f)
+
+
+def tune_in_child(kind, dtype_):
+    """Run tune_child in a child process, so that a failure while the tuner
+    creates, steps and destroys its many candidate handles cannot end the
+    measurement; returns (setting, report, None), or (None, [], why)."""
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        out = os.path.join(d, "tune.json")
+        cmd = [sys.executable, os.path.abspath(__file__), "--tune-child", kind, dtype_, out]
+        try:
+            r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+        except subprocess.TimeoutExpired:
+            return None, [], "timed out"
+        if r.returncode != 0 or not os.path.exists(out):
+            log(r.stderr[-2000:])
+            return None, [], f"exit status {r.returncode}"
+        with open(out) as f:
+            doc = json.load(f)
+        return doc["setting"], doc["report"], None
+
+
 def main():
     args = parse()
     if args.summarize_trace:
@@ -220,6 +282,9 @@ def main():
         return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, out_path=args.pmc_out)
+        return
+    if args.tune_child:
+        tune_child(*args.tune_child)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
@@ -242,7 +307,7 @@ def main():
         basin) on a non-default stream (graphs cannot be captured on the
         default one), HIP events recorded on that stream; ms per run."""
         ens = api.Ensemble(cfgs, device=dev)
-        if launch is not None:
+        if launch is not None and launch != DEFAULT_LAUNCH:
             ens.set_launch(**launch)
         w = ens.pack(w0s)
         Fp = ens.pack(Fs)
@@ -436,20 +501,20 @@ def main():
     # ---------------------------------------------------------------- ensembles
     ens_out = {}
 
-    def tuned_rate(cfgs, w0s, Fs, n_steps, label):
+    def tuned_rate(cfgs, w0s, Fs, n_steps, label, kind, dtype_):
         """The autotuner's choice of launch for this workload (every candidate
-        checked bit for bit against the reference launch), then R timed runs
-        of it; also the best time of each launch mode among the candidates."""
+        checked bit for bit against the reference launch; tuned in a process
+        of its own, see tune_in_child), then R timed runs of it; also the best
+        time of each launch mode among the candidates."""
         from paper_1308_3290_amd import autotune
-        probe = api.Ensemble(cfgs, device=dev)
-        Wp, Fpk = probe.pack(w0s), probe.pack(Fs)
-        probe.close()
         report = []
         if args.no_tune:
             setting = dict(autotune.REFERENCE)
         else:
-            setting = autotune.tune(cfgs, Wp, Fpk, steps=30, warmup=6, repeats=3, report=report,
-                                    retune=True)
+            setting, report, why = tune_in_child(kind, dtype_)
+            if setting is None:
+                log(f"{label}: tuning failed ({why}); timing the reference launch")
+                setting = dict(autotune.REFERENCE, tuning=f"failed ({why}); reference launch")
         ms, finite = timed_runs(autotune.configs(cfgs, setting), w0s, Fs, n_steps, 5,
                                 setting["use_graph"], max(3, R // 2), launch=setting["launch"])
         best_by_mode = {}
@@ -472,7 +537,7 @@ def main():
             cfgs = [api.config_from_case(m.case) for m in members]
             ms, finite, setting, by_mode = tuned_rate(
                 cfgs, [m.omega0 for m in members], [m.forcing for m in members], n_ens,
-                f"ensemble 64 {dt_}")
+                f"ensemble 64 {dt_}", "ens", dt_)
             pts = sum(m.case.points for m in members)
             es = 8 if dt_ == "f64" else 4
             alg = sum(step_bytes(m.case, es)["step"] for m in members)
@@ -496,7 +561,7 @@ def main():
         cfgs = [api.config_from_case(case)] * 16
         n_b = 100
         ms, finite, setting, by_mode = tuned_rate(cfgs, [w0] * 16, [F] * 16, n_b,
-                                                  "batch of 16 x 512x1024")
+                                                  "batch of 16 x 512x1024", "batch", "f64")
         t = median(ms) * 1e-3 / n_b
         sb = step_bytes(case, 8)["step"] * 16
         batch = {"value": round(16 * case.points / t / 1e6, 1), "unit": "Mpoint-steps/s",
