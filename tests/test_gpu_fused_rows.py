@@ -111,3 +111,29 @@ def test_two_layers_ignore_fused_rows():
     e2, W2 = _run([case], [w0], [F], 2, (3,))
     e4, W4 = _run([case], [w0], [F], 4, (3,))
     assert torch.equal(W4, W2)
+
+
+@pytest.mark.parametrize("nx,ny", [(256, 12), (384, 12), (24, 12), (48, 96), (96, 192)])
+def test_four_rows_on_small_and_runtime_length_grids(nx, ny):
+    """Six coarse rows, not a multiple of four: the handle takes the unfused
+    passes with fused_rows = 4 (the fused pass needs whole blocks), so both
+    settings are checked against the oracle.  Coarse row counts that are
+    multiples of four (48, 96) with row transforms of 48 and 96 points (the
+    runtime engine): the same bits as two rows per block, and the oracle."""
+    case = ci.make_case(nx, ny, level=1, inv_re=1 / 450, dt=1e-4)
+    rng = np.random.default_rng(85)
+    w0 = ci.initial_field(case, rng, 1e-3)
+    F = ci.forcing_field(case)
+    say(f"fused_rows 4 vs 2: {nx}x{ny} level 1, 6 steps")
+    e2, W2 = _run([case], [w0], [F], 2, (2, 4))
+    e4, W4 = _run([case], [w0], [F], 4, (2, 4))
+    if case.ny // 2 % 4 == 0:
+        assert torch.equal(W4, W2)
+    g, phys = oracle_setup(case)
+    w = w0
+    for _ in range(6):
+        w = om.step(w, F, g, case.level, phys, case.dt)
+    for e, W in ((e2, W2), (e4, W4)):
+        err = rel_l2(to_np(e.member_view(W, 0)), w)
+        say(f"  vs oracle: rel L2 {err:.3e}")
+        assert err < 1e-11
