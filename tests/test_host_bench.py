@@ -83,3 +83,32 @@ def test_algorithmic_bytes_per_step_and_in_step_launch():
     per_point = sb["step"] / (512 * 1024)
     assert abs(per_point - 8 * (11 + 12 / 4)) / per_point < 0.01
     assert bench.model_bytes(2, 8) == 184.0
+
+
+def test_tuning_child_failure_falls_back(monkeypatch):
+    """bench.tune_in_child: a child that aborts or times out gives no setting
+    (the bench then times the reference launch); a child that finishes gives
+    the setting and report it wrote."""
+    def aborted(cmd, **kw):
+        return subprocess.CompletedProcess(cmd, -6, "", "Aborted")
+    monkeypatch.setattr(subprocess, "run", aborted)
+    setting, report, why = bench.tune_in_child("ens", "f64")
+    assert setting is None and report == [] and "-6" in why
+
+    def timed_out(cmd, **kw):
+        raise subprocess.TimeoutExpired(cmd, kw.get("timeout", 0))
+    monkeypatch.setattr(subprocess, "run", timed_out)
+    assert bench.tune_in_child("batch", "f64")[2] == "timed out"
+
+    doc = {"setting": {"launch": dict(bench.DEFAULT_LAUNCH), "use_graph": True,
+                       "fused_rows": 4},
+           "report": [{"ms_per_step": 0.5, "accepted": True}]}
+
+    def finished(cmd, **kw):
+        assert cmd[-4:-1] == ["--tune-child", "ens", "f32"]
+        with open(cmd[-1], "w") as f:
+            json.dump(doc, f)
+        return subprocess.CompletedProcess(cmd, 0, "", "")
+    monkeypatch.setattr(subprocess, "run", finished)
+    setting, report, why = bench.tune_in_child("ens", "f32")
+    assert why is None and setting == doc["setting"] and report == doc["report"]
