@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--only", default="",
                     help="comma list of sections (profiling runs): l0,l1,l2,timed,adj,c2,ens,"
                          "batch,cpu; with --extras also fp32,l3,mg,adaptive")
+    ap.add_argument("--summarize-sq", nargs=2, metavar=("PASS1_CSV", "PASS2_CSV"),
+                    help="print the SQ instruction mix, VALUBusy and LDSBankConflict of each "
+                         "CGP kernel from two rocprofv3 --pmc passes as a markdown table and "
+                         "exit (no GPU needed)")
     ap.add_argument("--tune-child", nargs=3, metavar=("KIND", "DTYPE", "OUT_JSON"),
                     help=argparse.SUPPRESS)  # the autotuner's process (see tune_in_child)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -77,6 +81,45 @@ def parse():
 
 
 COPY_BYTES = 256 << 20
+
+
+def summarize_sq(csv1, csv2):
+    """Median per-dispatch SQ counters of each CGP kernel instantiation from two
+    rocprofv3 --pmc passes (pass 1: VALUBusy SQ_INSTS_VALU SQ_INSTS_LDS
+    SQ_WAVES ...; pass 2: LDSBankConflict SQ_INSTS_VALU_FMA_F64 / ADD / MUL
+    SQ_INSTS_SALU ...), per wave where a count, as a markdown table."""
+    import csv
+    import statistics
+    from collections import defaultdict
+
+    def load(path):
+        per = defaultdict(lambda: defaultdict(float))
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"]
+            if "cgp::" not in name:
+                continue
+            inst = name.split("cgp::")[1].split("(")[0]
+            per[(inst, r["Dispatch_Id"])][r["Counter_Name"]] += float(r["Counter_Value"])
+        by = defaultdict(lambda: defaultdict(list))
+        for (inst, _), cs in per.items():
+            for c, v in cs.items():
+                by[inst][c].append(v)
+        return {i: {c: statistics.median(v) for c, v in cs.items()} for i, cs in by.items()}
+
+    a, b = load(csv1), load(csv2)
+    print("| kernel | waves | VALU / wave | FP64 FMA / ADD / MUL per wave | LDS / wave "
+          "| SALU / wave | VALUBusy | LDSBankConflict |")
+    print("|---|---|---|---|---|---|---|---|")
+    for inst in sorted(a):
+        x, y = a[inst], b.get(inst, {})
+        w = x.get("SQ_WAVES", 0.0) or 1.0
+        print(f"| {inst} | {w:.0f} | {x.get('SQ_INSTS_VALU', 0) / w:.0f} | "
+              f"{y.get('SQ_INSTS_VALU_FMA_F64', 0) / w:.0f} / "
+              f"{y.get('SQ_INSTS_VALU_ADD_F64', 0) / w:.0f} / "
+              f"{y.get('SQ_INSTS_VALU_MUL_F64', 0) / w:.0f} | "
+              f"{x.get('SQ_INSTS_LDS', 0) / w:.0f} | {y.get('SQ_INSTS_SALU', 0) / w:.0f} | "
+              f"{x.get('VALUBusy', float('nan')):.1f} % | "
+              f"{y.get('LDSBankConflict', float('nan')):.1f} % |")
 
 
 def summarize_pmc(fetch_csv, write_csv, out_path=None):
@@ -282,6 +325,9 @@ def main():
         return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, out_path=args.pmc_out)
+        return
+    if args.summarize_sq:
+        summarize_sq(*args.summarize_sq)
         return
     if args.tune_child:
         tune_child(*args.tune_child)

@@ -70,6 +70,34 @@ def test_pmc_summary_scales_by_the_copy(tmp_path):
     assert t["source_hash"] == bench.source_hash()
 
 
+def test_sq_summary_is_per_wave_and_median_over_dispatches(tmp_path, capsys):
+    fields = ["Kernel_Name", "Dispatch_Id", "Counter_Name", "Counter_Value"]
+    name = "void cgp::k_col_solve<double, 1024, 0>(x)"
+    p1, p2 = [], []
+    # two dispatches of 8 waves; counters split over two rows (shader engines) are summed
+    for d, valu in ((1, 800.0), (2, 1200.0)):
+        p1 += [{"Kernel_Name": name, "Dispatch_Id": d, "Counter_Name": "SQ_WAVES",
+                "Counter_Value": 8}]
+        p1 += [{"Kernel_Name": name, "Dispatch_Id": d, "Counter_Name": c, "Counter_Value": v / 2}
+               for c, v in (("SQ_INSTS_VALU", valu), ("SQ_INSTS_LDS", 160.0))] * 2
+        p1 += [{"Kernel_Name": name, "Dispatch_Id": d, "Counter_Name": "VALUBusy",
+                "Counter_Value": 25.0}]
+        p2 += [{"Kernel_Name": name, "Dispatch_Id": d, "Counter_Name": c, "Counter_Value": v}
+               for c, v in (("SQ_INSTS_VALU_FMA_F64", 80.0), ("SQ_INSTS_VALU_ADD_F64", 40.0),
+                            ("SQ_INSTS_VALU_MUL_F64", 16.0), ("SQ_INSTS_SALU", 24.0),
+                            ("LDSBankConflict", 2.0))]
+    p1.append({"Kernel_Name": "MulFunctor copy", "Dispatch_Id": 3, "Counter_Name": "SQ_WAVES",
+               "Counter_Value": 4})
+    f1, f2 = tmp_path / "p1.csv", tmp_path / "p2.csv"
+    _write_csv(f1, p1, fields)
+    _write_csv(f2, p2, fields)
+    bench.summarize_sq(str(f1), str(f2))
+    out = capsys.readouterr().out.splitlines()
+    assert len(out) == 3
+    assert out[2] == ("| k_col_solve<double, 1024, 0> | 8 | 125 | 10 / 5 / 2 | 20 | 3 "
+                      "| 25.0 % | 2.0 % |")
+
+
 def test_algorithmic_bytes_per_step_and_in_step_launch():
     """A fused step moves 11 fine fields and 12 coarse spectra: per stage the
     fused pass reads the psi spectra, omega_s, the forcing and (stages 2, 3)
