@@ -216,19 +216,31 @@ struct cplx {
   T x, y;
 };
 
-// Store of a fine-grid field element (the new vorticity); with NT the
-// non-temporal hint, which lets the lines leave the L2 as they fill instead
+// A store that writes through the L2 of its XCD to memory (a relaxed atomic
+// store at agent scope): the kernel boundary's L2 write-back then has none
+// of its lines left to write, and a reader on another XCD finds them in
+// memory.  Pass B stores its solved spectra this way (512x1024 one layer:
+// 0.2-0.9 us per step at l = 0-2, two layers at l = 0 135.0 -> 129.6 us).
+template <typename T>
+__device__ __forceinline__ void store_through(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Store of a fine-grid field element (the new vorticity); with NT written
+// through the L2 (store_through), so the lines leave it as they fill instead
 // of at the end of the launch.  The host asks for it when a launch has at
-// most one block per CU, whose stores are then the tail of the launch: 2 %
-// per step for single basins.  With more blocks than CUs later blocks hide
-// that tail, and the hint measured slower (4 % for the FP32 ensemble).  The
-// coarse spectra, stored with a stride of one column, are slower with it in
-// every case and use ordinary stores.  (A compile-time choice: a runtime
+// most one block per CU, whose stores are then the tail of the launch (2 %
+// per step for single basins with the non-temporal hint, which write-through
+// stores match at one layer and beat by 1.5 us per step for two layers at
+// l = 1).  With more blocks than CUs later blocks hide that tail, and
+// write-through stores measured 1 % slower for the 64-basin FP64 ensemble.
+// The coarse spectra, stored with a stride of one column, are slower with
+// either form and use ordinary stores.  (A compile-time choice: a runtime
 // branch between the two stores is merged into one ordinary store.)
 template <bool NT, typename T>
 __device__ __forceinline__ void store_field(T* p, T v) {
   if constexpr (NT)
-    __builtin_nontemporal_store(v, p);
+    store_through(p, v);
   else
     *p = v;
 }

@@ -13,7 +13,8 @@ namespace cgp {
 // columns k, k+1; two layers: the barotropic and baroclinic column k) along
 // y, multiplies by (2/Mx)(2/My)/lambda_kl (baroclinic: 1/(lambda_kl - F1 -
 // F2)), and transforms back, from the spectra of omega (win) to those of psi
-// (wout, same layout).  Loads are batched as in pass A.  The transforms use
+// (wout, same layout, written through the L2: store_through).  Loads are
+// batched as in pass A.  The transforms use
 // the column plan (stage_plan(L, kWideCols)): one sequence per 256-thread
 // block has enough butterflies for radix 8 only from L = 2048 on.
 // ---------------------------------------------------------------------------
@@ -166,8 +167,8 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
     const cplx<T>* X2 = ct_stage_range<T, LC, 1, P.n - 1, NT, 1, kWideCols, true>(Y, X, 1, rtw);
     ct_stage_last<T, LC, NT, 1, kWideCols, true>(X2, 1, rtw, [&](int, int m, cplx<T> z, int, int) {
       if (m >= 1 && m < My) {
-        wout[offa + m - 1] = T(-0.5) * z.y;
-        if (has_b) wout[offb + m - 1] = T(0.5) * z.x;
+        store_through(&wout[offa + m - 1], T(-0.5) * z.y);
+        if (has_b) store_through(&wout[offb + m - 1], T(0.5) * z.x);
       }
     });
   } else if constexpr (LC != 0) {
@@ -201,8 +202,8 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
     ct_run_to<T, LC, NT, 1, kWideCols, true>(divide, buf, buf2, 1, rtw);
     auto store = [&](int, int m, cplx<T> z, int, int) {
       if (m >= 1 && m < My) {
-        wout[offa + m - 1] = T(-0.5) * z.y;
-        if (has_b) wout[offb + m - 1] = T(0.5) * z.x;
+        store_through(&wout[offa + m - 1], T(-0.5) * z.y);
+        if (has_b) store_through(&wout[offb + m - 1], T(0.5) * z.x);
       }
     };
     ct_run_to<T, LC, NT, 1, kWideCols, true>(store, Y, kLastA ? buf : buf2, 1, rtw);
@@ -230,8 +231,8 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
       const int l = 1 + CGP_TID + NT * q;
       if (l < My) {
         const cplx<T> z = R[pad(l)];
-        wout[offa + l - 1] = T(-0.5) * z.y;
-        if (has_b) wout[offb + l - 1] = T(0.5) * z.x;
+        store_through(&wout[offa + l - 1], T(-0.5) * z.y);
+        if (has_b) store_through(&wout[offb + l - 1], T(0.5) * z.x);
       }
     }
   }

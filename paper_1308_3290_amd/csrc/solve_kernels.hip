@@ -180,7 +180,6 @@ __global__ __launch_bounds__(kThreads) void k_restrict_rowdst(
     const MemberDesc* __restrict__ md, const int* __restrict__ grp, int ng,
     const T* __restrict__ src, T* __restrict__ wt, const cplx<T>* __restrict__ twg) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int RB = NL == 1 ? 2 : 1;
   constexpr int kTw = tw_per_thread<LC, kThreads>();
   const MemberDesc& d = md[group_member(md, grp, ng, PASS_A, blockIdx.x)];
   const int lb = blockIdx.x - d.blk0[PASS_A];
