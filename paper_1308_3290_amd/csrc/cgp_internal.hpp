@@ -220,7 +220,7 @@ struct cplx {
 // store at agent scope): the kernel boundary's L2 write-back then has none
 // of its lines left to write, and a reader on another XCD finds them in
 // memory.  Pass B stores its solved spectra this way (512x1024 one layer:
-// 0.2-0.9 us per step at l = 0-2, two layers at l = 0 135.0 -> 129.6 us).
+// 0.1-1.1 us per step at l = 0-2, two layers at l = 0 135.0 -> 129.6 us).
 template <typename T>
 __device__ __forceinline__ void store_through(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

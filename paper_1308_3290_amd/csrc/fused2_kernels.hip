@@ -464,7 +464,7 @@ hipError_t Launch<T>::prolong_stencil2(const MemberDesc* md, const Group& g, con
     case (4 << 16) | 256: LAUNCH(4, 1, 256, NX, NTS); break;   \
     default: return hipErrorInvalidValue;                      \
   }
-  // the new vorticity with the non-temporal hint only where asked for
+  // the new vorticity written through the L2 only where asked for
   if (!wnext) {
     BY_C(false, false)
   } else if (nt_store) {

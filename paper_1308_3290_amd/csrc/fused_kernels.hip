@@ -114,7 +114,7 @@ hipError_t Launch<T>::prolong_stencil(const MemberDesc* md, const Group& g, cons
     case 8: BY_LEN8(NX, NTS); break;      \
     default: return hipErrorInvalidValue; \
   }
-  // the new vorticity with the non-temporal hint only where asked for
+  // the new vorticity written through the L2 only where asked for
   if (!wnext) {
     BY_C(false, false)
   } else if (nt_store) {

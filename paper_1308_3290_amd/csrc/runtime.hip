@@ -613,7 +613,7 @@ hipError_t enqueue_fused(cgp_handle* h, const T* ws, const T* forcing, const T* 
     if (only >= 0 && i != only) continue;
     T* wnext = next ? h->at<T>(p.lay.wt) : nullptr;
     const Group g = h->group(3, i);
-    // at most one block per CU: the new vorticity with the non-temporal hint
+    // at most one block per CU: the new vorticity written through the L2
     const bool nt = g.nblk <= h->ncu;
     hipError_t e =
         p.nlayers == 1

@@ -69,7 +69,7 @@ def test_no_kernel_uses_scratch(kernels):
 
 def test_fused_c2_kernels_fit_two_blocks_per_cu(kernels):
     # k_prolong_stencil<T, C = 2, TJ = 2, LC, NEXT = true, NTS>, LC = 128 .. 512,
-    # with and without the non-temporal stores of the new vorticity
+    # with and without the write-through stores of the new vorticity
     pat = re.compile(r"_ZN3cgp17k_prolong_stencilI([df])Li2ELi2ELi(\d+)ELb1ELb[01]E")
     seen = 0
     for name, v in kernels.items():
