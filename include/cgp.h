@@ -315,6 +315,23 @@ cgp_status cgp_time_passes(cgp_handle* h, const void* omega_dev, const void* for
 cgp_status cgp_time_step_passes(cgp_handle* h, void* omega_dev, const void* forcing_dev,
                                 int32_t nsteps, double* ms_host, void* stream);
 
+/* Measurement build only: exported by libcgp_stamps.so, the library built
+ * with CGP_PHASE_STAMPS (libcgp.so does not have it).  In that build thread 0
+ * of every block of pass B and of the one-layer fused stage pass writes the
+ * device's steady clock at its phase boundaries (the arithmetic is
+ * unchanged); each launch overwrites the stamps of its blocks.  Copies the
+ * stamps of the last launch of pass B (kind 0) or of the fused pass (kind
+ * 1) to host_out: nblocks (1..4096, hardware block index order) x 8 slots of
+ * uint64 clock ticks, unwritten slots unspecified.  Pass B slots: 0 block
+ * start, 1 columns loaded, 2 forward transform and divide done, 3 results
+ * stored.  Fused pass slots: 0 block start, 1 spectra in LDS, 2 inverse x
+ * transform done, 3 vorticity tile in LDS, 4 stencil and RK3 combine done,
+ * 5 restriction done, 6 block end.  *clock_khz (if not NULL) receives the
+ * clock's rate.  Synchronises the device.  Bad kind, pointer or count:
+ * CGP_ERR_INVALID. */
+cgp_status cgp_phase_stamps(int32_t kind, uint64_t* host_out, int32_t nblocks,
+                            int32_t* clock_khz);
+
 /* Message for the calling thread's last failure ("" if none). */
 const char* cgp_last_error(void);
 

@@ -10,6 +10,9 @@ import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcgp.so")
+# the measurement build (phase stamps; cgp_phase_stamps): a program that wants
+# it sets LIB_PATH to this path before the first load()
+STAMPS_LIB_PATH = os.path.join(_PKG, "libcgp_stamps.so")
 
 CGP_OK, CGP_ERR_INVALID, CGP_ERR_UNSUPPORTED, CGP_ERR_DEVICE, CGP_ERR_NONFINITE = range(5)
 CGP_F32, CGP_F64 = 0, 1
@@ -74,12 +77,19 @@ SIGNATURES = {
     "cgp_version": (ctypes.c_char_p, []),
 }
 
+# Functions only the measurement build exports.
+OPTIONAL_SIGNATURES = {
+    "cgp_phase_stamps": (_I32, [_I32, ctypes.POINTER(ctypes.c_uint64), _I32,
+                                ctypes.POINTER(_I32)]),
+}
+
 _lib = None
 
 
 def load():
-    """Load libcgp.so once.  torch is imported first so that the library binds
-    to the same HIP runtime instance torch uses (streams and pointers are shared)."""
+    """Load libcgp.so (or the library LIB_PATH names) once.  torch is imported
+    first so that the library binds to the same HIP runtime instance torch
+    uses (streams and pointers are shared)."""
     global _lib
     if _lib is not None:
         return _lib
@@ -92,6 +102,11 @@ def load():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    for name, (res, args) in OPTIONAL_SIGNATURES.items():
+        if hasattr(lib, name):
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
     _lib = lib
     return lib
 

@@ -3,7 +3,11 @@
     python -m paper_1308_3290_amd.build
 
 Every call recompiles.  Objects go to paper_1308_3290_amd/_build/, the shared
-library to paper_1308_3290_amd/libcgp.so.
+library to paper_1308_3290_amd/libcgp.so.  The same call builds the
+measurement library paper_1308_3290_amd/libcgp_stamps.so: the sources that
+hold pass B, the fused one-layer stage pass and the C ABI compiled once more
+with CGP_PHASE_STAMPS (phase stamps and cgp_phase_stamps), linked with the
+other objects of libcgp.so.
 """
 from __future__ import annotations
 
@@ -18,8 +22,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcgp.so")
+STAMPS_LIB = os.path.join(PKG, "libcgp_stamps.so")
 SOURCES = ["solve_kernels.hip", "stencil_kernels.hip", "fused_kernels.hip", "fused2_kernels.hip",
            "adjoint_kernels.hip", "mg_kernels.hip", "persistent_kernels.hip", "runtime.hip"]
+# sources compiled a second time, with the phase stamps, for libcgp_stamps.so
+STAMPED = ["solve_kernels.hip", "fused_kernels.hip", "runtime.hip"]
 ARCH = "gfx950"
 
 
@@ -53,12 +60,14 @@ EXTRA_FLAGS = {"solve_kernels.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
 
 
 def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(os.path.join(BUILD, "stamps"), exist_ok=True)
     cc = hipcc()
 
-    def one(src):
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmd = [cc, *compile_flags(), *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src),
+    def one(job):
+        src, stamped = job
+        obj = os.path.join(BUILD, "stamps" if stamped else "", src.replace(".hip", ".o"))
+        cmd = [cc, *compile_flags(), *EXTRA_FLAGS.get(src, []),
+               *(["-DCGP_PHASE_STAMPS"] if stamped else []), "-c", os.path.join(CSRC, src),
                "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
@@ -67,14 +76,19 @@ def build(verbose: bool = False) -> str:
             print(r.stderr)
         return obj
 
+    jobs = [(s, False) for s in SOURCES] + [(s, True) for s in STAMPED]
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(one, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+        objs = list(ex.map(one, jobs))
+    plain = objs[:len(SOURCES)]
+    stamped = dict(zip(STAMPED, objs[len(SOURCES):]))
+    with_stamps = [stamped.get(s, o) for s, o in zip(SOURCES, plain)]
+    for objects, lib in ((plain, LIB), (with_stamps, STAMPS_LIB)):
+        tmp = lib + ".tmp"
+        cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objects, "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, lib)
     return LIB
 
 

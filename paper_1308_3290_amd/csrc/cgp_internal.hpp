@@ -456,4 +456,32 @@ struct AdjLaunch {
   static hipError_t prepare_fused(size_t bytes);
 };
 
+
+// Phase stamps, compiled in only for the measurement build of the library
+// (CGP_PHASE_STAMPS; libcgp_stamps.so): thread 0 of a block writes the
+// device's steady clock at the phase boundaries of pass B and of the fused
+// stage pass, slot s of block b (the hardware block index) at
+// b * kStampSlots + s of a per-source static device array that every launch
+// overwrites.  The kernels' arithmetic is unchanged; without the macro the
+// stamps compile to nothing.
+constexpr int kStampSlots = 8;
+constexpr int kStampBlocks = 4096;
+#ifdef CGP_PHASE_STAMPS
+static __device__ unsigned long long g_phase_stamps[kStampBlocks * kStampSlots];
+#define CGP_STAMP(slot)                                                              \
+  do {                                                                               \
+    if (threadIdx.x == 0 && blockIdx.x < (unsigned)::cgp::kStampBlocks)              \
+      ::cgp::g_phase_stamps[blockIdx.x * ::cgp::kStampSlots + (slot)] =              \
+          (unsigned long long)wall_clock64();                                        \
+  } while (0)
+// Copy the first nblocks blocks' stamps of pass B (solve_kernels.hip) or of
+// the fused one-layer stage pass (fused_kernels.hip) to host memory.
+hipError_t stamps_copy_solve(unsigned long long* host, int nblocks);
+hipError_t stamps_copy_fused(unsigned long long* host, int nblocks);
+#else
+#define CGP_STAMP(slot) \
+  do {                  \
+  } while (0)
+#endif
+
 }  // namespace cgp

@@ -63,6 +63,7 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
   const double* lamy = lamx + (Mx - 1);
   const double scale = 4.0 / ((double)Mx * (double)My);
   const double shift = nl == 2 ? d.f1 + d.f2 : 0.0;
+  CGP_STAMP(0);  // block start
 
   // the pair's columns (1-based); kb may be absent (one layer, Mx - 1 odd)
   const int ka = nl == 1 ? 1 + 2 * lb : 1 + lb;
@@ -136,6 +137,7 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
       buf[pad(2 * My - l)] = {-va[q], -vb[q]};
     }
   }
+  CGP_STAMP(1);  // the columns are loaded (thread 0's share in LDS)
   if constexpr (LC != 0 && ct_can_merge_ends<LC, kWideCols>()) {
     // Compile-time transform whose first and last radix agree (1024 and 256
     // points): the forward transform's last stage, the eigenvalue divide and
@@ -164,6 +166,7 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
       return cplx<T>{T(-0.5) * z.y * T(scale * recip(lxa + lyl[q][r])),
                      T(0.5) * z.x * T(scale * recip(lxb + lyl[q][r]))};
     });
+    CGP_STAMP(2);  // forward transform and divide done
     const cplx<T>* X2 = ct_stage_range<T, LC, 1, P.n - 1, NT, 1, kWideCols, true>(Y, X, 1, rtw);
     ct_stage_last<T, LC, NT, 1, kWideCols, true>(X2, 1, rtw, [&](int, int m, cplx<T> z, int, int) {
       if (m >= 1 && m < My) {
@@ -200,6 +203,7 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
       }
     };
     ct_run_to<T, LC, NT, 1, kWideCols, true>(divide, buf, buf2, 1, rtw);
+    CGP_STAMP(2);  // forward transform and divide done
     auto store = [&](int, int m, cplx<T> z, int, int) {
       if (m >= 1 && m < My) {
         store_through(&wout[offa + m - 1], T(-0.5) * z.y);
@@ -225,6 +229,7 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
       Y[pad(0)] = {T(0), T(0)};
       Y[pad(My)] = {T(0), T(0)};
     }
+    CGP_STAMP(2);  // forward transform and divide done
     const cplx<T>* R = fft_run<T, LC, NT, kWideCols>(Y, Z, 1, L, d.nst_c, d.stw_c, tw);
 #pragma unroll
     for (int q = 0; q < kRowIter; ++q) {
@@ -236,6 +241,7 @@ __device__ __forceinline__ void col_solve_block(const MemberDesc& d, int lb,
       }
     }
   }
+  CGP_STAMP(3);  // inverse transform done, results stored
   // first stage of a step: the member's dt
   if (ctl != nullptr && lb == 0) update_step_dt<NT>(d, ctl, red);
 }

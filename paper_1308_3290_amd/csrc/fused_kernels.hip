@@ -156,4 +156,14 @@ hipError_t Launch<T>::prepare_fused(size_t bytes) {
 template struct Launch<float>;
 template struct Launch<double>;
 
+#ifdef CGP_PHASE_STAMPS
+hipError_t stamps_copy_fused(unsigned long long* host, int nblocks) {
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_phase_stamps));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(host, p, sizeof(unsigned long long) * kStampSlots * (size_t)nblocks,
+                   hipMemcpyDeviceToHost);
+}
+#endif
+
 }  // namespace cgp

@@ -125,6 +125,7 @@ __device__ __forceinline__ void fused_stage_block(
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + region);
   T* psc = reinterpret_cast<T*>(tw + ntw);
   const int prow = Mx + 1;
+  CGP_STAMP(0);  // block start
 
   // ---- global loads are unconditional (a lane without an element reads
   // element 0 of the same array and discards it), so that they sit in one
@@ -209,6 +210,7 @@ __device__ __forceinline__ void fused_stage_block(
     // the transform's last stage writes its outputs straight into psc (no
     // LDS pass and barrier of a separate copy)
     __syncthreads();
+    CGP_STAMP(1);  // the spectra are in LDS
     constexpr int NLAST = stage_plan(LC).n - 1;
     const cplx<T>* X =
         ct_stage_range<T, LC, 0, NLAST, NT, NSQ, kWideRows>(buf, buf + NSQ * LP, nseq, tw);
@@ -245,6 +247,7 @@ __device__ __forceinline__ void fused_stage_block(
       }
     }
   }
+  CGP_STAMP(2);  // inverse x transform done, coarse psi rows in LDS
   __syncthreads();  // the transform's output is consumed: the tile may overwrite it
 #pragma unroll
   for (int q = 0; q < kWPer; ++q) {
@@ -252,6 +255,7 @@ __device__ __forceinline__ void fused_stage_block(
     if (e < nW) wtile[e] = wv[q];
   }
   __syncthreads();
+  CGP_STAMP(3);  // vorticity tile in LDS
 
   // ---- walls: columns 0 and nx of the own rows (of psi_out too)
   T* PO = psi_out ? psi_out + d.field_off : nullptr;
@@ -373,6 +377,7 @@ __device__ __forceinline__ void fused_stage_block(
       if (PO) PO[(size_t)ny * pitch + x] = T(0);
     }
   }
+  CGP_STAMP(4);  // stencil and RK3 combine done (stores issued)
   // last stage of an adaptive step: the velocity maxima for the next dt
   if (wants_vmax(d, ctl)) put_vmax_coarse<T, C, TJ, NT>(d, ctl, lb, psc, nullptr, prow, j0);
   if constexpr (NEXT) {
@@ -479,6 +484,7 @@ __device__ __forceinline__ void fused_stage_block(
     constexpr int MQ = NQ > 2 ? 4 : 2;
     if constexpr (LC != 0) {
       // the last stage stores its outputs straight to global memory
+      CGP_STAMP(5);  // restriction done
       __syncthreads();
       constexpr int NLAST = stage_plan(LC).n - 1;
       const cplx<T>* X =
@@ -513,6 +519,7 @@ __device__ __forceinline__ void fused_stage_block(
       }
     }
   }
+  CGP_STAMP(6);  // block end (the next stage's spectra stored)
 }
 
 }  // namespace cgp

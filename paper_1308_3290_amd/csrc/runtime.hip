@@ -1619,4 +1619,25 @@ cgp_status cgp_adjoint_step(cgp_handle* h, const void* omega_n, const void* forc
   return CGP_OK;
 }
 
+#ifdef CGP_PHASE_STAMPS
+cgp_status cgp_phase_stamps(int32_t kind, uint64_t* host_out, int32_t nblocks,
+                            int32_t* clock_khz) {
+  if (kind != 0 && kind != 1) return fail(CGP_ERR_INVALID, "kind must be 0 or 1 (got %d)", kind);
+  if (!host_out) return fail(CGP_ERR_INVALID, "host_out is NULL");
+  if (nblocks < 1 || nblocks > kStampBlocks)
+    return fail(CGP_ERR_INVALID, "nblocks must be in 1..%d (got %d)", kStampBlocks, nblocks);
+  HIP_TRY(hipDeviceSynchronize(), "phase stamps sync");
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(host_out);
+  HIP_TRY(kind == 0 ? stamps_copy_solve(out, nblocks) : stamps_copy_fused(out, nblocks),
+          "phase stamps copy");
+  if (clock_khz) {
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "clock rate");
+    *clock_khz = khz;
+  }
+  return CGP_OK;
+}
+#endif
+
 }  // extern "C"

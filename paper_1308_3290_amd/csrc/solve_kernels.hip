@@ -492,4 +492,14 @@ hipError_t Launch<T>::prepare(size_t bytes) {
 template struct Launch<float>;
 template struct Launch<double>;
 
+#ifdef CGP_PHASE_STAMPS
+hipError_t stamps_copy_solve(unsigned long long* host, int nblocks) {
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_phase_stamps));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(host, p, sizeof(unsigned long long) * kStampSlots * (size_t)nblocks,
+                   hipMemcpyDeviceToHost);
+}
+#endif
+
 }  // namespace cgp

@@ -30,9 +30,26 @@ def test_library_exports_every_declared_symbol():
     from paper_1308_3290_amd import _lib
     lib = _lib.load()
     for name in declared_functions():
+        if name in _lib.OPTIONAL_SIGNATURES:
+            continue
         assert hasattr(lib, name), name
         assert name in _lib.SIGNATURES, f"binding lacks {name}"
     assert "gfx950" in lib.cgp_version().decode()
+
+
+def test_measurement_build_exports_the_same_boundary_and_the_stamps():
+    """libcgp_stamps.so exports every declared function, cgp_phase_stamps
+    included; libcgp.so does not have cgp_phase_stamps."""
+    from paper_1308_3290_amd import _lib
+    if not os.path.exists(_lib.STAMPS_LIB_PATH):
+        pytest.skip("libcgp_stamps.so not built")
+    stamps = ctypes.CDLL(_lib.STAMPS_LIB_PATH)
+    names = declared_functions()
+    assert "cgp_phase_stamps" in names
+    for name in names:
+        assert hasattr(stamps, name), name
+        assert name in _lib.SIGNATURES or name in _lib.OPTIONAL_SIGNATURES, name
+    assert not hasattr(ctypes.CDLL(LIB), "cgp_phase_stamps")
 
 
 def _cfg(**kw):

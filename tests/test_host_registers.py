@@ -9,6 +9,9 @@ the budgets the kernels' launch shapes rely on:
   c = 2 use at most 128 VGPRs per lane, so that two 512-thread blocks share a
   CU (four waves per SIMD).  Ensembles of many blocks need that: at 129-132
   VGPRs the 64-basin FP64 ensemble ran a quarter slower.
+
+Both budgets hold for the measurement build (libcgp_stamps.so) too, so that
+its phase stamps time the same launch shapes.
 """
 import os
 import re
@@ -19,12 +22,14 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_1308_3290_amd", "libcgp.so")
+STAMPS_LIB = os.path.join(ROOT, "paper_1308_3290_amd", "libcgp_stamps.so")
 TOOLS = "/opt/rocm/llvm/bin"
 TARGET = "hipv4-amdgcn-amd-amdhsa--gfx950"
 
 
-@pytest.fixture(scope="module")
-def kernels(tmp_path_factory):
+@pytest.fixture(scope="module", params=[LIB, STAMPS_LIB], ids=["libcgp", "libcgp_stamps"])
+def kernels(request, tmp_path_factory):
+    LIB = request.param
     tools = [os.path.join(TOOLS, t) for t in ("llvm-objcopy", "clang-offload-bundler",
                                               "llvm-readelf")]
     if not os.path.exists(LIB) or not all(os.path.exists(t) for t in tools):
