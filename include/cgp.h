@@ -317,9 +317,10 @@ cgp_status cgp_time_step_passes(cgp_handle* h, void* omega_dev, const void* forc
 
 /* Measurement build only: exported by libcgp_stamps.so, the library built
  * with CGP_PHASE_STAMPS (libcgp.so does not have it).  In that build thread 0
- * of every block of pass B and of the one-layer fused stage pass writes the
- * device's steady clock at its phase boundaries (the arithmetic is
- * unchanged); each launch overwrites the stamps of its blocks.  Copies the
+ * of every block of a pass-B launch and of a one-layer fused stage pass
+ * launch writes the device's steady clock at its phase boundaries (the
+ * arithmetic is unchanged; the persistent stage kernel of ensembles writes
+ * no stamps); each launch overwrites the stamps of its blocks.  Copies the
  * stamps of the last launch of pass B (kind 0) or of the fused pass (kind
  * 1) to host_out: nblocks (1..4096, hardware block index order) x 8 slots of
  * uint64 clock ticks, unwritten slots unspecified.  Pass B slots: 0 block
