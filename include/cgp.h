@@ -144,7 +144,9 @@ cgp_status cgp_create(const cgp_config* cfg, void* workspace_dev, size_t bytes,
                       void* stream, cgp_handle** out);
 
 /* Release the handle's host state.  The workspace goes back to the caller
- * once work enqueued on the handle has finished. */
+ * once work enqueued on the handle has finished.  The handle's captured
+ * graphs are destroyed after the last replay it enqueued has finished (the
+ * call waits for that replay, not for other work). */
 cgp_status cgp_destroy(cgp_handle* h);
 
 /* Advance omega_dev ([L][ny+1][nx+1], in/out) by nsteps CGPRK3 steps
@@ -275,8 +277,10 @@ cgp_status cgp_ensemble_step(cgp_handle* h, void* omega_packed_dev,
 /* Select how h's time steps are launched (cgp_launch; the default is mode 0
  * with tiles of 1).  Mode 1 on a handle without it gives
  * CGP_ERR_UNSUPPORTED; tiles below 1 or wg_per_cu outside 0..16,
- * CGP_ERR_INVALID.  Uploads the work queue of mode 1 into the workspace on
- * `stream` and synchronises it; graphs captured before are dropped. */
+ * CGP_ERR_INVALID.  Graphs captured before are dropped once the last replay
+ * the handle enqueued has finished (the call waits for it); then the work
+ * queue of mode 1 is uploaded into the workspace on `stream`, which is
+ * synchronised. */
 cgp_status cgp_set_launch(cgp_handle* h, const cgp_launch* launch, void* stream);
 
 /* The handle's launch setting; *persistent_available (nullable) = 1 when

@@ -474,6 +474,9 @@ struct cgp_handle {
   // side streams and events of chained graph captures (made on first use)
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> events;
+  // recorded on the caller's stream after the last graph replay a call
+  // enqueued (made on first use); dropping the graphs waits for it
+  hipEvent_t graph_done = nullptr;
   // persistent stage kernel: tiles in the queue and the launch grid
   int persist_ntiles = 0, persist_grid = 0;
   int ncu = 0;  // compute units of the handle's device
@@ -1031,6 +1034,7 @@ cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_
   T* w = static_cast<T*>(omega);
   const T* F = static_cast<const T*>(forcing);
   const bool graph = use_graph && s != nullptr;
+  bool replayed = false;
   if (!h->plan.fused) {
     for (int n = 0; n < nsteps; ++n) {
       if (graph) {
@@ -1038,6 +1042,7 @@ cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_
         cgp_status st = step_graph<T>(h, w, F, 0, sum, s, &exec);
         if (st != CGP_OK) return st;
         HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
+        replayed = true;
       } else {
         HIP_TRY(enqueue_step<T>(h, w, F, s), "step launch");
         if (sum) HIP_TRY(enqueue_mean<T>(h, w, sum, s), "accumulate launch");
@@ -1056,6 +1061,7 @@ cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_
         cgp_status st = step_graph<T>(h, w, F, q, sum, s, &exec);
         if (st != CGP_OK) return st;
         HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
+        replayed = true;
         const int done = q == 3 ? 3 : 1;
         n += done;
         pos = (pos + done) % 3;
@@ -1074,8 +1080,21 @@ cgp_status step_impl(cgp_handle* h, void* omega, const void* forcing, void* psi_
               "state copy");
     }
   }
+  if (replayed) {
+    if (!h->graph_done)
+      HIP_TRY(hipEventCreateWithFlags(&h->graph_done, hipEventDisableTiming), "graph event");
+    HIP_TRY(hipEventRecord(h->graph_done, s), "graph event record");
+  }
   if (psi_out) HIP_TRY(enqueue_solve<T>(h, w, static_cast<T*>(psi_out), 0, s), "psi launch");
   return CGP_OK;
+}
+
+// Destroy the handle's graph executables once their last replay has finished
+// (a caller may drop them right after enqueueing a replay on its stream).
+void drop_graphs(cgp_handle* h) {
+  if (!h->graphs.empty() && h->graph_done) (void)hipEventSynchronize(h->graph_done);
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
 }
 
 // ---------------------------------------------------------------------------
@@ -1185,7 +1204,8 @@ cgp_status cgp_ensemble_create(const cgp_config* members, int32_t count, void* w
 
 cgp_status cgp_destroy(cgp_handle* h) {
   if (!h) return CGP_OK;
-  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  drop_graphs(h);
+  if (h->graph_done) (void)hipEventDestroy(h->graph_done);
   for (hipStream_t st : h->side) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
   delete h;
@@ -1370,6 +1390,9 @@ cgp_status cgp_set_launch(cgp_handle* h, const cgp_launch* l, void* stream) {
                 "the persistent stage kernel takes one layer at coarsening factor 2 with row "
                 "transforms of 128-512 and column transforms of 256-1024 points");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // the graphs of the old launch go first: their last replay may still read
+  // the work queue that the upload below rewrites
+  drop_graphs(h);
   p.launch = *l;
   if (p.persist_ok) {
     // the queue of the new tiles (same counters: they are zero between launches)
@@ -1386,8 +1409,6 @@ cgp_status cgp_set_launch(cgp_handle* h, const cgp_launch* l, void* stream) {
                               : persist_grid<float>(h, h->persist_ntiles, &h->persist_grid);
     if (st != CGP_OK) return st;
   }
-  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
-  h->graphs.clear();
   return CGP_OK;
 }
 

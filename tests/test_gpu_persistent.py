@@ -115,6 +115,38 @@ def test_persistent_mode_refused_where_unavailable():
         Ensemble([config_from_case(ci.make_case(128, 256, level=1))]).set_launch(mode=1, b_tile=0)
 
 
+def test_launch_change_and_destroy_right_after_graph_replays():
+    """cgp_set_launch and cgp_destroy called while the handle's graph replays
+    may still run on the caller's stream (no synchronisation between): both
+    wait for the last replay before dropping the graphs, so the state equals
+    that of the same steps run with synchronisations in between, bit for bit,
+    across a change to the persistent launch and back."""
+    from paper_1308_3290_amd.api import Ensemble, config_from_case
+    say("graphs dropped right after replays: 3 members, 3 + 3 + 3 steps")
+    cases = _cases("f64")[:3]
+    rng = np.random.default_rng(79)
+    w0s = [ci.initial_field(c, rng, 1.0) for c in cases]
+    Fs = [ci.forcing_field(c) for c in cases]
+    ref, W_ref, _ = _run(cases, w0s, Fs, 9, None, True)
+    ref.close()
+    ens = Ensemble([config_from_case(c) for c in cases])
+    W = ens.pack(w0s)
+    Fp = ens.pack(Fs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ens.step(W, Fp, nsteps=3, use_graph=True, stream=side)
+        ens.set_launch(mode=1, stream=side)
+        ens.step(W, Fp, nsteps=3, use_graph=True, stream=side)
+        ens.set_launch(mode=0, stream=side)
+        ens.step(W, Fp, nsteps=3, use_graph=True, stream=side)
+        fault = ens.persistent_fault(stream=side)
+        ens.close()
+    torch.cuda.synchronize()
+    assert fault == 0
+    assert torch.equal(W, W_ref)
+
+
 @pytest.mark.skip(reason="aborted once on the GPU (SIGABRT raised on a native thread, no HIP or "
                          "GPU fault message) after passing in earlier runs with the same kernels; "
                          "no cause found by reading the host and device code, so it stays off the "
