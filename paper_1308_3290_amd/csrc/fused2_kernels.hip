@@ -136,7 +136,14 @@ __global__ __launch_bounds__(kFusedThreads) void k_prolong_stencil2(
 #pragma unroll
   for (int q = 0; q < kTwPer; ++q) {
     const int m = t + NT * q;
-    if (m < ntw) tw[m] = {twx[q], twy[q]};
+    // with the psi rows after the table (C > 1) a thread past it writes slot
+    // ntw, which they overwrite later: an unconditional store keeps the
+    // twiddle load first instead of sunk behind the other loads and waited
+    // for with them (the one-layer fused pass does the same)
+    if constexpr (!INPLACE)
+      tw[m < ntw ? m : ntw] = {twx[q], twy[q]};
+    else if (m < ntw)
+      tw[m] = {twx[q], twy[q]};
   }
   if (t < NS) {
     buf[t * LP + pad(0)] = {T(0), T(0)};
