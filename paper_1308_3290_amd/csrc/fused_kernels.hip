@@ -20,9 +20,9 @@
 // overlap with other blocks.  The twiddles and spectra are loaded first (the
 // transform waits for them only); once they are in LDS the forcing and
 // omega_n are issued, and they arrive while the transform runs.  The
-// vorticity rows are issued with the spectra at c = 2 (measured faster, for
-// single basins and ensembles) and with the forcing at c = 1, 4 and 8
-// (measured faster at c = 1 and 4).  Rows are at most kFusedMaxNx + 1 nodes
+// vorticity rows are issued with the spectra at c = 1, 2 and 4 (measured
+// faster, for single basins and ensembles, once the first barrier no longer
+// waits for them) and with the forcing in the split blocks of c = 8.  Rows are at most kFusedMaxNx + 1 nodes
 // wide.
 #include "cgp_internal.hpp"
 #include "fft_lds.hpp"
@@ -52,7 +52,7 @@ k_prolong_stencil(
                                                            out, psi_out, a_, b_, ctl, smem);
   } else {
     static_assert(C < 4 || split_blocks(C) == 1, "one or two blocks per coarse row");
-    fused_stage_block<T, C, TJ, LC, NEXT, (C == 2), NTS>(d, lb, wt, wnext, twg, ws, forcing, wn,
+    fused_stage_block<T, C, TJ, LC, NEXT, true, NTS>(d, lb, wt, wnext, twg, ws, forcing, wn,
                                                         out, psi_out, a_, b_, ctl, smem);
   }
 }
